@@ -1,0 +1,112 @@
+"""Brute-force ground truth for the eigenvalues inside a contour (oracle; test
+infrastructure only).
+
+* polynomial T: every eigenvalue of the full first companion linearisation (Sec. 2),
+  or, for large n, the eigenvalues nearest a point from shift-invert Arnoldi (ARPACK)
+  on that linearisation, applying (L(sigma))^{-1} through one LU of T(sigma) by block
+  elimination;
+* any T: the number of eigenvalues inside C as the winding number of det T(z) along C
+  (argument principle), with log det T(z) taken from LU factors.
+"""
+import numpy as np
+import scipy.linalg
+import scipy.sparse.linalg as spla
+
+from .reduced import companion_first
+
+
+def poly_coeffs(problem):
+    """C_0..C_k of a polynomial Problem."""
+    if not problem.is_polynomial:
+        raise ValueError("not polynomial")
+    k = problem.degree
+    C = [np.zeros((problem.n, problem.n), dtype=complex) for _ in range(k + 1)]
+    for (_, p), A in zip(problem.terms, problem.mats):
+        C[int(p)] = C[int(p)] + A
+    return C
+
+
+def companion_eigs(problem):
+    """All k n eigenvalues of the polynomial problem (inf where B is singular), by QZ on
+    the first companion form."""
+    A, B = companion_first(poly_coeffs(problem))
+    ab = scipy.linalg.eigvals(-A, B, homogeneous_eigvals=True)
+    alpha, beta = ab[0], ab[1]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(np.abs(beta) > 0, alpha / np.where(beta == 0, 1, beta), np.inf)
+
+
+def companion_eigs_near(problem, sigma, k, tol=1e-13):
+    """The k eigenvalues nearest sigma, by shift-invert Arnoldi on the first companion
+    pencil (-A) v = lambda B v, i.e. eigenvalues nu = 1/(lambda - sigma) of
+    (-A - sigma B)^{-1} B.  The solve with M = -(A + sigma B) reduces to one solve with
+    P(sigma) = sum_i sigma^i C_i by eliminating the lower block rows."""
+    C = poly_coeffs(problem)
+    deg = len(C) - 1
+    n = problem.n
+    sigma = complex(sigma)
+    lu = scipy.linalg.lu_factor(sum(sigma ** i * C[i] for i in range(deg + 1)), check_finite=False)
+
+    # Companion rows 2..k read  -v_{i-1} + ... :  M = -(A + sigma B).  Writing the
+    # unknown as blocks u_0..u_{k-1} (u_{k-1} = y-part), rows i >= 1 of M u = b give
+    # u_{i-1} = b_i + sigma u_i, so every u_i is u_{k-1} times a power of sigma plus
+    # known terms; the first row then gives P(sigma) u_{k-1} = -(b_0 + ...).
+    def apply(v):
+        v = v.reshape(deg, n)
+        b = np.empty_like(v)
+        b[0] = C[deg] @ v[0]
+        b[1:] = v[1:]
+        # u_i = sigma^{k-1-i} u_{k-1} + s_i, with s_{k-1} = 0, s_{i-1} = b_i + sigma s_i
+        s = np.zeros_like(v)
+        for i in range(deg - 1, 0, -1):
+            s[i - 1] = b[i] + sigma * s[i]
+        # first row of M u = b: -(sum_i C_{k-1-i} u_i + sigma C_k u_0) = b_0
+        rhs = -b[0] - sigma * (C[deg] @ s[0])
+        for i in range(deg):
+            rhs = rhs - C[deg - 1 - i] @ s[i]
+        ylast = scipy.linalg.lu_solve(lu, rhs, check_finite=False)
+        u = np.empty_like(v)
+        for i in range(deg):
+            u[i] = sigma ** (deg - 1 - i) * ylast + s[i]
+        return u.ravel()
+
+    N = deg * n
+    op = spla.LinearOperator((N, N), matvec=apply, dtype=complex)
+    nu = spla.eigs(op, k=k, which="LM", tol=tol, return_eigenvectors=False,
+                   ncv=min(N - 1, max(2 * k + 1, 40)))
+    lam = sigma + 1.0 / nu
+    return lam[np.argsort(np.abs(lam - sigma))]
+
+
+def logdet(M):
+    """log det M (complex, branch not normalised) from LU with partial pivoting."""
+    lu, piv = scipy.linalg.lu_factor(M, check_finite=False)
+    d = np.diag(lu)
+    sign = (-1.0) ** int(np.sum(piv != np.arange(len(piv))))
+    return np.sum(np.log(d.astype(complex))) + (0 if sign > 0 else 1j * np.pi)
+
+
+def winding_count(problem, contour, npts=256, max_step=0.5):
+    """Number of eigenvalues of T inside C: (1/2 pi) times the total change of
+    arg det T(z) around C.  The sampling is refined until every step of the unwrapped
+    phase is below max_step radians."""
+    theta = np.linspace(0.0, 2 * np.pi, npts + 1)
+    vals = {}
+
+    def phase(t):
+        if t not in vals:
+            vals[t] = np.angle(np.exp(1j * logdet(problem.T(contour.point(t))).imag))
+        return vals[t]
+
+    pts = list(theta)
+    total = 0.0
+    i = 0
+    while i < len(pts) - 1:
+        a, b = pts[i], pts[i + 1]
+        d = np.angle(np.exp(1j * (phase(b) - phase(a))))
+        if abs(d) > max_step and b - a > 1e-9:
+            pts.insert(i + 1, 0.5 * (a + b))
+            continue
+        total += d
+        i += 1
+    return int(round(total / (2 * np.pi)))

@@ -1,0 +1,112 @@
+"""Write tests/golden/contours.json: the contour (centre, radius) of each named workload
+and the brute-force eigenvalues inside it.  Calls only the oracle's brute-force routines
+and the seeded generators; nothing here touches the GPU library.
+
+    python tests/golden/make_contours.py [name ...]
+
+Recipes (contour seed 3000 + id):
+  qep200      all 400 companion eigenvalues; centre = a seeded pick among them; radius =
+              midpoint between the 10th and 11th distances (the centre is the 1st); a
+              draw is rejected when the relative gap at that boundary is under 5%.
+  damped4096  centre = the eigenvalue nearest i y0, y0 ~ U(0.3, 1.5); the 64 eigenvalues
+              nearest the centre from shift-invert Arnoldi on the companion pencil;
+              radius = midpoint between the 40th and 41st distances; rejected under a 2%
+              relative gap.
+  qep2048x8   all 4096 companion eigenvalues; 8 disjoint circles with p_r = round(0.625
+              m0_r) eigenvalues each, centres drawn in the bulk |lambda| < 0.8, radius at
+              the gap midpoint, rejected under a 5% gap or when two circles come closer
+              than 10% of the larger radius.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as wl  # noqa: E402
+from oracle import brute, problem as pb  # noqa: E402
+
+OUT = os.path.join(HERE, "contours.json")
+
+
+def ring(lam, centre, k):
+    d = np.sort(np.abs(lam - centre))
+    return d, 0.5 * (d[k - 1] + d[k]), (d[k] - d[k - 1]) / d[k]
+
+
+def qep200():
+    cfg = wl.CONFIGS["qep200"]
+    terms, mats = wl.make_problem("qep200")
+    lam = brute.companion_eigs(pb.Problem(terms, mats))
+    rng = np.random.default_rng(3000 + cfg["id"])
+    while True:
+        c = lam[rng.integers(len(lam))]
+        _, r, gap = ring(lam, c, cfg["inside"])
+        if gap >= 0.05:
+            break
+    inside = lam[np.abs(lam - c) < r]
+    return dict(regions=[dict(centre=[c.real, c.imag], radius=r, gap=gap,
+                              eigenvalues=[[v.real, v.imag] for v in inside])])
+
+
+def damped4096():
+    cfg = wl.CONFIGS["damped4096"]
+    terms, mats = wl.make_problem("damped4096")
+    P = pb.Problem(terms, mats)
+    rng = np.random.default_rng(3000 + cfg["id"])
+    while True:
+        y0 = rng.uniform(0.3, 1.5)
+        near = brute.companion_eigs_near(P, 1j * y0, 8)
+        c = near[0]
+        lam = brute.companion_eigs_near(P, c, 64)
+        d, r, gap = ring(lam, c, cfg["inside"])
+        if gap >= 0.02:
+            break
+    inside = lam[np.abs(lam - c) < r]
+    return dict(regions=[dict(centre=[c.real, c.imag], radius=r, gap=gap,
+                              eigenvalues=[[v.real, v.imag] for v in inside])])
+
+
+def qep2048x8():
+    cfg = wl.CONFIGS["qep2048x8"]
+    terms, mats = wl.make_problem("qep2048x8")
+    lam = brute.companion_eigs(pb.Problem(terms, mats))
+    rng = np.random.default_rng(3000 + cfg["id"])
+    bulk = lam[np.abs(lam) < 0.8]
+    regions = []
+    for m0 in cfg["m0s"]:
+        p = int(round(0.625 * m0))
+        while True:
+            c = bulk[rng.integers(len(bulk))]
+            _, r, gap = ring(lam, c, p)
+            ok = gap >= 0.05 and all(
+                abs(c - complex(*g["centre"])) > 1.1 * (r + g["radius"]) for g in regions)
+            if ok:
+                break
+        inside = lam[np.abs(lam - c) < r]
+        regions.append(dict(centre=[c.real, c.imag], radius=r, gap=gap, m0=m0,
+                            eigenvalues=[[v.real, v.imag] for v in inside]))
+    return dict(regions=regions)
+
+
+RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8}
+
+
+def main(names):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name in names:
+        t0 = time.time()
+        data[name] = RECIPES[name]()
+        data[name]["seconds"] = time.time() - t0
+        print(name, "regions", len(data[name]["regions"]),
+              "inside", [len(g["eigenvalues"]) for g in data[name]["regions"]],
+              "%.1fs" % data[name]["seconds"], flush=True)
+        json.dump(data, open(OUT, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or list(RECIPES))

@@ -1,0 +1,332 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics, not by the
+oracle itself: closed-form spectra (mass-spring QEPs of Sec. 5), values printed in the
+paper (Table 1), closed forms of the quadrature filter, the reduction of Step 4 to the
+linear FEAST filter for a linear pencil (Sec. 4.2), brute-force companion eigenvalues,
+and a known-spectrum non-polynomial family."""
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.linalg
+
+import workloads as wl
+from oracle import brute, dense, nlfeast, problem as pb, quadrature as qd, reduced
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def mass_spring_closed_form(n, tau, kappa):
+    """Eigenvalues of lambda^2 I + lambda tau T3 + kappa T3, T3 = tridiag(-1, 3, -1):
+    T3 has eigenvalues mu_j = 3 - 2 cos(j pi / (n + 1)) with the same eigenvectors for
+    all three coefficients, so each mu_j gives the scalar quadratic
+    lambda^2 + tau mu_j lambda + kappa mu_j = 0."""
+    j = np.arange(1, n + 1)
+    mu = 3.0 - 2.0 * np.cos(j * np.pi / (n + 1))
+    disc = np.sqrt((tau * mu) ** 2 - 4.0 * kappa * mu + 0j)
+    return np.concatenate([(-tau * mu + disc) / 2.0, (-tau * mu - disc) / 2.0])
+
+
+def load_table1():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "table1_ex1.txt")) if l.strip() and not l.startswith("#")]
+    return np.array([float(r[1]) for r in rows]), np.array([float(r[2]) for r in rows])
+
+
+def match_error(a, b, scale):
+    """Largest |a_i - b_pi(i)| / scale over the optimal one-to-one matching."""
+    from scipy.optimize import linear_sum_assignment
+    a = np.asarray(a)
+    b = np.asarray(b)
+    assert len(a) == len(b)
+    if len(a) == 0:
+        return 0.0
+    cost = np.abs(a[:, None] - b[None, :])
+    r, c = linear_sum_assignment(cost)
+    return float(np.max(cost[r, c]) / scale)
+
+
+# ---------------------------------------------------------------- quadrature
+
+@pytest.mark.parametrize("nc", [4, 8, 16, 24])
+def test_gauss_filter_is_one_at_centre(nc):
+    # on a circle omega_k / (z_k - c) = w_k / 2, and the Legendre weights sum to 2
+    C = qd.Contour(0.3 - 0.2j, 0.7)
+    z, w = qd.nodes_weights(C, nc)
+    assert abs(qd.filter_value(z, w, C.c) - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("nc", [4, 8, 16])
+def test_trapezoid_filter_closed_form(nc):
+    # nodes at the nc-th roots of -1 give rho(lambda) = 1 / (1 + mu^nc), mu = (lambda-c)/r
+    C = qd.Contour(1.0 + 1.0j, 2.0)
+    z, w = qd.nodes_weights(C, nc, rule="trapezoid")
+    rng = np.random.default_rng(5)
+    lam = C.c + 2.0 * (rng.uniform(-1.5, 1.5, 20) + 1j * rng.uniform(-1.5, 1.5, 20))
+    mu = (lam - C.c) / 2.0
+    assert np.max(np.abs(qd.filter_value(z, w, lam) - 1.0 / (1.0 + mu ** nc))) < 1e-12
+
+
+@pytest.mark.parametrize("shape,nc", [((0.0, 1.0, 1.0), 64), ((-1.55, 0.05, 0.0035), 512),
+                                      ((2 + 1j, 0.5, 2.0), 256)])
+def test_weights_against_adaptive_integration(shape, nc):
+    # sum_k omega_k g(z_k) for g(z) = z^2 / (z - lam) vs adaptive integration of the
+    # parametrised contour integral (independent of the Legendre rule)
+    c, a, b = shape
+    C = qd.Contour(c, a, b)
+    lam = C.c + 0.3 * a + 0.2j * b
+    z, w = qd.nodes_weights(C, nc)
+    g = lambda zz: zz ** 2 / (zz - lam)
+    approx = np.sum(w * g(z))
+
+    def integrand(t, part):
+        v = g(C.point(t)) * C.dpoint(t) / (2j * np.pi)
+        return v.real if part == 0 else v.imag
+
+    ref = sum(s * scipy.integrate.quad(integrand, 0, 2 * np.pi, args=(p,), limit=400, epsabs=1e-14)[0]
+              for p, s in ((0, 1), (1, 1j)))
+    # residue theorem: the integral equals lam^2 (lam inside)
+    assert abs(ref - lam ** 2) < 1e-9 * max(1, abs(lam) ** 2)
+    assert abs(approx - ref) < 1e-8 * max(1, abs(ref))
+
+
+def test_inside_is_strict():
+    C = qd.Contour(0.0, 2.0, 1.0)
+    assert not C.inside(2.0 + 0j)
+    assert C.inside(1.999 + 0j)
+    assert not C.inside(np.inf)
+
+
+# ---------------------------------------------------------------- brute force
+
+def test_companion_matches_mass_spring_closed_form():
+    terms, mats = wl.mass_spring(60, 0.6202, 0.4807)
+    lam = brute.companion_eigs(pb.Problem(terms, mats))
+    ref = mass_spring_closed_form(60, 0.6202, 0.4807)
+    assert match_error(lam, ref, 1.0) < 1e-12
+
+
+def test_table1_is_the_closed_form():
+    # the printed Table 1 (10 digits) agrees with the closed form to its rounding
+    tab, _ = load_table1()
+    ref = mass_spring_closed_form(1000, 0.6202, 0.4807)
+    C = qd.Contour(-1.55, 0.05, 0.0035)
+    inside = ref[C.inside(ref)]
+    assert len(inside) == 20
+    assert np.max(np.abs(np.sort(inside.real) - np.sort(tab))) < 6e-11
+    assert np.max(np.abs(inside.imag)) == 0.0
+
+
+def test_shift_invert_near_matches_full_companion():
+    terms, mats = wl.random_qep(80, 11)
+    P = pb.Problem(terms, mats)
+    full = brute.companion_eigs(P)
+    sigma = full[17] + 0.01
+    near = brute.companion_eigs_near(P, sigma, 12)
+    ref = full[np.argsort(np.abs(full - sigma))[:12]]
+    assert match_error(near, ref, 1.0) < 1e-11
+
+
+def test_winding_count_matches_companion():
+    terms, mats = wl.random_qep(40, 12)
+    P = pb.Problem(terms, mats)
+    full = brute.companion_eigs(P)
+    C = qd.Contour(full[3], 0.4)
+    assert brute.winding_count(P, C) == int(C.inside(full).sum())
+
+
+# ---------------------------------------------------------------- reduced solve
+
+def test_companion_first_general_degree():
+    rng = np.random.default_rng(3)
+    coeffs = [wl.cn(rng, (5, 5)) for _ in range(4)]       # cubic
+    lam, Y = reduced._poly_eigs(coeffs)
+    assert len(lam) == 15
+    for l, y in zip(lam, Y.T):
+        P = sum(l ** i * c for i, c in enumerate(coeffs))
+        s = np.linalg.svd(P, compute_uv=False)
+        assert s[-1] < 1e-10 * s[0]
+        assert np.linalg.norm(P @ y) < 1e-9 * s[0] * np.linalg.norm(y)
+
+
+def test_taylor_coeffs_sum_to_function():
+    for kind, p in (("pow", 3), ("pow", 0), ("exp", 1.7)):
+        t = pb.taylor_coeffs(kind, p, 0.3 + 0.4j, 20)
+        mu = 0.05 - 0.02j
+        approx = sum(t[q] * mu ** q for q in range(21))
+        exact = pb.f_eval(kind, p, 0.3 + 0.4j + mu)
+        assert abs(approx - exact) < 1e-15 * max(1, abs(exact))
+
+
+def test_select_orders_by_normalised_radius():
+    C = qd.Contour(0.0, 2.0, 1.0)
+    lam = np.array([3.0, 0.5j, np.inf, 1.0, 0.9j, 1.0])
+    assert list(reduced.select(lam, C, 6)) == [1, 3, 5, 4, 0, 2]   # radii .5 .5 .5 .9 1.5 inf
+
+
+# ---------------------------------------------------------------- Step 4
+
+def test_step4_is_linear_feast_filter_for_a_pencil():
+    # T(lambda) = lambda I - D: X - T^{-1}(z) T(X, Lambda) = (zI - D)^{-1} X (zI - Lambda),
+    # so Step 4 gives Q = rho(D) X for every Lambda off the nodes (Sec. 4.2: the
+    # nonlinear integral reduces to the linear FEAST one for a linear pencil)
+    rng = np.random.default_rng(4)
+    n, m = 30, 6
+    d = wl.cn(rng, n)
+    P = pb.Problem([("pow", 1), ("pow", 0)], [np.eye(n), -np.diag(d)])
+    C = qd.Contour(0.1, 0.9)
+    z, w = qd.nodes_weights(C, 12)
+    X = wl.cn(rng, (n, m))
+    lam = wl.cn(rng, m)
+    R = P.block_residual(X, lam)
+    facs = [scipy.linalg.lu_factor(P.T(zk)) for zk in z]
+    Q = nlfeast.step4(facs, X, R, lam, z, w)
+    rho = qd.filter_value(z, w, d)
+    assert np.max(np.abs(Q - rho[:, None] * X)) < 1e-12 * np.max(np.abs(X))
+
+
+def test_step4_fixed_point_at_exact_eigenpairs():
+    # exact eigenpairs give T(X, Lambda) = 0 and Q = X rho(Lambda)
+    terms, mats = wl.mass_spring(40, 0.6202, 0.4807)
+    P = pb.Problem(terms, mats)
+    j = np.arange(1, 41)
+    V = np.sin(np.outer(j, j) * np.pi / 41)          # eigenvectors of T3
+    lam = mass_spring_closed_form(40, 0.6202, 0.4807)[:40]
+    X = V / np.linalg.norm(V, axis=0)
+    R = P.block_residual(X.astype(complex), lam)
+    assert np.max(np.linalg.norm(R, axis=0)) < 1e-13
+    C = qd.Contour(-0.5, 1.0)
+    z, w = qd.nodes_weights(C, 8)
+    facs = [scipy.linalg.lu_factor(P.T(zk)) for zk in z]
+    Q = nlfeast.step4(facs, X, R, lam, z, w)
+    assert np.max(np.abs(Q - X * qd.filter_value(z, w, lam)[None, :])) < 1e-11
+
+
+# ---------------------------------------------------------------- dense steps
+
+def test_lu_partial_pivot_definition():
+    rng = np.random.default_rng(6)
+    A = wl.cn(rng, (40, 40))
+    LU, ipiv = dense.lu_partial_pivot(A)
+    L = np.tril(LU, -1) + np.eye(40)
+    U = np.triu(LU)
+    assert np.max(np.abs(dense.apply_pivots(ipiv, A) - L @ U)) < 1e-13
+    assert np.max(np.abs(L)) <= np.sqrt(2.0) + 1e-15        # |l| <= sqrt 2 with |Re|+|Im| pivots
+    lu2, piv2 = scipy.linalg.lu_factor(A)
+    assert np.array_equal(ipiv, piv2)                        # same pivot choices as LAPACK
+    assert np.max(np.abs(LU - lu2)) < 1e-12
+    B = wl.cn(rng, (40, 3))
+    assert np.max(np.abs(dense.lu_solve(LU, ipiv, B) - np.linalg.solve(A, B))) < 1e-11
+
+
+def test_lu_pivot_convention_small():
+    A = np.array([[1, 2, 3], [4, 5, 6], [7, 8, 10]], dtype=complex)
+    _, ipiv = dense.lu_partial_pivot(A)
+    assert list(ipiv) == [2, 2, 2]
+
+
+# ---------------------------------------------------------------- full Algorithm 1
+
+def test_example1_reproduces_table1():
+    terms, mats = wl.mass_spring(1000, 0.6202, 0.4807)
+    P = pb.Problem(terms, mats)
+    C = qd.Contour(-1.55, 0.05, 0.0035)
+    z, w = qd.nodes_weights(C, 16)
+    r = nlfeast.solve(P, C, z, w, wl.initial_block(1000, 22, 2101), 22, 1e-10)
+    tab, _ = load_table1()
+    assert r.converged and r.inside.sum() == 20
+    assert np.max(np.abs(np.sort(r.eigenvalues.real) - np.sort(tab))) < 6e-11
+    assert np.max(r.res[r.inside]) <= 1e-10
+    assert r.iters <= 6            # the paper reports 3; the count depends on X0
+
+
+def test_example2_overdamped():
+    # the printed radius r = 19 encloses 34 eigenvalues (> m0 = 25); the half-width of
+    # the interval (-30, -11), r = 9.5, encloses the 19 the paper reports
+    terms, mats = wl.mass_spring(50, 10.0, 5.0)
+    ref = mass_spring_closed_form(50, 10.0, 5.0)
+    assert qd.Contour(-20.5, 19.0).inside(ref).sum() == 34
+    C = qd.Contour(-20.5, 9.5)
+    assert C.inside(ref).sum() == 19
+    z, w = qd.nodes_weights(C, 8)
+    r = nlfeast.solve(pb.Problem(terms, mats), C, z, w, wl.initial_block(50, 25, 2102), 25, 1e-10)
+    assert r.converged and r.inside.sum() == 19
+    assert match_error(r.eigenvalues, ref[C.inside(ref)], 20.5) < 1e-12
+
+
+def test_random_qep_matches_companion():
+    terms, mats = wl.random_qep(200, 1001)
+    P = pb.Problem(terms, mats)
+    full = brute.companion_eigs(P)
+    C = qd.Contour(full[0] + 0.05, 0.35)
+    k = int(C.inside(full).sum())
+    assert 2 <= k < 20
+    z, w = qd.nodes_weights(C, 8)
+    r = nlfeast.solve(P, C, z, w, wl.initial_block(200, 20, 2001), 20, 1e-12)
+    assert r.converged and r.inside.sum() == k
+    assert match_error(r.eigenvalues, full[C.inside(full)], 0.35) < 1e-10
+    assert np.max(r.res[r.inside]) <= 1e-12
+
+
+def test_m0_too_small_raises():
+    terms, mats = wl.mass_spring(50, 10.0, 5.0)
+    C = qd.Contour(-20.5, 19.0)                   # 34 inside
+    z, w = qd.nodes_weights(C, 8)
+    with pytest.raises(nlfeast.M0TooSmall):
+        nlfeast.solve(pb.Problem(terms, mats), C, z, w, wl.initial_block(50, 25, 5), 25, 1e-10, max_iter=8)
+
+
+def known_spectrum_delay(n, seed, centre, radius, n_in):
+    """T(lambda) = U diag(p_i(lambda)) V^H with p_i = lambda^2 + b_i lambda + c_i +
+    e_i exp(-lambda), U, V unitary.  det T = det(U V^H) prod p_i, so the eigenvalues are
+    the roots of the scalar p_i.  c_i is set so that p_i has a root at a chosen s_i;
+    the first n_in roots are placed inside the circle, the rest outside."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(wl.cn(rng, (n, n)))
+    V, _ = np.linalg.qr(wl.cn(rng, (n, n)))
+    ang = rng.uniform(0, 2 * np.pi, n)
+    rad = np.where(np.arange(n) < n_in, rng.uniform(0.0, 0.7, n), rng.uniform(1.4, 4.0, n)) * radius
+    s = centre + rad * np.exp(1j * ang)
+    b = wl.cn(rng, n) * 0.3
+    e = 0.2 * wl.cn(rng, n)
+    c = -(s ** 2 + b * s + e * np.exp(-s))
+    mk = lambda d: (U * d[None, :]) @ V.conj().T
+    mats = [mk(np.ones(n)), mk(b), mk(c), mk(e)]
+    terms = [("pow", 2), ("pow", 1), ("pow", 0), ("exp", 1.0)]
+    return terms, mats, (b, c, e)
+
+
+def scalar_roots_inside(b, c, e, contour):
+    """Roots of p(l) = l^2 + b l + c + e exp(-l) strictly inside the contour: Newton from
+    a grid of starts, deduplicated, with the count checked by the scalar argument
+    principle (1/2 pi i) oint p'/p dz."""
+    p = lambda l: l ** 2 + b * l + c + e * np.exp(-l)
+    dp = lambda l: 2 * l + b - e * np.exp(-l)
+    th = np.linspace(0, 2 * np.pi, 4001)
+    zz = contour.point(th)
+    count = int(round(np.sum(np.diff(np.unwrap(np.angle(p(zz))))) / (2 * np.pi)))
+    roots = []
+    g = np.linspace(-1, 1, 15)
+    for x in g:
+        for y in g:
+            l = contour.c + contour.a * x + 1j * contour.b * y
+            for _ in range(60):
+                l = l - p(l) / dp(l)
+            if abs(p(l)) < 1e-13 and contour.inside(l) and all(abs(l - r) > 1e-8 for r in roots):
+                roots.append(l)
+    assert len(roots) == count
+    return roots
+
+
+def test_delay_known_spectrum():
+    C = qd.Contour(0.4 + 0.6j, 0.3)
+    terms, mats, (b, c, e) = known_spectrum_delay(40, 21, C.c, C.a, 6)
+    truth = []
+    for i in range(40):
+        truth += scalar_roots_inside(b[i], c[i], e[i], C)
+    assert len(truth) >= 6
+    P = pb.Problem(terms, mats)
+    z, w = qd.nodes_weights(C, 16)
+    m0 = len(truth) + 6
+    r = nlfeast.solve(P, C, z, w, wl.initial_block(40, m0, 22), m0, 1e-12)
+    assert r.converged and r.inside.sum() == len(truth)
+    assert match_error(r.eigenvalues, np.array(truth), C.a) < 1e-10
