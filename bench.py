@@ -1,0 +1,231 @@
+"""Benchmark: converged eigenpairs/sec of nonlinear FEAST on one MI355X.
+
+One step = one full nlfeast_solve of the workload (assembly of T(z_k) for all nodes, batched
+LU of all T(z_k), and every NLFEAST iteration: projections, reduced problem, residuals,
+triangular solves against the residual block, accumulation, orthonormalisation) with the
+coefficient matrices and X0 already resident in HBM.  The factorisation cache is invalidated
+before every step so each step pays the LU.
+
+Prints one JSON line with the headline FP64 figure, the FP32-LU + FP64-refinement form on the
+same problem, the roofline of the dominant kernel (the complex GEMMs of the LU trailing
+updates, timed with HIP events on the solve stream inside the timed region), and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu] [--no-fp32]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64_mfma_tflops": 78.6, "fp32_mfma_tflops": 157.3, "hbm_gbs": 8000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="damped4096")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    return ap.parse_args()
+
+
+def load_workload(name):
+    import numpy as np
+    import workloads as wl
+    cfg = wl.CONFIGS[name]
+    terms, mats = wl.make_problem(name)
+    regions_json = json.load(open(os.path.join(ROOT, "tests", "golden", "contours.json")))[name]["regions"]
+    regions = []
+    for g in regions_json:
+        regions.append(dict(centre=complex(*g["centre"]), a=g["radius"], nc=cfg["nc"],
+                            m0=g.get("m0", cfg.get("m0"))))
+    X0 = np.concatenate([wl.initial_block(cfg["n"], r["m0"], 2000 + cfg["id"] + i)
+                         for i, r in enumerate(regions)], axis=1)
+    return cfg, terms, mats, regions, X0
+
+
+def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile):
+    import torch
+    import paper_1801_09794_amd as nl
+    n = cfg["n"]
+    S = nl.NLFEAST(n, 0)
+    dmats = [nl.to_colmajor(M, "cuda:0") for M in mats]
+    S.set_coeffs(terms, dmats)
+    S.set_contour(regions)
+    X0d = nl.to_colmajor(X0, "cuda:0")
+    opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3)
+    for _ in range(args.warmup):
+        S.set_contour(regions)
+        S.solve(opts, X0d)
+    torch.cuda.synchronize()
+    nl.nlfeast_set_profiling(S.h, profile)
+    prof = None
+    outs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        S.set_contour(regions)          # invalidate the cached factorisations
+        outs.append(S.solve(opts, X0d))
+        if profile:
+            p = S.profile()
+            if prof is None:
+                prof = {k: dict(v) for k, v in p.items()}
+            else:
+                for k, v in p.items():
+                    for f in v:
+                        prof[k][f] += v[f]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nl.nlfeast_set_profiling(S.h, False)
+    out = outs[-1]
+    S.close()
+    return (t1 - t0) / args.steps, out, prof
+
+
+def converged_pairs(out, tol):
+    import numpy as np
+    ok = out["inside"] & (out["res"] <= tol)
+    return int(np.sum(ok))
+
+
+def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters):
+    """The oracle on a bounded sample: LU of 4 of the n_c node matrices and one full
+    iteration (Steps 1-5 with every node's solve), extrapolated to the whole solve."""
+    import numpy as np
+    import scipy.linalg
+    from oracle import nlfeast as onl, problem as pb, quadrature as qd, reduced
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 0) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    P = pb.Problem(terms, mats)
+    g = regions[0]
+    C = qd.Contour(g["centre"], g["a"])
+    z, w = qd.nodes_weights(C, g["nc"])
+    m0 = g["m0"]
+    nsample = 4
+    t0 = time.perf_counter()
+    facs = [scipy.linalg.lu_factor(P.T(zk), check_finite=False) for zk in z[:nsample]]
+    t_lu = (time.perf_counter() - t0) / nsample
+    # one iteration of Steps 1-5 (solves re-use the sampled factors cyclically)
+    Q = onl.orthonormalise(X0[:, :m0])
+    t0 = time.perf_counter()
+    Ahat = P.project(Q)
+    lam_all, Y_all = reduced.solve_reduced(P.terms, Ahat, C)
+    sel = reduced.select(lam_all, C, m0)
+    lam = lam_all[sel]
+    X = Q @ Y_all[:, sel]
+    X /= np.linalg.norm(X, axis=0)
+    R = P.block_residual(X, lam)
+    facs_all = [facs[k % nsample] for k in range(len(z))]
+    Q = onl.orthonormalise(onl.step4(facs_all, X, R, lam, z, w))
+    t_it = time.perf_counter() - t0
+    est = t_lu * len(z) + t_it * (gpu_iters + 1)
+    return est, cores, dict(t_lu=t_lu, t_iter=t_it, nodes=len(z), sample_lus=nsample)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1801_09794_amd as nl
+    nl.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg, terms, mats, regions, X0 = load_workload(args.workload)
+    n = cfg["n"]
+
+    t64, out64, prof = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, True)
+    conv64 = converged_pairs(out64, cfg["tol"])
+    value = conv64 / t64
+    lu = prof["lu_gemm"]
+    lu_tflops = lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0
+    nnodes = sum(r["nc"] for r in regions)
+    lu_flops_total = 8.0 / 3.0 * n ** 3 * nnodes
+    lu_phase_ms = sum(prof[k]["ms"] for k in ("lu_gemm", "lu_panel", "lu_trsm", "lu_laswp")) / args.steps
+    result = {
+        "metric": "converged eigenpairs/sec + LU TFLOP/s (% MFMA peak), FP32+refine vs FP64",
+        "value": value,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: quadratic mass-spring-damper T(l) = l^2 A2 + l A1 + A0, n=%d dense "
+                        "complex128, circle enclosing %d eigenvalues, m0=%d, %d Gauss-Legendre "
+                        "nodes, tol %.0e, FP64 LU" % (args.workload, n, conv64, regions[0]["m0"],
+                                                      regions[0]["nc"], cfg["tol"]),
+            "n": n, "m0": regions[0]["m0"], "nodes": nnodes, "regions": len(regions),
+            "parallelism": "single GPU, nodes batched",
+        },
+        "converged": conv64,
+        "iterations": int(out64["iters"][0]),
+        "lu": {"tflops_phase": lu_flops_total / (lu_phase_ms * 1e-3) / 1e12 if lu_phase_ms > 0 else None,
+               "phase_ms": lu_phase_ms,
+               "trailing_gemm_tflops": lu_tflops,
+               "trailing_gemm_frac_fp64_peak": lu_tflops / PEAK["fp64_mfma_tflops"]},
+        "roofline": {
+            "kernel": "gemm_kernel<double> (LU trailing updates)",
+            "bound": "mfma",
+            "achieved": lu_tflops,
+            "peak": PEAK["fp64_mfma_tflops"],
+            "unit": "TFLOP/s",
+            "frac": lu_tflops / PEAK["fp64_mfma_tflops"],
+            "traffic": None,
+            "launches_per_step": lu["launches"] / args.steps,
+            "avg_launch_us": lu["ms"] * 1e3 / max(lu["launches"], 1),
+            "flops_per_step": lu["flops"] / args.steps,
+        },
+        "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+    }
+    if not args.no_fp32:
+        t32, out32, prof32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True)
+        conv32 = converged_pairs(out32, cfg["tol"])
+        import numpy as np
+        l64 = np.sort_complex(out64["lam"][out64["inside"]])
+        l32 = np.sort_complex(out32["lam"][out32["inside"]])
+        err = None
+        if len(l64) == len(l32) and len(l64):
+            err = float(max(np.min(np.abs(l32 - a)) / max(abs(a), regions[0]["a"]) for a in l64))
+        lu32 = prof32["lu_gemm"]
+        result["fp32_refine"] = {
+            "value": conv32 / t32, "ms_per_step": t32 * 1e3, "converged": conv32,
+            "iterations": int(out32["iters"][0]), "speedup_vs_fp64": t64 / t32,
+            "max_rel_eig_diff_vs_fp64": err,
+            "trailing_gemm_tflops": lu32["flops"] / (lu32["ms"] * 1e-3) / 1e12 if lu32["ms"] > 0 else None,
+            "trailing_gemm_frac_fp32_peak": (lu32["flops"] / (lu32["ms"] * 1e-3) / 1e12) / PEAK["fp32_mfma_tflops"]
+            if lu32["ms"] > 0 else None,
+            "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof32.items()},
+        }
+    if not args.no_cpu:
+        est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
+        result["cpu_baseline"] = {
+            "value": conv64 / est, "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle (numpy/scipy complex128) on the same workload: LU of %d of the %d "
+                      "node matrices (%.2f s each) and one full NLFEAST iteration (%.2f s), "
+                      "extrapolated to %d LUs + %d iterations = %.1f s per solve"
+                      % (detail["sample_lus"], detail["nodes"], detail["t_lu"], detail["t_iter"],
+                         detail["nodes"], int(out64["iters"][0]) + 1, est),
+        }
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * nlfeast.h -- C ABI of the MI355X (gfx950) nonlinear FEAST library.
+ *
+ * Computes the eigenpairs (lambda, x) of T(lambda) x = 0 whose eigenvalues lie inside one
+ * or more closed contours in the complex plane (Gavin, Miedlar, Polizzi, "FEAST Eigensolver
+ * for Nonlinear Eigenvalue Problems", arXiv 1801.09794: problem statement in Sec. 1 eq. nlevp
+ * and Sec. 2 eq. NLEVP; the method is Algorithm 1 of Sec. 4.2), with
+ *
+ *     T(lambda) = sum_j f_j(lambda) A_j,   f_j(lambda) = lambda^p  or  exp(-tau lambda)
+ *
+ * (polynomial form of Sec. 2 eq. polynomialeig; non-polynomial form named in Sec. 6).
+ *
+ * Conventions for every entry point below
+ *   - complex numbers are stored as interleaved (re, im) pairs: "c128" = two doubles,
+ *     "c64" = two floats;
+ *   - matrices are column-major with a leading dimension ld >= rows: element (i, j) of a
+ *     matrix at p is p[i + j * ld];
+ *   - a "batch" of matrices is `batch` matrices at p + b * stride (elements), b = 0..batch-1;
+ *   - pointers named *_dev are device (HBM) pointers on the device the call runs on; all
+ *     other pointers are host pointers; device memory passed in is owned by the caller and
+ *     only borrowed for the duration of the call (A_j: until the next set_coeffs/destroy);
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream); calls enqueue
+ *     on it and, unless stated otherwise, return before the device work finishes;
+ *   - no call throws; every call returns an nlfeast_status; NLF_ERR_ARG is returned, before
+ *     any device work is enqueued, for null pointers, negative sizes or ld < rows.
+ */
+#ifndef NLFEAST_H
+#define NLFEAST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NLF_OK = 0,
+    NLF_ERR_ARG = 1,             /* invalid argument (checked on the host before any launch) */
+    NLF_ERR_NOMEM = 2,           /* workspace too small, or a host allocation failed */
+    NLF_ERR_DEVICE = 3,          /* a HIP runtime call failed; see nlfeast_last_error */
+    NLF_ERR_STATE = 4,           /* call out of order (e.g. solve before set_contour) */
+    NLF_ERR_SINGULAR = 5,        /* exact zero pivot: a quadrature node sits on an eigenvalue */
+    NLF_ERR_M0_TOO_SMALL = 6,    /* m0 or more Ritz values inside a contour (Algorithm 1
+                                    requires fewer than m0 eigenvalues inside C) */
+    NLF_ERR_NOT_CONVERGED = 7    /* max_iter reached; outputs hold the last iterate */
+} nlfeast_status;
+
+typedef enum {
+    NLF_F_POW = 0,               /* f(lambda) = lambda^p, param = p (integer 0..16) */
+    NLF_F_EXP = 1                /* f(lambda) = exp(-tau lambda), param = tau */
+} nlfeast_fkind;
+
+typedef enum {
+    NLF_PREC_FP64 = 0,           /* LU and triangular solves in complex128 */
+    NLF_PREC_FP32_REFINE = 1     /* LU and triangular solves in complex64 with FP32
+                                    accumulation, FP64 iterative refinement of each solve;
+                                    residuals, orthonormalisation, projections and the
+                                    reduced problem stay in FP64 */
+} nlfeast_precision;
+
+typedef enum {
+    NLF_QUAD_GAUSS_LEGENDRE = 0, /* Gauss-Legendre on the contour parameter [0, 2 pi] */
+    NLF_QUAD_TRAPEZOID = 1       /* theta_k = 2 pi (k + 1/2) / n_c */
+} nlfeast_quad;
+
+typedef enum { NLF_C64 = 0, NLF_C128 = 1 } nlfeast_dtype;
+
+typedef struct {
+    double tol;                  /* Step 3 threshold on ||T(lambda_i) x_i||_2, ||x_i||_2 = 1 */
+    int32_t max_iter;            /* cap on Step 4 executions (default 50) */
+    int32_t precision;           /* nlfeast_precision */
+    int32_t max_refine;          /* FP32_REFINE: refinement sweeps per solve, at most 5 */
+    double refine_eta;           /* FP32_REFINE: stop sweeps once ||E||_F <= eta ||R||_F */
+    uint64_t seed;               /* X0 when the caller passes none (counter-based normal draws) */
+    int32_t autotune;            /* 1: time the GEMM tile variants on first use of a shape */
+    int32_t verbose;             /* 1: one line per iteration on stderr */
+} nlfeast_options;
+
+typedef struct nlfeast_ctx* nlfeast_handle;
+
+/* Library-owned context for problems of size n on HIP device `device`, enqueuing on
+ * `stream`.  The handle owns only small host/device arrays (quadrature, pivots' book-keeping). */
+nlfeast_status nlfeast_create(nlfeast_handle* h, int64_t n, int device, void* stream);
+
+/* The coefficients of T (Sec. 2 eq. polynomialeig; Sec. 4.2 block residual): J terms, term j
+ * is fkind[j] with parameter fparam[j] times the c128 n x n matrix A_dev[j] (leading
+ * dimension lda).  The A_j are borrowed, not copied.  Invalidates cached factorisations. */
+nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fkind,
+                                  const double* fparam, const void* const* A_dev, int64_t lda);
+
+/* nreg disjoint regions (Sec. 1 and Sec. 3: independent subregions of the plane).  Region r is
+ * the axis-aligned ellipse with centre (centre[2r] + i centre[2r+1]) and semi-axes
+ * semi_axes[2r] (real direction), semi_axes[2r+1] (imaginary direction) -- a circle when they
+ * are equal -- with n_nodes[r] quadrature nodes (Algorithm 1 inputs) and subspace size m0[r].
+ * Invalidates cached factorisations. */
+nlfeast_status nlfeast_set_contour(nlfeast_handle h, int32_t nreg, const double* centre,
+                                   const double* semi_axes, const int32_t* n_nodes,
+                                   const int32_t* m0, int32_t quad_rule);
+
+/* Device workspace bytes that nlfeast_solve needs for these options. */
+nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* opt, size_t* bytes);
+
+/* Algorithm 1 for every region.  Blocks until the outputs are valid.
+ *   ws_dev, ws_bytes   caller-owned device workspace (>= nlfeast_workspace_size)
+ *   X0_dev             c128 n x sum(m0) initial blocks, region by region (ld n), or NULL for
+ *                      seeded random blocks
+ *   X_dev_out          c128 n x sum(m0): the Ritz vectors (unit 2-norm), region by region
+ *   lambda_out         2 * sum(m0) doubles: the Ritz values (re, im), selection order
+ *   resid_out          sum(m0) doubles: ||T(lambda_i) x_i||_2
+ *   inside_out         sum(m0) int32: 1 if lambda_i is strictly inside its contour
+ *   m_out, iters_out   per region: eigenpairs inside, Step 4 executions
+ * Factorisations of T(z_k) are cached in the workspace and reused by the next solve with the
+ * same handle, coefficients, contours, precision and workspace pointer.
+ * Returns NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL or NLF_ERR_SINGULAR (the last
+ * region's status when several fail). */
+nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws_dev,
+                             size_t ws_bytes, const void* X0_dev, void* X_dev_out,
+                             double* lambda_out, double* resid_out, int32_t* inside_out,
+                             int32_t* m_out, int32_t* iters_out);
+
+/* Per-kernel-class device time of the last solve, measured with HIP events on the solve's
+ * stream when profiling is on (nlfeast_set_profiling).  For class c (see nlfeast_kernel_class):
+ * launches[c], milliseconds[c], and the algorithmic flops[c] / bytes[c] of those launches. */
+typedef enum {
+    NLF_K_ASSEMBLE = 0, NLF_K_LU_GEMM = 1, NLF_K_LU_PANEL = 2, NLF_K_LU_TRSM = 3,
+    NLF_K_LU_LASWP = 4, NLF_K_SOLVE = 5, NLF_K_REFINE = 6, NLF_K_RESIDUAL = 7,
+    NLF_K_ACCUMULATE = 8, NLF_K_ORTH = 9, NLF_K_PROJECT = 10, NLF_K_HOST_REDUCED = 11,
+    NLF_K_COUNT = 12
+} nlfeast_kernel_class;
+nlfeast_status nlfeast_set_profiling(nlfeast_handle h, int32_t on);
+nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* milliseconds,
+                                   double* flops, double* bytes);
+
+const char* nlfeast_last_error(nlfeast_handle h);
+void nlfeast_destroy(nlfeast_handle h);   /* NULL is a no-op */
+
+/* ------------------------------------------------------------------------------------------
+ * Step-level entry points: each performs one step of Algorithm 1's hot path on caller-owned
+ * device buffers, enqueued on `stream` (asynchronous).  The solver above is built from the
+ * same kernels.
+ * ---------------------------------------------------------------------------------------- */
+
+/* T(z_k) = sum_j f_j(z_k) A_j for k = 0..nz-1 (the matrices whose inverses Step 4 applies).
+ * A_dev[j]: c128 n x n (lda).  z: 2*nz doubles (host).  Outputs: T64_dev (c128, may be NULL)
+ * and/or T32_dev (c64, rounded once from the FP64 sum, may be NULL), each a batch of nz n x n
+ * matrices with leading dimension ldt and stride strideT. */
+nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const double* fparam,
+                            const void* const* A_dev, int64_t lda, int32_t nz, const double* z,
+                            void* T64_dev, void* T32_dev, int64_t ldt, int64_t strideT,
+                            void* stream);
+
+/* In-place LU with partial pivoting of a batch of n x n matrices (dtype c128 or c64):
+ * P_b A_b = L_b U_b, unit-lower L below the diagonal, U on and above it (the factorisation
+ * that makes each multiplication by T^{-1}(z_j) in Step 4 a pair of triangular solves).
+ * The pivot of column k is the entry of largest |Re| + |Im| on or below the diagonal (first
+ * on ties).  ipiv_dev: int32 batch x n, ipiv[b*n + k] = 0-based row exchanged with row k.
+ * perm_dev (int32 batch x n, may be NULL): the composed permutation, (P A)[i] = A[perm[i]].
+ * info_dev (int32 batch): 0, or k+1 for the first exact zero pivot U(k,k) = 0.
+ * Blocked recursively; trailing updates are complex GEMMs on MFMA. */
+nlfeast_status nlf_getrf_batched(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
+                                 int64_t lda, int64_t strideA, int32_t* ipiv_dev,
+                                 int32_t* perm_dev, int32_t* info_dev, void* stream);
+
+/* X_b = A_b^{-1} B_b from nlf_getrf_batched factors (same dtype), nrhs columns.  B_dev
+ * (ldb, strideB; strideB = 0 shares one right-hand side across the batch) is read, X_dev
+ * (ldx, strideX) is written and must not overlap B.  perm_dev is the composed permutation
+ * written by nlf_getrf_batched.  Forward substitution with unit L, then back substitution
+ * with U, both blocked recursively with complex GEMMs on MFMA. */
+nlfeast_status nlf_getrs_batched(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                 const void* LU_dev, int64_t lda, int64_t strideA,
+                                 const int32_t* perm_dev, const void* B_dev, int64_t ldb,
+                                 int64_t strideB, void* X_dev, int64_t ldx, int64_t strideX,
+                                 void* stream);
+
+/* C_b = alpha op(A_b) op(B_b) + beta C_b, complex (dtype c128 or c64), op 'N' or 'C'
+ * (conjugate transpose); alpha, beta: 2 doubles each (host).  The MFMA GEMM used by every
+ * dense contraction of the path. */
+nlfeast_status nlf_gemm_batched(int32_t dtype, char opA, char opB, int64_t M, int64_t N,
+                                int64_t K, const double* alpha, const void* A_dev, int64_t lda,
+                                int64_t strideA, const void* B_dev, int64_t ldb, int64_t strideB,
+                                const double* beta, void* C_dev, int64_t ldc, int64_t strideC,
+                                int32_t batch, void* stream);
+
+/* Block residual T(X, Lambda) = sum_j A_j X f_j(Lambda) (Sec. 4.2) and its column 2-norms
+ * (the Step 3 quantities).  X_dev: c128 n x m (ldx); lambda: 2*m doubles (host); R_dev: c128
+ * n x m (ldr); norms_dev: m doubles (device).  ws_dev: c128 scratch of n * m elements. */
+nlfeast_status nlf_block_residual(int64_t n, int32_t m, int32_t J, const int32_t* fkind,
+                                  const double* fparam, const void* const* A_dev, int64_t lda,
+                                  const void* X_dev, int64_t ldx, const double* lambda,
+                                  void* R_dev, int64_t ldr, double* norms_dev, void* ws_dev,
+                                  void* stream);
+
+/* Step 4 accumulation: Q = sum_k omega_k (X - Y_k) (z_k I - Lambda)^{-1}, evaluated as
+ * X rho(Lambda) - sum_k omega_k Y_k (z_k I - Lambda)^{-1} with rho(l) = sum_k omega_k/(z_k - l).
+ * X_dev, Q_dev: c128 n x m (ld n); Y_dev: nz blocks c128 n x m (ld n, stride n*m);
+ * z, omega: 2*nz doubles, lambda: 2*m doubles (host). */
+nlfeast_status nlf_accumulate(int64_t n, int32_t m, int32_t nz, const void* X_dev,
+                              const void* Y_dev, const double* z, const double* omega,
+                              const double* lambda, void* Q_dev, void* stream);
+
+/* Steps 0/5: orthonormalise the columns of the c128 n x m block Q_dev (ld n) in place, by
+ * Cholesky QR twice (Gram matrix on MFMA, m x m Cholesky on the host).  ws_dev: c128 scratch
+ * of nlf_orth_workspace(n, m) elements.  Blocking (host Cholesky). */
+int64_t nlf_orth_workspace(int64_t n, int32_t m);
+nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_dev, void* stream);
+
+/* Step 1 projections: W_j = A_j Q (c128 n x m each, stored side by side in W_dev, ld n) and
+ * Ahat_j = Q^H W_j (c128 m x m each, stored in Ahat_dev with ld m, stride m*m).
+ * ws_dev: c128 scratch of nlf_project_workspace(n, m, J) elements. */
+int64_t nlf_project_workspace(int64_t n, int32_t m, int32_t J);
+nlfeast_status nlf_project(int64_t n, int32_t m, int32_t J, const void* const* A_dev,
+                           int64_t lda, const void* Q_dev, void* W_dev, void* Ahat_dev,
+                           void* ws_dev, void* stream);
+
+/* Contour quadrature (Algorithm 1 inputs): n_c nodes z and weights omega (2*nc doubles each)
+ * of the rule `quad_rule` on the ellipse (centre, semi-axes a, b); the weights include
+ * 1/(2 pi i), so sum_k omega_k g(z_k) approximates (1/2 pi i) oint g(z) dz. */
+nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_t nc,
+                              int32_t quad_rule, double* z, double* omega);
+
+/* Step 1/2 on the host: all eigenpairs of the reduced problem sum_j f_j(lambda) Ahat_j y = 0
+ * (m x m c128 matrices Ahat, host, ld m, stride m*m) near the ellipse (centre, a, b), of which
+ * the m_keep closest to its interior (ascending normalised radius) are returned: lambda_out
+ * (2*m_keep doubles) and Y_out (c128 m x m_keep, ld m, unit-norm columns). */
+nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind,
+                                 const double* fparam, const double* Ahat, double cre,
+                                 double cim, double a, double b, int32_t m_keep,
+                                 double* lambda_out, double* Y_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLFEAST_H */

@@ -78,6 +78,35 @@ def companion_eigs_near(problem, sigma, k, tol=1e-13):
     return lam[np.argsort(np.abs(lam - sigma))]
 
 
+def refine_eigenvalue(problem, lam, steps=3, seed=0):
+    """Two-sided Rayleigh functional iteration on T itself: with x = T(l)^{-1} b and
+    y = T(l)^{-H} c (one LU of T(l) per step), l <- l - (y^H T(l) x) / (y^H T'(l) x).
+    Used to sharpen eigenvalues from the companion operator, whose non-normality lets
+    Arnoldi's residual test leave errors far above the residual.  Returns (l, ||T(l) x||)
+    with ||x|| = 1 from the last step."""
+    rng = np.random.default_rng(seed)
+    n = problem.n
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    l = complex(lam)
+    res = np.inf
+    for _ in range(steps):
+        T = problem.T(l)
+        lu = scipy.linalg.lu_factor(T, check_finite=False)
+        x = scipy.linalg.lu_solve(lu, b, check_finite=False)
+        x /= np.linalg.norm(x)
+        y = scipy.linalg.lu_solve(lu, c, trans=2, check_finite=False)
+        y /= np.linalg.norm(y)
+        res = float(np.linalg.norm(T @ x))
+        num = np.vdot(y, T @ x)
+        den = np.vdot(y, problem.dT(l) @ x)
+        if den == 0:
+            break
+        l = l - num / den
+    res = float(np.linalg.norm(problem.T(l) @ x))
+    return l, res
+
+
 def logdet(M):
     """log det M (complex, branch not normalised) from LU with partial pivoting."""
     lu, piv = scipy.linalg.lu_factor(M, check_finite=False)

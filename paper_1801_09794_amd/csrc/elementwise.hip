@@ -1,0 +1,230 @@
+// HBM-bound kernels of the nonlinear FEAST hot path: assembly of T(z_k) for every node,
+// Step 4 accumulation, column norms (Step 3 residuals), precision casts of the refinement,
+// and the counter-based initial block.  Grid-stride loops over interleaved complex elements,
+// consecutive threads on consecutive rows of column-major blocks (coalesced).
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+
+namespace nlf {
+
+constexpr int MAXJ = 8;
+
+struct APtrs {
+    const z128* p[MAXJ];
+};
+
+static inline unsigned grid_for(int64_t total, int64_t cap = 8192) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), cap));
+}
+
+// T_k(i, c) = sum_j coef[k J + j] A_j(i, c): each A_j element is read once and all nz
+// outputs are written from registers.
+__global__ __launch_bounds__(256) void assemble_kernel(int64_t n, int J, APtrs A, int64_t lda,
+                                                       int nz, const z128* __restrict__ coef,
+                                                       z128* T64, z64* T32, int64_t ldt,
+                                                       int64_t sT) {
+    const int64_t total = n * n;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % n, c = e / n;
+        z128 a[MAXJ];
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j)
+            if (j < J) a[j] = A.p[j][i + c * lda];
+        const int64_t off = i + c * ldt;
+        for (int k = 0; k < nz; ++k) {
+            z128 acc(0, 0);
+#pragma unroll
+            for (int j = 0; j < MAXJ; ++j)
+                if (j < J) cfma(acc, coef[k * J + j], a[j]);
+            if (T64) T64[k * sT + off] = acc;
+            if (T32) T32[k * sT + off] = z64((float)acc.re, (float)acc.im);
+        }
+    }
+}
+
+void assemble(hipStream_t s, int64_t n, int J, const z128* const* A, int64_t lda, int nz,
+              const z128* coef_dev, z128* T64, z64* T32, int64_t ldt, int64_t sT) {
+    NLF_REQUIRE(J >= 1 && J <= MAXJ, 1, "assemble: 1 <= J <= 8 terms");
+    APtrs ap{};
+    for (int j = 0; j < J; ++j) ap.p[j] = A[j];
+    const double bytes = (double)n * n * (16.0 * J + nz * ((T64 ? 16.0 : 0) + (T32 ? 8.0 : 0)));
+    ProfScope ps(NLF_PROF_ASSEMBLE, s, 8.0 * n * n * J * nz, bytes);
+    hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n * n, 16384)), dim3(256), 0, s, n, J, ap,
+                       lda, nz, coef_dev, T64, T32, ldt, sT);
+    NLF_HIP(hipGetLastError());
+}
+
+// one workgroup per column: sqrt(sum |x|^2)
+__global__ __launch_bounds__(256) void col_norms_kernel(int64_t n, const z128* X, int64_t ld,
+                                                        double* out) {
+    __shared__ double red[4];
+    const int64_t c = blockIdx.x;
+    double s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += norm2(X[i + c * ld]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = sqrt(red[0] + red[1] + red[2] + red[3]);
+}
+
+void col_norms(hipStream_t s, int64_t n, int m, const z128* X, int64_t ld, double* out) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(col_norms_kernel, dim3(m), dim3(256), 0, s, n, X, ld, out);
+    NLF_HIP(hipGetLastError());
+}
+
+// Q = X diag(rho) - sum_k Y_k diag(c_k)
+__global__ __launch_bounds__(256) void accumulate_kernel(int64_t n, int m, int nz,
+                                                         const z128* __restrict__ X,
+                                                         const z128* __restrict__ Y, int64_t sY,
+                                                         const z128* __restrict__ rho,
+                                                         const z128* __restrict__ coef, z128* Q) {
+    const int64_t total = n * m;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int c = (int)(e / n);
+        z128 q = rho[c] * X[e];
+        for (int k = 0; k < nz; ++k) cfms(q, coef[(int64_t)k * m + c], Y[k * sY + e]);
+        Q[e] = q;
+    }
+}
+
+void accumulate(hipStream_t s, int64_t n, int m, int nz, const z128* X, const z128* Y,
+                int64_t sY, const z128* rho, const z128* c, z128* Q) {
+    ProfScope ps(NLF_PROF_ACCUMULATE, s, 8.0 * n * m * nz, 16.0 * n * m * (nz + 2));
+    hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(n * m)), dim3(256), 0, s, n, m, nz, X, Y,
+                       sY, rho, c, Q);
+    NLF_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void cast_128_64_kernel(int64_t rows, int64_t cols,
+                                                          const z128* in, int64_t ldi, int64_t si,
+                                                          z64* out, int64_t ldo, int64_t so) {
+    const int64_t b = blockIdx.y, total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % rows, c = e / rows;
+        const z128 v = in[b * si + i + c * ldi];
+        out[b * so + i + c * ldo] = z64((float)v.re, (float)v.im);
+    }
+}
+
+__global__ __launch_bounds__(256) void cast_64_128_kernel(int64_t rows, int64_t cols,
+                                                          const z64* in, int64_t ldi, int64_t si,
+                                                          z128* out, int64_t ldo, int64_t so,
+                                                          int acc) {
+    const int64_t b = blockIdx.y, total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % rows, c = e / rows;
+        const z64 v = in[b * si + i + c * ldi];
+        z128* o = out + b * so + i + c * ldo;
+        const z128 w((double)v.re, (double)v.im);
+        *o = acc ? (*o + w) : w;
+    }
+}
+
+void cast_128_to_64(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* in,
+                    int64_t ldi, int64_t si, z64* out, int64_t ldo, int64_t so) {
+    hipLaunchKernelGGL(cast_128_64_kernel, dim3(grid_for(rows * cols, 2048), batch), dim3(256), 0,
+                       s, rows, cols, in, ldi, si, out, ldo, so);
+    NLF_HIP(hipGetLastError());
+}
+
+void cast_64_to_128(hipStream_t s, int64_t rows, int64_t cols, int batch, const z64* in,
+                    int64_t ldi, int64_t si, z128* out, int64_t ldo, int64_t so, bool acc) {
+    hipLaunchKernelGGL(cast_64_128_kernel, dim3(grid_for(rows * cols, 2048), batch), dim3(256), 0,
+                       s, rows, cols, in, ldi, si, out, ldo, so, acc ? 1 : 0);
+    NLF_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(1024) void block_sqnorm_kernel(int64_t rows, int64_t cols,
+                                                            const z128* X, int64_t ld, int64_t sX,
+                                                            double* out) {
+    __shared__ double red[16];
+    const int64_t b = blockIdx.x, total = rows * cols;
+    double s = 0;
+    for (int64_t e = threadIdx.x; e < total; e += 1024) {
+        const int64_t i = e % rows, c = e / rows;
+        s += norm2(X[b * sX + i + c * ld]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int q = 0; q < 16; ++q) t += red[q];
+        out[b] = t;
+    }
+}
+
+void block_sqnorms(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* X,
+                   int64_t ld, int64_t sX, double* out) {
+    hipLaunchKernelGGL(block_sqnorm_kernel, dim3(batch), dim3(1024), 0, s, rows, cols, X, ld, sX, out);
+    NLF_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void copy_block_kernel(int64_t rows, int64_t cols, const z128* in,
+                                                         int64_t ldi, z128* out, int64_t ldo) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % rows, c = e / rows;
+        out[i + c * ldo] = in[i + c * ldi];
+    }
+}
+
+void copy_block(hipStream_t s, int64_t rows, int64_t cols, const z128* in, int64_t ldi, z128* out,
+                int64_t ldo) {
+    hipLaunchKernelGGL(copy_block_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, rows, cols,
+                       in, ldi, out, ldo);
+    NLF_HIP(hipGetLastError());
+}
+
+// splitmix64 finaliser (Steele, Lea, Flood 2014) as a counter-based generator; two 53-bit
+// uniforms per element feed the Box-Muller transform.  CN(0,1) = (N + iN)/sqrt 2.
+__device__ __forceinline__ uint64_t splitmix(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+__global__ __launch_bounds__(256) void random_normal_kernel(int64_t rows, int64_t cols,
+                                                            uint64_t seed, z128* out, int64_t ld) {
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * 256) {
+        const uint64_t h1 = splitmix(seed ^ splitmix(2 * (uint64_t)e));
+        const uint64_t h2 = splitmix(seed ^ splitmix(2 * (uint64_t)e + 1));
+        const double u1 = ((h1 >> 11) + 1.0) * (1.0 / 9007199254740993.0);   // (0, 1]
+        const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
+        const double r = sqrt(-2.0 * log(u1)), t = 6.283185307179586 * u2;
+        const int64_t i = e % rows, c = e / rows;
+        out[i + c * ld] = z128(r * cos(t) * 0.7071067811865476, r * sin(t) * 0.7071067811865476);
+    }
+}
+
+void random_normal(hipStream_t s, int64_t rows, int64_t cols, uint64_t seed, z128* out, int64_t ld) {
+    hipLaunchKernelGGL(random_normal_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, s, rows,
+                       cols, seed, out, ld);
+    NLF_HIP(hipGetLastError());
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t v) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        p[e] = v;
+}
+
+void fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, v);
+    NLF_HIP(hipGetLastError());
+}
+
+}  // namespace nlf

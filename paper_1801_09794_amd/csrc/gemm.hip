@@ -1,0 +1,337 @@
+// Complex GEMM on gfx950 matrix cores: C = alpha op(A) B + beta C, op(A) = A or A^H.
+//
+// Every dense contraction of the nonlinear FEAST hot path goes through this kernel: the
+// trailing updates and off-diagonal blocks of the blocked LU of T(z_k), the triangular solves
+// against the residual block, the projections Q^H A_j Q, the block residual, the Ritz vectors
+// and the Gram matrices of the orthonormalisation.
+//
+// There is no complex MFMA, so one complex multiply-add of a 16x16x4 block is four real
+// v_mfma_*_16x16x4 instructions (the "4M" scheme): Cr += Ar Br, Cr -= Ai Bi, Ci += Ar Bi,
+// Ci += Ai Br.  The MFMA's A operand is fed from op(B) and its B operand from op(A), so the
+// 16 consecutive output columns of one MFMA row are 16 consecutive rows m of C: each store
+// instruction writes 256-byte contiguous runs of the column-major C without an LDS transpose.
+//
+// Work decomposition: a 256-thread workgroup (4 waves as 2x2) owns a (32 TM) x (32 TN)
+// complex tile of C; each wave owns (16 TM) x (16 TN), i.e. TM x TN MFMA tiles with a real
+// and an imaginary accumulator each.  K advances in steps of BK complex elements staged in
+// LDS as [k][m] and [k][n] (interleaved complex, so one ds_read_b64/b128 gives re and im).
+// The next K step is fetched into registers while the current one is multiplied.
+// Optional split-K writes alpha-scaled partial products to a workspace; gemm_reduce sums them.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nlf {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+// Accumulator layout of a 16x16 output block: lane l, register r holds row acc_row(l >> 4, r)
+// and column (l & 15).  Measured on gfx950: v_mfma_f64_16x16x4f64 puts rows (l >> 4) + 4r in
+// a lane, v_mfma_f32_16x16x4f32 rows 4 (l >> 4) + r.
+template <> struct Mfma<double> {
+    using acc_t = v4d;
+    static __device__ __forceinline__ int acc_row(int q, int r) { return q + 4 * r; }
+    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<float> {
+    using acc_t = v4f;
+    static __device__ __forceinline__ int acc_row(int q, int r) { return 4 * q + r; }
+    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename R>
+struct GemmArgs {
+    int64_t M, N, K;
+    Cx<R> alpha, beta;
+    const Cx<R>* A; int64_t lda, sA;
+    const Cx<R>* B; int64_t ldb, sB;
+    Cx<R>* C; int64_t ldc, sC;
+    int tilesM, tilesN;
+    int64_t kchunk;        // K range per split (split-K only)
+    Cx<R>* P;              // split-K partials: [batch][split][N][M] (ld M)
+    int nsplit;
+};
+
+// Map the hardware workgroup id to a tile so that each XCD (workgroups are dispatched
+// round-robin over the 8 XCDs) receives a contiguous range of tiles, which then share
+// A-row and B-column blocks in that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int w, int nT) {
+    const int q = nT >> 3, r = nT & 7;
+    const int xcd = w & 7, slot = w >> 3;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    constexpr int LA = BM * BK / 256, LB = BN * BK / 256;   // loads per thread per K step
+    static_assert(LA * 256 == BM * BK && LB * 256 == BN * BK, "tile/thread mismatch");
+    using acc_t = typename Mfma<R>::acc_t;
+
+    __shared__ Cx<R> As[BK][BM];
+    __shared__ Cx<R> Bs[BK][BN];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int nT = g.tilesM * g.tilesN;
+    const int tile = xcd_remap(blockIdx.x, nT);
+    const int tm = tile % g.tilesM, tn = tile / g.tilesM;
+    const int64_t batch = blockIdx.y;
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+
+    const Cx<R>* __restrict__ A = g.A + batch * g.sA;
+    const Cx<R>* __restrict__ B = g.B + batch * g.sB;
+
+    int64_t kbeg = 0, kend = g.K;
+    if (SPLIT) {
+        kbeg = (int64_t)blockIdx.z * g.kchunk;
+        kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    }
+
+    acc_t accR[TM][TN], accI[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            accR[i][j] = acc_t{0, 0, 0, 0};
+            accI[i][j] = acc_t{0, 0, 0, 0};
+        }
+
+    Cx<R> ra[LA], rb[LB];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            const int idx = tid + 256 * e;
+            int m, k;
+            if (!CONJA) { m = idx % BM; k = idx / BM; }
+            else        { k = idx % BK; m = idx / BK; }
+            const int64_t gm = m0 + m, gk = k0 + k;
+            Cx<R> v(0, 0);
+            if (gm < g.M && gk < kend) {
+                if (!CONJA) v = A[gm + gk * g.lda];
+                else { v = A[gk + gm * g.lda]; v.im = -v.im; }
+            }
+            ra[e] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < LB; ++e) {
+            const int idx = tid + 256 * e;
+            const int k = idx % BK, n = idx / BK;
+            const int64_t gn = n0 + n, gk = k0 + k;
+            Cx<R> v(0, 0);
+            if (gn < g.N && gk < kend) v = B[gk + gn * g.ldb];
+            rb[e] = v;
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int e = 0; e < LA; ++e) {
+            const int idx = tid + 256 * e;
+            int m, k;
+            if (!CONJA) { m = idx % BM; k = idx / BM; }
+            else        { k = idx % BK; m = idx / BK; }
+            As[k][m] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < LB; ++e) {
+            const int idx = tid + 256 * e;
+            const int k = idx % BK, n = idx / BK;
+            Bs[k][n] = rb[e];
+        }
+    };
+
+    const int col = lane & 15, krow = lane >> 4;
+    if (kbeg < kend) {
+        fetch(kbeg);
+        stash();
+        __syncthreads();
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+            const bool more = k0 + BK < kend;
+            if (more) fetch(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                Cx<R> a[TM], b[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) a[i] = As[kk + krow][wm * 16 * TM + i * 16 + col];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) b[j] = Bs[kk + krow][wn * 16 * TN + j * 16 + col];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) accR[i][j] = Mfma<R>::mma(b[j].re, a[i].re, accR[i][j]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) accI[i][j] = Mfma<R>::mma(b[j].re, a[i].im, accI[i][j]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) accR[i][j] = Mfma<R>::mma(-b[j].im, a[i].im, accR[i][j]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) accI[i][j] = Mfma<R>::mma(b[j].im, a[i].re, accI[i][j]);
+            }
+            __syncthreads();
+            if (more) {
+                stash();
+                __syncthreads();
+            }
+        }
+    }
+
+    // epilogue: lane holds, for tile (i, j) and register r, C(m, n) with
+    // m = m0 + wm*16TM + 16i + (lane & 15), n = n0 + wn*16TN + 16j + acc_row(lane >> 4, r)
+    if (SPLIT) {
+        Cx<R>* P = g.P + (batch * g.nsplit + blockIdx.z) * g.M * g.N;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = m0 + wm * 16 * TM + i * 16 + col;
+                    const int64_t n = n0 + wn * 16 * TN + j * 16 + Mfma<R>::acc_row(krow, r);
+                    if (m < g.M && n < g.N) {
+                        Cx<R> v(accR[i][j][r], accI[i][j][r]);
+                        P[m + n * g.M] = g.alpha * v;
+                    }
+                }
+    } else {
+        Cx<R>* C = g.C + batch * g.sC;
+        const bool useBeta = (g.beta.re != R(0) || g.beta.im != R(0));
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = m0 + wm * 16 * TM + i * 16 + col;
+                    const int64_t n = n0 + wn * 16 * TN + j * 16 + Mfma<R>::acc_row(krow, r);
+                    if (m < g.M && n < g.N) {
+                        Cx<R> v(accR[i][j][r], accI[i][j][r]);
+                        Cx<R> out = g.alpha * v;
+                        if (useBeta) out = out + g.beta * C[m + n * g.ldc];
+                        C[m + n * g.ldc] = out;
+                    }
+                }
+    }
+}
+
+// C = sum_s P_s + beta C over the split-K partials.
+template <typename R>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, int nsplit,
+                                                           const Cx<R>* __restrict__ P,
+                                                           Cx<R> beta, Cx<R>* C, int64_t ldc,
+                                                           int64_t sC) {
+    const int64_t batch = blockIdx.y;
+    const int64_t MN = M * N;
+    const bool useBeta = (beta.re != R(0) || beta.im != R(0));
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < MN; e += (int64_t)gridDim.x * 256) {
+        const int64_t m = e % M, n = e / M;
+        Cx<R> s(0, 0);
+        const Cx<R>* p = P + batch * nsplit * MN + e;
+        for (int k = 0; k < nsplit; ++k) s = s + p[k * MN];
+        Cx<R>* c = C + batch * sC + m + n * ldc;
+        if (useBeta) s = s + beta * (*c);
+        *c = s;
+    }
+}
+
+// ---------------------------------------------------------------------------- host side
+
+template <typename R, int TM, int TN, int BK, bool CONJA>
+static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit) {
+    constexpr int BM = 32 * TM, BN = 32 * TN;
+    g.tilesM = (int)ceil_div(g.M, BM);
+    g.tilesN = (int)ceil_div(g.N, BN);
+    dim3 grid(g.tilesM * g.tilesN, batch, nsplit);
+    if (nsplit > 1)
+        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, true>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, false>), grid, dim3(256), 0, s, g);
+}
+
+template <typename R>
+static GemmConfig pick_config(int64_t M, int64_t N, int64_t K, int batch) {
+    // Tile shape: large tiles when there are enough of them to fill 256 CUs twice.
+    GemmConfig c;
+    const int64_t big = ceil_div(M, 128) * ceil_div(N, 64) * batch;
+    if (sizeof(R) == 4) {
+        c.tm = (ceil_div(M, 128) * ceil_div(N, 128) * batch >= 512) ? 4 : 2;
+        c.tn = c.tm;
+    } else {
+        c.tm = (big >= 512) ? 4 : 2;
+        c.tn = 2;
+    }
+    (void)K;
+    return c;
+}
+
+template <typename R>
+void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alpha,
+          const Cx<R>* A, int64_t lda, int64_t sA, const Cx<R>* B, int64_t ldb, int64_t sB,
+          Cx<R> beta, Cx<R>* C, int64_t ldc, int64_t sC, int batch, Cx<R>* ws,
+          int64_t ws_elems, const GemmConfig* force) {
+    if (M <= 0 || N <= 0 || batch <= 0) return;
+    GemmArgs<R> g;
+    g.M = M; g.N = N; g.K = K;
+    g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.sA = sA;
+    g.B = B; g.ldb = ldb; g.sB = sB;
+    g.C = C; g.ldc = ldc; g.sC = sC;
+    g.P = nullptr; g.nsplit = 1; g.kchunk = K;
+    if (K <= 0) {
+        // C = beta C
+        g.K = 0;
+    }
+    GemmConfig c = force ? *force : pick_config<R>(M, N, K, batch);
+    // split-K for small outputs with long reductions (projections, Gram matrices)
+    int nsplit = 1;
+    const int64_t tiles = ceil_div(M, 32 * c.tm) * ceil_div(N, 32 * c.tn) * batch;
+    if (ws && tiles < 128 && K >= 1024) {
+        int want = (int)std::min<int64_t>(ceil_div(512, tiles), ceil_div(K, 256));
+        while (want > 1 && (int64_t)want * M * N * batch > ws_elems) --want;
+        if (want > 1) {
+            nsplit = want;
+            g.kchunk = ceil_div(ceil_div(K, nsplit), 16) * 16;
+            nsplit = (int)ceil_div(K, g.kchunk);
+            g.P = ws;
+            g.nsplit = nsplit;
+        }
+    }
+#define NLF_GEMM_CASE(TM_, TN_)                                                          \
+    if (c.tm == TM_ && c.tn == TN_) {                                                   \
+        if (conjA) launch_tiles<R, TM_, TN_, 16, true>(s, g, batch, nsplit);            \
+        else       launch_tiles<R, TM_, TN_, 16, false>(s, g, batch, nsplit);           \
+    } else
+    NLF_GEMM_CASE(2, 2)
+    NLF_GEMM_CASE(4, 2)
+    NLF_GEMM_CASE(4, 4)
+    { throw Error{1, "gemm: unsupported tile config"}; }
+#undef NLF_GEMM_CASE
+    NLF_HIP(hipGetLastError());
+    if (nsplit > 1) {
+        const int64_t MN = M * N;
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(MN, 256), 1024), batch);
+        hipLaunchKernelGGL((gemm_reduce_kernel<R>), grid, dim3(256), 0, s, M, N, nsplit,
+                           (const Cx<R>*)g.P, beta, C, ldc, sC);
+        NLF_HIP(hipGetLastError());
+    }
+}
+
+template void gemm<double>(hipStream_t, bool, int64_t, int64_t, int64_t, Cx<double>,
+                           const Cx<double>*, int64_t, int64_t, const Cx<double>*, int64_t,
+                           int64_t, Cx<double>, Cx<double>*, int64_t, int64_t, int,
+                           Cx<double>*, int64_t, const GemmConfig*);
+template void gemm<float>(hipStream_t, bool, int64_t, int64_t, int64_t, Cx<float>,
+                          const Cx<float>*, int64_t, int64_t, const Cx<float>*, int64_t,
+                          int64_t, Cx<float>, Cx<float>*, int64_t, int64_t, int, Cx<float>*,
+                          int64_t, const GemmConfig*);
+
+}  // namespace nlf

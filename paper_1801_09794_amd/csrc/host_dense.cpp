@@ -1,0 +1,523 @@
+// Host-side small dense routines (see host_dense.hpp).
+#include "host_dense.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <numeric>
+
+namespace nlf {
+
+static const double kEps = 2.220446049250313e-16;
+static const double kPi = 3.14159265358979323846;
+
+double Ellipse::radius(cplx l) const {
+    if (!std::isfinite(l.real()) || !std::isfinite(l.imag())) return std::numeric_limits<double>::infinity();
+    const cplx d = l - c;
+    return std::sqrt((d.real() / a) * (d.real() / a) + (d.imag() / b) * (d.imag() / b));
+}
+
+// Legendre points/weights on [-1, 1], ascending: Newton's method on P_n from the
+// asymptotic first guesses cos(pi (i + 3/4) / (n + 1/2)); weight 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double t = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = t;
+            for (int k = 1; k < n; ++k) {
+                const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = t; p0 = 1.0; }
+            dp = n * (t * p1 - p0) / (t * t - 1.0);
+            const double dt = p1 / dp;
+            t -= dt;
+            if (std::fabs(dt) < 1e-16) {
+                // one more evaluation for the derivative at the converged point
+                p0 = 1.0; p1 = t;
+                for (int k = 1; k < n; ++k) {
+                    const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+                    p0 = p1;
+                    p1 = p2;
+                }
+                if (n == 1) { p1 = t; p0 = 1.0; }
+                dp = n * (t * p1 - p0) / (t * t - 1.0);
+                break;
+            }
+        }
+        x[n - 1 - i] = t;                      // the guesses descend; store ascending
+        w[n - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+}
+
+void quadrature(const Ellipse& E, int nc, int rule, std::vector<cplx>& z, std::vector<cplx>& w) {
+    std::vector<double> theta(nc), W(nc);
+    if (rule == 0) {
+        std::vector<double> t, wt;
+        gauss_legendre(nc, t, wt);
+        for (int k = 0; k < nc; ++k) {
+            theta[k] = kPi * (1.0 + t[k]);
+            W[k] = kPi * wt[k];
+        }
+    } else {
+        for (int k = 0; k < nc; ++k) {
+            theta[k] = 2.0 * kPi * (k + 0.5) / nc;
+            W[k] = 2.0 * kPi / nc;
+        }
+    }
+    z.resize(nc);
+    w.resize(nc);
+    for (int k = 0; k < nc; ++k) {
+        const double ct = std::cos(theta[k]), st = std::sin(theta[k]);
+        z[k] = E.c + cplx(E.a * ct, E.b * st);
+        const cplx dz(-E.a * st, E.b * ct);              // dz / dtheta
+        w[k] = W[k] * dz / cplx(0.0, 2.0 * kPi);          // includes 1 / (2 pi i)
+    }
+}
+
+bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv) {
+    std::vector<cplx> R(m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double d = G[j + j * m].real();
+        for (int k = 0; k < j; ++k) d -= std::norm(R[k + j * m]);
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        const double rjj = std::sqrt(d);
+        R[j + j * m] = rjj;
+        for (int i = j + 1; i < m; ++i) {
+            cplx s = G[j + i * m];
+            for (int k = 0; k < j; ++k) s -= std::conj(R[k + j * m]) * R[k + i * m];
+            R[j + i * m] = s / rjj;
+        }
+    }
+    Rinv.assign(m * m, 0.0);
+    for (int c = 0; c < m; ++c) {           // solve R x = e_c by back substitution
+        Rinv[c + c * m] = 1.0 / R[c + c * m];
+        for (int i = c - 1; i >= 0; --i) {
+            cplx s = 0.0;
+            for (int k = i + 1; k <= c; ++k) s += R[i + k * m] * Rinv[k + c * m];
+            Rinv[i + c * m] = -s / R[i + i * m];
+        }
+    }
+    return true;
+}
+
+cplx term_value(const Term& t, cplx l) {
+    if (t.kind == 0) {
+        const int p = (int)t.param;
+        cplx r = 1.0;
+        for (int i = 0; i < p; ++i) r *= l;
+        return r;
+    }
+    return std::exp(-t.param * l);
+}
+
+cplx term_deriv(const Term& t, cplx l) {
+    if (t.kind == 0) {
+        const int p = (int)t.param;
+        if (p == 0) return 0.0;
+        cplx r = (double)p;
+        for (int i = 0; i < p - 1; ++i) r *= l;
+        return r;
+    }
+    return -t.param * std::exp(-t.param * l);
+}
+
+static inline double abs1(cplx a) { return std::fabs(a.real()) + std::fabs(a.imag()); }
+
+// Givens rotation G = [[c, s], [-conj(s), c]] (c real) with G [x; y] = [rho; 0].
+static inline void givens(cplx x, cplx y, double& c, cplx& s, cplx& rho) {
+    const double ax = std::abs(x), ay = std::abs(y);
+    if (ay == 0.0) { c = 1.0; s = 0.0; rho = x; return; }
+    if (ax == 0.0) { c = 0.0; s = std::conj(y) / ay; rho = ay; return; }
+    const double r = std::hypot(ax, ay);
+    c = ax / r;
+    const cplx ph = x / ax;
+    s = ph * std::conj(y) / r;
+    rho = ph * r;
+}
+
+bool Schur::compute(int N_, std::vector<cplx>& A, bool vecs) {
+    N = N_;
+    std::vector<cplx>& H = A;
+    Z.clear();
+    if (vecs) {
+        Z.assign((size_t)N * N, 0.0);
+        for (int i = 0; i < N; ++i) Z[i + (size_t)i * N] = 1.0;
+    }
+    std::vector<cplx> v(N), s(N);
+    // Householder reduction to upper Hessenberg form, H <- P H P, Z <- Z P
+    for (int k = 0; k + 2 < N; ++k) {
+        double xn2 = 0.0;
+        for (int i = k + 1; i < N; ++i) xn2 += std::norm(H[i + (size_t)k * N]);
+        if (xn2 == 0.0) continue;
+        const double xn = std::sqrt(xn2);
+        const cplx x0 = H[k + 1 + (size_t)k * N];
+        const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
+        const cplx alpha = -ph * xn;
+        for (int i = k + 1; i < N; ++i) v[i] = H[i + (size_t)k * N];
+        v[k + 1] -= alpha;
+        double vn2 = 0.0;
+        for (int i = k + 1; i < N; ++i) vn2 += std::norm(v[i]);
+        if (vn2 == 0.0) continue;
+        const double beta = 2.0 / vn2;
+        for (int j = k + 1; j < N; ++j) {                  // rows k+1.., columns k+1..
+            cplx t = 0.0;
+            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * H[i + (size_t)j * N];
+            t *= beta;
+            for (int i = k + 1; i < N; ++i) H[i + (size_t)j * N] -= v[i] * t;
+        }
+        std::fill(s.begin(), s.end(), cplx(0.0));          // columns k+1.., all rows
+        for (int j = k + 1; j < N; ++j)
+            for (int i = 0; i < N; ++i) s[i] += H[i + (size_t)j * N] * v[j];
+        for (int j = k + 1; j < N; ++j) {
+            const cplx cv = beta * std::conj(v[j]);
+            for (int i = 0; i < N; ++i) H[i + (size_t)j * N] -= s[i] * cv;
+        }
+        if (vecs) {
+            std::fill(s.begin(), s.end(), cplx(0.0));
+            for (int j = k + 1; j < N; ++j)
+                for (int i = 0; i < N; ++i) s[i] += Z[i + (size_t)j * N] * v[j];
+            for (int j = k + 1; j < N; ++j) {
+                const cplx cv = beta * std::conj(v[j]);
+                for (int i = 0; i < N; ++i) Z[i + (size_t)j * N] -= s[i] * cv;
+            }
+        }
+        H[k + 1 + (size_t)k * N] = alpha;
+        for (int i = k + 2; i < N; ++i) H[i + (size_t)k * N] = 0.0;
+    }
+    double hnorm = 0.0;
+    for (size_t e = 0; e < (size_t)N * N; ++e) hnorm = std::max(hnorm, abs1(H[e]));
+    if (hnorm == 0.0) hnorm = 1.0;
+    // shifted QR iterations (Wilkinson shift, exceptional shifts at 10 and 20 stalled steps)
+    int ihi = N - 1, its = 0, total = 0;
+    while (ihi >= 0) {
+        int l = ihi;
+        while (l > 0) {
+            double sc = abs1(H[l - 1 + (size_t)(l - 1) * N]) + abs1(H[l + (size_t)l * N]);
+            if (sc == 0.0) sc = hnorm;
+            if (abs1(H[l + (size_t)(l - 1) * N]) <= kEps * sc) {
+                H[l + (size_t)(l - 1) * N] = 0.0;
+                break;
+            }
+            --l;
+        }
+        if (l == ihi) {
+            --ihi;
+            its = 0;
+            continue;
+        }
+        if (++its > 80 || ++total > 100 * N) return false;
+        cplx mu;
+        const cplx a = H[ihi - 1 + (size_t)(ihi - 1) * N], b = H[ihi - 1 + (size_t)ihi * N];
+        const cplx c = H[ihi + (size_t)(ihi - 1) * N], d = H[ihi + (size_t)ihi * N];
+        if (its == 10 || its == 20 || its == 40) {
+            mu = d + std::abs(c.real()) * 0.75;
+        } else {
+            const cplx tr2 = 0.5 * (a + d);
+            const cplx disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+            const cplx m1 = tr2 + disc, m2 = tr2 - disc;
+            mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+        }
+        cplx x = H[l + (size_t)l * N] - mu, y = H[l + 1 + (size_t)l * N];
+        for (int k = l; k < ihi; ++k) {
+            if (k > l) {
+                x = H[k + (size_t)(k - 1) * N];
+                y = H[k + 1 + (size_t)(k - 1) * N];
+            }
+            double cs;
+            cplx sn, rho;
+            givens(x, y, cs, sn, rho);
+            if (k > l) {
+                H[k + (size_t)(k - 1) * N] = rho;
+                H[k + 1 + (size_t)(k - 1) * N] = 0.0;
+            }
+            const cplx csn = std::conj(sn);
+            for (int j = k; j < N; ++j) {
+                const cplx p = H[k + (size_t)j * N], q = H[k + 1 + (size_t)j * N];
+                H[k + (size_t)j * N] = cs * p + sn * q;
+                H[k + 1 + (size_t)j * N] = -csn * p + cs * q;
+            }
+            const int iend = std::min(k + 2, ihi);
+            cplx* ck = &H[(size_t)k * N];
+            cplx* ck1 = &H[(size_t)(k + 1) * N];
+            for (int i = 0; i <= iend; ++i) {
+                const cplx p = ck[i], q = ck1[i];
+                ck[i] = cs * p + csn * q;
+                ck1[i] = -sn * p + cs * q;
+            }
+            if (vecs) {
+                cplx* zk = &Z[(size_t)k * N];
+                cplx* zk1 = &Z[(size_t)(k + 1) * N];
+                for (int i = 0; i < N; ++i) {
+                    const cplx p = zk[i], q = zk1[i];
+                    zk[i] = cs * p + csn * q;
+                    zk1[i] = -sn * p + cs * q;
+                }
+            }
+        }
+    }
+    evals.resize(N);
+    for (int i = 0; i < N; ++i) evals[i] = H[i + (size_t)i * N];
+    T.swap(H);
+    norm = hnorm;
+    return true;
+}
+
+void Schur::vectors(const std::vector<int>& want, std::vector<cplx>& out_vecs) const {
+    const std::vector<cplx>& H = T;
+    // eigenvectors of the triangular Schur factor by back substitution, then x = Z v
+    const double smin = std::max(kEps * norm, std::numeric_limits<double>::min() * N);
+    out_vecs.assign((size_t)N * want.size(), 0.0);
+    std::vector<cplx> w(N);
+    for (size_t q = 0; q < want.size(); ++q) {
+        const int k = want[q];
+        std::fill(w.begin(), w.end(), cplx(0.0));
+        w[k] = 1.0;
+        const cplx lk = H[k + (size_t)k * N];
+        for (int i = k - 1; i >= 0; --i) {
+            cplx t = 0.0;
+            for (int j = i + 1; j <= k; ++j) t += H[i + (size_t)j * N] * w[j];
+            cplx dd = H[i + (size_t)i * N] - lk;
+            if (std::abs(dd) < smin) dd = smin;
+            w[i] = -t / dd;
+            if (std::abs(w[i]) > 1e100) {
+                for (int j = i; j <= k; ++j) w[j] *= 1e-100;
+            }
+        }
+        cplx* out = &out_vecs[(size_t)q * N];
+        for (int j = 0; j <= k; ++j) {
+            const cplx wj = w[j];
+            if (wj == 0.0) continue;
+            const cplx* zj = &Z[(size_t)j * N];
+            for (int i = 0; i < N; ++i) out[i] += zj[i] * wj;
+        }
+        double nr = 0.0;
+        for (int i = 0; i < N; ++i) nr += std::norm(out[i]);
+        nr = std::sqrt(nr);
+        if (nr > 0.0)
+            for (int i = 0; i < N; ++i) out[i] /= nr;
+    }
+}
+
+bool eig_dense(int N, std::vector<cplx>& A, std::vector<cplx>& evals, const std::vector<int>* want,
+               std::vector<cplx>* evecs) {
+    Schur S;
+    const bool vecs = want && evecs;
+    if (!S.compute(N, A, vecs)) return false;
+    evals = S.evals;
+    if (vecs) S.vectors(*want, *evecs);
+    return true;
+}
+
+// LU with partial pivoting (|Re| + |Im| pivots) of an m x m matrix; solves M X = B in place.
+static bool lu_solve_small(int m, std::vector<cplx> M, cplx* B, int nrhs) {
+    std::vector<int> piv(m);
+    for (int k = 0; k < m; ++k) {
+        int p = k;
+        double best = abs1(M[k + (size_t)k * m]);
+        for (int i = k + 1; i < m; ++i) {
+            const double v = abs1(M[i + (size_t)k * m]);
+            if (v > best) { best = v; p = i; }
+        }
+        piv[k] = p;
+        if (best == 0.0) return false;
+        if (p != k)
+            for (int j = 0; j < m; ++j) std::swap(M[k + (size_t)j * m], M[p + (size_t)j * m]);
+        const cplx inv = 1.0 / M[k + (size_t)k * m];
+        for (int i = k + 1; i < m; ++i) M[i + (size_t)k * m] *= inv;
+        for (int j = k + 1; j < m; ++j) {
+            const cplx u = M[k + (size_t)j * m];
+            if (u == 0.0) continue;
+            for (int i = k + 1; i < m; ++i) M[i + (size_t)j * m] -= M[i + (size_t)k * m] * u;
+        }
+    }
+    for (int c = 0; c < nrhs; ++c) {
+        cplx* b = B + (size_t)c * m;
+        for (int k = 0; k < m; ++k)
+            if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+        for (int k = 0; k < m; ++k)
+            for (int i = k + 1; i < m; ++i) b[i] -= M[i + (size_t)k * m] * b[k];
+        for (int k = m - 1; k >= 0; --k) {
+            b[k] /= M[k + (size_t)k * m];
+            for (int i = 0; i < k; ++i) b[i] -= M[i + (size_t)k * m] * b[k];
+        }
+    }
+    return true;
+}
+
+// Taylor coefficients of f(c + mu) up to degree d.
+static std::vector<cplx> taylor(const Term& t, cplx c, int d) {
+    std::vector<cplx> out(d + 1, 0.0);
+    if (t.kind == 0) {
+        const int p = (int)t.param;
+        double binom = 1.0;
+        for (int q = 0; q <= std::min(p, d); ++q) {
+            cplx cp = 1.0;
+            for (int i = 0; i < p - q; ++i) cp *= c;
+            out[q] = binom * cp;
+            binom = binom * (p - q) / (q + 1);
+        }
+    } else {
+        const cplx e = std::exp(-t.param * c);
+        double f = 1.0;
+        for (int q = 0; q <= d; ++q) {
+            if (q > 0) f *= q;
+            out[q] = e * std::pow(-t.param, q) / f;
+        }
+    }
+    return out;
+}
+
+ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
+                            const Ellipse& E, int m_keep) {
+    ReducedResult res;
+    const int J = (int)terms.size();
+    bool poly = true;
+    int deg = 1;
+    for (const Term& t : terms) {
+        if (t.kind == 0) deg = std::max(deg, (int)t.param);
+        else poly = false;
+    }
+    if (!poly) {
+        // smallest d with (tau rho)^{d+1} e^{tau rho} / (d+1)! <= 1e-16 on |mu| <= 1.5 max(a, b)
+        const double rho = 1.5 * std::max(E.a, E.b);
+        for (const Term& t : terms) {
+            if (t.kind != 1) continue;
+            const double x = std::fabs(t.param) * rho;
+            int e = 1;
+            double term = x * x / 2.0;
+            while (term * std::exp(x) > 1e-16) {
+                ++e;
+                term *= x / (e + 1);
+            }
+            deg = std::max(deg, e);
+        }
+    }
+    const size_t mm = (size_t)m * m;
+    std::vector<std::vector<cplx>> B(deg + 1, std::vector<cplx>(mm, 0.0));
+    for (int j = 0; j < J; ++j) {
+        const std::vector<cplx> tc = taylor(terms[j], E.c, deg);
+        const cplx* A = Ahat + (size_t)j * mm;
+        for (int q = 0; q <= deg; ++q) {
+            if (tc[q] == 0.0) continue;
+            for (size_t e = 0; e < mm; ++e) B[q][e] += tc[q] * A[e];
+        }
+    }
+    // monic polynomial in nu = 1/mu:  nu^deg I + sum_{q>=1} nu^{deg-q} D_q,  D_q = B_0^{-1} B_q
+    const int N = deg * m;
+    std::vector<cplx> D((size_t)m * m * deg);
+    for (int q = 1; q <= deg; ++q) std::copy(B[q].begin(), B[q].end(), D.begin() + (size_t)(q - 1) * mm);
+    if (!lu_solve_small(m, B[0], D.data(), m * deg)) {
+        res.ok = false;
+        return res;
+    }
+    std::vector<cplx> M((size_t)N * N, 0.0);
+    for (int q = 1; q <= deg; ++q)
+        for (int c = 0; c < m; ++c)
+            for (int r = 0; r < m; ++r)
+                M[r + (size_t)((q - 1) * m + c) * N] = -D[(size_t)(q - 1) * mm + r + (size_t)c * m];
+    for (int bI = 1; bI < deg; ++bI)
+        for (int i = 0; i < m; ++i) M[(size_t)bI * m + i + (size_t)((bI - 1) * m + i) * N] = 1.0;
+    Schur S;
+    if (!S.compute(N, M, true)) {
+        res.ok = false;
+        return res;
+    }
+    const std::vector<cplx>& nu = S.evals;
+    std::vector<cplx> lam(N);
+    std::vector<double> rad(N);
+    for (int i = 0; i < N; ++i) {
+        lam[i] = (nu[i] == 0.0) ? cplx(INFINITY, 0.0) : E.c + 1.0 / nu[i];
+        rad[i] = E.radius(lam[i]);
+    }
+    std::vector<int> order(N);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return rad[p] < rad[q]; });
+    const int keep = std::min(m_keep, N);
+    std::vector<int> want(order.begin(), order.begin() + keep);
+    std::vector<cplx> V;
+    S.vectors(want, V);
+    const std::vector<cplx>& nu2 = nu;
+    res.lambda.resize(keep);
+    res.Y.assign((size_t)m * keep, 0.0);
+    for (int q = 0; q < keep; ++q) {
+        const int k = want[q];
+        res.lambda[q] = (nu2[k] == 0.0) ? cplx(INFINITY, 0.0) : E.c + 1.0 / nu2[k];
+        const cplx* v = &V[(size_t)q * N];
+        int bb = 0;
+        double bn = -1.0;
+        for (int bI = 0; bI < deg; ++bI) {
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += std::norm(v[(size_t)bI * m + i]);
+            if (s > bn) { bn = s; bb = bI; }
+        }
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += std::norm(v[(size_t)bb * m + i]);
+        s = std::sqrt(s);
+        for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = v[(size_t)bb * m + i] / s;
+    }
+    if (!poly) {
+        // Newton on F(y, l) = [T(l) y; v^H y - 1], Jacobian [[T(l), T'(l) y], [v^H, 0]]
+        std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
+        for (int q = 0; q < keep; ++q) {
+            cplx l = res.lambda[q];
+            if (!std::isfinite(l.real())) continue;
+            std::vector<cplx> y(res.Y.begin() + (size_t)q * m, res.Y.begin() + (size_t)(q + 1) * m);
+            const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
+            for (int it = 0; it < 3; ++it) {
+                std::fill(Tl.begin(), Tl.end(), cplx(0.0));
+                std::fill(dT.begin(), dT.end(), cplx(0.0));
+                double scale = 0.0;
+                for (int j = 0; j < J; ++j) {
+                    const cplx f = term_value(terms[j], l), fd = term_deriv(terms[j], l);
+                    const cplx* A = Ahat + (size_t)j * mm;
+                    double an = 0.0;
+                    for (size_t e = 0; e < mm; ++e) {
+                        Tl[e] += f * A[e];
+                        dT[e] += fd * A[e];
+                        an += std::norm(A[e]);
+                    }
+                    scale += std::abs(f) * std::sqrt(an);
+                }
+                double rn = 0.0;
+                for (int r = 0; r < m; ++r) {
+                    cplx t = 0.0;
+                    for (int c = 0; c < m; ++c) t += Tl[r + (size_t)c * m] * y[c];
+                    rhs[r] = -t;
+                    rn += std::norm(t);
+                }
+                cplx vy = 0.0;
+                for (int i = 0; i < m; ++i) vy += std::conj(v0[i]) * y[i];
+                rhs[m] = -(vy - 1.0);
+                if (std::sqrt(rn) <= 1e-15 * scale && std::abs(rhs[m]) < 1e-15) break;
+                for (int c = 0; c < m; ++c)
+                    for (int r = 0; r < m; ++r) Jm[r + (size_t)c * (m + 1)] = Tl[r + (size_t)c * m];
+                for (int r = 0; r < m; ++r) {
+                    cplx t = 0.0;
+                    for (int c = 0; c < m; ++c) t += dT[r + (size_t)c * m] * y[c];
+                    Jm[r + (size_t)m * (m + 1)] = t;
+                }
+                for (int c = 0; c < m; ++c) Jm[m + (size_t)c * (m + 1)] = std::conj(v0[c]);
+                Jm[m + (size_t)m * (m + 1)] = 0.0;
+                if (!lu_solve_small(m + 1, Jm, rhs.data(), 1)) break;
+                for (int i = 0; i < m; ++i) y[i] += rhs[i];
+                l += rhs[m];
+            }
+            double s = 0.0;
+            for (int i = 0; i < m; ++i) s += std::norm(y[i]);
+            s = std::sqrt(s);
+            for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = y[i] / s;
+            res.lambda[q] = l;
+        }
+    }
+    res.n_finite = 0;
+    for (int q = 0; q < keep; ++q)
+        if (std::isfinite(res.lambda[q].real())) ++res.n_finite;
+    return res;
+}
+
+}  // namespace nlf

@@ -1,0 +1,67 @@
+// Internal launch interfaces of the HIP kernels (not part of the C ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace nlf {
+
+struct GemmConfig {
+    int tm = 2, tn = 2;   // MFMA tiles per wave in m and n (workgroup tile 32tm x 32tn)
+};
+
+// C_b = alpha op(A_b) B_b + beta C_b, op(A) = A^H when conjA.  ws (optional) enables split-K
+// for small outputs with long reductions.  force overrides the tile choice.
+template <typename R>
+void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alpha,
+          const Cx<R>* A, int64_t lda, int64_t sA, const Cx<R>* B, int64_t ldb, int64_t sB,
+          Cx<R> beta, Cx<R>* C, int64_t ldc, int64_t sC, int batch, Cx<R>* ws = nullptr,
+          int64_t ws_elems = 0, const GemmConfig* force = nullptr);
+
+// Blocked recursive LU with partial pivoting (in place), batched over strided matrices.
+template <typename R>
+void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
+           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch);
+// Scratch (int32 elements) that getrf needs for its row-exchange lists.
+int64_t getrf_scratch_ints(int64_t n, int batch);
+
+// X_b = A_b^{-1} B_b from getrf factors; B may be shared (sB = 0).  X must not alias B.
+template <typename R>
+void getrs(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+           int64_t sA, const int32_t* perm, const Cx<R>* B, int64_t ldb, int64_t sB, Cx<R>* X,
+           int64_t ldx, int64_t sX);
+
+// In-place triangular solves B <- L^{-1} B (unit lower) and B <- U^{-1} B (upper).
+template <typename R>
+void trsm_lower_unit(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* L,
+                     int64_t ldl, int64_t sL, Cx<R>* B, int64_t ldb, int64_t sB);
+template <typename R>
+void trsm_upper(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* U, int64_t ldu,
+                int64_t sU, Cx<R>* B, int64_t ldb, int64_t sB);
+
+// ---- elementwise / reduction kernels (elementwise.hip)
+
+// T_k = sum_j coef[k*J + j] A_j for k < nz; outputs in c128 (T64) and/or c64 (T32).
+void assemble(hipStream_t s, int64_t n, int J, const z128* const* A, int64_t lda,
+              int nz, const z128* coef_dev, z128* T64, z64* T32, int64_t ldt, int64_t sT);
+// column 2-norms of a c128 n x m block (ld) into out (device doubles)
+void col_norms(hipStream_t s, int64_t n, int m, const z128* X, int64_t ld, double* out);
+// Q = X diag(rho) - sum_k Y_k diag(c_k) with rho (m) and c (nz x m) on the device
+void accumulate(hipStream_t s, int64_t n, int m, int nz, const z128* X, const z128* Y,
+                int64_t sY, const z128* rho, const z128* c, z128* Q);
+// precision casts of an n x m block (ld in, ld out), batched
+void cast_128_to_64(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* in,
+                    int64_t ldi, int64_t si, z64* out, int64_t ldo, int64_t so);
+void cast_64_to_128(hipStream_t s, int64_t rows, int64_t cols, int batch, const z64* in,
+                    int64_t ldi, int64_t si, z128* out, int64_t ldo, int64_t so, bool accumulate);
+// sum of squared magnitudes of each of `batch` n x m blocks into out[b] (device doubles)
+void block_sqnorms(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* X,
+                   int64_t ld, int64_t sX, double* out);
+// copy an n x m c128 block (ld in, ld out)
+void copy_block(hipStream_t s, int64_t rows, int64_t cols, const z128* in, int64_t ldi,
+                z128* out, int64_t ldo);
+// p[0..count) = v (a kernel, so that the sequence stays capturable in a HIP graph)
+void fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v);
+// counter-based standard complex normal draws CN(0,1) for an n x m block
+void random_normal(hipStream_t s, int64_t rows, int64_t cols, uint64_t seed, z128* out, int64_t ld);
+
+}  // namespace nlf

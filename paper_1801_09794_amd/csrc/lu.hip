@@ -1,0 +1,554 @@
+// Batched complex LU with partial pivoting and the triangular solves that apply T(z_k)^{-1}
+// (Step 4 of Algorithm 1 multiplies by T^{-1}(z_j) by solving linear systems; the shifts are
+// fixed for the whole iteration, so each T(z_k) is factored once and the factors are reused).
+//
+// Factorisation: recursive (column-halving) LU.  Columns [k0, k0+nc) of the trailing rows are
+// split into halves: factor the left half, apply its row exchanges to the right half, solve
+// with the unit-lower diagonal block (recursive TRSM), update the lower-right block with a
+// complex GEMM on MFMA, factor it, and apply its exchanges back to the left half.  Almost all
+// flops land in large GEMMs; the recursion stops at panels of at most 32 columns.
+//
+// Panel kernel: one 1024-thread workgroup per matrix factors an (n-k0) x w panel (w <= 32).
+// Each thread owns RPT fixed rows; the panel is processed in sub-blocks of SB columns held in
+// registers (left-looking between sub-blocks: the sub-block is updated with the L columns
+// already factored, through a small LDS forward substitution for its top rows).  Pivot search
+// is a wavefront shuffle reduction followed by a 16-wave LDS reduction on |Re| + |Im|.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <climits>
+
+namespace nlf {
+
+constexpr int PANEL_NT = 1024;
+constexpr int PANEL_WMAX = 32;
+constexpr int TRSM_NB = 64;
+
+template <typename R>
+__device__ __forceinline__ void wave_argmax(R& v, int& row) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        R ov = __shfl_xor(v, off, 64);
+        int orow = __shfl_xor(row, off, 64);
+        if (ov > v || (ov == v && orow < row)) {
+            v = ov;
+            row = orow;
+        }
+    }
+}
+
+template <typename R, int RPT, int SB>
+__global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
+                                                        int64_t n, int64_t k0, int w,
+                                                        int32_t* ipiv, int32_t* info) {
+    constexpr int NT = PANEL_NT;
+    const int64_t bidx = blockIdx.x;
+    Cx<R>* A = A0 + bidx * sA + k0 + k0 * lda;      // panel origin
+    int32_t* piv = ipiv + bidx * n;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mp = (int)(n - k0);
+
+    __shared__ Cx<R> Ltop[PANEL_WMAX][PANEL_WMAX + 1];
+    __shared__ Cx<R> Utop[PANEL_WMAX][SB];
+    __shared__ R redv[NT / 64];
+    __shared__ int redr[NT / 64];
+    __shared__ Cx<R> rowJ[SB], rowP[SB];
+
+    Cx<R> x[RPT][SB];
+
+    for (int s0 = 0; s0 < w; s0 += SB) {
+        const int bw = min(SB, w - s0);
+        // (1) top rows of the sub-block: U = L11^{-1} A[0:s0, s0:s0+bw] (unit-lower L11)
+        if (s0 > 0) {
+            for (int e = tid; e < s0 * s0; e += NT) {
+                const int t = e % s0, u = e / s0;
+                if (u < t) Ltop[t][u] = A[t + (int64_t)u * lda];
+            }
+            for (int e = tid; e < s0 * bw; e += NT) {
+                const int t = e % s0, c = e / s0;
+                Utop[t][c] = A[t + (int64_t)(s0 + c) * lda];
+            }
+            __syncthreads();
+            if (wave == 0) {
+                for (int u = 0; u + 1 < s0; ++u) {
+                    const int rows = s0 - 1 - u;
+                    for (int e = lane; e < rows * bw; e += 64) {
+                        const int t = u + 1 + e % rows, c = e / rows;
+                        Cx<R> v = Utop[t][c];
+                        cfms(v, Ltop[t][u], Utop[u][c]);
+                        Utop[t][c] = v;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            __syncthreads();
+            for (int e = tid; e < s0 * bw; e += NT) {
+                const int t = e % s0, c = e / s0;
+                A[t + (int64_t)(s0 + c) * lda] = Utop[t][c];
+            }
+        }
+        // (2) load the sub-block rows >= s0 and (3) left-looking update with L[:, 0:s0]
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = tid + NT * i;
+            const bool ok = r >= s0 && r < mp;
+#pragma unroll
+            for (int c = 0; c < SB; ++c)
+                x[i][c] = (ok && c < bw) ? A[r + (int64_t)(s0 + c) * lda] : Cx<R>(0, 0);
+        }
+        for (int u = 0; u < s0; ++u) {
+            Cx<R> ucol[SB];
+#pragma unroll
+            for (int c = 0; c < SB; ++c) ucol[c] = (c < bw) ? Utop[u][c] : Cx<R>(0, 0);
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = tid + NT * i;
+                if (r >= s0 && r < mp) {
+                    const Cx<R> l = A[r + (int64_t)u * lda];
+#pragma unroll
+                    for (int c = 0; c < SB; ++c) cfms(x[i][c], l, ucol[c]);
+                }
+            }
+        }
+        // (4) factor the sub-block column by column
+#pragma unroll
+        for (int c = 0; c < SB; ++c) {
+          if (c < bw) {
+            const int j = s0 + c;
+            R best = R(-1);
+            int brow = INT_MAX;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = tid + NT * i;
+                if (r >= j && r < mp) {
+                    const R v = abs1(x[i][c]);
+                    if (v > best) { best = v; brow = r; }
+                }
+            }
+            wave_argmax(best, brow);
+            if (lane == 0) { redv[wave] = best; redr[wave] = brow; }
+            __syncthreads();
+            R pv = redv[0];
+            int pr = redr[0];
+#pragma unroll
+            for (int q = 1; q < NT / 64; ++q) {
+                const R v = redv[q];
+                const int rr = redr[q];
+                if (v > pv || (v == pv && rr < pr)) { pv = v; pr = rr; }
+            }
+            if (pr == INT_MAX || !(pv > R(0))) {   // all zero (or NaN): no exchange
+                pr = j;
+                pv = R(0);
+            }
+            if (tid == 0) {
+                piv[k0 + j] = (int32_t)(k0 + pr);
+                if (pv == R(0) && info[bidx] == 0) info[bidx] = (int32_t)(k0 + j + 1);
+            }
+            const int ownJ = j % NT, iJ = j / NT, ownP = pr % NT, iP = pr / NT;
+            if (tid == ownJ) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == iJ)
+#pragma unroll
+                        for (int cc = 0; cc < SB; ++cc) rowJ[cc] = x[i][cc];
+            }
+            if (tid == ownP) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == iP)
+#pragma unroll
+                        for (int cc = 0; cc < SB; ++cc) rowP[cc] = x[i][cc];
+            }
+            __syncthreads();
+            if (pr != j) {
+                if (tid == ownJ) {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i)
+                        if (i == iJ)
+#pragma unroll
+                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = rowP[cc];
+                }
+                if (tid == ownP) {
+#pragma unroll
+                    for (int i = 0; i < RPT; ++i)
+                        if (i == iP)
+#pragma unroll
+                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = rowJ[cc];
+                }
+                if (tid < w && (tid < s0 || tid >= s0 + bw)) {
+                    Cx<R>* a = A + (int64_t)tid * lda;
+                    const Cx<R> t = a[j];
+                    a[j] = a[pr];
+                    a[pr] = t;
+                }
+            }
+            if (pv > R(0)) {
+                const Cx<R> inv = cdiv(Cx<R>(1, 0), rowP[c]);
+                Cx<R> prow[SB];
+#pragma unroll
+                for (int cc = 0; cc < SB; ++cc) prow[cc] = rowP[cc];
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = tid + NT * i;
+                    if (r > j && r < mp) {
+                        const Cx<R> l = x[i][c] * inv;
+                        x[i][c] = l;
+#pragma unroll
+                        for (int cc = 0; cc < SB; ++cc)
+                            if (cc > c && cc < bw) cfms(x[i][cc], l, prow[cc]);
+                    }
+                }
+            }
+          }
+        }
+        // (5) store the sub-block
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = tid + NT * i;
+            if (r >= s0 && r < mp) {
+#pragma unroll
+                for (int c = 0; c < SB; ++c)
+                    if (c < bw) A[r + (int64_t)(s0 + c) * lda] = x[i][c];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Composed permutation of all row exchanges: (P A)[i] = A[perm[i]].  One workgroup per matrix.
+__global__ __launch_bounds__(1024) void perm_kernel(int64_t n, const int32_t* ipiv, int32_t* perm) {
+    extern __shared__ int sp[];
+    const int64_t b = blockIdx.x;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) sp[r] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t* p = ipiv + b * n;
+        for (int k = 0; k < n; ++k) {
+            const int q = p[k];
+            const int t = sp[k];
+            sp[k] = sp[q];
+            sp[q] = t;
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) perm[b * n + r] = sp[r];
+}
+
+// (dst, src) row pairs that realise the exchanges k in [k1, k2) (applied in order).
+// list layout per matrix: [2][L] with L = 2 (k2 - k1); dst = -1 marks an unused entry.
+__global__ __launch_bounds__(1024) void swaplist_kernel(int64_t n, int64_t k1, int64_t k2,
+                                                        const int32_t* ipiv, int32_t* list) {
+    extern __shared__ int sp[];               // rows [k1, n)
+    const int64_t b = blockIdx.x;
+    const int span = (int)(n - k1), cnt = (int)(k2 - k1), L = 2 * cnt;
+    const int32_t* p = ipiv + b * n;
+    int32_t* dst = list + b * 2 * (int64_t)L;
+    int32_t* src = dst + L;
+    for (int r = threadIdx.x; r < span; r += blockDim.x) sp[r] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < cnt; ++k) {
+            const int q = p[k1 + k] - (int)k1;
+            const int t = sp[k];
+            sp[k] = sp[q];
+            sp[q] = t;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        dst[e] = (int)k1 + e;
+        src[e] = (int)k1 + sp[e];
+        const int q = p[k1 + e];
+        if (q >= k2) {
+            dst[cnt + e] = q;
+            src[cnt + e] = (int)k1 + sp[q - k1];
+        } else {
+            dst[cnt + e] = -1;
+            src[cnt + e] = 0;
+        }
+    }
+}
+
+template <typename R, int EPT>
+__global__ __launch_bounds__(1024) void laswp_apply_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
+                                                           int64_t c0, int64_t ncols, int cw,
+                                                           const int32_t* list, int L) {
+    const int64_t b = blockIdx.y;
+    Cx<R>* A = A0 + b * sA;
+    const int32_t* dst = list + b * 2 * (int64_t)L;
+    const int32_t* src = dst + L;
+    int d[EPT], s[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + 1024 * i;
+        d[i] = e < L ? dst[e] : -1;
+        s[i] = e < L ? src[e] : 0;
+    }
+    const int64_t cbeg = c0 + (int64_t)blockIdx.x * cw;
+    const int64_t cend = std::min<int64_t>(cbeg + cw, c0 + ncols);
+    for (int64_t c = cbeg; c < cend; ++c) {
+        Cx<R>* col = A + c * lda;
+        Cx<R> v[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (d[i] >= 0) v[i] = col[s[i]];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (d[i] >= 0) col[d[i]] = v[i];
+        __syncthreads();
+    }
+}
+
+// B <- T^{-1} B for one diagonal block of order nb <= 64 (unit-lower or upper triangular T),
+// CB columns of B per workgroup, T and the B block staged in LDS.
+template <typename R, bool UPPER>
+__global__ __launch_bounds__(256) void trsm_leaf_kernel(int nb, int64_t N, const Cx<R>* T0,
+                                                        int64_t ldt, int64_t sT, Cx<R>* B0,
+                                                        int64_t ldb, int64_t sB) {
+    constexpr int CB = 16;
+    __shared__ Cx<R> Ts[TRSM_NB][TRSM_NB + 1];
+    __shared__ Cx<R> Bs[TRSM_NB][CB];
+    const int64_t b = blockIdx.y;
+    const Cx<R>* T = T0 + b * sT;
+    Cx<R>* B = B0 + b * sB;
+    const int64_t cbase = (int64_t)blockIdx.x * CB;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e % nb, j = e / nb;
+        Ts[i][j] = T[i + (int64_t)j * ldt];
+    }
+    for (int e = tid; e < nb * CB; e += 256) {
+        const int i = e % nb, c = e / nb;
+        Bs[i][c] = (cbase + c < N) ? B[i + (cbase + c) * ldb] : Cx<R>(0, 0);
+    }
+    __syncthreads();
+    if (!UPPER) {
+        for (int t = 0; t + 1 < nb; ++t) {
+            for (int e = tid; e < nb * CB; e += 256) {
+                const int i = e % nb, c = e / nb;
+                if (i > t) {
+                    Cx<R> v = Bs[i][c];
+                    cfms(v, Ts[i][t], Bs[t][c]);
+                    Bs[i][c] = v;
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int t = nb - 1; t >= 0; --t) {
+            if (tid < CB) Bs[t][tid] = cdiv(Bs[t][tid], Ts[t][t]);
+            __syncthreads();
+            for (int e = tid; e < nb * CB; e += 256) {
+                const int i = e % nb, c = e / nb;
+                if (i < t) {
+                    Cx<R> v = Bs[i][c];
+                    cfms(v, Ts[i][t], Bs[t][c]);
+                    Bs[i][c] = v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = tid; e < nb * CB; e += 256) {
+        const int i = e % nb, c = e / nb;
+        if (cbase + c < N) B[i + (cbase + c) * ldb] = Bs[i][c];
+    }
+}
+
+// X_b[i, c] = B_b[perm_b[i], c]
+template <typename R>
+__global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int64_t ncols,
+                                                          const int32_t* perm, const Cx<R>* B0,
+                                                          int64_t ldb, int64_t sB, Cx<R>* X0,
+                                                          int64_t ldx, int64_t sX) {
+    const int64_t b = blockIdx.y;
+    const int32_t* p = perm + b * n;
+    const Cx<R>* B = B0 + b * sB;
+    Cx<R>* X = X0 + b * sX;
+    const int64_t total = n * ncols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % n, c = e / n;
+        X[i + c * ldx] = B[p[i] + c * ldb];
+    }
+}
+
+// ------------------------------------------------------------------------------ host side
+
+template <typename R>
+void trsm_lower_unit(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* L,
+                     int64_t ldl, int64_t sL, Cx<R>* B, int64_t ldb, int64_t sB) {
+    if (n <= 0 || N <= 0) return;
+    if (n <= TRSM_NB) {
+        ProfScope ps(trsm_class(), s, 4.0 * n * n * N * batch, 0);
+        dim3 grid((unsigned)ceil_div(N, 16), batch);
+        hipLaunchKernelGGL((trsm_leaf_kernel<R, false>), grid, dim3(256), 0, s, (int)n, N, L,
+                           ldl, sL, B, ldb, sB);
+        NLF_HIP(hipGetLastError());
+        return;
+    }
+    const int64_t n1 = std::max<int64_t>(TRSM_NB, (n / 2) / TRSM_NB * TRSM_NB);
+    trsm_lower_unit<R>(s, n1, N, batch, L, ldl, sL, B, ldb, sB);
+    {
+        ProfScope ps(trsm_class(), s, 8.0 * (n - n1) * N * n1 * batch, 0);
+        gemm<R>(s, false, n - n1, N, n1, Cx<R>(-1, 0), L + n1, ldl, sL, B, ldb, sB,
+                Cx<R>(1, 0), B + n1, ldb, sB, batch);
+    }
+    trsm_lower_unit<R>(s, n - n1, N, batch, L + n1 + n1 * ldl, ldl, sL, B + n1, ldb, sB);
+}
+
+template <typename R>
+void trsm_upper(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* U, int64_t ldu,
+                int64_t sU, Cx<R>* B, int64_t ldb, int64_t sB) {
+    if (n <= 0 || N <= 0) return;
+    if (n <= TRSM_NB) {
+        ProfScope ps(trsm_class(), s, 4.0 * n * n * N * batch, 0);
+        dim3 grid((unsigned)ceil_div(N, 16), batch);
+        hipLaunchKernelGGL((trsm_leaf_kernel<R, true>), grid, dim3(256), 0, s, (int)n, N, U,
+                           ldu, sU, B, ldb, sB);
+        NLF_HIP(hipGetLastError());
+        return;
+    }
+    const int64_t n1 = std::max<int64_t>(TRSM_NB, (n / 2) / TRSM_NB * TRSM_NB);
+    trsm_upper<R>(s, n - n1, N, batch, U + n1 + n1 * ldu, ldu, sU, B + n1, ldb, sB);
+    {
+        ProfScope ps(trsm_class(), s, 8.0 * n1 * N * (n - n1) * batch, 0);
+        gemm<R>(s, false, n1, N, n - n1, Cx<R>(-1, 0), U + n1 * ldu, ldu, sU, B + n1, ldb,
+                sB, Cx<R>(1, 0), B, ldb, sB, batch);
+    }
+    trsm_upper<R>(s, n1, N, batch, U, ldu, sU, B, ldb, sB);
+}
+
+template <typename R>
+static void launch_panel(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_t sA,
+                         int64_t n, int64_t k0, int w, int32_t* ipiv, int32_t* info) {
+    const int64_t mp = n - k0;
+    const double fl = 8.0 * batch * ((double)mp * w * w - (double)w * w * w / 3.0) / 2.0;
+    ProfScope ps(NLF_PROF_PANEL, s, fl, 0);
+#define NLF_PANEL(RPT_, SB_) \
+    hipLaunchKernelGGL((panel_kernel<R, RPT_, SB_>), dim3(batch), dim3(PANEL_NT), 0, s, A, lda, sA, n, k0, w, ipiv, info)
+    // sub-block width SB: RPT x SB complex values per thread stay within the 128-VGPR budget
+    // of a 1024-thread workgroup
+    if constexpr (sizeof(R) == 8) {
+        if (mp <= 1024) NLF_PANEL(1, 8);
+        else if (mp <= 2048) NLF_PANEL(2, 8);
+        else if (mp <= 4096) NLF_PANEL(4, 4);
+        else if (mp <= 8192) NLF_PANEL(8, 2);
+        else throw Error{1, "getrf: matrix order above 8192 is not supported"};
+    } else {
+        if (mp <= 1024) NLF_PANEL(1, 16);
+        else if (mp <= 2048) NLF_PANEL(2, 16);
+        else if (mp <= 4096) NLF_PANEL(4, 8);
+        else if (mp <= 8192) NLF_PANEL(8, 4);
+        else throw Error{1, "getrf: matrix order above 8192 is not supported"};
+    }
+#undef NLF_PANEL
+    NLF_HIP(hipGetLastError());
+}
+
+template <typename R>
+static void laswp(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_t sA, int64_t n,
+                  int64_t k1, int64_t k2, int64_t c0, int64_t ncols, const int32_t* ipiv,
+                  int32_t* list) {
+    if (ncols <= 0 || k2 <= k1) return;
+    const int L = (int)(2 * (k2 - k1));
+    ProfScope ps(NLF_PROF_LASWP, s, 0, 2.0 * L * ncols * sizeof(Cx<R>) * batch);
+    hipLaunchKernelGGL(swaplist_kernel, dim3(batch), dim3(1024), (size_t)(n - k1) * sizeof(int), s,
+                       n, k1, k2, ipiv, list);
+    NLF_HIP(hipGetLastError());
+    const int cw = 4;
+    dim3 grid((unsigned)ceil_div(ncols, cw), batch);
+    if (L <= 1024)
+        hipLaunchKernelGGL((laswp_apply_kernel<R, 1>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
+    else if (L <= 2048)
+        hipLaunchKernelGGL((laswp_apply_kernel<R, 2>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
+    else if (L <= 4096)
+        hipLaunchKernelGGL((laswp_apply_kernel<R, 4>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
+    else if (L <= 8192)
+        hipLaunchKernelGGL((laswp_apply_kernel<R, 8>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
+    else
+        throw Error{1, "laswp: exchange range too large"};
+    NLF_HIP(hipGetLastError());
+}
+
+template <typename R>
+static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
+                      int64_t k0, int64_t nc, int32_t* ipiv, int32_t* info, int32_t* list) {
+    if (nc <= PANEL_WMAX) {
+        launch_panel<R>(s, batch, A, lda, sA, n, k0, (int)nc, ipiv, info);
+        return;
+    }
+    int64_t n1 = (nc / 2) / PANEL_WMAX * PANEL_WMAX;
+    if (n1 < PANEL_WMAX) n1 = PANEL_WMAX;
+    const int64_t n2 = nc - n1;
+    getrf_rec<R>(s, n, batch, A, lda, sA, k0, n1, ipiv, info, list);
+    laswp<R>(s, batch, A, lda, sA, n, k0, k0 + n1, k0 + n1, n2, ipiv, list);
+    trsm_lower_unit<R>(s, n1, n2, batch, A + k0 + k0 * lda, lda, sA, A + k0 + (k0 + n1) * lda,
+                       lda, sA);
+    const int64_t mrest = n - (k0 + n1);
+    {
+        ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * mrest * n2 * n1 * batch,
+                     sizeof(Cx<R>) * (2.0 * mrest * n2 + (double)mrest * n1 + (double)n1 * n2) * batch);
+        gemm<R>(s, false, mrest, n2, n1, Cx<R>(-1, 0), A + (k0 + n1) + k0 * lda, lda, sA,
+                A + k0 + (k0 + n1) * lda, lda, sA, Cx<R>(1, 0),
+                A + (k0 + n1) + (k0 + n1) * lda, lda, sA, batch);
+    }
+    getrf_rec<R>(s, n, batch, A, lda, sA, k0 + n1, n2, ipiv, info, list);
+    laswp<R>(s, batch, A, lda, sA, n, k0 + n1, k0 + nc, k0, n1, ipiv, list);
+}
+
+int64_t getrf_scratch_ints(int64_t n, int batch) { return (int64_t)batch * 2 * (2 * n); }
+
+template <typename R>
+void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
+           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch) {
+    if (n <= 0 || batch <= 0) return;
+    NLF_REQUIRE(n <= 8192, 1, "getrf: n > 8192 not supported");
+    fill_i32(s, info, batch, 0);
+    getrf_rec<R>(s, n, batch, A, lda, sA, 0, n, ipiv, info, scratch);
+    if (perm) {
+        hipLaunchKernelGGL(perm_kernel, dim3(batch), dim3(1024), (size_t)n * sizeof(int), s, n,
+                           (const int32_t*)ipiv, perm);
+        NLF_HIP(hipGetLastError());
+    }
+}
+
+template <typename R>
+void getrs(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+           int64_t sA, const int32_t* perm, const Cx<R>* B, int64_t ldb, int64_t sB, Cx<R>* X,
+           int64_t ldx, int64_t sX) {
+    if (n <= 0 || nrhs <= 0 || batch <= 0) return;
+    {
+        ProfScope ps(trsm_class(), s, 0, 2.0 * n * nrhs * sizeof(Cx<R>) * batch);
+        const int64_t total = n * nrhs;
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), batch);
+        hipLaunchKernelGGL((gather_rows_kernel<R>), grid, dim3(256), 0, s, n, (int64_t)nrhs,
+                           perm, B, ldb, sB, X, ldx, sX);
+        NLF_HIP(hipGetLastError());
+    }
+    trsm_lower_unit<R>(s, n, nrhs, batch, LU, lda, sA, X, ldx, sX);
+    trsm_upper<R>(s, n, nrhs, batch, LU, lda, sA, X, ldx, sX);
+}
+
+template void getrf<double>(hipStream_t, int64_t, int, Cx<double>*, int64_t, int64_t, int32_t*,
+                            int32_t*, int32_t*, int32_t*);
+template void getrf<float>(hipStream_t, int64_t, int, Cx<float>*, int64_t, int64_t, int32_t*,
+                           int32_t*, int32_t*, int32_t*);
+template void getrs<double>(hipStream_t, int64_t, int, int, const Cx<double>*, int64_t, int64_t,
+                            const int32_t*, const Cx<double>*, int64_t, int64_t, Cx<double>*,
+                            int64_t, int64_t);
+template void getrs<float>(hipStream_t, int64_t, int, int, const Cx<float>*, int64_t, int64_t,
+                           const int32_t*, const Cx<float>*, int64_t, int64_t, Cx<float>*,
+                           int64_t, int64_t);
+template void trsm_lower_unit<double>(hipStream_t, int64_t, int64_t, int, const Cx<double>*,
+                                      int64_t, int64_t, Cx<double>*, int64_t, int64_t);
+template void trsm_lower_unit<float>(hipStream_t, int64_t, int64_t, int, const Cx<float>*,
+                                     int64_t, int64_t, Cx<float>*, int64_t, int64_t);
+template void trsm_upper<double>(hipStream_t, int64_t, int64_t, int, const Cx<double>*, int64_t,
+                                 int64_t, Cx<double>*, int64_t, int64_t);
+template void trsm_upper<float>(hipStream_t, int64_t, int64_t, int, const Cx<float>*, int64_t,
+                                int64_t, Cx<float>*, int64_t, int64_t);
+
+}  // namespace nlf

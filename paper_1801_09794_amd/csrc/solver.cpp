@@ -1,0 +1,850 @@
+// Orchestration of Algorithm 1 (NLFEAST) on one GPU, and the C ABI of include/nlfeast.h.
+//
+// Per contour (fixed shifts): assemble T(z_k) = sum_j f_j(z_k) A_j for all nodes of all regions
+// in one HBM pass, factor them in one batched LU (complex128, or complex64 for the precision
+// form, which also keeps T(z_k) in complex128 for the refinement residuals), and keep the
+// factors in the caller's workspace for the following solves.
+//
+// Per iteration and region (Sec. 4.2, Algorithm 1):
+//   Step 1  W_j = A_j Q, Ahat_j = Q^H W_j on the device; the reduced problem on the host
+//   Step 2  selection of m0 pairs; X = Q Y on the device
+//   Step 3  R = T(X, Lambda) = sum_j W_j (Y f_j(Lambda)) as one GEMM, column norms
+//   Step 4  Y_k = T(z_k)^{-1} R for all nodes (batched triangular solves; refinement sweeps in
+//           the precision form), Q = X rho(Lambda) - sum_k omega_k Y_k (z_k I - Lambda)^{-1}
+//   Step 5  Cholesky QR twice (Gram matrix on the device, m0 x m0 Cholesky on the host)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nlfeast.h"
+#include "common.hpp"
+#include "host_dense.hpp"
+#include "kernels.hpp"
+
+namespace nlf {
+
+// ------------------------------------------------------------------------------- profiler
+struct Profiler {
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    double ms[NLF_PROF_COUNT] = {}, flops[NLF_PROF_COUNT] = {}, bytes[NLF_PROF_COUNT] = {};
+    int64_t launches[NLF_PROF_COUNT] = {};
+
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            NLF_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void reset() {
+        recs.clear();
+        used = 0;
+        std::fill(ms, ms + NLF_PROF_COUNT, 0.0);
+        std::fill(flops, flops + NLF_PROF_COUNT, 0.0);
+        std::fill(bytes, bytes + NLF_PROF_COUNT, 0.0);
+        std::fill(launches, launches + NLF_PROF_COUNT, 0);
+    }
+    void collect() {   // call after the stream has been synchronised
+        for (const Rec& r : recs) {
+            float t = 0;
+            NLF_HIP(hipEventElapsedTime(&t, r.a, r.b));
+            ms[r.cls] += t;
+            flops[r.cls] += r.flops;
+            bytes[r.cls] += r.bytes;
+            launches[r.cls] += 1;
+        }
+        recs.clear();
+        used = 0;
+    }
+    ~Profiler() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+Profiler*& active_profiler() {
+    static thread_local Profiler* p = nullptr;
+    return p;
+}
+
+int& trsm_class() {
+    static thread_local int c = NLF_PROF_TRSM;
+    return c;
+}
+
+ProfScope::ProfScope(int cls_, hipStream_t s_, double fl, double by)
+    : p(active_profiler()), cls(cls_), s(s_), flops(fl), bytes(by), ev0(nullptr) {
+    if (p) {
+        hipEvent_t e = p->get();
+        NLF_HIP(hipEventRecord(e, s));
+        ev0 = e;
+    }
+}
+
+ProfScope::~ProfScope() {
+    if (p) {
+        hipEvent_t e = p->get();
+        (void)hipEventRecord(e, s);
+        p->recs.push_back({cls, (hipEvent_t)ev0, e, flops, bytes});
+    }
+}
+
+struct TrsmClassGuard {
+    int saved;
+    explicit TrsmClassGuard(int c) : saved(trsm_class()) { trsm_class() = c; }
+    ~TrsmClassGuard() { trsm_class() = saved; }
+};
+
+struct ProfilerGuard {
+    Profiler* saved;
+    explicit ProfilerGuard(Profiler* p) : saved(active_profiler()) { active_profiler() = p; }
+    ~ProfilerGuard() { active_profiler() = saved; }
+};
+
+static thread_local std::string g_last_error;
+
+}  // namespace nlf
+
+using namespace nlf;
+
+struct nlfeast_ctx {
+    int64_t n = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string last_error;
+    int J = 0;
+    std::vector<Term> terms;
+    std::vector<const z128*> A;
+    int64_t lda = 0;
+    struct Region {
+        Ellipse E;
+        int nc = 0, m0 = 0;
+        std::vector<cplx> z, w;
+    };
+    std::vector<Region> regions;
+    int quad_rule = 0;
+    bool factors_valid = false;
+    const void* factors_ws = nullptr;
+    int factors_prec = -1;
+    bool profiling = false;
+    Profiler prof;
+};
+
+namespace {
+
+struct Layout {
+    size_t total = 0;
+    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0;
+    size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
+    size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0,
+           coef = 0;
+    int64_t splitws_elems = 0;
+    int NZ = 0, M = 0, mmax = 0, ncmax = 0;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+Layout make_layout(const nlfeast_ctx* h, int prec) {
+    Layout L;
+    const int64_t n = h->n;
+    for (const auto& r : h->regions) {
+        L.NZ += r.nc;
+        L.M += r.m0;
+        L.mmax = std::max(L.mmax, r.m0);
+        L.ncmax = std::max(L.ncmax, r.nc);
+    }
+    const int J = std::max(h->J, 1);
+    const size_t nn = (size_t)n * n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const bool p32 = prec == NLF_PREC_FP32_REFINE;
+    L.fact = take(nn * L.NZ * (p32 ? 8 : 16));
+    L.t64 = p32 ? take(nn * L.NZ * 16) : 0;
+    L.ipiv = take(sizeof(int32_t) * n * L.NZ);
+    L.perm = take(sizeof(int32_t) * n * L.NZ);
+    L.info = take(sizeof(int32_t) * L.NZ);
+    L.list = take(sizeof(int32_t) * getrf_scratch_ints(n, L.NZ));
+    const size_t blk = (size_t)n * L.mmax;
+    L.Q = take(16 * blk);
+    L.X = take(16 * blk);
+    L.W = take(16 * blk * J);
+    L.R = take(16 * blk);
+    L.Ys = take(16 * blk * L.ncmax);
+    L.QT = take(16 * blk);
+    if (p32) {
+        L.R32 = take(8 * blk);
+        L.Y32 = take(8 * blk * L.ncmax);
+        L.E = take(16 * blk * L.ncmax);
+        L.E32 = take(8 * blk * L.ncmax);
+    }
+    const size_t mm = (size_t)L.mmax * L.mmax;
+    L.Ahat = take(16 * mm * J);
+    L.G = take(16 * mm);
+    L.Ymat = take(16 * mm);
+    L.Gall = take(16 * mm * J);
+    L.rho = take(16 * L.mmax);
+    L.acoef = take(16 * (size_t)L.mmax * L.ncmax);
+    L.norms = take(8 * (size_t)(L.mmax + L.ncmax + 8));
+    L.splitws_elems = (int64_t)std::max<size_t>(64 * mm * J, 1 << 16);
+    L.splitws = take(16 * (size_t)L.splitws_elems);
+    L.coef = take(16 * (size_t)L.NZ * J);
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+void h2d(hipStream_t s, void* dst, const void* src, size_t bytes) {
+    NLF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+void d2h_sync(hipStream_t s, void* dst, const void* src, size_t bytes) {
+    NLF_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    NLF_HIP(hipStreamSynchronize(s));
+}
+
+// Steps 0/5: Cholesky QR, twice; a diagonal shift rescues a numerically rank-deficient Gram
+// matrix (then a third pass restores orthonormality).
+void orthonormalize(hipStream_t s, int64_t n, int m, z128* Q, z128* QT, z128* Gd, z128* Rd,
+                    z128* splitws, int64_t split_elems) {
+    std::vector<cplx> G((size_t)m * m), Rinv;
+    int passes = 2;
+    for (int p = 0; p < passes; ++p) {
+        {
+            ProfScope ps(NLF_PROF_ORTH, s, 8.0 * n * m * m, 16.0 * n * m);
+            gemm<double>(s, true, m, m, n, z128(1, 0), Q, n, 0, Q, n, 0, z128(0, 0), Gd, m, 0, 1,
+                         splitws, split_elems);
+        }
+        d2h_sync(s, G.data(), Gd, sizeof(cplx) * m * m);
+        if (!cholesky_upper_inverse(m, G.data(), Rinv)) {
+            double tr = 0.0;
+            for (int i = 0; i < m; ++i) tr += std::abs(G[i + (size_t)i * m].real());
+            const double shift = 1e-13 * std::max(tr, 1e-300);
+            for (int i = 0; i < m; ++i) G[i + (size_t)i * m] += shift;
+            NLF_REQUIRE(cholesky_upper_inverse(m, G.data(), Rinv), NLF_ERR_DEVICE,
+                        "orthonormalisation: Gram matrix is not positive definite");
+            passes = 3;
+        }
+        h2d(s, Rd, Rinv.data(), sizeof(cplx) * m * m);
+        {
+            ProfScope ps(NLF_PROF_ORTH, s, 8.0 * n * m * m, 32.0 * n * m);
+            gemm<double>(s, false, n, m, m, z128(1, 0), Q, n, 0, Rd, m, 0, z128(0, 0), QT, n, 0, 1);
+        }
+        copy_block(s, n, m, QT, n, Q, n);
+    }
+}
+
+void project(hipStream_t s, int64_t n, int m, int J, const z128* const* A, int64_t lda,
+             const z128* Q, z128* W, z128* Ahat, z128* splitws, int64_t split_elems) {
+    for (int j = 0; j < J; ++j) {
+        ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * n * m, 16.0 * ((double)n * n + 2.0 * n * m));
+        gemm<double>(s, false, n, m, n, z128(1, 0), A[j], lda, 0, Q, n, 0, z128(0, 0),
+                     W + (size_t)j * n * m, n, 0, 1);
+    }
+    ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
+    gemm<double>(s, true, m, m, n, z128(1, 0), Q, n, 0, W, n, (int64_t)n * m, z128(0, 0), Ahat, m,
+                 (int64_t)m * m, J, splitws, split_elems);
+}
+
+}  // namespace
+
+// =============================================================================== C ABI
+
+#define NLF_TRY(h, ...)                                                         \
+    try {                                                                       \
+        __VA_ARGS__                                                             \
+    } catch (const nlf::Error& e_) {                                            \
+        g_last_error = e_.msg;                                                  \
+        if (h) (h)->last_error = e_.msg;                                        \
+        return (nlfeast_status)e_.status;                                       \
+    } catch (const std::exception& e_) {                                        \
+        g_last_error = e_.what();                                               \
+        if (h) (h)->last_error = e_.what();                                     \
+        return NLF_ERR_DEVICE;                                                  \
+    }
+
+extern "C" {
+
+nlfeast_status nlfeast_create(nlfeast_handle* out, int64_t n, int device, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(out && n > 0 && n <= 8192, NLF_ERR_ARG, "create: need 0 < n <= 8192");
+        int count = 0;
+        NLF_HIP(hipGetDeviceCount(&count));
+        NLF_REQUIRE(device >= 0 && device < count, NLF_ERR_ARG, "create: bad device index");
+        NLF_HIP(hipSetDevice(device));
+        h = new nlfeast_ctx();
+        h->n = n;
+        h->device = device;
+        h->stream = (hipStream_t)stream;
+        *out = h;
+        return NLF_OK;
+    })
+}
+
+void nlfeast_destroy(nlfeast_handle h) { delete h; }
+
+const char* nlfeast_last_error(nlfeast_handle h) {
+    return h ? h->last_error.c_str() : g_last_error.c_str();
+}
+
+nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fkind,
+                                  const double* fparam, const void* const* A_dev, int64_t lda) {
+    NLF_TRY(h, {
+        NLF_REQUIRE(h, NLF_ERR_ARG, "null handle");
+        NLF_REQUIRE(J >= 1 && J <= 8 && fkind && fparam && A_dev && lda >= h->n, NLF_ERR_ARG,
+                    "set_coeffs: need 1 <= J <= 8, non-null arrays, lda >= n");
+        std::vector<Term> terms(J);
+        for (int j = 0; j < J; ++j) {
+            NLF_REQUIRE(fkind[j] == NLF_F_POW || fkind[j] == NLF_F_EXP, NLF_ERR_ARG, "set_coeffs: bad kind");
+            if (fkind[j] == NLF_F_POW)
+                NLF_REQUIRE(fparam[j] >= 0 && fparam[j] <= 16 && fparam[j] == std::floor(fparam[j]),
+                            NLF_ERR_ARG, "set_coeffs: power must be an integer in 0..16");
+            NLF_REQUIRE(A_dev[j], NLF_ERR_ARG, "set_coeffs: null matrix");
+            terms[j] = Term{fkind[j], fparam[j]};
+        }
+        h->J = J;
+        h->terms = terms;
+        h->A.assign(J, nullptr);
+        for (int j = 0; j < J; ++j) h->A[j] = (const z128*)A_dev[j];
+        h->lda = lda;
+        h->factors_valid = false;
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlfeast_set_contour(nlfeast_handle h, int32_t nreg, const double* centre,
+                                   const double* semi_axes, const int32_t* n_nodes,
+                                   const int32_t* m0, int32_t quad_rule) {
+    NLF_TRY(h, {
+        NLF_REQUIRE(h, NLF_ERR_ARG, "null handle");
+        NLF_REQUIRE(nreg >= 1 && centre && semi_axes && n_nodes && m0, NLF_ERR_ARG,
+                    "set_contour: need nreg >= 1 and non-null arrays");
+        NLF_REQUIRE(quad_rule == NLF_QUAD_GAUSS_LEGENDRE || quad_rule == NLF_QUAD_TRAPEZOID,
+                    NLF_ERR_ARG, "set_contour: bad quadrature rule");
+        std::vector<nlfeast_ctx::Region> regs(nreg);
+        for (int r = 0; r < nreg; ++r) {
+            NLF_REQUIRE(semi_axes[2 * r] > 0 && semi_axes[2 * r + 1] > 0, NLF_ERR_ARG,
+                        "set_contour: semi-axes must be positive");
+            NLF_REQUIRE(n_nodes[r] >= 1 && n_nodes[r] <= 256, NLF_ERR_ARG, "set_contour: 1 <= n_nodes <= 256");
+            NLF_REQUIRE(m0[r] >= 1 && m0[r] <= h->n && m0[r] <= 512, NLF_ERR_ARG,
+                        "set_contour: 1 <= m0 <= min(n, 512)");
+            regs[r].E = Ellipse{cplx(centre[2 * r], centre[2 * r + 1]), semi_axes[2 * r], semi_axes[2 * r + 1]};
+            regs[r].nc = n_nodes[r];
+            regs[r].m0 = m0[r];
+            quadrature(regs[r].E, regs[r].nc, quad_rule, regs[r].z, regs[r].w);
+        }
+        h->regions = regs;
+        h->quad_rule = quad_rule;
+        h->factors_valid = false;
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* opt, size_t* bytes) {
+    NLF_TRY(h, {
+        NLF_REQUIRE(h && opt && bytes, NLF_ERR_ARG, "workspace_size: null argument");
+        NLF_REQUIRE(!h->regions.empty() && h->J > 0, NLF_ERR_STATE,
+                    "workspace_size: call set_coeffs and set_contour first");
+        *bytes = make_layout(h, opt->precision).total;
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlfeast_set_profiling(nlfeast_handle h, int32_t on) {
+    if (!h) return NLF_ERR_ARG;
+    h->profiling = on != 0;
+    return NLF_OK;
+}
+
+nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* milliseconds,
+                                   double* flops, double* bytes) {
+    if (!h) return NLF_ERR_ARG;
+    for (int c = 0; c < NLF_K_COUNT; ++c) {
+        if (launches) launches[c] = h->prof.launches[c];
+        if (milliseconds) milliseconds[c] = h->prof.ms[c];
+        if (flops) flops[c] = h->prof.flops[c];
+        if (bytes) bytes[c] = h->prof.bytes[c];
+    }
+    return NLF_OK;
+}
+
+nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws,
+                             size_t ws_bytes, const void* X0_dev, void* X_dev_out,
+                             double* lambda_out, double* resid_out, int32_t* inside_out,
+                             int32_t* m_out, int32_t* iters_out) {
+    NLF_TRY(h, {
+        NLF_REQUIRE(h && opt, NLF_ERR_ARG, "solve: null argument");
+        NLF_REQUIRE(!h->regions.empty() && h->J > 0, NLF_ERR_STATE,
+                    "solve: call set_coeffs and set_contour first");
+        NLF_REQUIRE(ws && X_dev_out && lambda_out && resid_out && inside_out && m_out && iters_out,
+                    NLF_ERR_ARG, "solve: null output or workspace");
+        NLF_REQUIRE(opt->precision == NLF_PREC_FP64 || opt->precision == NLF_PREC_FP32_REFINE,
+                    NLF_ERR_ARG, "solve: bad precision");
+        NLF_REQUIRE(opt->tol > 0 && opt->max_iter >= 1, NLF_ERR_ARG, "solve: need tol > 0, max_iter >= 1");
+        const Layout L = make_layout(h, opt->precision);
+        NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
+        NLF_HIP(hipSetDevice(h->device));
+        hipStream_t s = h->stream;
+        const int64_t n = h->n;
+        const int J = h->J;
+        const bool p32 = opt->precision == NLF_PREC_FP32_REFINE;
+        if (h->profiling) h->prof.reset();
+        ProfilerGuard pg(h->profiling ? &h->prof : nullptr);
+        auto host_ms = [&](double ms) {
+            if (h->profiling) {
+                h->prof.ms[NLF_PROF_HOST] += ms;
+                h->prof.launches[NLF_PROF_HOST] += 1;
+            }
+        };
+
+        const size_t nn = (size_t)n * n;
+        // ---- fixed shifts: assemble and factor T(z_k) once per contour
+        if (!(h->factors_valid && h->factors_ws == ws && h->factors_prec == opt->precision)) {
+            std::vector<cplx> coef((size_t)L.NZ * J);
+            int k = 0;
+            for (const auto& r : h->regions)
+                for (int q = 0; q < r.nc; ++q, ++k)
+                    for (int j = 0; j < J; ++j) coef[(size_t)k * J + j] = term_value(h->terms[j], r.z[q]);
+            h2d(s, at<void>(ws, L.coef), coef.data(), sizeof(cplx) * coef.size());
+            if (p32)
+                assemble(s, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.t64),
+                         at<z64>(ws, L.fact), n, (int64_t)nn);
+            else
+                assemble(s, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.fact),
+                         nullptr, n, (int64_t)nn);
+            TrsmClassGuard tg(NLF_PROF_TRSM);
+            if (p32)
+                getrf<float>(s, n, L.NZ, at<z64>(ws, L.fact), n, (int64_t)nn, at<int32_t>(ws, L.ipiv),
+                             at<int32_t>(ws, L.perm), at<int32_t>(ws, L.info), at<int32_t>(ws, L.list));
+            else
+                getrf<double>(s, n, L.NZ, at<z128>(ws, L.fact), n, (int64_t)nn, at<int32_t>(ws, L.ipiv),
+                              at<int32_t>(ws, L.perm), at<int32_t>(ws, L.info), at<int32_t>(ws, L.list));
+            std::vector<int32_t> info(L.NZ);
+            d2h_sync(s, info.data(), at<void>(ws, L.info), sizeof(int32_t) * L.NZ);
+            for (int q = 0; q < L.NZ; ++q)
+                NLF_REQUIRE(info[q] == 0, NLF_ERR_SINGULAR,
+                            "solve: T(z_k) is singular at node " + std::to_string(q) +
+                                " (exact zero pivot " + std::to_string(info[q]) + ")");
+            h->factors_valid = true;
+            h->factors_ws = ws;
+            h->factors_prec = opt->precision;
+        }
+
+        int status = NLF_OK;
+        int node0 = 0, col0 = 0;
+        for (size_t ri = 0; ri < h->regions.size(); ++ri) {
+            const auto& reg = h->regions[ri];
+            const int m = reg.m0, nc = reg.nc;
+            z128* Q = at<z128>(ws, L.Q);
+            z128* X = at<z128>(ws, L.X);
+            z128* W = at<z128>(ws, L.W);
+            z128* R = at<z128>(ws, L.R);
+            z128* Ys = at<z128>(ws, L.Ys);
+            z128* QT = at<z128>(ws, L.QT);
+            z128* Ahat_d = at<z128>(ws, L.Ahat);
+            z128* Gd = at<z128>(ws, L.G);
+            z128* Ymat = at<z128>(ws, L.Ymat);
+            z128* Gall = at<z128>(ws, L.Gall);
+            z128* rho_d = at<z128>(ws, L.rho);
+            z128* acoef_d = at<z128>(ws, L.acoef);
+            double* norms_d = at<double>(ws, L.norms);
+            z128* splitws = at<z128>(ws, L.splitws);
+            const size_t blk = (size_t)n * m;
+            // Step 0
+            if (X0_dev)
+                copy_block(s, n, m, (const z128*)X0_dev + (size_t)col0 * n, n, Q, n);
+            else
+                random_normal(s, n, m, opt->seed * 0x9E3779B97F4A7C15ull + ri + 1, Q, n);
+            orthonormalize(s, n, m, Q, QT, Gd, at<z128>(ws, L.Ymat), splitws, L.splitws_elems);
+
+            std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
+                acoef((size_t)nc * m);
+            std::vector<double> res(m), enorm(nc);
+            ReducedResult rr;
+            int it = 0, n_in = 0;
+            std::vector<int> inside(m);
+            int rstatus = NLF_OK;
+            const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
+            const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
+            const int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)node0 * n;
+            while (true) {
+                // Step 1: projections and the reduced problem
+                project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, L.splitws_elems);
+                d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
+                const auto t0 = std::chrono::steady_clock::now();
+                rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m);
+                host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+                NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
+                            "reduced eigenproblem failed (singular T at the contour centre or QR did not converge)");
+                // Step 2: X = Q Y
+                for (int i = 0; i < m; ++i) lam[i] = std::isfinite(rr.lambda[i].real()) ? rr.lambda[i] : cplx(0.0);
+                h2d(s, Ymat, rr.Y.data(), sizeof(cplx) * m * m);
+                {
+                    ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m, 32.0 * n * m);
+                    gemm<double>(s, false, n, m, m, z128(1, 0), Q, n, 0, Ymat, m, 0, z128(0, 0), X, n, 0, 1);
+                }
+                // Step 3: R = sum_j W_j (Y f_j(Lambda)), res_i = ||R e_i||
+                for (int j = 0; j < J; ++j)
+                    for (int c = 0; c < m; ++c) {
+                        const cplx f = term_value(h->terms[j], lam[c]);
+                        for (int r = 0; r < m; ++r)
+                            Gh[(size_t)j * m + r + (size_t)c * J * m] = rr.Y[r + (size_t)c * m] * f;
+                    }
+                h2d(s, Gall, Gh.data(), sizeof(cplx) * Gh.size());
+                {
+                    ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
+                    gemm<double>(s, false, n, m, (int64_t)J * m, z128(1, 0), W, n, 0, Gall, (int64_t)J * m, 0,
+                                 z128(0, 0), R, n, 0, 1);
+                    col_norms(s, n, m, R, n, norms_d);
+                }
+                d2h_sync(s, res.data(), norms_d, sizeof(double) * m);
+                n_in = 0;
+                double maxres = 0.0;
+                for (int i = 0; i < m; ++i) {
+                    if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
+                    inside[i] = reg.E.radius(rr.lambda[i]) < 1.0;
+                    if (inside[i]) {
+                        ++n_in;
+                        maxres = std::max(maxres, res[i]);
+                    }
+                }
+                if (opt->verbose)
+                    fprintf(stderr, "[nlfeast] region %zu it %d inside %d max_res %.3e\n", ri, it, n_in, maxres);
+                if (n_in >= m) { rstatus = NLF_ERR_M0_TOO_SMALL; break; }
+                if (it >= 1 && n_in > 0 && maxres <= opt->tol) break;
+                if (it >= 3 && n_in == 0) break;
+                if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
+                // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
+                {
+                    TrsmClassGuard tg(NLF_PROF_SOLVE);
+                    if (!p32) {
+                        getrs<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, R, n, 0, Ys, n, (int64_t)blk);
+                    } else {
+                        z64* R32 = at<z64>(ws, L.R32);
+                        z64* Y32 = at<z64>(ws, L.Y32);
+                        z128* E = at<z128>(ws, L.E);
+                        z64* E32 = at<z64>(ws, L.E32);
+                        const z128* T64 = at<z128>(ws, L.t64) + (size_t)node0 * nn;
+                        cast_128_to_64(s, n, m, 1, R, n, 0, R32, n, 0);
+                        getrs<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, R32, n, 0, Y32, n, (int64_t)blk);
+                        cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
+                        double rn2 = 0.0;
+                        for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
+                        for (int sweep = 0; sweep < std::min(opt->max_refine, 5); ++sweep) {
+                            TrsmClassGuard tg2(NLF_PROF_REFINE);
+                            ProfScope ps(NLF_PROF_REFINE, s, 8.0 * n * n * m * nc, 16.0 * nn * nc);
+                            // E_k = R - T(z_k) Y_k in FP64
+                            for (int q = 0; q < nc; ++q) copy_block(s, n, m, R, n, E + q * blk, n);
+                            gemm<double>(s, false, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
+                                         z128(1, 0), E, n, (int64_t)blk, nc);
+                            block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d);
+                            d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
+                            double worst = 0.0;
+                            for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);
+                            if (worst <= opt->refine_eta * opt->refine_eta * rn2) break;
+                            cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
+                            getrs<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, E32, n, (int64_t)blk, Y32, n,
+                                         (int64_t)blk);
+                            cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, true);
+                        }
+                    }
+                }
+                // Step 4 accumulation: Q = X rho(Lambda) - sum_k omega_k Y_k (z_k - Lambda)^{-1}
+                for (int i = 0; i < m; ++i) {
+                    cplx rsum = 0.0;
+                    for (int q = 0; q < nc; ++q) {
+                        const cplx cq = reg.w[q] / (reg.z[q] - lam[i]);
+                        acoef[(size_t)q * m + i] = cq;
+                        rsum += cq;
+                    }
+                    rho[i] = rsum;
+                }
+                h2d(s, rho_d, rho.data(), sizeof(cplx) * m);
+                h2d(s, acoef_d, acoef.data(), sizeof(cplx) * acoef.size());
+                accumulate(s, n, m, nc, X, Ys, (int64_t)blk, rho_d, acoef_d, Q);
+                // Step 5
+                orthonormalize(s, n, m, Q, QT, Gd, Ymat, splitws, L.splitws_elems);
+                ++it;
+            }
+            // outputs for this region
+            NLF_HIP(hipMemcpyAsync((z128*)X_dev_out + (size_t)col0 * n, X, sizeof(z128) * blk,
+                                   hipMemcpyDeviceToDevice, s));
+            for (int i = 0; i < m; ++i) {
+                lambda_out[2 * (col0 + i)] = rr.lambda[i].real();
+                lambda_out[2 * (col0 + i) + 1] = rr.lambda[i].imag();
+                resid_out[col0 + i] = res[i];
+                inside_out[col0 + i] = inside[i];
+            }
+            m_out[ri] = n_in;
+            iters_out[ri] = it;
+            if (rstatus != NLF_OK) status = rstatus;
+            node0 += nc;
+            col0 += m;
+        }
+        NLF_HIP(hipStreamSynchronize(s));
+        if (h->profiling) h->prof.collect();
+        if (status != NLF_OK) {
+            h->last_error = status == NLF_ERR_M0_TOO_SMALL ? "m0 or more Ritz values inside a contour"
+                                                           : "not converged within max_iter";
+        }
+        return (nlfeast_status)status;
+    })
+}
+
+// ------------------------------------------------------------------ step-level entry points
+
+static hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const double* fparam,
+                            const void* const* A_dev, int64_t lda, int32_t nz, const double* z,
+                            void* T64_dev, void* T32_dev, int64_t ldt, int64_t strideT, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && J >= 1 && J <= 8 && fkind && fparam && A_dev && lda >= n && nz >= 1 && z &&
+                        (T64_dev || T32_dev) && ldt >= n && strideT >= ldt * n,
+                    NLF_ERR_ARG, "nlf_assemble: bad arguments");
+        std::vector<cplx> coef((size_t)nz * J);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < J; ++j)
+                coef[(size_t)k * J + j] = term_value(Term{fkind[j], fparam[j]}, cplx(z[2 * k], z[2 * k + 1]));
+        z128* coef_d = nullptr;
+        NLF_HIP(hipMallocAsync((void**)&coef_d, sizeof(cplx) * coef.size(), as_stream(stream)));
+        h2d(as_stream(stream), coef_d, coef.data(), sizeof(cplx) * coef.size());
+        assemble(as_stream(stream), n, J, (const z128* const*)A_dev, lda, nz, coef_d, (z128*)T64_dev,
+                 (z64*)T32_dev, ldt, strideT);
+        NLF_HIP(hipFreeAsync(coef_d, as_stream(stream)));
+        NLF_HIP(hipStreamSynchronize(as_stream(stream)));
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_getrf_batched(int32_t dtype, int64_t n, int32_t batch, void* A_dev, int64_t lda,
+                                 int64_t strideA, int32_t* ipiv_dev, int32_t* perm_dev,
+                                 int32_t* info_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && n <= 8192 && batch >= 1 && A_dev && lda >= n && strideA >= lda * n &&
+                        ipiv_dev && info_dev && (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_getrf_batched: bad arguments");
+        hipStream_t s = as_stream(stream);
+        int32_t* list = nullptr;
+        NLF_HIP(hipMallocAsync((void**)&list, sizeof(int32_t) * getrf_scratch_ints(n, batch), s));
+        if (dtype == NLF_C128)
+            getrf<double>(s, n, batch, (z128*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list);
+        else
+            getrf<float>(s, n, batch, (z64*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list);
+        NLF_HIP(hipFreeAsync(list, s));
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_getrs_batched(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                 const void* LU_dev, int64_t lda, int64_t strideA,
+                                 const int32_t* perm_dev, const void* B_dev, int64_t ldb,
+                                 int64_t strideB, void* X_dev, int64_t ldx, int64_t strideX,
+                                 void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && nrhs >= 1 && batch >= 1 && LU_dev && perm_dev && B_dev && X_dev &&
+                        lda >= n && ldb >= n && ldx >= n && strideB >= 0 && strideX >= ldx * nrhs &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_getrs_batched: bad arguments");
+        TrsmClassGuard tg(NLF_PROF_SOLVE);
+        if (dtype == NLF_C128)
+            getrs<double>(as_stream(stream), n, nrhs, batch, (const z128*)LU_dev, lda, strideA, perm_dev,
+                          (const z128*)B_dev, ldb, strideB, (z128*)X_dev, ldx, strideX);
+        else
+            getrs<float>(as_stream(stream), n, nrhs, batch, (const z64*)LU_dev, lda, strideA, perm_dev,
+                         (const z64*)B_dev, ldb, strideB, (z64*)X_dev, ldx, strideX);
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_gemm_batched(int32_t dtype, char opA, char opB, int64_t M, int64_t N, int64_t K,
+                                const double* alpha, const void* A_dev, int64_t lda, int64_t strideA,
+                                const void* B_dev, int64_t ldb, int64_t strideB, const double* beta,
+                                void* C_dev, int64_t ldc, int64_t strideC, int32_t batch, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        const bool cA = opA == 'C' || opA == 'c';
+        NLF_REQUIRE((opA == 'N' || opA == 'n' || cA) && (opB == 'N' || opB == 'n'), NLF_ERR_ARG,
+                    "nlf_gemm_batched: opA in {N, C}, opB = N");
+        NLF_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 1 && alpha && beta && C_dev && ldc >= M &&
+                        (K == 0 || (A_dev && B_dev && ldb >= K && lda >= (cA ? K : M))) &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_gemm_batched: bad arguments");
+        hipStream_t s = as_stream(stream);
+        if (dtype == NLF_C128)
+            gemm<double>(s, cA, M, N, K, z128(alpha[0], alpha[1]), (const z128*)A_dev, lda, strideA,
+                         (const z128*)B_dev, ldb, strideB, z128(beta[0], beta[1]), (z128*)C_dev, ldc,
+                         strideC, batch);
+        else
+            gemm<float>(s, cA, M, N, K, z64((float)alpha[0], (float)alpha[1]), (const z64*)A_dev, lda,
+                        strideA, (const z64*)B_dev, ldb, strideB, z64((float)beta[0], (float)beta[1]),
+                        (z64*)C_dev, ldc, strideC, batch);
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_block_residual(int64_t n, int32_t m, int32_t J, const int32_t* fkind,
+                                  const double* fparam, const void* const* A_dev, int64_t lda,
+                                  const void* X_dev, int64_t ldx, const double* lambda, void* R_dev,
+                                  int64_t ldr, double* norms_dev, void* ws_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && m >= 1 && J >= 1 && J <= 8 && fkind && fparam && A_dev && lda >= n && X_dev &&
+                        ldx >= n && lambda && R_dev && ldr >= n && norms_dev && ws_dev,
+                    NLF_ERR_ARG, "nlf_block_residual: bad arguments");
+        hipStream_t s = as_stream(stream);
+        z128* XF = (z128*)ws_dev;     // X f_j(Lambda), one term at a time
+        std::vector<cplx> f((size_t)m);
+        ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * n * m * J, 16.0 * n * n * J);
+        for (int j = 0; j < J; ++j) {
+            // R += A_j (X diag f_j): scale columns through a diagonal GEMM-free path: copy then
+            // fold the scaling into the GEMM's B operand by one small diagonal product per column
+            std::vector<cplx> D((size_t)m * m, 0.0);
+            for (int c = 0; c < m; ++c)
+                D[c + (size_t)c * m] = term_value(Term{fkind[j], fparam[j]}, cplx(lambda[2 * c], lambda[2 * c + 1]));
+            z128* Dd = nullptr;
+            NLF_HIP(hipMallocAsync((void**)&Dd, sizeof(cplx) * m * m, s));
+            h2d(s, Dd, D.data(), sizeof(cplx) * m * m);
+            gemm<double>(s, false, n, m, m, z128(1, 0), (const z128*)X_dev, ldx, 0, Dd, m, 0, z128(0, 0), XF, n,
+                         0, 1);
+            gemm<double>(s, false, n, m, n, z128(1, 0), (const z128*)A_dev[j], lda, 0, XF, n, 0,
+                         z128(j == 0 ? 0.0 : 1.0, 0), (z128*)R_dev, ldr, 0, 1);
+            NLF_HIP(hipFreeAsync(Dd, s));
+        }
+        col_norms(s, n, m, (const z128*)R_dev, ldr, norms_dev);
+        NLF_HIP(hipStreamSynchronize(s));
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_accumulate(int64_t n, int32_t m, int32_t nz, const void* X_dev, const void* Y_dev,
+                              const double* z, const double* omega, const double* lambda, void* Q_dev,
+                              void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && m >= 1 && nz >= 1 && X_dev && Y_dev && z && omega && lambda && Q_dev,
+                    NLF_ERR_ARG, "nlf_accumulate: bad arguments");
+        hipStream_t s = as_stream(stream);
+        std::vector<cplx> rho(m), coef((size_t)nz * m);
+        for (int i = 0; i < m; ++i) {
+            const cplx l(lambda[2 * i], lambda[2 * i + 1]);
+            cplx rs = 0.0;
+            for (int k = 0; k < nz; ++k) {
+                const cplx c = cplx(omega[2 * k], omega[2 * k + 1]) / (cplx(z[2 * k], z[2 * k + 1]) - l);
+                coef[(size_t)k * m + i] = c;
+                rs += c;
+            }
+            rho[i] = rs;
+        }
+        z128* buf = nullptr;
+        NLF_HIP(hipMallocAsync((void**)&buf, sizeof(cplx) * (m + coef.size()), s));
+        h2d(s, buf, rho.data(), sizeof(cplx) * m);
+        h2d(s, buf + m, coef.data(), sizeof(cplx) * coef.size());
+        accumulate(s, n, m, nz, (const z128*)X_dev, (const z128*)Y_dev, n * m, buf, buf + m, (z128*)Q_dev);
+        NLF_HIP(hipFreeAsync(buf, s));
+        NLF_HIP(hipStreamSynchronize(s));
+        return NLF_OK;
+    })
+}
+
+int64_t nlf_orth_workspace(int64_t n, int32_t m) {
+    return n * m + 2 * (int64_t)m * m + std::max<int64_t>(64 * (int64_t)m * m, 1 << 16);
+}
+
+nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && m >= 1 && m <= n && Q_dev && ws_dev, NLF_ERR_ARG, "nlf_orthonormalize: bad arguments");
+        z128* w = (z128*)ws_dev;
+        z128* QT = w;
+        z128* G = QT + n * m;
+        z128* Rd = G + (int64_t)m * m;
+        z128* sp = Rd + (int64_t)m * m;
+        orthonormalize(as_stream(stream), n, m, (z128*)Q_dev, QT, G, Rd, sp,
+                       std::max<int64_t>(64 * (int64_t)m * m, 1 << 16));
+        NLF_HIP(hipStreamSynchronize(as_stream(stream)));
+        return NLF_OK;
+    })
+}
+
+int64_t nlf_project_workspace(int64_t n, int32_t m, int32_t J) {
+    (void)n;
+    return std::max<int64_t>(64 * (int64_t)m * m * J, 1 << 16);
+}
+
+nlfeast_status nlf_project(int64_t n, int32_t m, int32_t J, const void* const* A_dev, int64_t lda,
+                           const void* Q_dev, void* W_dev, void* Ahat_dev, void* ws_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && m >= 1 && J >= 1 && A_dev && lda >= n && Q_dev && W_dev && Ahat_dev && ws_dev,
+                    NLF_ERR_ARG, "nlf_project: bad arguments");
+        project(as_stream(stream), n, m, J, (const z128* const*)A_dev, lda, (const z128*)Q_dev, (z128*)W_dev,
+                (z128*)Ahat_dev, (z128*)ws_dev, nlf_project_workspace(n, m, J));
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_t nc, int32_t quad_rule,
+                              double* z, double* omega) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(a > 0 && b > 0 && nc >= 1 && z && omega && (quad_rule == 0 || quad_rule == 1),
+                    NLF_ERR_ARG, "nlf_quadrature: bad arguments");
+        std::vector<cplx> zz, ww;
+        quadrature(Ellipse{cplx(cre, cim), a, b}, nc, quad_rule, zz, ww);
+        for (int k = 0; k < nc; ++k) {
+            z[2 * k] = zz[k].real();
+            z[2 * k + 1] = zz[k].imag();
+            omega[2 * k] = ww[k].real();
+            omega[2 * k + 1] = ww[k].imag();
+        }
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind, const double* fparam,
+                                 const double* Ahat, double cre, double cim, double a, double b,
+                                 int32_t m_keep, double* lambda_out, double* Y_out) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(m >= 1 && J >= 1 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
+                        lambda_out && Y_out,
+                    NLF_ERR_ARG, "nlf_reduced_solve: bad arguments");
+        std::vector<Term> terms(J);
+        for (int j = 0; j < J; ++j) terms[j] = Term{fkind[j], fparam[j]};
+        ReducedResult rr = reduced_solve(m, terms, (const cplx*)Ahat, Ellipse{cplx(cre, cim), a, b}, m_keep);
+        NLF_REQUIRE(rr.ok, NLF_ERR_DEVICE, "nlf_reduced_solve: eigen-decomposition failed");
+        const int keep = (int)rr.lambda.size();
+        for (int q = 0; q < keep; ++q) {
+            lambda_out[2 * q] = rr.lambda[q].real();
+            lambda_out[2 * q + 1] = rr.lambda[q].imag();
+        }
+        std::memcpy(Y_out, rr.Y.data(), sizeof(cplx) * rr.Y.size());
+        return NLF_OK;
+    })
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+"""Step-level parity of the HIP path with the oracle (each test calls the C ABI through the
+binding, on seeded inputs, and compares with the oracle's plain definition of that step).
+Sizes span several GEMM/LU tiles with ragged tails."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import dense, quadrature as qd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1801_09794_amd as nl  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    nl.lib()      # raises if the library is not built
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(A, dtype=torch.complex128):
+    return nl.to_colmajor(A, "cuda", dtype)
+
+
+def batch_dev(mats, dtype=torch.complex128):
+    return torch.stack([dev(M, dtype) for M in mats])
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("dt,tol", [(torch.complex128, 1e-14), (torch.complex64, 3e-6)])
+def test_mfma_lane_layout_single_tile(dt, tol):
+    # one 16x16x4 block per dtype: catches a wrong MFMA operand/accumulator lane layout
+    rng = np.random.default_rng(0)
+    if True:
+        A = wl.cn(rng, (16, 4))
+        B = wl.cn(rng, (4, 16))
+        C = torch.zeros((16, 16), dtype=dt, device="cuda")
+        nl.nlf_gemm_batched("N", 16, 16, 4, 1.0, dev(A, dt), 16, 0, dev(B, dt), 4, 0, 0.0, C, 16, 0, 1)
+        torch.cuda.synchronize()
+        assert rel(nl.from_colmajor(C), A @ B) < tol
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("opA", ["N", "C"])
+@pytest.mark.parametrize("M,N,K,batch", [(37, 53, 29, 1), (130, 70, 300, 3), (257, 129, 64, 2),
+                                         (64, 64, 3000, 2), (1, 1, 1, 1), (200, 5, 0, 1)])
+def test_gemm_matches_definition(dtype, opA, M, N, K, batch):
+    rng = np.random.default_rng(M * 7 + N + K)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    tol = 1e-13 if dtype == "c128" else 2e-5
+    As = [wl.cn(rng, (M, K) if opA == "N" else (K, M)) for _ in range(batch)]
+    Bs = [wl.cn(rng, (K, N)) for _ in range(batch)]
+    Cs = [wl.cn(rng, (M, N)) for _ in range(batch)]
+    alpha, beta = 0.7 - 0.2j, -0.3 + 1.1j
+    Ad, Bd, Cd = batch_dev(As, dt), batch_dev(Bs, dt), batch_dev(Cs, dt)
+    lda = M if opA == "N" else K
+    nl.nlf_gemm_batched(opA, M, N, K, alpha, Ad, max(lda, 1), As[0].size, Bd, max(K, 1), Bs[0].size,
+                        beta, Cd, M, Cs[0].size, batch)
+    torch.cuda.synchronize()
+    for b in range(batch):
+        opa = As[b] if opA == "N" else As[b].conj().T
+        ref = alpha * (opa @ Bs[b]) + beta * Cs[b]
+        got = nl.from_colmajor(Cd[b])
+        assert rel(got, ref) < tol * max(1, np.sqrt(K))
+
+
+def test_assemble_matches_oracle():
+    rng = np.random.default_rng(1)
+    n = 300
+    terms = wl.DELAY
+    mats = [wl.cn(rng, (n, n)) for _ in terms]
+    C = qd.Contour(0.2 + 0.5j, 0.3)
+    z, _ = qd.nodes_weights(C, 5)
+    T64 = torch.empty((5, n, n), dtype=torch.complex128, device="cuda")
+    T32 = torch.empty((5, n, n), dtype=torch.complex64, device="cuda")
+    nl.nlf_assemble(terms, [dev(M) for M in mats], z, T64, T32)
+    torch.cuda.synchronize()
+    ref = dense.assemble(terms, mats, z)
+    for k in range(5):
+        assert rel(nl.from_colmajor(T64[k]), ref[k]) < 1e-15
+        r32 = ref[k].astype(np.complex64)
+        assert np.array_equal(nl.from_colmajor(T32[k]), r32) or rel(nl.from_colmajor(T32[k]), ref[k]) < 1e-7
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,batch", [(1, 2), (7, 3), (33, 2), (100, 2), (257, 2), (600, 1)])
+def test_getrf_matches_oracle_lu(dtype, n, batch):
+    rng = np.random.default_rng(n + batch)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    mats = [wl.cn(rng, (n, n)) for _ in range(batch)]
+    if dtype == "c64":
+        mats = [M.astype(np.complex64).astype(complex) for M in mats]
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(A, ipiv, perm, info)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0] * batch
+    for b in range(batch):
+        LU = nl.from_colmajor(A[b]).astype(complex)
+        piv = ipiv[b].cpu().numpy()
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
+        PA = dense.apply_pivots(piv, mats[b])
+        eps = 2.2e-16 if dtype == "c128" else 1.2e-7
+        assert np.max(np.abs(PA - L @ U)) <= 30 * n * eps * np.max(np.abs(mats[b]))
+        assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+        p = perm[b].cpu().numpy()
+        assert np.array_equal(np.sort(p), np.arange(n))
+        assert np.array_equal(mats[b][p], PA)
+        if dtype == "c128" and n <= 257:
+            LU0, piv0 = dense.lu_partial_pivot(mats[b])
+            assert np.array_equal(piv, piv0)
+            assert rel(LU, LU0) < 1e-12
+
+
+def test_getrf_zero_pivot_info():
+    A = np.eye(40, dtype=complex)
+    A[17, 17] = 0.0
+    A[:, 17] = 0.0
+    d = batch_dev([A, np.eye(40, dtype=complex)])
+    ipiv = torch.empty((2, 40), dtype=torch.int32, device="cuda")
+    info = torch.empty(2, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(d, ipiv, None, info)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [18, 0]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,nrhs,batch", [(100, 7, 2), (300, 64, 3), (1000, 20, 2)])
+def test_getrs_matches_solve(dtype, n, nrhs, batch):
+    rng = np.random.default_rng(n + nrhs)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    mats = [wl.cn(rng, (n, n)) + 3 * np.eye(n) for _ in range(batch)]
+    B = wl.cn(rng, (n, nrhs))
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(A, ipiv, perm, info)
+    X = torch.empty((batch, nrhs, n), dtype=dt, device="cuda")
+    nl.nlf_getrs_batched(A, perm, dev(B, dt), X, shared_rhs=True)
+    torch.cuda.synchronize()
+    tol = 1e-11 if dtype == "c128" else 2e-3
+    for b in range(batch):
+        ref = np.linalg.solve(mats[b], B)
+        assert rel(nl.from_colmajor(X[b]), ref) < tol
+
+
+def test_getrf_large_backward_error():
+    # n = 4096: several recursion levels, 4 rows per panel thread, full-size panels
+    n, batch = 4096, 2
+    rng = np.random.default_rng(44)
+    mats = [wl.cn(rng, (n, n)) / np.sqrt(n) for _ in range(batch)]
+    A = batch_dev(mats)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(A, ipiv, perm, info)
+    B = wl.cn(rng, (n, 8))
+    X = torch.empty((batch, 8, n), dtype=torch.complex128, device="cuda")
+    nl.nlf_getrs_batched(A, perm, dev(B), X, shared_rhs=True)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0, 0]
+    for b in range(batch):
+        x = nl.from_colmajor(X[b])
+        r = mats[b] @ x - B
+        berr = np.linalg.norm(r) / (np.linalg.norm(mats[b]) * np.linalg.norm(x) + np.linalg.norm(B))
+        assert berr < 1e-14, berr
+        assert np.array_equal(np.sort(perm[b].cpu().numpy()), np.arange(n))
+
+
+def test_accumulate_matches_oracle():
+    rng = np.random.default_rng(5)
+    n, m, nz = 333, 11, 6
+    X = wl.cn(rng, (n, m))
+    Ys = [wl.cn(rng, (n, m)) for _ in range(nz)]
+    C = qd.Contour(0.1, 0.5)
+    z, w = qd.nodes_weights(C, nz)
+    lam = 0.2 * wl.cn(rng, m)
+    Q = torch.empty((m, n), dtype=torch.complex128, device="cuda")
+    nl.nlf_accumulate(dev(X), batch_dev(Ys), z, w, lam, Q)
+    torch.cuda.synchronize()
+    assert rel(nl.from_colmajor(Q), dense.step4_sum(X, Ys, lam, z, w)) < 1e-13
+
+
+def test_block_residual_matches_oracle():
+    rng = np.random.default_rng(6)
+    n, m = 257, 9
+    terms = wl.DELAY
+    mats = [wl.cn(rng, (n, n)) for _ in terms]
+    X = wl.cn(rng, (n, m))
+    lam = 0.3 * wl.cn(rng, m)
+    R = torch.empty((m, n), dtype=torch.complex128, device="cuda")
+    norms = torch.empty(m, dtype=torch.float64, device="cuda")
+    ws = torch.empty((m, n), dtype=torch.complex128, device="cuda")
+    nl.nlf_block_residual(terms, [dev(M) for M in mats], dev(X), lam, R, norms, ws)
+    torch.cuda.synchronize()
+    R0, n0 = dense.block_residual(terms, mats, X, lam)
+    assert rel(nl.from_colmajor(R), R0) < 1e-13
+    assert rel(norms.cpu().numpy(), n0) < 1e-13
+
+
+def test_project_matches_oracle():
+    rng = np.random.default_rng(7)
+    n, m = 700, 24
+    mats = [wl.cn(rng, (n, n)) for _ in range(3)]
+    Q, _ = np.linalg.qr(wl.cn(rng, (n, m)))
+    W = torch.empty((3 * m, n), dtype=torch.complex128, device="cuda")
+    Ah = torch.empty((3, m, m), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(nl.nlf_project_workspace(n, m, 3), dtype=torch.complex128, device="cuda")
+    nl.nlf_project([dev(M) for M in mats], dev(Q), W, Ah, ws)
+    torch.cuda.synchronize()
+    ref = dense.project(mats, Q)
+    for j in range(3):
+        assert rel(nl.from_colmajor(Ah[j]), ref[j]) < 1e-13
+
+
+def test_orthonormalize_keeps_span():
+    rng = np.random.default_rng(8)
+    n, m = 2000, 40
+    Q0 = wl.cn(rng, (n, m)) @ np.diag(np.logspace(0, -6, m))     # ill-conditioned columns
+    Q = dev(Q0)
+    ws = torch.empty(nl.nlf_orth_workspace(n, m), dtype=torch.complex128, device="cuda")
+    nl.nlf_orthonormalize(Q, ws)
+    torch.cuda.synchronize()
+    q = nl.from_colmajor(Q)
+    assert np.max(np.abs(q.conj().T @ q - np.eye(m))) < 1e-13
+    ref, _ = np.linalg.qr(Q0)
+    # same column space: the projector onto span(Q0) reproduces q
+    assert np.max(np.abs(ref @ (ref.conj().T @ q) - q)) < 1e-11

@@ -1,0 +1,152 @@
+"""End-to-end parity of nlfeast_solve (Algorithm 1 on the GPU) with the oracle, with
+brute-force eigenvalues (stored by tests/golden/make_contours.py from the oracle) and with
+the paper's Table 1, in FP64 and in the FP32-LU + FP64-refinement form."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+import workloads as wl
+from oracle import nlfeast as onl, problem as pb, quadrature as qd
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1801_09794_amd as nl  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    nl.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def contours(name):
+    return json.load(open(os.path.join(GOLDEN, "contours.json")))[name]["regions"]
+
+
+def match_err(a, b, scale):
+    a, b = np.asarray(a), np.asarray(b)
+    assert len(a) == len(b), (len(a), len(b))
+    if len(a) == 0:
+        return 0.0
+    cost = np.abs(a[:, None] - b[None, :]) / np.maximum(np.abs(b)[None, :], scale)
+    r, c = linear_sum_assignment(cost)
+    return float(cost[r, c].max())
+
+
+def gpu_solve(terms, mats, regions, X0, opts):
+    S = nl.NLFEAST(mats[0].shape[0])
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    S.set_contour(regions)
+    out = S.solve(opts, None if X0 is None else nl.to_colmajor(X0))
+    torch.cuda.synchronize()
+    out["Xh"] = nl.from_colmajor(out["X"])
+    S.close()
+    return out
+
+
+def host_residuals(terms, mats, X, lam):
+    P = pb.Problem(terms, mats)
+    return np.linalg.norm(P.block_residual(X, lam), axis=0)
+
+
+@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
+def test_qep200_matches_oracle_and_brute_force(prec, tol_eig):
+    cfg = wl.CONFIGS["qep200"]
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    X0 = wl.initial_block(200, 20, 2001)
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=8, m0=20)], X0,
+                    nl.options(tol=cfg["tol"], precision=prec))
+    assert out["status"] == nl.NLF_OK
+    ins = out["inside"]
+    assert ins.sum() == len(brute) == 10 and out["m"][0] == 10
+    assert match_err(out["lam"][ins], brute, r) < tol_eig
+    assert np.max(out["res"][ins]) <= cfg["tol"]
+    # residuals recomputed on the host from the returned vectors
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+    assert np.allclose(np.linalg.norm(out["Xh"], axis=0), 1.0, atol=1e-12)
+    # the oracle on the same inputs
+    C = qd.Contour(c, r)
+    z, w = qd.nodes_weights(C, 8)
+    ro = onl.solve(pb.Problem(terms, mats), C, z, w, X0, 20, cfg["tol"])
+    assert match_err(out["lam"][ins], ro.eigenvalues, r) < tol_eig
+    assert abs(int(out["iters"][0]) - ro.iters) <= 2
+
+
+def test_example1_table1_on_gpu():
+    # Sec. 5 Example 1: ellipse c = -1.55, a = 0.05, b = 0.0035, 16 nodes, m0 = 22, tol 1e-10
+    terms, mats = wl.mass_spring(1000, 0.6202, 0.4807)
+    tab = np.array([float(l.split()[1]) for l in open(os.path.join(GOLDEN, "table1_ex1.txt"))
+                    if l.strip() and not l.startswith("#")])
+    out = gpu_solve(terms, mats, [dict(centre=-1.55, a=0.05, b=0.0035, nc=16, m0=22)],
+                    wl.initial_block(1000, 22, 2101), nl.options(tol=1e-10))
+    assert out["status"] == nl.NLF_OK
+    ins = out["inside"]
+    assert ins.sum() == 20
+    assert np.max(np.abs(np.sort(out["lam"][ins].real) - np.sort(tab))) < 6e-11
+    assert np.max(np.abs(out["lam"][ins].imag)) < 1e-11
+    assert np.max(out["res"][ins]) <= 1e-10
+    assert out["iters"][0] <= 6
+
+
+@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
+def test_damped4096_matches_brute_force(prec, tol_eig):
+    cfg = wl.CONFIGS["damped4096"]
+    terms, mats = wl.make_problem("damped4096")
+    g = contours("damped4096")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
+                    wl.initial_block(4096, cfg["m0"], 2002),
+                    nl.options(tol=cfg["tol"], precision=prec))
+    assert out["status"] == nl.NLF_OK
+    ins = out["inside"]
+    assert ins.sum() == len(brute) == 40
+    assert match_err(out["lam"][ins], brute, r) < tol_eig
+    assert np.max(out["res"][ins]) <= cfg["tol"]
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+
+
+def test_m0_too_small_status():
+    terms, mats = wl.mass_spring(50, 10.0, 5.0)      # r = 19 encloses 34 > m0 = 25
+    out = gpu_solve(terms, mats, [dict(centre=-20.5, a=19.0, nc=8, m0=25)],
+                    wl.initial_block(50, 25, 5), nl.options(tol=1e-10, max_iter=8))
+    assert out["status"] == nl.NLF_ERR_M0_TOO_SMALL
+
+
+def test_not_converged_status_returns_pairs():
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    out = gpu_solve(terms, mats, [dict(centre=complex(*g["centre"]), a=g["radius"], nc=8, m0=20)],
+                    wl.initial_block(200, 20, 2001), nl.options(tol=1e-30, max_iter=1))
+    assert out["status"] == nl.NLF_ERR_NOT_CONVERGED and out["iters"][0] == 1
+    assert np.all(np.isfinite(out["lam"]))
+
+
+def test_node_on_eigenvalue_is_singular():
+    # T(lambda) = lambda I - diag(d) with d_0 equal to a quadrature node: exact zero pivot
+    n = 64
+    z, _ = nl.nlf_quadrature(0.0, 1.0, 1.0, 4, nl.NLF_QUAD_TRAPEZOID)   # the library's own nodes
+    d = np.linspace(-0.5, 0.5, n).astype(complex)
+    d[0] = z[0]
+    mats = [np.eye(n, dtype=complex), -np.diag(d)]
+    terms = [("pow", 1), ("pow", 0)]
+    S = nl.NLFEAST(n)
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    S.set_contour([dict(centre=0.0, a=1.0, nc=4, m0=8)], quad_rule=nl.NLF_QUAD_TRAPEZOID)
+    with pytest.raises(nl.NLFError) as e:
+        S.solve(nl.options(tol=1e-10))
+    assert e.value.status == nl.NLF_ERR_SINGULAR
+    S.close()
