@@ -182,6 +182,16 @@ nlfeast_status nlf_gemm_batched(int32_t dtype, char opA, char opB, int64_t M, in
                                 const double* beta, void* C_dev, int64_t ldc, int64_t strideC,
                                 int32_t batch, void* stream);
 
+/* nlf_gemm_batched with an explicit workgroup tile of (32 tm) x (32 tn) complex elements,
+ * (tm, tn) in {(1, 1), (2, 2), (4, 2)}, and (4, 4) for c64.  Used by the GEMM autotuner; returns NLF_ERR_ARG
+ * for a tile that is not compiled. */
+nlfeast_status nlf_gemm_batched_tile(int32_t dtype, char opA, int64_t M, int64_t N, int64_t K,
+                                     const double* alpha, const void* A_dev, int64_t lda,
+                                     int64_t strideA, const void* B_dev, int64_t ldb,
+                                     int64_t strideB, const double* beta, void* C_dev, int64_t ldc,
+                                     int64_t strideC, int32_t batch, int32_t tm, int32_t tn,
+                                     void* stream);
+
 /* Block residual T(X, Lambda) = sum_j A_j X f_j(Lambda) (Sec. 4.2) and its column 2-norms
  * (the Step 3 quantities).  X_dev: c128 n x m (ldx); lambda: 2*m doubles (host); R_dev: c128
  * n x m (ldr); norms_dev: m doubles (device).  ws_dev: c128 scratch of n * m elements. */
@@ -222,11 +232,14 @@ nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_
 /* Step 1/2 on the host: all eigenpairs of the reduced problem sum_j f_j(lambda) Ahat_j y = 0
  * (m x m c128 matrices Ahat, host, ld m, stride m*m) near the ellipse (centre, a, b), of which
  * the m_keep closest to its interior (ascending normalised radius) are returned: lambda_out
- * (2*m_keep doubles) and Y_out (c128 m x m_keep, ld m, unit-norm columns). */
+ * (2*m_keep doubles) and Y_out (c128 m x m_keep, ld m, unit-norm columns).  The linearisation
+ * is inverted about a shift inside the contour: the centre, unless one of the n_avoid values in
+ * `avoid` (2*n_avoid doubles, e.g. the previous Ritz values; may be NULL) lies close to it. */
 nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind,
                                  const double* fparam, const double* Ahat, double cre,
                                  double cim, double a, double b, int32_t m_keep,
-                                 double* lambda_out, double* Y_out);
+                                 const double* avoid, int32_t n_avoid, double* lambda_out,
+                                 double* Y_out);
 
 #ifdef __cplusplus
 }

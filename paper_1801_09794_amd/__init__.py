@@ -75,6 +75,9 @@ _SIGS = {
     "nlf_gemm_batched": (c_i32, [c_i32, ctypes.c_char, ctypes.c_char, c_i64, c_i64, c_i64, P_dbl,
                                  c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, P_dbl, c_vp, c_i64, c_i64,
                                  c_i32, c_vp]),
+    "nlf_gemm_batched_tile": (c_i32, [c_i32, ctypes.c_char, c_i64, c_i64, c_i64, P_dbl, c_vp, c_i64,
+                                      c_i64, c_vp, c_i64, c_i64, P_dbl, c_vp, c_i64, c_i64, c_i32,
+                                      c_i32, c_i32, c_vp]),
     "nlf_block_residual": (c_i32, [c_i64, c_i32, c_i32, P_i32, P_dbl, P_vp, c_i64, c_vp, c_i64,
                                    P_dbl, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "nlf_accumulate": (c_i32, [c_i64, c_i32, c_i32, c_vp, c_vp, P_dbl, P_dbl, P_dbl, c_vp, c_vp]),
@@ -84,7 +87,7 @@ _SIGS = {
     "nlf_project": (c_i32, [c_i64, c_i32, c_i32, P_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "nlf_quadrature": (c_i32, [c_dbl, c_dbl, c_dbl, c_dbl, c_i32, c_i32, P_dbl, P_dbl]),
     "nlf_reduced_solve": (c_i32, [c_i32, c_i32, P_i32, P_dbl, P_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
-                                  c_i32, P_dbl, P_dbl]),
+                                  c_i32, P_dbl, c_i32, P_dbl, P_dbl]),
 }
 
 
@@ -284,6 +287,17 @@ def nlf_gemm_batched(opA, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, 
                                   _ptr(C), ldc, sC, batch, _stream(stream)))
 
 
+def nlf_gemm_batched_tile(opA, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
+                          tm, tn, stream=None):
+    import torch
+    dtype = NLF_C128 if C.dtype == torch.complex128 else NLF_C64
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    _check(lib().nlf_gemm_batched_tile(dtype, opA.encode(), M, N, K, al.ctypes.data_as(P_dbl),
+                                       _ptr(A), lda, sA, _ptr(B), ldb, sB, be.ctypes.data_as(P_dbl),
+                                       _ptr(C), ldc, sC, batch, tm, tn, _stream(stream)))
+
+
 def nlf_block_residual(terms, mats, X, lam, R, norms, ws, stream=None):
     kinds, params = _kinds(terms)
     n, m = mats[0].shape[-1], X.shape[0]
@@ -332,8 +346,9 @@ def nlf_quadrature(centre, a, b, nc, rule=NLF_QUAD_GAUSS_LEGENDRE):
     return z[0::2] + 1j * z[1::2], w[0::2] + 1j * w[1::2]
 
 
-def nlf_reduced_solve(terms, Ahat, centre, a, b, m_keep):
-    """Ahat: list of m x m complex numpy matrices.  Returns (lam, Y)."""
+def nlf_reduced_solve(terms, Ahat, centre, a, b, m_keep, avoid=None):
+    """Ahat: list of m x m complex numpy matrices; avoid: values the inversion shift keeps
+    away from (e.g. the previous Ritz values).  Returns (lam, Y)."""
     kinds, params = _kinds(terms)
     m = Ahat[0].shape[0]
     A = np.concatenate([np.asfortranarray(M, dtype=complex).ravel(order="F") for M in Ahat])
@@ -342,9 +357,11 @@ def nlf_reduced_solve(terms, Ahat, centre, a, b, m_keep):
     lam = np.zeros(2 * m_keep)
     Y = np.zeros(2 * m * m_keep)
     c = complex(centre)
+    av = _cplx_pairs([] if avoid is None else avoid)
     _check(lib().nlf_reduced_solve(m, len(Ahat), kinds.ctypes.data_as(P_i32),
                                    params.ctypes.data_as(P_dbl), Af.ctypes.data_as(P_dbl), c.real,
                                    c.imag, float(a), float(b), int(m_keep),
+                                   av.ctypes.data_as(P_dbl), len(av) // 2,
                                    lam.ctypes.data_as(P_dbl), Y.ctypes.data_as(P_dbl)))
     Yc = (Y[0::2] + 1j * Y[1::2]).reshape(m_keep, m).T
     return lam[0::2] + 1j * lam[1::2], Yc

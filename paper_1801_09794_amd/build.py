@@ -22,15 +22,17 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-HOST_ONLY = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", "-I", INCLUDE]
+# host-only numerics (the reduced eigenproblem): AVX2/FMA and Fortran complex arithmetic rules
+# (no C99 NaN recovery in complex multiply; Smith's division)
+HOST_FLAGS = ["-march=x86-64-v3", "-fcx-fortran-rules"]
+HOST_ONLY_SOURCES = {"host_dense.cpp"}
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    if src.endswith(".hip"):
-        cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
-    else:
-        cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    if os.path.basename(src) in HOST_ONLY_SOURCES:
+        cmd = [HIPCC] + COMMON + HOST_FLAGS + ["-x", "c++", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     errs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops" not in l and l.strip())

@@ -66,15 +66,67 @@ __device__ __forceinline__ int xcd_remap(int w, int nT) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// Global -> register staging of one K step.  A thread loads LA elements of op(A) and LB of B;
+// element e of the thread sits at (row, k) = (a_r[e], a_k[e]) of the BM x BK tile of op(A)
+// and (b_k[e], b_n[e]) of the BK x BN tile of B.
+template <typename R, int TM, int TN, int BK, bool CONJA>
+struct GemmTile {
+    static constexpr int BM = 32 * TM, BN = 32 * TN;
+    static constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+    static constexpr int PAD = 1;                       // LDS row padding (complex elements)
+    static __device__ __forceinline__ void a_coord(int tid, int e, int& m, int& k) {
+        const int idx = tid + 256 * e;
+        if (!CONJA) { m = idx % BM; k = idx / BM; }      // op(A) = A: consecutive threads along m
+        else        { k = idx % BK; m = idx / BK; }      // op(A) = A^H: along k (contiguous in A)
+    }
+    static __device__ __forceinline__ void b_coord(int tid, int e, int& k, int& n) {
+        const int idx = tid + 256 * e;
+        k = idx % BK; n = idx / BK;                      // consecutive threads along k
+    }
+};
+
+template <typename R, int TM, int TN, int BK, bool CONJA>
+__device__ __forceinline__ void gemm_fetch(int64_t M, int64_t N, int64_t lda, int64_t ldb,
+                                           const Cx<R>* __restrict__ A,
+                                           const Cx<R>* __restrict__ B, int64_t m0, int64_t n0,
+                                           int64_t k0, int64_t kend, int tid,
+                                           Cx<R> (&ra)[GemmTile<R, TM, TN, BK, CONJA>::LA],
+                                           Cx<R> (&rb)[GemmTile<R, TM, TN, BK, CONJA>::LB]) {
+    using T = GemmTile<R, TM, TN, BK, CONJA>;
+#pragma unroll
+    for (int e = 0; e < T::LA; ++e) {
+        int m, k;
+        T::a_coord(tid, e, m, k);
+        const int64_t gm = m0 + m, gk = k0 + k;
+        // branch-free: out-of-range lanes read element 0 (always valid here) and keep zero
+        const bool ok = gm < M && gk < kend;
+        const int64_t off = ok ? (!CONJA ? gm + gk * lda : gk + gm * lda) : 0;
+        const Cx<R> v = A[off];
+        ra[e].re = ok ? v.re : R(0);
+        ra[e].im = ok ? (CONJA ? -v.im : v.im) : R(0);
+    }
+#pragma unroll
+    for (int e = 0; e < T::LB; ++e) {
+        int k, n;
+        T::b_coord(tid, e, k, n);
+        const int64_t gn = n0 + n, gk = k0 + k;
+        const bool ok = gn < N && gk < kend;
+        const Cx<R> v = B[ok ? gk + gn * ldb : 0];
+        rb[e].re = ok ? v.re : R(0);
+        rb[e].im = ok ? v.im : R(0);
+    }
+}
+
 template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
-    constexpr int BM = 32 * TM, BN = 32 * TN;
-    constexpr int LA = BM * BK / 256, LB = BN * BK / 256;   // loads per thread per K step
+    using T = GemmTile<R, TM, TN, BK, CONJA>;
+    constexpr int BM = T::BM, BN = T::BN, LA = T::LA, LB = T::LB, PAD = T::PAD;
     static_assert(LA * 256 == BM * BK && LB * 256 == BN * BK, "tile/thread mismatch");
     using acc_t = typename Mfma<R>::acc_t;
 
-    __shared__ Cx<R> As[BK][BM];
-    __shared__ Cx<R> Bs[BK][BN];
+    // double-buffered staging: step s reads buffer s & 1 while step s+1 is written to the other
+    __shared__ Cx<R> As[2][BK][BM + PAD];
+    __shared__ Cx<R> Bs[2][BK][BN + PAD];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -86,6 +138,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
 
     const Cx<R>* __restrict__ A = g.A + batch * g.sA;
     const Cx<R>* __restrict__ B = g.B + batch * g.sB;
+    const int64_t M = g.M, N = g.N, lda = g.lda, ldb = g.ldb;
 
     int64_t kbeg = 0, kend = g.K;
     if (SPLIT) {
@@ -103,63 +156,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
         }
 
     Cx<R> ra[LA], rb[LB];
-    auto fetch = [&](int64_t k0) {
-#pragma unroll
-        for (int e = 0; e < LA; ++e) {
-            const int idx = tid + 256 * e;
-            int m, k;
-            if (!CONJA) { m = idx % BM; k = idx / BM; }
-            else        { k = idx % BK; m = idx / BK; }
-            const int64_t gm = m0 + m, gk = k0 + k;
-            Cx<R> v(0, 0);
-            if (gm < g.M && gk < kend) {
-                if (!CONJA) v = A[gm + gk * g.lda];
-                else { v = A[gk + gm * g.lda]; v.im = -v.im; }
-            }
-            ra[e] = v;
-        }
-#pragma unroll
-        for (int e = 0; e < LB; ++e) {
-            const int idx = tid + 256 * e;
-            const int k = idx % BK, n = idx / BK;
-            const int64_t gn = n0 + n, gk = k0 + k;
-            Cx<R> v(0, 0);
-            if (gn < g.N && gk < kend) v = B[gk + gn * g.ldb];
-            rb[e] = v;
-        }
-    };
-    auto stash = [&]() {
-#pragma unroll
-        for (int e = 0; e < LA; ++e) {
-            const int idx = tid + 256 * e;
-            int m, k;
-            if (!CONJA) { m = idx % BM; k = idx / BM; }
-            else        { k = idx % BK; m = idx / BK; }
-            As[k][m] = ra[e];
-        }
-#pragma unroll
-        for (int e = 0; e < LB; ++e) {
-            const int idx = tid + 256 * e;
-            const int k = idx % BK, n = idx / BK;
-            Bs[k][n] = rb[e];
-        }
-    };
-
     const int col = lane & 15, krow = lane >> 4;
     if (kbeg < kend) {
-        fetch(kbeg);
-        stash();
+        gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, kbeg, kend, tid, ra, rb);
+#pragma unroll
+        for (int e = 0; e < LA; ++e) { int m, k; T::a_coord(tid, e, m, k); As[0][k][m] = ra[e]; }
+#pragma unroll
+        for (int e = 0; e < LB; ++e) { int k, n; T::b_coord(tid, e, k, n); Bs[0][k][n] = rb[e]; }
         __syncthreads();
+        int buf = 0;
         for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             const bool more = k0 + BK < kend;
-            if (more) fetch(k0 + BK);
+            if (more) gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, k0 + BK, kend, tid, ra, rb);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 Cx<R> a[TM], b[TN];
 #pragma unroll
-                for (int i = 0; i < TM; ++i) a[i] = As[kk + krow][wm * 16 * TM + i * 16 + col];
+                for (int i = 0; i < TM; ++i) a[i] = As[buf][kk + krow][wm * 16 * TM + i * 16 + col];
 #pragma unroll
-                for (int j = 0; j < TN; ++j) b[j] = Bs[kk + krow][wn * 16 * TN + j * 16 + col];
+                for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + krow][wn * 16 * TN + j * 16 + col];
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -177,11 +192,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
 #pragma unroll
                     for (int j = 0; j < TN; ++j) accI[i][j] = Mfma<R>::mma(b[j].im, a[i].re, accI[i][j]);
             }
-            __syncthreads();
             if (more) {
-                stash();
-                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < LA; ++e) { int m, k; T::a_coord(tid, e, m, k); As[buf ^ 1][k][m] = ra[e]; }
+#pragma unroll
+                for (int e = 0; e < LB; ++e) { int k, n; T::b_coord(tid, e, k, n); Bs[buf ^ 1][k][n] = rb[e]; }
             }
+            __syncthreads();
+            buf ^= 1;
         }
     }
 
@@ -257,19 +275,21 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit) {
         hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, false>), grid, dim3(256), 0, s, g);
 }
 
+// Default tile choice, from measured sweeps on MI355X: FP64 runs best with the 64 x 64 tile
+// (two waves per SIMD); FP32 with 128 x 64 once there are enough tiles to fill the chip.
+// Small problems (the deep levels of the recursive triangular solves) take the 32 x 32 tile,
+// which quadruples the number of workgroups and cuts the serial MFMA chain per tile by 4.
 template <typename R>
 static GemmConfig pick_config(int64_t M, int64_t N, int64_t K, int batch) {
-    // Tile shape: large tiles when there are enough of them to fill 256 CUs twice.
     GemmConfig c;
-    const int64_t big = ceil_div(M, 128) * ceil_div(N, 64) * batch;
-    if (sizeof(R) == 4) {
-        c.tm = (ceil_div(M, 128) * ceil_div(N, 128) * batch >= 512) ? 4 : 2;
-        c.tn = c.tm;
-    } else {
-        c.tm = (big >= 512) ? 4 : 2;
-        c.tn = 2;
-    }
     (void)K;
+    if (sizeof(R) == 4 && ceil_div(M, 128) * ceil_div(N, 64) * batch >= 512) {
+        c.tm = 4;
+        c.tn = 2;
+    } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch < 256) {
+        c.tm = 1;
+        c.tn = 1;
+    }
     return c;
 }
 
@@ -294,7 +314,7 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // split-K for small outputs with long reductions (projections, Gram matrices)
     int nsplit = 1;
     const int64_t tiles = ceil_div(M, 32 * c.tm) * ceil_div(N, 32 * c.tn) * batch;
-    if (ws && tiles < 128 && K >= 1024) {
+    if (ws && tiles < 256 && K >= 512) {
         int want = (int)std::min<int64_t>(ceil_div(512, tiles), ceil_div(K, 256));
         while (want > 1 && (int64_t)want * M * N * batch > ws_elems) --want;
         if (want > 1) {
@@ -310,10 +330,15 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
         if (conjA) launch_tiles<R, TM_, TN_, 16, true>(s, g, batch, nsplit);            \
         else       launch_tiles<R, TM_, TN_, 16, false>(s, g, batch, nsplit);           \
     } else
+    NLF_GEMM_CASE(1, 1)
     NLF_GEMM_CASE(2, 2)
     NLF_GEMM_CASE(4, 2)
-    NLF_GEMM_CASE(4, 4)
-    { throw Error{1, "gemm: unsupported tile config"}; }
+    if constexpr (sizeof(R) == 4) {
+        NLF_GEMM_CASE(4, 4)
+        { throw Error{1, "gemm: unsupported tile config"}; }
+    } else {
+        throw Error{1, "gemm: unsupported tile config"};
+    }
 #undef NLF_GEMM_CASE
     NLF_HIP(hipGetLastError());
     if (nsplit > 1) {

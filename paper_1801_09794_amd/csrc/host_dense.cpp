@@ -95,11 +95,11 @@ bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv) {
     }
     Rinv.assign(m * m, 0.0);
     for (int c = 0; c < m; ++c) {           // solve R x = e_c by back substitution
-        Rinv[c + c * m] = 1.0 / R[c + c * m];
+        Rinv[c + (size_t)c * m] = 1.0 / R[c + (size_t)c * m];
         for (int i = c - 1; i >= 0; --i) {
             cplx s = 0.0;
-            for (int k = i + 1; k <= c; ++k) s += R[i + k * m] * Rinv[k + c * m];
-            Rinv[i + c * m] = -s / R[i + i * m];
+            for (int k = i + 1; k <= c; ++k) s += R[i + (size_t)k * m] * Rinv[k + (size_t)c * m];
+            Rinv[i + (size_t)c * m] = -s / R[i + (size_t)i * m];
         }
     }
     return true;
@@ -313,9 +313,192 @@ bool eig_dense(int N, std::vector<cplx>& A, std::vector<cplx>& evals, const std:
     return true;
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Eigenvalues by the QR algorithm restricted to the active window (no Schur vectors), and
+// eigenvectors of selected eigenvalues by inverse iteration on the Hessenberg matrix followed
+// by the Householder back-transformation.  Work ~ (10/3 + ~4) N^3 real-complex operations
+// instead of the ~25 N^3 of the full Schur form with vectors.
+bool HessEig::compute(int N_, std::vector<cplx>& A) {
+    N = N_;
+    H.swap(A);
+    V.assign((size_t)N * N, 0.0);
+    beta.assign(N, 0.0);
+    std::vector<cplx> s(N);
+    for (int k = 0; k + 2 < N; ++k) {
+        double xn2 = 0.0;
+        for (int i = k + 1; i < N; ++i) xn2 += std::norm(H[i + (size_t)k * N]);
+        if (xn2 == 0.0) continue;
+        const double xn = std::sqrt(xn2);
+        const cplx x0 = H[k + 1 + (size_t)k * N];
+        const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
+        const cplx alpha = -ph * xn;
+        cplx* v = &V[(size_t)k * N];
+        for (int i = k + 1; i < N; ++i) v[i] = H[i + (size_t)k * N];
+        v[k + 1] -= alpha;
+        double vn2 = 0.0;
+        for (int i = k + 1; i < N; ++i) vn2 += std::norm(v[i]);
+        if (vn2 == 0.0) continue;
+        const double bt = 2.0 / vn2;
+        beta[k] = bt;
+        for (int j = k + 1; j < N; ++j) {
+            cplx t = 0.0;
+            const cplx* hj = &H[(size_t)j * N];
+            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * hj[i];
+            t *= bt;
+            cplx* hw = &H[(size_t)j * N];
+            for (int i = k + 1; i < N; ++i) hw[i] -= v[i] * t;
+        }
+        std::fill(s.begin(), s.end(), cplx(0.0));
+        for (int j = k + 1; j < N; ++j) {
+            const cplx vj = v[j];
+            const cplx* hj = &H[(size_t)j * N];
+            for (int i = 0; i < N; ++i) s[i] += hj[i] * vj;
+        }
+        for (int j = k + 1; j < N; ++j) {
+            const cplx cv = bt * std::conj(v[j]);
+            cplx* hj = &H[(size_t)j * N];
+            for (int i = 0; i < N; ++i) hj[i] -= s[i] * cv;
+        }
+        H[k + 1 + (size_t)k * N] = alpha;
+        for (int i = k + 2; i < N; ++i) H[i + (size_t)k * N] = 0.0;
+    }
+    H0 = H;   // Hessenberg matrix before the QR sweeps (for inverse iteration)
+    norm = 0.0;
+    for (size_t e = 0; e < (size_t)N * N; ++e) norm = std::max(norm, abs1(H[e]));
+    if (norm == 0.0) norm = 1.0;
+    int ihi = N - 1, its = 0, total = 0;
+    while (ihi >= 0) {
+        int l = ihi;
+        while (l > 0) {
+            double sc = abs1(H[l - 1 + (size_t)(l - 1) * N]) + abs1(H[l + (size_t)l * N]);
+            if (sc == 0.0) sc = norm;
+            if (abs1(H[l + (size_t)(l - 1) * N]) <= kEps * sc) {
+                H[l + (size_t)(l - 1) * N] = 0.0;
+                break;
+            }
+            --l;
+        }
+        if (l == ihi) {
+            --ihi;
+            its = 0;
+            continue;
+        }
+        if (++its > 80 || ++total > 100 * N) return false;
+        cplx mu;
+        const cplx a = H[ihi - 1 + (size_t)(ihi - 1) * N], b = H[ihi - 1 + (size_t)ihi * N];
+        const cplx c = H[ihi + (size_t)(ihi - 1) * N], d = H[ihi + (size_t)ihi * N];
+        if (its == 10 || its == 20 || its == 40) {
+            mu = d + std::abs(c.real()) * 0.75;
+        } else {
+            const cplx tr2 = 0.5 * (a + d);
+            const cplx disc = std::sqrt(0.25 * (a - d) * (a - d) + b * c);
+            const cplx m1 = tr2 + disc, m2 = tr2 - disc;
+            mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+        }
+        cplx x = H[l + (size_t)l * N] - mu, y = H[l + 1 + (size_t)l * N];
+        for (int k = l; k < ihi; ++k) {
+            if (k > l) {
+                x = H[k + (size_t)(k - 1) * N];
+                y = H[k + 1 + (size_t)(k - 1) * N];
+            }
+            double cs;
+            cplx sn, rho;
+            givens(x, y, cs, sn, rho);
+            if (k > l) {
+                H[k + (size_t)(k - 1) * N] = rho;
+                H[k + 1 + (size_t)(k - 1) * N] = 0.0;
+            }
+            const cplx csn = std::conj(sn);
+            for (int j = k; j <= ihi; ++j) {            // rows k, k+1 inside the window
+                const cplx p = H[k + (size_t)j * N], q = H[k + 1 + (size_t)j * N];
+                H[k + (size_t)j * N] = cs * p + sn * q;
+                H[k + 1 + (size_t)j * N] = -csn * p + cs * q;
+            }
+            const int iend = std::min(k + 2, ihi);
+            cplx* ck = &H[(size_t)k * N];
+            cplx* ck1 = &H[(size_t)(k + 1) * N];
+            for (int i = l; i <= iend; ++i) {            // columns k, k+1 inside the window
+                const cplx p = ck[i], q = ck1[i];
+                ck[i] = cs * p + csn * q;
+                ck1[i] = -sn * p + cs * q;
+            }
+        }
+    }
+    evals.resize(N);
+    for (int i = 0; i < N; ++i) evals[i] = H[i + (size_t)i * N];
+    return true;
+}
+
+void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) const {
+    out.assign((size_t)N * want.size(), 0.0);
+    // row-major copy of the Hessenberg matrix: the elimination below works on rows
+    std::vector<cplx> Hr((size_t)N * N), M((size_t)N * N), x(N);
+    for (int j = 0; j < N; ++j)
+        for (int i = 0; i < N; ++i) Hr[(size_t)i * N + j] = H0[i + (size_t)j * N];
+    std::vector<int> piv(N);
+    const double smin = std::max(kEps * norm, std::numeric_limits<double>::min() * N);
+    for (size_t q = 0; q < want.size(); ++q) {
+        const cplx lam = evals[want[q]];
+        // LU of H0 - lam I with row exchanges between neighbours only (row i of M at M + i N)
+        M = Hr;
+        for (int i = 0; i < N; ++i) M[(size_t)i * N + i] -= lam;
+        for (int k = 0; k + 1 < N; ++k) {
+            cplx* rk = &M[(size_t)k * N];
+            cplx* rk1 = &M[(size_t)(k + 1) * N];
+            piv[k] = k;
+            if (abs1(rk1[k]) > abs1(rk[k])) {
+                piv[k] = k + 1;
+                for (int j = k; j < N; ++j) std::swap(rk[j], rk1[j]);
+            }
+            if (rk[k] == 0.0) rk[k] = smin;
+            const cplx lk = rk1[k] / rk[k];
+            rk1[k] = lk;
+            if (lk != 0.0)
+                for (int j = k + 1; j < N; ++j) rk1[j] -= lk * rk[j];
+        }
+        if (M[(size_t)(N - 1) * N + N - 1] == 0.0) M[(size_t)(N - 1) * N + N - 1] = smin;
+        for (int i = 0; i < N; ++i) x[i] = 1.0 / std::sqrt((double)N);
+        for (int it = 0; it < 2; ++it) {
+            for (int k = 0; k + 1 < N; ++k) {          // forward: L^{-1} P x
+                if (piv[k] != k) std::swap(x[k], x[k + 1]);
+                x[k + 1] -= M[(size_t)(k + 1) * N + k] * x[k];
+            }
+            for (int i = N - 1; i >= 0; --i) {         // back: U^{-1}
+                const cplx* ri = &M[(size_t)i * N];
+                cplx t = x[i];
+                for (int j = i + 1; j < N; ++j) t -= ri[j] * x[j];
+                cplx d = ri[i];
+                if (std::abs(d) < smin) d = smin;
+                x[i] = t / d;
+            }
+            double nr = 0.0;
+            for (int i = 0; i < N; ++i) nr += std::norm(x[i]);
+            nr = std::sqrt(nr);
+            for (int i = 0; i < N; ++i) x[i] /= nr;
+        }
+        // back-transform with the reflectors: x <- P_0 P_1 ... P_{N-3} x
+        for (int k = N - 3; k >= 0; --k) {
+            if (beta[k] == 0.0) continue;
+            const cplx* v = &V[(size_t)k * N];
+            cplx t = 0.0;
+            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * x[i];
+            t *= beta[k];
+            for (int i = k + 1; i < N; ++i) x[i] -= v[i] * t;
+        }
+        double nr = 0.0;
+        for (int i = 0; i < N; ++i) nr += std::norm(x[i]);
+        nr = std::sqrt(nr);
+        cplx* o = &out[(size_t)q * N];
+        for (int i = 0; i < N; ++i) o[i] = x[i] / nr;
+    }
+}
+
 // LU with partial pivoting (|Re| + |Im| pivots) of an m x m matrix; solves M X = B in place.
-static bool lu_solve_small(int m, std::vector<cplx> M, cplx* B, int nrhs) {
+// pivot_ratio (optional) receives min |u_kk| / max |u_kk|.
+static bool lu_solve_small(int m, std::vector<cplx> M, cplx* B, int nrhs, double* pivot_ratio = nullptr) {
     std::vector<int> piv(m);
+    double umin = INFINITY, umax = 0.0;
     for (int k = 0; k < m; ++k) {
         int p = k;
         double best = abs1(M[k + (size_t)k * m]);
@@ -325,6 +508,8 @@ static bool lu_solve_small(int m, std::vector<cplx> M, cplx* B, int nrhs) {
         }
         piv[k] = p;
         if (best == 0.0) return false;
+        umin = std::min(umin, best);
+        umax = std::max(umax, best);
         if (p != k)
             for (int j = 0; j < m; ++j) std::swap(M[k + (size_t)j * m], M[p + (size_t)j * m]);
         const cplx inv = 1.0 / M[k + (size_t)k * m];
@@ -335,6 +520,7 @@ static bool lu_solve_small(int m, std::vector<cplx> M, cplx* B, int nrhs) {
             for (int i = k + 1; i < m; ++i) M[i + (size_t)j * m] -= M[i + (size_t)k * m] * u;
         }
     }
+    if (pivot_ratio) *pivot_ratio = umin / umax;
     for (int c = 0; c < nrhs; ++c) {
         cplx* b = B + (size_t)c * m;
         for (int k = 0; k < m; ++k)
@@ -372,49 +558,97 @@ static std::vector<cplx> taylor(const Term& t, cplx c, int d) {
     return out;
 }
 
+// Shift for the inverted linearisation: the contour centre unless a previous Ritz value lies
+// within 0.2 rho of it (rho = smaller semi-axis), else the candidate on the circle of radius
+// rho / 2 farthest from every previous Ritz value.  An eigenvalue at the shift makes
+// T_red(shift) singular and the inverted companion matrix huge, which costs every other Ritz
+// value its accuracy.
+static std::vector<cplx> shift_candidates(const Ellipse& E, const std::vector<cplx>* avoid) {
+    const double rho = std::min(E.a, E.b);
+    std::vector<cplx> cand;
+    cand.push_back(E.c);
+    for (int k = 0; k < 7; ++k) {
+        const double th = 2.0 * kPi * k / 7.0 + 0.3;
+        cand.push_back(E.c + 0.5 * rho * cplx(std::cos(th), std::sin(th)));
+    }
+    if (!avoid || avoid->empty()) return cand;
+    auto dist = [&](cplx s) {
+        double d = INFINITY;
+        for (cplx l : *avoid)
+            if (std::isfinite(l.real()) && std::isfinite(l.imag())) d = std::min(d, std::abs(l - s));
+        return d / rho;
+    };
+    std::vector<std::pair<double, int>> score;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        double d = dist(cand[i]);
+        if (i == 0 && d >= 0.2) d = INFINITY;        // keep the centre when it is clear
+        score.push_back({-d, (int)i});
+    }
+    std::stable_sort(score.begin(), score.end());
+    std::vector<cplx> out;
+    for (auto& sc : score) out.push_back(cand[sc.second]);
+    return out;
+}
+
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
-                            const Ellipse& E, int m_keep) {
+                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid) {
     ReducedResult res;
     const int J = (int)terms.size();
     bool poly = true;
-    int deg = 1;
+    int maxpow = 1;
     for (const Term& t : terms) {
-        if (t.kind == 0) deg = std::max(deg, (int)t.param);
+        if (t.kind == 0) maxpow = std::max(maxpow, (int)t.param);
         else poly = false;
     }
-    if (!poly) {
-        // smallest d with (tau rho)^{d+1} e^{tau rho} / (d+1)! <= 1e-16 on |mu| <= 1.5 max(a, b)
-        const double rho = 1.5 * std::max(E.a, E.b);
-        for (const Term& t : terms) {
-            if (t.kind != 1) continue;
-            const double x = std::fabs(t.param) * rho;
-            int e = 1;
-            double term = x * x / 2.0;
-            while (term * std::exp(x) > 1e-16) {
-                ++e;
-                term *= x / (e + 1);
-            }
-            deg = std::max(deg, e);
-        }
-    }
     const size_t mm = (size_t)m * m;
-    std::vector<std::vector<cplx>> B(deg + 1, std::vector<cplx>(mm, 0.0));
-    for (int j = 0; j < J; ++j) {
-        const std::vector<cplx> tc = taylor(terms[j], E.c, deg);
-        const cplx* A = Ahat + (size_t)j * mm;
-        for (int q = 0; q <= deg; ++q) {
-            if (tc[q] == 0.0) continue;
-            for (size_t e = 0; e < mm; ++e) B[q][e] += tc[q] * A[e];
+    const std::vector<cplx> shifts = shift_candidates(E, avoid);
+    int deg = maxpow, N = 0;
+    cplx sigma = E.c;
+    std::vector<cplx> D;
+    bool have = false;
+    for (cplx sg : shifts) {
+        deg = maxpow;
+        if (!poly) {
+            // smallest d with (tau R)^{d+1} e^{tau R} / (d+1)! <= 1e-16 on the disk about the
+            // shift that covers |lambda - c| <= 1.5 max(a, b)
+            const double R = 1.5 * std::max(E.a, E.b) + std::abs(sg - E.c);
+            for (const Term& t : terms) {
+                if (t.kind != 1) continue;
+                const double x = std::fabs(t.param) * R;
+                int e = 1;
+                double term = x * x / 2.0;
+                while (term * std::exp(x) > 1e-16) {
+                    ++e;
+                    term *= x / (e + 1);
+                }
+                deg = std::max(deg, e);
+            }
+        }
+        std::vector<std::vector<cplx>> B(deg + 1, std::vector<cplx>(mm, 0.0));
+        for (int j = 0; j < J; ++j) {
+            const std::vector<cplx> tc = taylor(terms[j], sg, deg);
+            const cplx* A = Ahat + (size_t)j * mm;
+            for (int q = 0; q <= deg; ++q) {
+                if (tc[q] == 0.0) continue;
+                for (size_t e = 0; e < mm; ++e) B[q][e] += tc[q] * A[e];
+            }
+        }
+        // monic polynomial in nu = 1/(lambda - sigma): nu^deg I + sum_{q>=1} nu^{deg-q} D_q,
+        // D_q = B_0^{-1} B_q
+        D.assign(mm * deg, 0.0);
+        for (int q = 1; q <= deg; ++q) std::copy(B[q].begin(), B[q].end(), D.begin() + (size_t)(q - 1) * mm);
+        double ratio = 0.0;
+        if (lu_solve_small(m, B[0], D.data(), m * deg, &ratio) && ratio > 1e-12) {
+            sigma = sg;
+            have = true;
+            break;
         }
     }
-    // monic polynomial in nu = 1/mu:  nu^deg I + sum_{q>=1} nu^{deg-q} D_q,  D_q = B_0^{-1} B_q
-    const int N = deg * m;
-    std::vector<cplx> D((size_t)m * m * deg);
-    for (int q = 1; q <= deg; ++q) std::copy(B[q].begin(), B[q].end(), D.begin() + (size_t)(q - 1) * mm);
-    if (!lu_solve_small(m, B[0], D.data(), m * deg)) {
+    if (!have) {
         res.ok = false;
         return res;
     }
+    N = deg * m;
     std::vector<cplx> M((size_t)N * N, 0.0);
     for (int q = 1; q <= deg; ++q)
         for (int c = 0; c < m; ++c)
@@ -422,8 +656,8 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
                 M[r + (size_t)((q - 1) * m + c) * N] = -D[(size_t)(q - 1) * mm + r + (size_t)c * m];
     for (int bI = 1; bI < deg; ++bI)
         for (int i = 0; i < m; ++i) M[(size_t)bI * m + i + (size_t)((bI - 1) * m + i) * N] = 1.0;
-    Schur S;
-    if (!S.compute(N, M, true)) {
+    HessEig S;
+    if (!S.compute(N, M)) {
         res.ok = false;
         return res;
     }
@@ -431,7 +665,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
     std::vector<cplx> lam(N);
     std::vector<double> rad(N);
     for (int i = 0; i < N; ++i) {
-        lam[i] = (nu[i] == 0.0) ? cplx(INFINITY, 0.0) : E.c + 1.0 / nu[i];
+        lam[i] = (nu[i] == 0.0) ? cplx(INFINITY, 0.0) : sigma + 1.0 / nu[i];
         rad[i] = E.radius(lam[i]);
     }
     std::vector<int> order(N);
@@ -446,7 +680,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
     res.Y.assign((size_t)m * keep, 0.0);
     for (int q = 0; q < keep; ++q) {
         const int k = want[q];
-        res.lambda[q] = (nu2[k] == 0.0) ? cplx(INFINITY, 0.0) : E.c + 1.0 / nu2[k];
+        res.lambda[q] = (nu2[k] == 0.0) ? cplx(INFINITY, 0.0) : sigma + 1.0 / nu2[k];
         const cplx* v = &V[(size_t)q * N];
         int bb = 0;
         double bn = -1.0;

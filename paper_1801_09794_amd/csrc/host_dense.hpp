@@ -43,11 +43,12 @@ struct ReducedResult {
 
 // All eigenpairs of sum_j f_j(lambda) Ahat_j y = 0 (Ahat: J matrices m x m, column-major,
 // consecutive), then the m_keep closest to the interior of E (ascending normalised radius,
-// stable, non-finite last).  Polynomial terms: exact companion linearisation about the
-// contour centre; exponential terms: Taylor expansion about the centre followed by Newton
-// refinement on the exact reduced function.
+// stable, non-finite last).  Polynomial terms: exact companion linearisation, inverted about
+// a shift inside the contour (the centre unless a Ritz value in `avoid` is close to it);
+// exponential terms: Taylor expansion about that shift followed by Newton refinement on the
+// exact reduced function.
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
-                            const Ellipse& E, int m_keep);
+                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid = nullptr);
 
 // Complex Schur decomposition A = Z T Z^H of a dense N x N matrix (column-major) by
 // Householder reduction to Hessenberg form and the shifted QR algorithm (Givens rotations,
@@ -57,6 +58,18 @@ struct Schur {
     std::vector<cplx> T, Z, evals;
     double norm = 0.0;
     bool compute(int N, std::vector<cplx>& A, bool with_vectors);   // A is overwritten
+    void vectors(const std::vector<int>& want, std::vector<cplx>& out) const;   // unit columns
+};
+
+// Eigenvalues of a dense N x N matrix by Householder reduction to Hessenberg form and the
+// shifted QR algorithm confined to the active window; eigenvectors of selected eigenvalues by
+// inverse iteration on the Hessenberg matrix and the reflectors' back-transformation.
+struct HessEig {
+    int N = 0;
+    std::vector<cplx> H, H0, V, evals;
+    std::vector<double> beta;
+    double norm = 0.0;
+    bool compute(int N, std::vector<cplx>& A);                               // A is consumed
     void vectors(const std::vector<int>& want, std::vector<cplx>& out) const;   // unit columns
 };
 

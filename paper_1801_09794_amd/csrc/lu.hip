@@ -24,6 +24,7 @@ namespace nlf {
 constexpr int PANEL_NT = 1024;
 constexpr int PANEL_WMAX = 32;
 constexpr int TRSM_NB = 64;
+constexpr int TRSM_CB = 8;      // right-hand-side columns per wavefront in the TRSM leaf
 
 template <typename R>
 __device__ __forceinline__ void wave_argmax(R& v, int& row) {
@@ -302,60 +303,73 @@ __global__ __launch_bounds__(1024) void laswp_apply_kernel(Cx<R>* A0, int64_t ld
     }
 }
 
-// B <- T^{-1} B for one diagonal block of order nb <= 64 (unit-lower or upper triangular T),
-// CB columns of B per workgroup, T and the B block staged in LDS.
-template <typename R, bool UPPER>
+// B <- T^{-1} B for one diagonal block of order nb <= 64 (unit-lower or upper triangular T).
+// Four wavefronts per workgroup share T, staged transposed in LDS (lane i reads T(i, t) from
+// consecutive addresses); each wavefront owns CB columns of B with lane i holding row i in
+// registers, and broadcasts the solved row t through its own LDS slot.  After T is staged all
+// communication stays inside a wavefront, whose LDS operations complete in issue order, so
+// the substitution itself needs no workgroup barrier.
+template <typename R, bool UPPER, int CB>
 __global__ __launch_bounds__(256) void trsm_leaf_kernel(int nb, int64_t N, const Cx<R>* T0,
                                                         int64_t ldt, int64_t sT, Cx<R>* B0,
                                                         int64_t ldb, int64_t sB) {
-    constexpr int CB = 16;
-    __shared__ Cx<R> Ts[TRSM_NB][TRSM_NB + 1];
-    __shared__ Cx<R> Bs[TRSM_NB][CB];
+    __shared__ Cx<R> Tt[TRSM_NB][TRSM_NB + 1];      // Tt[t][i] = T(i, t)
+    __shared__ Cx<R> xts[4][CB];
     const int64_t b = blockIdx.y;
     const Cx<R>* T = T0 + b * sT;
     Cx<R>* B = B0 + b * sB;
-    const int64_t cbase = (int64_t)blockIdx.x * CB;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e % nb, j = e / nb;
-        Ts[i][j] = T[i + (int64_t)j * ldt];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t cbase = ((int64_t)blockIdx.x * 4 + wave) * CB;
+    Cx<R>* xt = xts[wave];
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+        const int i = e % nb, t = e / nb;
+        Tt[t][i] = T[i + (int64_t)t * ldt];
     }
-    for (int e = tid; e < nb * CB; e += 256) {
-        const int i = e % nb, c = e / nb;
-        Bs[i][c] = (cbase + c < N) ? B[i + (cbase + c) * ldb] : Cx<R>(0, 0);
-    }
+    Cx<R> x[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        x[c] = (lane < nb && cbase + c < N) ? B[lane + (cbase + c) * ldb] : Cx<R>(0, 0);
     __syncthreads();
     if (!UPPER) {
         for (int t = 0; t + 1 < nb; ++t) {
-            for (int e = tid; e < nb * CB; e += 256) {
-                const int i = e % nb, c = e / nb;
-                if (i > t) {
-                    Cx<R> v = Bs[i][c];
-                    cfms(v, Ts[i][t], Bs[t][c]);
-                    Bs[i][c] = v;
-                }
+            if (lane == t) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) xt[c] = x[c];
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane > t) {
+                const Cx<R> l = Tt[t][lane];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cfms(x[c], l, xt[c]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     } else {
         for (int t = nb - 1; t >= 0; --t) {
-            if (tid < CB) Bs[t][tid] = cdiv(Bs[t][tid], Ts[t][t]);
-            __syncthreads();
-            for (int e = tid; e < nb * CB; e += 256) {
-                const int i = e % nb, c = e / nb;
-                if (i < t) {
-                    Cx<R> v = Bs[i][c];
-                    cfms(v, Ts[i][t], Bs[t][c]);
-                    Bs[i][c] = v;
+            if (lane == t) {
+                const Cx<R> inv = cdiv(Cx<R>(1, 0), Tt[t][t]);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    x[c] = x[c] * inv;
+                    xt[c] = x[c];
                 }
             }
-            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane < t) {
+                const Cx<R> u = Tt[t][lane];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) cfms(x[c], u, xt[c]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    for (int e = tid; e < nb * CB; e += 256) {
-        const int i = e % nb, c = e / nb;
-        if (cbase + c < N) B[i + (cbase + c) * ldb] = Bs[i][c];
-    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        if (lane < nb && cbase + c < N) B[lane + (cbase + c) * ldb] = x[c];
 }
 
 // X_b[i, c] = B_b[perm_b[i], c]
@@ -383,9 +397,9 @@ void trsm_lower_unit(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>
     if (n <= 0 || N <= 0) return;
     if (n <= TRSM_NB) {
         ProfScope ps(trsm_class(), s, 4.0 * n * n * N * batch, 0);
-        dim3 grid((unsigned)ceil_div(N, 16), batch);
-        hipLaunchKernelGGL((trsm_leaf_kernel<R, false>), grid, dim3(256), 0, s, (int)n, N, L,
-                           ldl, sL, B, ldb, sB);
+        dim3 grid((unsigned)ceil_div(N, 4 * TRSM_CB), batch);
+        hipLaunchKernelGGL((trsm_leaf_kernel<R, false, TRSM_CB>), grid, dim3(256), 0, s, (int)n, N,
+                           L, ldl, sL, B, ldb, sB);
         NLF_HIP(hipGetLastError());
         return;
     }
@@ -405,9 +419,9 @@ void trsm_upper(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* U, 
     if (n <= 0 || N <= 0) return;
     if (n <= TRSM_NB) {
         ProfScope ps(trsm_class(), s, 4.0 * n * n * N * batch, 0);
-        dim3 grid((unsigned)ceil_div(N, 16), batch);
-        hipLaunchKernelGGL((trsm_leaf_kernel<R, true>), grid, dim3(256), 0, s, (int)n, N, U,
-                           ldu, sU, B, ldb, sB);
+        dim3 grid((unsigned)ceil_div(N, 4 * TRSM_CB), batch);
+        hipLaunchKernelGGL((trsm_leaf_kernel<R, true, TRSM_CB>), grid, dim3(256), 0, s, (int)n, N,
+                           U, ldu, sU, B, ldb, sB);
         NLF_HIP(hipGetLastError());
         return;
     }

@@ -202,7 +202,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
     L.rho = take(16 * L.mmax);
     L.acoef = take(16 * (size_t)L.mmax * L.ncmax);
     L.norms = take(8 * (size_t)(L.mmax + L.ncmax + 8));
-    L.splitws_elems = (int64_t)std::max<size_t>(64 * mm * J, 1 << 16);
+    L.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
     L.splitws = take(16 * (size_t)L.splitws_elems);
     L.coef = take(16 * (size_t)L.NZ * J);
     L.total = off;
@@ -258,7 +258,7 @@ void project(hipStream_t s, int64_t n, int m, int J, const z128* const* A, int64
     for (int j = 0; j < J; ++j) {
         ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * n * m, 16.0 * ((double)n * n + 2.0 * n * m));
         gemm<double>(s, false, n, m, n, z128(1, 0), A[j], lda, 0, Q, n, 0, z128(0, 0),
-                     W + (size_t)j * n * m, n, 0, 1);
+                     W + (size_t)j * n * m, n, 0, 1, splitws, split_elems);
     }
     ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
     gemm<double>(s, true, m, m, n, z128(1, 0), Q, n, 0, W, n, (int64_t)n * m, z128(0, 0), Ahat, m,
@@ -492,7 +492,9 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                 project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, L.splitws_elems);
                 d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
                 const auto t0 = std::chrono::steady_clock::now();
-                rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m);
+                std::vector<cplx> prev;
+                if (it > 0) prev = rr.lambda;
+                rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr);
                 host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
                 NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
                             "reduced eigenproblem failed (singular T at the contour centre or QR did not converge)");
@@ -706,6 +708,38 @@ nlfeast_status nlf_gemm_batched(int32_t dtype, char opA, char opB, int64_t M, in
     })
 }
 
+nlfeast_status nlf_gemm_batched_tile(int32_t dtype, char opA, int64_t M, int64_t N, int64_t K,
+                                     const double* alpha, const void* A_dev, int64_t lda,
+                                     int64_t strideA, const void* B_dev, int64_t ldb,
+                                     int64_t strideB, const double* beta, void* C_dev, int64_t ldc,
+                                     int64_t strideC, int32_t batch, int32_t tm, int32_t tn,
+                                     void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        const bool cA = opA == 'C' || opA == 'c';
+        NLF_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 1 && alpha && beta && C_dev && ldc >= M &&
+                        (K == 0 || (A_dev && B_dev && ldb >= K && lda >= (cA ? K : M))) &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_gemm_batched_tile: bad arguments");
+        const bool ok = (tm == 1 && tn == 1) || (tm == 2 && tn == 2) || (tm == 4 && tn == 2) ||
+                        (tm == 4 && tn == 4 && dtype == NLF_C64);
+        NLF_REQUIRE(ok, NLF_ERR_ARG, "nlf_gemm_batched_tile: tile not compiled");
+        GemmConfig c;
+        c.tm = tm;
+        c.tn = tn;
+        hipStream_t s = as_stream(stream);
+        if (dtype == NLF_C128)
+            gemm<double>(s, cA, M, N, K, z128(alpha[0], alpha[1]), (const z128*)A_dev, lda, strideA,
+                         (const z128*)B_dev, ldb, strideB, z128(beta[0], beta[1]), (z128*)C_dev, ldc,
+                         strideC, batch, nullptr, 0, &c);
+        else
+            gemm<float>(s, cA, M, N, K, z64((float)alpha[0], (float)alpha[1]), (const z64*)A_dev, lda,
+                        strideA, (const z64*)B_dev, ldb, strideB, z64((float)beta[0], (float)beta[1]),
+                        (z64*)C_dev, ldc, strideC, batch, nullptr, 0, &c);
+        return NLF_OK;
+    })
+}
+
 nlfeast_status nlf_block_residual(int64_t n, int32_t m, int32_t J, const int32_t* fkind,
                                   const double* fparam, const void* const* A_dev, int64_t lda,
                                   const void* X_dev, int64_t ldx, const double* lambda, void* R_dev,
@@ -791,8 +825,7 @@ nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_de
 }
 
 int64_t nlf_project_workspace(int64_t n, int32_t m, int32_t J) {
-    (void)n;
-    return std::max<int64_t>(64 * (int64_t)m * m * J, 1 << 16);
+    return std::max<int64_t>(std::max<int64_t>(64 * (int64_t)m * m * J, 8 * n * (int64_t)m), 1 << 16);
 }
 
 nlfeast_status nlf_project(int64_t n, int32_t m, int32_t J, const void* const* A_dev, int64_t lda,
@@ -827,7 +860,8 @@ nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_
 
 nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind, const double* fparam,
                                  const double* Ahat, double cre, double cim, double a, double b,
-                                 int32_t m_keep, double* lambda_out, double* Y_out) {
+                                 int32_t m_keep, const double* avoid, int32_t n_avoid,
+                                 double* lambda_out, double* Y_out) {
     nlfeast_ctx* h = nullptr;
     NLF_TRY(h, {
         NLF_REQUIRE(m >= 1 && J >= 1 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
@@ -835,7 +869,10 @@ nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind, con
                     NLF_ERR_ARG, "nlf_reduced_solve: bad arguments");
         std::vector<Term> terms(J);
         for (int j = 0; j < J; ++j) terms[j] = Term{fkind[j], fparam[j]};
-        ReducedResult rr = reduced_solve(m, terms, (const cplx*)Ahat, Ellipse{cplx(cre, cim), a, b}, m_keep);
+        std::vector<cplx> av;
+        for (int i = 0; avoid && i < n_avoid; ++i) av.push_back(cplx(avoid[2 * i], avoid[2 * i + 1]));
+        ReducedResult rr = reduced_solve(m, terms, (const cplx*)Ahat, Ellipse{cplx(cre, cim), a, b}, m_keep,
+                                         av.empty() ? nullptr : &av);
         NLF_REQUIRE(rr.ok, NLF_ERR_DEVICE, "nlf_reduced_solve: eigen-decomposition failed");
         const int keep = (int)rr.lambda.size();
         for (int q = 0; q < keep; ++q) {
