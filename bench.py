@@ -33,7 +33,56 @@ def parse():
     ap.add_argument("--workload", default="damped4096")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--probe-gemm", action="store_true",
+                    help="counter runs: one 1 GiB device copy (calibration), then the dominant "
+                         "LU trailing-update GEMM shape three times, nothing else")
     return ap.parse_args()
+
+
+# The largest trailing update of the LU of 16 nodes at n = 4096: C -= A B with M = N = K = 2048.
+PROBE = dict(M=2048, N=2048, K=2048, batch=16)
+
+
+def probe_gemm():
+    """Plain copy of known size (to scale HBM counters), then the dominant GEMM launch."""
+    import torch
+    import paper_1801_09794_amd as nl
+    torch.cuda.set_device(0)
+    a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")     # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    M, N, K, bt = PROBE["M"], PROBE["N"], PROBE["K"], PROBE["batch"]
+    A = torch.randn((bt, K, M), dtype=torch.complex128, device="cuda")
+    B = torch.randn((bt, N, K), dtype=torch.complex128, device="cuda")
+    C = torch.randn((bt, N, M), dtype=torch.complex128, device="cuda")
+    for _ in range(3):
+        nl.nlf_gemm_batched("N", M, N, K, -1.0, A, M, M * K, B, K, K * N, 1.0, C, M, M * N, bt)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(probe="gemm c128", copy_bytes=2 * a.numel() * 8,
+                          gemm_algorithmic_bytes=16.0 * bt * (M * K + K * N + 2 * M * N), **PROBE)))
+
+
+def load_traffic():
+    """HBM traffic of the probe launch from the committed counter summary, or None when the
+    GEMM source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gemm_c128_2048x2048x2048_b16_traffic.txt")
+    src = os.path.join(ROOT, "paper_1801_09794_amd", "csrc", "gemm.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("gemm_source_sha256_16") != digest:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def load_workload(name):
@@ -134,6 +183,9 @@ def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters):
 
 def main():
     args = parse()
+    if args.probe_gemm:
+        probe_gemm()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -188,7 +240,11 @@ def main():
             "peak": PEAK["fp64_mfma_tflops"],
             "unit": "TFLOP/s",
             "frac": lu_tflops / PEAK["fp64_mfma_tflops"],
-            "traffic": None,
+            "traffic": load_traffic(),
+            "traffic_note": "HBM bytes per launch of the largest trailing update (M=N=K=2048, "
+                            "16 matrices; algorithmic %.3g B) from FETCH_SIZE + WRITE_SIZE "
+                            "counters scaled by a 1 GiB copy; see profiles/" % (
+                                16.0 * 16 * (3 * 2048 * 2048 + 2048 * 2048)),
             "launches_per_step": lu["launches"] / args.steps,
             "avg_launch_us": lu["ms"] * 1e3 / max(lu["launches"], 1),
             "flops_per_step": lu["flops"] / args.steps,

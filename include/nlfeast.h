@@ -173,6 +173,23 @@ nlfeast_status nlf_getrs_batched(int32_t dtype, int64_t n, int32_t nrhs, int32_t
                                  int64_t strideB, void* X_dev, int64_t ldx, int64_t strideX,
                                  void* stream);
 
+/* Explicit inverses of the 256 x 256 diagonal blocks of the L and U factors written by
+ * nlf_getrf_batched (same dtype): per matrix nlf_lu_inverse_elems(n) complex elements at
+ * dinv_dev + b * nlf_lu_inverse_elems(n) (block q: L_qq^{-1} then U_qq^{-1}, each 256 x 256,
+ * leading dimension 256).  Computed once per factorisation for nlf_getrs_batched_inv. */
+int64_t nlf_lu_inverse_elems(int64_t n);
+nlfeast_status nlf_lu_block_inverses(int32_t dtype, int64_t n, int32_t batch, const void* LU_dev,
+                                     int64_t lda, int64_t strideA, void* dinv_dev, void* stream);
+
+/* As nlf_getrs_batched, with the triangular solves done block by block: X_q = L_qq^{-1} X_q and
+ * a rank-256 update of the rows below (then the same upwards with U), every step a batched
+ * MFMA GEMM.  dinv_dev from nlf_lu_block_inverses; tmp_dev: 256 * nrhs * batch elements. */
+nlfeast_status nlf_getrs_batched_inv(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                     const void* LU_dev, int64_t lda, int64_t strideA,
+                                     const int32_t* perm_dev, const void* dinv_dev,
+                                     const void* B_dev, int64_t ldb, int64_t strideB, void* X_dev,
+                                     int64_t ldx, int64_t strideX, void* tmp_dev, void* stream);
+
 /* C_b = alpha op(A_b) op(B_b) + beta C_b, complex (dtype c128 or c64), op 'N' or 'C'
  * (conjugate transpose); alpha, beta: 2 doubles each (host).  The MFMA GEMM used by every
  * dense contraction of the path. */

@@ -72,6 +72,10 @@ _SIGS = {
     "nlf_getrf_batched": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "nlf_getrs_batched": (c_i32, [c_i32, c_i64, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp,
                                   c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
+    "nlf_lu_inverse_elems": (c_i64, [c_i64]),
+    "nlf_lu_block_inverses": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "nlf_getrs_batched_inv": (c_i32, [c_i32, c_i64, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp,
+                                      c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp]),
     "nlf_gemm_batched": (c_i32, [c_i32, ctypes.c_char, ctypes.c_char, c_i64, c_i64, c_i64, P_dbl,
                                  c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, P_dbl, c_vp, c_i64, c_i64,
                                  c_i32, c_vp]),
@@ -274,6 +278,30 @@ def nlf_getrs_batched(LU, perm, B, X, shared_rhs=False, stream=None):
     sB = 0 if shared_rhs else n * nrhs
     _check(lib().nlf_getrs_batched(dtype, n, nrhs, batch, _ptr(LU), n, n * n, _ptr(perm), _ptr(B),
                                    n, sB, _ptr(X), n, n * nrhs, _stream(stream)))
+
+
+def nlf_lu_inverse_elems(n):
+    return lib().nlf_lu_inverse_elems(n)
+
+
+def nlf_lu_block_inverses(LU, dinv, stream=None):
+    """LU: (batch, n, n) factors from nlf_getrf_batched; dinv: batch * nlf_lu_inverse_elems(n)."""
+    import torch
+    dtype = NLF_C128 if LU.dtype == torch.complex128 else NLF_C64
+    batch, n = LU.shape[0], LU.shape[-1]
+    _check(lib().nlf_lu_block_inverses(dtype, n, batch, _ptr(LU), n, n * n, _ptr(dinv),
+                                       _stream(stream)))
+
+
+def nlf_getrs_batched_inv(LU, perm, dinv, B, X, tmp, shared_rhs=False, stream=None):
+    import torch
+    dtype = NLF_C128 if LU.dtype == torch.complex128 else NLF_C64
+    batch, n = LU.shape[0], LU.shape[-1]
+    nrhs = X.shape[-2]
+    sB = 0 if shared_rhs else n * nrhs
+    _check(lib().nlf_getrs_batched_inv(dtype, n, nrhs, batch, _ptr(LU), n, n * n, _ptr(perm),
+                                       _ptr(dinv), _ptr(B), n, sB, _ptr(X), n, n * nrhs, _ptr(tmp),
+                                       _stream(stream)))
 
 
 def nlf_gemm_batched(opA, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,

@@ -30,6 +30,17 @@ void getrs(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64
            int64_t sA, const int32_t* perm, const Cx<R>* B, int64_t ldb, int64_t sB, Cx<R>* X,
            int64_t ldx, int64_t sX);
 
+// Explicit inverses of the 256 x 256 diagonal blocks of the L and U factors (once per
+// factorisation), and the triangular solves built on them (one batched GEMM per block step).
+int64_t lu_inverse_elems(int64_t n);     // per matrix
+template <typename R>
+void lu_block_inverses(hipStream_t s, int64_t n, int batch, const Cx<R>* LU, int64_t lda,
+                       int64_t sA, Cx<R>* dinv);
+template <typename R>
+void getrs_inv(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+               int64_t sA, const int32_t* perm, const Cx<R>* dinv, const Cx<R>* B, int64_t ldb,
+               int64_t sB, Cx<R>* X, int64_t ldx, int64_t sX, Cx<R>* tmp);   // tmp: 256 x nrhs per matrix
+
 // In-place triangular solves B <- L^{-1} B (unit lower) and B <- U^{-1} B (upper).
 template <typename R>
 void trsm_lower_unit(hipStream_t s, int64_t n, int64_t N, int batch, const Cx<R>* L,

@@ -24,6 +24,7 @@ namespace nlf {
 constexpr int PANEL_NT = 1024;
 constexpr int PANEL_WMAX = 32;
 constexpr int TRSM_NB = 64;
+constexpr int64_t LU_INV_NB = 256;   // diagonal block order of the explicit L/U block inverses
 constexpr int TRSM_CB = 8;      // right-hand-side columns per wavefront in the TRSM leaf
 
 template <typename R>
@@ -389,6 +390,29 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int64_t nco
     }
 }
 
+// Identity in every s x s block of a strided set (the right-hand sides of the block inversion).
+template <typename R>
+__global__ __launch_bounds__(256) void identity_blocks_kernel(int64_t s, int64_t ld, int64_t count,
+                                                              int64_t stride, Cx<R>* out) {
+    const int64_t per = s * s, total = per * count;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t q = e / per, r = e % per;
+        const int64_t i = r % s, j = r / s;
+        out[q * stride + i + j * ld] = Cx<R>(i == j ? R(1) : R(0), R(0));
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void copy_batched_kernel(int64_t rows, int64_t cols,
+                                                           const Cx<R>* in, int64_t ldi, int64_t si,
+                                                           Cx<R>* out, int64_t ldo, int64_t so) {
+    const int64_t b = blockIdx.y, total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % rows, c = e / rows;
+        out[b * so + i + c * ldo] = in[b * si + i + c * ldi];
+    }
+}
+
 // ------------------------------------------------------------------------------ host side
 
 template <typename R>
@@ -545,6 +569,95 @@ void getrs(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64
     trsm_lower_unit<R>(s, n, nrhs, batch, LU, lda, sA, X, ldx, sX);
     trsm_upper<R>(s, n, nrhs, batch, LU, lda, sA, X, ldx, sX);
 }
+
+int64_t lu_inverse_elems(int64_t n) {
+    const int64_t nblk = ceil_div(n, LU_INV_NB);
+    return nblk * 2 * LU_INV_NB * LU_INV_NB;
+}
+
+// Explicit inverses of the LU_INV_NB x LU_INV_NB diagonal blocks of L (unit lower) and U, per
+// matrix: block b of matrix q holds L_bb^{-1} at dinv + q * lu_inverse_elems(n) + 2 b NB^2 and
+// U_bb^{-1} NB^2 further, each NB x NB with leading dimension NB.  Solved as L_bb X = I and
+// U_bb X = I with the recursive triangular solves, batched over the matrices.
+template <typename R>
+void lu_block_inverses(hipStream_t s, int64_t n, int batch, const Cx<R>* LU, int64_t lda,
+                       int64_t sA, Cx<R>* dinv) {
+    const int64_t NB = LU_INV_NB, nblk = ceil_div(n, NB), per = lu_inverse_elems(n);
+    {
+        const int64_t total = NB * NB * 2 * nblk * batch;
+        hipLaunchKernelGGL((identity_blocks_kernel<R>), dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)),
+                           dim3(256), 0, s, NB, NB, 2 * nblk * batch, NB * NB, dinv);
+        NLF_HIP(hipGetLastError());
+    }
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t s0 = b * NB, sb = std::min<int64_t>(NB, n - s0);
+        const Cx<R>* D = LU + s0 + s0 * lda;
+        trsm_lower_unit<R>(s, sb, sb, batch, D, lda, sA, dinv + 2 * b * NB * NB, NB, per);
+        trsm_upper<R>(s, sb, sb, batch, D, lda, sA, dinv + (2 * b + 1) * NB * NB, NB, per);
+    }
+}
+
+// X_b = A_b^{-1} B_b with the block inverses: forward substitution X_i = Linv_i X_i followed by
+// the rank-NB update of the rows below (right-looking), then the same upwards with U.  Every
+// step is a batched MFMA GEMM; tmp holds NB x nrhs per matrix.
+template <typename R>
+void getrs_inv(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+               int64_t sA, const int32_t* perm, const Cx<R>* dinv, const Cx<R>* B, int64_t ldb,
+               int64_t sB, Cx<R>* X, int64_t ldx, int64_t sX, Cx<R>* tmp) {
+    if (n <= 0 || nrhs <= 0 || batch <= 0) return;
+    const int64_t NB = LU_INV_NB, nblk = ceil_div(n, NB), per = lu_inverse_elems(n);
+    const int64_t st = NB * nrhs;
+    const Cx<R> one(1, 0), mone(-1, 0), zero(0, 0);
+    {
+        ProfScope ps(trsm_class(), s, 0, 2.0 * n * nrhs * sizeof(Cx<R>) * batch);
+        const int64_t total = n * nrhs;
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), batch);
+        hipLaunchKernelGGL((gather_rows_kernel<R>), grid, dim3(256), 0, s, n, (int64_t)nrhs, perm, B,
+                           ldb, sB, X, ldx, sX);
+        NLF_HIP(hipGetLastError());
+    }
+    auto solve_block = [&](int64_t b, bool upper) {
+        const int64_t s0 = b * NB, sb = std::min<int64_t>(NB, n - s0);
+        const Cx<R>* Dinv = dinv + (2 * b + (upper ? 1 : 0)) * NB * NB;
+        ProfScope ps(trsm_class(), s, 8.0 * sb * sb * nrhs * batch, 0);
+        gemm<R>(s, false, sb, nrhs, sb, one, Dinv, NB, per, X + s0, ldx, sX, zero, tmp, NB, st, batch);
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(sb * nrhs, 256), 1024), batch);
+        hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, sb, (int64_t)nrhs,
+                           (const Cx<R>*)tmp, NB, st, X + s0, ldx, sX);
+        NLF_HIP(hipGetLastError());
+    };
+    for (int64_t b = 0; b < nblk; ++b) {
+        solve_block(b, false);
+        const int64_t s1 = (b + 1) * NB;
+        if (s1 < n) {
+            const int64_t sb = std::min<int64_t>(NB, n - b * NB);
+            ProfScope ps(trsm_class(), s, 8.0 * (n - s1) * nrhs * sb * batch, 0);
+            gemm<R>(s, false, n - s1, nrhs, sb, mone, LU + s1 + b * NB * lda, lda, sA, X + b * NB, ldx, sX,
+                    one, X + s1, ldx, sX, batch);
+        }
+    }
+    for (int64_t b = nblk - 1; b >= 0; --b) {
+        solve_block(b, true);
+        const int64_t s0 = b * NB;
+        if (s0 > 0) {
+            const int64_t sb = std::min<int64_t>(NB, n - s0);
+            ProfScope ps(trsm_class(), s, 8.0 * s0 * nrhs * sb * batch, 0);
+            gemm<R>(s, false, s0, nrhs, sb, mone, LU + s0 * lda, lda, sA, X + s0, ldx, sX, one, X, ldx, sX,
+                    batch);
+        }
+    }
+}
+
+template void lu_block_inverses<double>(hipStream_t, int64_t, int, const Cx<double>*, int64_t, int64_t,
+                                        Cx<double>*);
+template void lu_block_inverses<float>(hipStream_t, int64_t, int, const Cx<float>*, int64_t, int64_t,
+                                       Cx<float>*);
+template void getrs_inv<double>(hipStream_t, int64_t, int, int, const Cx<double>*, int64_t, int64_t,
+                                const int32_t*, const Cx<double>*, const Cx<double>*, int64_t, int64_t,
+                                Cx<double>*, int64_t, int64_t, Cx<double>*);
+template void getrs_inv<float>(hipStream_t, int64_t, int, int, const Cx<float>*, int64_t, int64_t,
+                               const int32_t*, const Cx<float>*, const Cx<float>*, int64_t, int64_t,
+                               Cx<float>*, int64_t, int64_t, Cx<float>*);
 
 template void getrf<double>(hipStream_t, int64_t, int, Cx<double>*, int64_t, int64_t, int32_t*,
                             int32_t*, int32_t*, int32_t*);

@@ -147,7 +147,7 @@ namespace {
 
 struct Layout {
     size_t total = 0;
-    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0;
+    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, stmp = 0;
     size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
     size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0,
            coef = 0;
@@ -181,6 +181,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
     L.perm = take(sizeof(int32_t) * n * L.NZ);
     L.info = take(sizeof(int32_t) * L.NZ);
     L.list = take(sizeof(int32_t) * getrf_scratch_ints(n, L.NZ));
+    L.dinv = take((size_t)lu_inverse_elems(n) * L.NZ * (p32 ? 8 : 16));
     const size_t blk = (size_t)n * L.mmax;
     L.Q = take(16 * blk);
     L.X = take(16 * blk);
@@ -188,6 +189,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
     L.R = take(16 * blk);
     L.Ys = take(16 * blk * L.ncmax);
     L.QT = take(16 * blk);
+    L.stmp = take((size_t)256 * L.mmax * L.ncmax * (p32 ? 8 : 16));
     if (p32) {
         L.R32 = take(8 * blk);
         L.Y32 = take(8 * blk * L.ncmax);
@@ -439,6 +441,10 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             else
                 getrf<double>(s, n, L.NZ, at<z128>(ws, L.fact), n, (int64_t)nn, at<int32_t>(ws, L.ipiv),
                               at<int32_t>(ws, L.perm), at<int32_t>(ws, L.info), at<int32_t>(ws, L.list));
+            if (p32)
+                lu_block_inverses<float>(s, n, L.NZ, at<z64>(ws, L.fact), n, (int64_t)nn, at<z64>(ws, L.dinv));
+            else
+                lu_block_inverses<double>(s, n, L.NZ, at<z128>(ws, L.fact), n, (int64_t)nn, at<z128>(ws, L.dinv));
             std::vector<int32_t> info(L.NZ);
             d2h_sync(s, info.data(), at<void>(ws, L.info), sizeof(int32_t) * L.NZ);
             for (int q = 0; q < L.NZ; ++q)
@@ -487,6 +493,9 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
             const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
             const int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)node0 * n;
+            const int64_t dper = lu_inverse_elems(n);
+            const z128* D128 = at<z128>(ws, L.dinv) + (size_t)node0 * dper;
+            const z64* D64 = at<z64>(ws, L.dinv) + (size_t)node0 * dper;
             while (true) {
                 // Step 1: projections and the reduced problem
                 project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, L.splitws_elems);
@@ -540,7 +549,8 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                 {
                     TrsmClassGuard tg(NLF_PROF_SOLVE);
                     if (!p32) {
-                        getrs<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, R, n, 0, Ys, n, (int64_t)blk);
+                        getrs_inv<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, D128, R, n, 0, Ys, n,
+                                          (int64_t)blk, at<z128>(ws, L.stmp));
                     } else {
                         z64* R32 = at<z64>(ws, L.R32);
                         z64* Y32 = at<z64>(ws, L.Y32);
@@ -548,7 +558,8 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                         z64* E32 = at<z64>(ws, L.E32);
                         const z128* T64 = at<z128>(ws, L.t64) + (size_t)node0 * nn;
                         cast_128_to_64(s, n, m, 1, R, n, 0, R32, n, 0);
-                        getrs<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, R32, n, 0, Y32, n, (int64_t)blk);
+                        getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, Y32, n,
+                                         (int64_t)blk, at<z64>(ws, L.stmp));
                         cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
                         double rn2 = 0.0;
                         for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
@@ -565,8 +576,8 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                             for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);
                             if (worst <= opt->refine_eta * opt->refine_eta * rn2) break;
                             cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
-                            getrs<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, E32, n, (int64_t)blk, Y32, n,
-                                         (int64_t)blk);
+                            getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
+                                             Y32, n, (int64_t)blk, at<z64>(ws, L.stmp));
                             cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, true);
                         }
                     }
@@ -678,6 +689,48 @@ nlfeast_status nlf_getrs_batched(int32_t dtype, int64_t n, int32_t nrhs, int32_t
         else
             getrs<float>(as_stream(stream), n, nrhs, batch, (const z64*)LU_dev, lda, strideA, perm_dev,
                          (const z64*)B_dev, ldb, strideB, (z64*)X_dev, ldx, strideX);
+        return NLF_OK;
+    })
+}
+
+int64_t nlf_lu_inverse_elems(int64_t n) { return n > 0 ? lu_inverse_elems(n) : 0; }
+
+nlfeast_status nlf_lu_block_inverses(int32_t dtype, int64_t n, int32_t batch, const void* LU_dev,
+                                     int64_t lda, int64_t strideA, void* dinv_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && batch >= 1 && LU_dev && dinv_dev && lda >= n && strideA >= lda * n &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_lu_block_inverses: bad arguments");
+        TrsmClassGuard tg(NLF_PROF_TRSM);
+        if (dtype == NLF_C128)
+            lu_block_inverses<double>(as_stream(stream), n, batch, (const z128*)LU_dev, lda, strideA, (z128*)dinv_dev);
+        else
+            lu_block_inverses<float>(as_stream(stream), n, batch, (const z64*)LU_dev, lda, strideA, (z64*)dinv_dev);
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_getrs_batched_inv(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                     const void* LU_dev, int64_t lda, int64_t strideA,
+                                     const int32_t* perm_dev, const void* dinv_dev,
+                                     const void* B_dev, int64_t ldb, int64_t strideB, void* X_dev,
+                                     int64_t ldx, int64_t strideX, void* tmp_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && nrhs >= 1 && batch >= 1 && LU_dev && perm_dev && dinv_dev && B_dev && X_dev &&
+                        tmp_dev && lda >= n && ldb >= n && ldx >= n && strideB >= 0 && strideX >= ldx * nrhs &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_getrs_batched_inv: bad arguments");
+        TrsmClassGuard tg(NLF_PROF_SOLVE);
+        if (dtype == NLF_C128)
+            getrs_inv<double>(as_stream(stream), n, nrhs, batch, (const z128*)LU_dev, lda, strideA, perm_dev,
+                              (const z128*)dinv_dev, (const z128*)B_dev, ldb, strideB, (z128*)X_dev, ldx, strideX,
+                              (z128*)tmp_dev);
+        else
+            getrs_inv<float>(as_stream(stream), n, nrhs, batch, (const z64*)LU_dev, lda, strideA, perm_dev,
+                             (const z64*)dinv_dev, (const z64*)B_dev, ldb, strideB, (z64*)X_dev, ldx, strideX,
+                             (z64*)tmp_dev);
         return NLF_OK;
     })
 }

@@ -154,6 +154,31 @@ def test_getrs_matches_solve(dtype, n, nrhs, batch):
         assert rel(nl.from_colmajor(X[b]), ref) < tol
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,nrhs,batch", [(100, 7, 2), (300, 64, 3), (700, 20, 2), (1000, 33, 1)])
+def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
+    # n spans one partial 256-block, several blocks and a ragged last block
+    rng = np.random.default_rng(n + 3 * nrhs)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    mats = [wl.cn(rng, (n, n)) + 3 * np.eye(n) for _ in range(batch)]
+    B = wl.cn(rng, (n, nrhs))
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(A, ipiv, perm, info)
+    dinv = torch.empty(batch * nl.nlf_lu_inverse_elems(n), dtype=dt, device="cuda")
+    nl.nlf_lu_block_inverses(A, dinv)
+    X = torch.empty((batch, nrhs, n), dtype=dt, device="cuda")
+    tmp = torch.empty(batch * 256 * nrhs, dtype=dt, device="cuda")
+    nl.nlf_getrs_batched_inv(A, perm, dinv, dev(B, dt), X, tmp, shared_rhs=True)
+    torch.cuda.synchronize()
+    tol = 1e-11 if dtype == "c128" else 2e-3
+    for b in range(batch):
+        ref = np.linalg.solve(mats[b], B)
+        assert rel(nl.from_colmajor(X[b]), ref) < tol
+
+
 def test_getrf_large_backward_error():
     # n = 4096: several recursion levels, 4 rows per panel thread, full-size panels
     n, batch = 4096, 2
@@ -167,13 +192,19 @@ def test_getrf_large_backward_error():
     B = wl.cn(rng, (n, 8))
     X = torch.empty((batch, 8, n), dtype=torch.complex128, device="cuda")
     nl.nlf_getrs_batched(A, perm, dev(B), X, shared_rhs=True)
+    dinv = torch.empty(batch * nl.nlf_lu_inverse_elems(n), dtype=torch.complex128, device="cuda")
+    nl.nlf_lu_block_inverses(A, dinv)
+    X2 = torch.empty((batch, 8, n), dtype=torch.complex128, device="cuda")
+    tmp = torch.empty(batch * 256 * 8, dtype=torch.complex128, device="cuda")
+    nl.nlf_getrs_batched_inv(A, perm, dinv, dev(B), X2, tmp, shared_rhs=True)
     torch.cuda.synchronize()
     assert info.cpu().numpy().tolist() == [0, 0]
     for b in range(batch):
-        x = nl.from_colmajor(X[b])
-        r = mats[b] @ x - B
-        berr = np.linalg.norm(r) / (np.linalg.norm(mats[b]) * np.linalg.norm(x) + np.linalg.norm(B))
-        assert berr < 1e-14, berr
+        for XX in (X, X2):
+            x = nl.from_colmajor(XX[b])
+            r = mats[b] @ x - B
+            berr = np.linalg.norm(r) / (np.linalg.norm(mats[b]) * np.linalg.norm(x) + np.linalg.norm(B))
+            assert berr < 1e-14, berr
         assert np.array_equal(np.sort(perm[b].cpu().numpy()), np.arange(n))
 
 
