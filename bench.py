@@ -33,6 +33,10 @@ def parse():
     ap.add_argument("--workload", default="damped4096")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--panel-width", type=int, default=0,
+                    help="LU panel width per workgroup, 4..32 (0 = library default)")
+    ap.add_argument("--lu-streams", type=int, default=0,
+                    help="node-matrix groups factored on separate streams (0 = library default)")
     ap.add_argument("--probe-gemm", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration), then the dominant "
                          "LU trailing-update GEMM shape three times, nothing else")
@@ -109,7 +113,8 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile):
     S.set_coeffs(terms, dmats)
     S.set_contour(regions)
     X0d = nl.to_colmajor(X0, "cuda:0")
-    opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3)
+    opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3,
+                      lu_streams=args.lu_streams, panel_width=args.panel_width)
     for _ in range(args.warmup):
         S.set_contour(regions)
         S.solve(opts, X0d)

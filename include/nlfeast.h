@@ -75,6 +75,10 @@ typedef struct {
     uint64_t seed;               /* X0 when the caller passes none (counter-based normal draws) */
     int32_t autotune;            /* 1: time the GEMM tile variants on first use of a shape */
     int32_t verbose;             /* 1: one line per iteration on stderr */
+    int32_t lu_streams;          /* factor the node matrices in this many groups on separate
+                                    streams (1..4; 0 = default, one stream), so that one group's
+                                    panel factorisations overlap another group's GEMMs */
+    int32_t panel_width;         /* columns per single-workgroup panel of the LU, 4..32 (0 = 32) */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -161,6 +165,16 @@ nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const do
 nlfeast_status nlf_getrf_batched(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
                                  int64_t lda, int64_t strideA, int32_t* ipiv_dev,
                                  int32_t* perm_dev, int32_t* info_dev, void* stream);
+
+/* The same factorisation computed right-looking with 256-column panels (each panel factored as
+ * above, U12 = L11^{-1} A12 by a GEMM with the explicit inverse, rank-256 trailing updates on
+ * MFMA); it also writes the diagonal-block inverses that nlf_lu_block_inverses would
+ * (dinv_dev: batch * nlf_lu_inverse_elems(n) elements).  Temporary device memory of
+ * 256 * (n - 256) elements per matrix is allocated on the stream for the call. */
+nlfeast_status nlf_getrf_batched_blocked(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
+                                         int64_t lda, int64_t strideA, int32_t* ipiv_dev,
+                                         int32_t* perm_dev, int32_t* info_dev, void* dinv_dev,
+                                         void* stream);
 
 /* X_b = A_b^{-1} B_b from nlf_getrf_batched factors (same dtype), nrhs columns.  B_dev
  * (ldb, strideB; strideB = 0 shares one right-hand side across the batch) is read, X_dev

@@ -42,12 +42,14 @@ class Options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("max_refine", ctypes.c_int32),
                 ("refine_eta", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("autotune", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("lu_streams", ctypes.c_int32), ("panel_width", ctypes.c_int32)]
 
 
 def options(tol=1e-10, max_iter=50, precision=NLF_PREC_FP64, max_refine=5, refine_eta=1e-3,
-            seed=2024, autotune=0, verbose=0):
-    return Options(tol, max_iter, precision, max_refine, refine_eta, seed, autotune, verbose)
+            seed=2024, autotune=0, verbose=0, lu_streams=0, panel_width=0):
+    return Options(tol, max_iter, precision, max_refine, refine_eta, seed, autotune, verbose,
+                   lu_streams, panel_width)
 
 
 _lib = None
@@ -70,6 +72,8 @@ _SIGS = {
     "nlf_assemble": (c_i32, [c_i64, c_i32, P_i32, P_dbl, P_vp, c_i64, c_i32, P_dbl, c_vp, c_vp,
                              c_i64, c_i64, c_vp]),
     "nlf_getrf_batched": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "nlf_getrf_batched_blocked": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp,
+                                          c_vp, c_vp]),
     "nlf_getrs_batched": (c_i32, [c_i32, c_i64, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp,
                                   c_i64, c_i64, c_vp, c_i64, c_i64, c_vp]),
     "nlf_lu_inverse_elems": (c_i64, [c_i64]),
@@ -267,6 +271,16 @@ def nlf_getrf_batched(A, ipiv, perm, info, stream=None):
     batch, n = A.shape[0], A.shape[-1]
     _check(lib().nlf_getrf_batched(dtype, n, batch, _ptr(A), n, n * n, _ptr(ipiv), _ptr(perm),
                                    _ptr(info), _stream(stream)))
+
+
+def nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv, stream=None):
+    """Right-looking blocked LU of (batch, n, n) column-major matrices, in place; also writes the
+    diagonal-block inverses (batch * nlf_lu_inverse_elems(n) elements) into dinv."""
+    import torch
+    dtype = NLF_C128 if A.dtype == torch.complex128 else NLF_C64
+    batch, n = A.shape[0], A.shape[-1]
+    _check(lib().nlf_getrf_batched_blocked(dtype, n, batch, _ptr(A), n, n * n, _ptr(ipiv), _ptr(perm),
+                                           _ptr(info), _ptr(dinv), _stream(stream)))
 
 
 def nlf_getrs_batched(LU, perm, B, X, shared_rhs=False, stream=None):

@@ -66,6 +66,21 @@ __device__ __forceinline__ int xcd_remap(int w, int nT) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
+// Tile order inside an XCD's range: groups of GROUP_M tile rows are swept column by column, so
+// the workgroups resident on one XCD at a time cover a roughly square patch of C and share the
+// K-slices of A and B in that XCD's L2 (a plain column-major order would pair all tile rows
+// with only a couple of tile columns).
+constexpr int GROUP_M = 8;
+__device__ __forceinline__ void tile_coords(int t, int tilesM, int tilesN, int& tm, int& tn) {
+    const int per_group = GROUP_M * tilesN;
+    const int group = t / per_group;
+    const int first = group * GROUP_M;
+    const int gsize = min(tilesM - first, GROUP_M);
+    const int r = t - group * per_group;
+    tm = first + r % gsize;
+    tn = r / gsize;
+}
+
 // Global -> register staging of one K step.  A thread loads LA elements of op(A) and LB of B;
 // element e of the thread sits at (row, k) = (a_r[e], a_k[e]) of the BM x BK tile of op(A)
 // and (b_k[e], b_n[e]) of the BK x BN tile of B.
@@ -131,8 +146,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int nT = g.tilesM * g.tilesN;
-    const int tile = xcd_remap(blockIdx.x, nT);
-    const int tm = tile % g.tilesM, tn = tile / g.tilesM;
+    int tm, tn;
+    tile_coords(xcd_remap(blockIdx.x, nT), g.tilesM, g.tilesN, tm, tn);
     const int64_t batch = blockIdx.y;
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 

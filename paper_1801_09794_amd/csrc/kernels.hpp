@@ -17,10 +17,17 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
           Cx<R> beta, Cx<R>* C, int64_t ldc, int64_t sC, int batch, Cx<R>* ws = nullptr,
           int64_t ws_elems = 0, const GemmConfig* force = nullptr);
 
-// Blocked recursive LU with partial pivoting (in place), batched over strided matrices.
+// LU with partial pivoting (in place), batched over strided matrices.  With dinv and tmp
+// (getrf_tmp_elems per matrix) it runs right-looking with 256-column panels and leaves the
+// explicit inverses of the diagonal blocks of L and U in dinv (as lu_block_inverses does);
+// without them it is the plain column-halving recursion.
+int64_t getrf_tmp_elems(int64_t n);
+// Width of the panels factored by one workgroup (4..32, default 32); set per calling thread.
+int& lu_panel_width();
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
-           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch);
+           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch,
+           Cx<R>* dinv = nullptr, Cx<R>* tmp = nullptr);
 // Scratch (int32 elements) that getrf needs for its row-exchange lists.
 int64_t getrf_scratch_ints(int64_t n, int batch);
 

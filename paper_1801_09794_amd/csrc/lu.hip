@@ -511,15 +511,21 @@ static void laswp(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_t sA, i
     NLF_HIP(hipGetLastError());
 }
 
+int& lu_panel_width() {
+    static thread_local int w = PANEL_WMAX;
+    return w;
+}
+
 template <typename R>
 static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
                       int64_t k0, int64_t nc, int32_t* ipiv, int32_t* info, int32_t* list) {
-    if (nc <= PANEL_WMAX) {
+    const int pw = std::max(4, std::min(lu_panel_width(), PANEL_WMAX));
+    if (nc <= pw) {
         launch_panel<R>(s, batch, A, lda, sA, n, k0, (int)nc, ipiv, info);
         return;
     }
-    int64_t n1 = (nc / 2) / PANEL_WMAX * PANEL_WMAX;
-    if (n1 < PANEL_WMAX) n1 = PANEL_WMAX;
+    int64_t n1 = (nc / 2) / pw * pw;
+    if (n1 < pw) n1 = pw;
     const int64_t n2 = nc - n1;
     getrf_rec<R>(s, n, batch, A, lda, sA, k0, n1, ipiv, info, list);
     laswp<R>(s, batch, A, lda, sA, n, k0, k0 + n1, k0 + n1, n2, ipiv, list);
@@ -539,13 +545,73 @@ static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda
 
 int64_t getrf_scratch_ints(int64_t n, int batch) { return (int64_t)batch * 2 * (2 * n); }
 
+// I in the two NB x NB blocks at p + q * per and p + q * per + NB^2, q < batch.
+template <typename R>
+static void identity_pair(hipStream_t s, int batch, int64_t NB, int64_t per, Cx<R>* p) {
+    for (int h = 0; h < 2; ++h) {
+        const int64_t total = NB * NB * batch;
+        hipLaunchKernelGGL((identity_blocks_kernel<R>), dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 4096)),
+                           dim3(256), 0, s, NB, NB, (int64_t)batch, per, p + h * NB * NB);
+        NLF_HIP(hipGetLastError());
+    }
+}
+
+// Right-looking blocked LU with LU_INV_NB-column panels.  Per panel k:
+//   factor the panel (rows k0.., recursive LU above) and apply its exchanges to the columns
+//   left and right of it; invert the diagonal blocks L11 and U11 (kept for the solves: later
+//   exchanges only touch rows below the block, so both are final here);
+//   U12 = L11^{-1} A12 as a GEMM with the explicit inverse; A22 -= A21 U12 (rank-256 GEMM).
+// tmp holds LU_INV_NB x (n - LU_INV_NB) elements per matrix.
+template <typename R>
+static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
+                          int32_t* ipiv, int32_t* info, int32_t* list, Cx<R>* dinv, Cx<R>* tmp) {
+    const int64_t NB = LU_INV_NB, per = lu_inverse_elems(n);
+    const int64_t st = NB * std::max<int64_t>(n - NB, 1);
+    const Cx<R> one(1, 0), mone(-1, 0), zero(0, 0);
+    for (int64_t k0 = 0; k0 < n; k0 += NB) {
+        const int64_t kb = std::min<int64_t>(NB, n - k0), k1 = k0 + kb, rest = n - k1;
+        getrf_rec<R>(s, n, batch, A, lda, sA, k0, kb, ipiv, info, list);
+        laswp<R>(s, batch, A, lda, sA, n, k0, k1, 0, k0, ipiv, list);
+        laswp<R>(s, batch, A, lda, sA, n, k0, k1, k1, rest, ipiv, list);
+        const int64_t b = k0 / NB;
+        Cx<R>* Li = dinv + 2 * b * NB * NB;
+        Cx<R>* Ui = Li + NB * NB;
+        identity_pair<R>(s, batch, NB, per, Li);
+        const Cx<R>* D = A + k0 + k0 * lda;
+        trsm_lower_unit<R>(s, kb, kb, batch, D, lda, sA, Li, NB, per);
+        trsm_upper<R>(s, kb, kb, batch, D, lda, sA, Ui, NB, per);
+        if (rest > 0) {
+            Cx<R>* A12 = A + k0 + k1 * lda;
+            {
+                dim3 grid((unsigned)std::min<int64_t>(ceil_div(kb * rest, 256), 2048), batch);
+                hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, kb, rest,
+                                   (const Cx<R>*)A12, lda, sA, tmp, NB, st);
+                NLF_HIP(hipGetLastError());
+            }
+            {
+                ProfScope ps(NLF_PROF_TRSM, s, 8.0 * kb * rest * kb * batch, 0);
+                gemm<R>(s, false, kb, rest, kb, one, Li, NB, per, tmp, NB, st, zero, A12, lda, sA, batch);
+            }
+            ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * rest * kb * batch,
+                         sizeof(Cx<R>) * (2.0 * rest * rest + 2.0 * rest * kb) * batch);
+            gemm<R>(s, false, rest, rest, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
+                    A + k1 + k1 * lda, lda, sA, batch);
+        }
+    }
+}
+
+int64_t getrf_tmp_elems(int64_t n) { return LU_INV_NB * std::max<int64_t>(n - LU_INV_NB, 1); }
+
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
-           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch) {
+           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch, Cx<R>* dinv, Cx<R>* tmp) {
     if (n <= 0 || batch <= 0) return;
     NLF_REQUIRE(n <= 8192, 1, "getrf: n > 8192 not supported");
     fill_i32(s, info, batch, 0);
-    getrf_rec<R>(s, n, batch, A, lda, sA, 0, n, ipiv, info, scratch);
+    if (dinv && tmp)
+        getrf_blocked<R>(s, n, batch, A, lda, sA, ipiv, info, scratch, dinv, tmp);
+    else
+        getrf_rec<R>(s, n, batch, A, lda, sA, 0, n, ipiv, info, scratch);
     if (perm) {
         hipLaunchKernelGGL(perm_kernel, dim3(batch), dim3(1024), (size_t)n * sizeof(int), s, n,
                            (const int32_t*)ipiv, perm);
@@ -660,9 +726,9 @@ template void getrs_inv<float>(hipStream_t, int64_t, int, int, const Cx<float>*,
                                Cx<float>*, int64_t, int64_t, Cx<float>*);
 
 template void getrf<double>(hipStream_t, int64_t, int, Cx<double>*, int64_t, int64_t, int32_t*,
-                            int32_t*, int32_t*, int32_t*);
+                            int32_t*, int32_t*, int32_t*, Cx<double>*, Cx<double>*);
 template void getrf<float>(hipStream_t, int64_t, int, Cx<float>*, int64_t, int64_t, int32_t*,
-                           int32_t*, int32_t*, int32_t*);
+                           int32_t*, int32_t*, int32_t*, Cx<float>*, Cx<float>*);
 template void getrs<double>(hipStream_t, int64_t, int, int, const Cx<double>*, int64_t, int64_t,
                             const int32_t*, const Cx<double>*, int64_t, int64_t, Cx<double>*,
                             int64_t, int64_t);

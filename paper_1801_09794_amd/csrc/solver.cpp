@@ -141,13 +141,22 @@ struct nlfeast_ctx {
     int factors_prec = -1;
     bool profiling = false;
     Profiler prof;
+    hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};   // factorisation streams
+    hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~nlfeast_ctx() {
+        for (int i = 0; i < 4; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+    }
 };
 
 namespace {
 
 struct Layout {
     size_t total = 0;
-    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, stmp = 0;
+    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, stmp = 0, ftmp = 0;
     size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
     size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0,
            coef = 0;
@@ -182,6 +191,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
     L.info = take(sizeof(int32_t) * L.NZ);
     L.list = take(sizeof(int32_t) * getrf_scratch_ints(n, L.NZ));
     L.dinv = take((size_t)lu_inverse_elems(n) * L.NZ * (p32 ? 8 : 16));
+    L.ftmp = take((size_t)getrf_tmp_elems(n) * L.NZ * (p32 ? 8 : 16));
     const size_t blk = (size_t)n * L.mmax;
     L.Q = take(16 * blk);
     L.X = take(16 * blk);
@@ -403,6 +413,14 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         NLF_REQUIRE(opt->precision == NLF_PREC_FP64 || opt->precision == NLF_PREC_FP32_REFINE,
                     NLF_ERR_ARG, "solve: bad precision");
         NLF_REQUIRE(opt->tol > 0 && opt->max_iter >= 1, NLF_ERR_ARG, "solve: need tol > 0, max_iter >= 1");
+        NLF_REQUIRE(opt->lu_streams >= 0 && opt->lu_streams <= 4, NLF_ERR_ARG, "solve: lu_streams in 0..4");
+        NLF_REQUIRE(opt->panel_width == 0 || (opt->panel_width >= 4 && opt->panel_width <= 32), NLF_ERR_ARG,
+                    "solve: panel_width 0 or 4..32");
+        struct PanelGuard {
+            int saved;
+            explicit PanelGuard(int w) : saved(lu_panel_width()) { if (w) lu_panel_width() = w; }
+            ~PanelGuard() { lu_panel_width() = saved; }
+        } panel_guard(opt->panel_width);
         const Layout L = make_layout(h, opt->precision);
         NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
         NLF_HIP(hipSetDevice(h->device));
@@ -435,16 +453,48 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                 assemble(s, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.fact),
                          nullptr, n, (int64_t)nn);
             TrsmClassGuard tg(NLF_PROF_TRSM);
-            if (p32)
-                getrf<float>(s, n, L.NZ, at<z64>(ws, L.fact), n, (int64_t)nn, at<int32_t>(ws, L.ipiv),
-                             at<int32_t>(ws, L.perm), at<int32_t>(ws, L.info), at<int32_t>(ws, L.list));
-            else
-                getrf<double>(s, n, L.NZ, at<z128>(ws, L.fact), n, (int64_t)nn, at<int32_t>(ws, L.ipiv),
-                              at<int32_t>(ws, L.perm), at<int32_t>(ws, L.info), at<int32_t>(ws, L.list));
-            if (p32)
-                lu_block_inverses<float>(s, n, L.NZ, at<z64>(ws, L.fact), n, (int64_t)nn, at<z64>(ws, L.dinv));
-            else
-                lu_block_inverses<double>(s, n, L.NZ, at<z128>(ws, L.fact), n, (int64_t)nn, at<z128>(ws, L.dinv));
+            // groups of node matrices on separate streams: the latency-bound panels of one group
+            // run while the GEMMs of another fill the machine
+            int groups = opt->lu_streams > 0 ? opt->lu_streams : 1;
+            groups = std::max(1, std::min({groups, 4, L.NZ}));
+            if (groups > 1) {
+                if (!h->ev_fork) NLF_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+                NLF_HIP(hipEventRecord(h->ev_fork, s));
+            }
+            const int64_t dper = lu_inverse_elems(n);
+            const int64_t lper = getrf_scratch_ints(n, 1);
+            for (int g = 0; g < groups; ++g) {
+                const int q0 = (int)((int64_t)L.NZ * g / groups), q1 = (int)((int64_t)L.NZ * (g + 1) / groups);
+                if (q1 <= q0) continue;
+                hipStream_t sg = s;
+                if (groups > 1) {
+                    if (!h->side[g]) {
+                        NLF_HIP(hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking));
+                        NLF_HIP(hipEventCreateWithFlags(&h->ev_join[g], hipEventDisableTiming));
+                    }
+                    sg = h->side[g];
+                    NLF_HIP(hipStreamWaitEvent(sg, h->ev_fork, 0));
+                }
+                const int nb = q1 - q0;
+                int32_t* ipiv = at<int32_t>(ws, L.ipiv) + (size_t)q0 * n;
+                int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)q0 * n;
+                int32_t* info = at<int32_t>(ws, L.info) + q0;
+                int32_t* list = at<int32_t>(ws, L.list) + (size_t)q0 * lper;
+                const int64_t tper = getrf_tmp_elems(n);
+                if (p32) {
+                    z64* F = at<z64>(ws, L.fact) + (size_t)q0 * nn;
+                    getrf<float>(sg, n, nb, F, n, (int64_t)nn, ipiv, perm, info, list,
+                                 at<z64>(ws, L.dinv) + (size_t)q0 * dper, at<z64>(ws, L.ftmp) + (size_t)q0 * tper);
+                } else {
+                    z128* F = at<z128>(ws, L.fact) + (size_t)q0 * nn;
+                    getrf<double>(sg, n, nb, F, n, (int64_t)nn, ipiv, perm, info, list,
+                                  at<z128>(ws, L.dinv) + (size_t)q0 * dper, at<z128>(ws, L.ftmp) + (size_t)q0 * tper);
+                }
+                if (groups > 1) {
+                    NLF_HIP(hipEventRecord(h->ev_join[g], sg));
+                    NLF_HIP(hipStreamWaitEvent(s, h->ev_join[g], 0));
+                }
+            }
             std::vector<int32_t> info(L.NZ);
             d2h_sync(s, info.data(), at<void>(ws, L.info), sizeof(int32_t) * L.NZ);
             for (int q = 0; q < L.NZ; ++q)
@@ -666,6 +716,34 @@ nlfeast_status nlf_getrf_batched(int32_t dtype, int64_t n, int32_t batch, void* 
             getrf<double>(s, n, batch, (z128*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list);
         else
             getrf<float>(s, n, batch, (z64*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list);
+        NLF_HIP(hipFreeAsync(list, s));
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_getrf_batched_blocked(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
+                                         int64_t lda, int64_t strideA, int32_t* ipiv_dev,
+                                         int32_t* perm_dev, int32_t* info_dev, void* dinv_dev,
+                                         void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && n <= 8192 && batch >= 1 && A_dev && lda >= n && strideA >= lda * n &&
+                        ipiv_dev && info_dev && dinv_dev && (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_getrf_batched_blocked: bad arguments");
+        hipStream_t s = as_stream(stream);
+        int32_t* list = nullptr;
+        void* tmp = nullptr;
+        const size_t es = dtype == NLF_C128 ? 16 : 8;
+        NLF_HIP(hipMallocAsync((void**)&list, sizeof(int32_t) * getrf_scratch_ints(n, batch), s));
+        NLF_HIP(hipMallocAsync(&tmp, es * getrf_tmp_elems(n) * batch, s));
+        TrsmClassGuard tg(NLF_PROF_TRSM);
+        if (dtype == NLF_C128)
+            getrf<double>(s, n, batch, (z128*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list,
+                          (z128*)dinv_dev, (z128*)tmp);
+        else
+            getrf<float>(s, n, batch, (z64*)A_dev, lda, strideA, ipiv_dev, perm_dev, info_dev, list,
+                         (z64*)dinv_dev, (z64*)tmp);
+        NLF_HIP(hipFreeAsync(tmp, s));
         NLF_HIP(hipFreeAsync(list, s));
         return NLF_OK;
     })

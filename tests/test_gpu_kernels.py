@@ -121,6 +121,48 @@ def test_getrf_matches_oracle_lu(dtype, n, batch):
             assert rel(LU, LU0) < 1e-12
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,batch", [(33, 2), (256, 2), (300, 2), (700, 2)])
+def test_getrf_blocked_matches_oracle_and_inverses(dtype, n, batch):
+    # right-looking blocked LU: one partial panel, exactly one panel, a ragged second panel,
+    # three panels; the diagonal-block inverses it leaves behind are checked as well
+    rng = np.random.default_rng(7 * n + batch)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    mats = [wl.cn(rng, (n, n)) for _ in range(batch)]
+    if dtype == "c64":
+        mats = [M.astype(np.complex64).astype(complex) for M in mats]
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    per = nl.nlf_lu_inverse_elems(n)
+    dinv = torch.empty(batch * per, dtype=dt, device="cuda")
+    nl.nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0] * batch
+    eps = 2.2e-16 if dtype == "c128" else 1.2e-7
+    D = dinv.cpu().numpy().astype(complex)
+    for b in range(batch):
+        LU = nl.from_colmajor(A[b]).astype(complex)
+        piv = ipiv[b].cpu().numpy()
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
+        assert np.max(np.abs(dense.apply_pivots(piv, mats[b]) - L @ U)) <= 30 * n * eps * np.max(np.abs(mats[b]))
+        assert np.array_equal(mats[b][perm[b].cpu().numpy()], dense.apply_pivots(piv, mats[b]))
+        if dtype == "c128":
+            LU0, piv0 = dense.lu_partial_pivot(mats[b])
+            assert np.array_equal(piv, piv0)
+            assert rel(LU, LU0) < 1e-11
+        for q in range(-(-n // 256)):
+            s0, sb = 256 * q, min(256, n - 256 * q)
+            blk = D[b * per + 2 * q * 65536: b * per + (2 * q + 2) * 65536]
+            Li = blk[:65536].reshape(256, 256).T[:sb, :sb]
+            Ui = blk[65536:].reshape(256, 256).T[:sb, :sb]
+            tol = 1e-10 if dtype == "c128" else 1e-3
+            assert np.max(np.abs(Li @ L[s0:s0 + sb, s0:s0 + sb] - np.eye(sb))) < tol
+            assert np.max(np.abs(Ui @ U[s0:s0 + sb, s0:s0 + sb] - np.eye(sb))) < tol
+
+
 def test_getrf_zero_pivot_info():
     A = np.eye(40, dtype=complex)
     A[17, 17] = 0.0
