@@ -73,12 +73,24 @@ typedef struct {
     int32_t max_refine;          /* FP32_REFINE: refinement sweeps per solve, at most 5 */
     double refine_eta;           /* FP32_REFINE: stop sweeps once ||E||_F <= eta ||R||_F */
     uint64_t seed;               /* X0 when the caller passes none (counter-based normal draws) */
-    int32_t autotune;            /* 1: time the GEMM tile variants on first use of a shape */
+    int32_t autotune;            /* 1: on first use of a (precision, n, node count) shape, time
+                                    trial factorisations over panel width, trailing-update GEMM
+                                    tile and stream groups, and keep the fastest (process-wide
+                                    cache); explicit lu_streams / panel_width then act as fixed */
     int32_t verbose;             /* 1: one line per iteration on stderr */
     int32_t lu_streams;          /* factor the node matrices in this many groups on separate
                                     streams (1..4; 0 = default, one stream), so that one group's
                                     panel factorisations overlap another group's GEMMs */
     int32_t panel_width;         /* columns per single-workgroup panel of the LU, 4..32 (0 = 32) */
+    int32_t region_streams;      /* 0 (default): with several regions, each region's iteration
+                                    runs on its own stream and host thread after the shared
+                                    factorisation; 1: regions one after another on the caller's
+                                    stream */
+    int32_t graph;               /* 1: capture assembly + batched factorisation of all nodes in
+                                    a hipGraph on first use and replay it on later solves with
+                                    the same shapes, coefficient pointers and workspace (per-launch
+                                    profiling of those kernels is then replaced by one
+                                    NLF_K_FACTOR_GRAPH entry) */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -130,7 +142,9 @@ typedef enum {
     NLF_K_ASSEMBLE = 0, NLF_K_LU_GEMM = 1, NLF_K_LU_PANEL = 2, NLF_K_LU_TRSM = 3,
     NLF_K_LU_LASWP = 4, NLF_K_SOLVE = 5, NLF_K_REFINE = 6, NLF_K_RESIDUAL = 7,
     NLF_K_ACCUMULATE = 8, NLF_K_ORTH = 9, NLF_K_PROJECT = 10, NLF_K_HOST_REDUCED = 11,
-    NLF_K_COUNT = 12
+    NLF_K_FACTOR_GRAPH = 12,     /* assembly + factorisation replayed as one hipGraph launch */
+    NLF_K_AUTOTUNE = 13,         /* trial factorisations of the LU tuner (first use of a shape) */
+    NLF_K_COUNT = 14
 } nlfeast_kernel_class;
 nlfeast_status nlfeast_set_profiling(nlfeast_handle h, int32_t on);
 nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* milliseconds,

@@ -24,6 +24,8 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
 int64_t getrf_tmp_elems(int64_t n);
 // Width of the panels factored by one workgroup (4..32, default 32); set per calling thread.
 int& lu_panel_width();
+// Per-thread override of the LU trailing-update GEMM tile ({0, 0} = default choice).
+GemmConfig& lu_update_tile();
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
            int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch,

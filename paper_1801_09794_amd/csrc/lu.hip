@@ -516,6 +516,17 @@ int& lu_panel_width() {
     return w;
 }
 
+GemmConfig& lu_update_tile() {
+    static thread_local GemmConfig c{0, 0};
+    return c;
+}
+
+// The tile of the trailing-update GEMMs: the override when one is set, else the default choice.
+static const GemmConfig* update_tile() {
+    const GemmConfig& c = lu_update_tile();
+    return c.tm > 0 ? &c : nullptr;
+}
+
 template <typename R>
 static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
                       int64_t k0, int64_t nc, int32_t* ipiv, int32_t* info, int32_t* list) {
@@ -537,7 +548,7 @@ static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda
                      sizeof(Cx<R>) * (2.0 * mrest * n2 + (double)mrest * n1 + (double)n1 * n2) * batch);
         gemm<R>(s, false, mrest, n2, n1, Cx<R>(-1, 0), A + (k0 + n1) + k0 * lda, lda, sA,
                 A + k0 + (k0 + n1) * lda, lda, sA, Cx<R>(1, 0),
-                A + (k0 + n1) + (k0 + n1) * lda, lda, sA, batch);
+                A + (k0 + n1) + (k0 + n1) * lda, lda, sA, batch, nullptr, 0, update_tile());
     }
     getrf_rec<R>(s, n, batch, A, lda, sA, k0 + n1, n2, ipiv, info, list);
     laswp<R>(s, batch, A, lda, sA, n, k0 + n1, k0 + nc, k0, n1, ipiv, list);
@@ -595,7 +606,7 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
             ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * rest * kb * batch,
                          sizeof(Cx<R>) * (2.0 * rest * rest + 2.0 * rest * kb) * batch);
             gemm<R>(s, false, rest, rest, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
-                    A + k1 + k1 * lda, lda, sA, batch);
+                    A + k1 + k1 * lda, lda, sA, batch, nullptr, 0, update_tile());
         }
     }
 }

@@ -15,11 +15,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/nlfeast.h"
@@ -69,6 +74,14 @@ struct Profiler {
         }
         recs.clear();
         used = 0;
+    }
+    void merge(const Profiler& o) {   // add another profiler's collected totals
+        for (int c = 0; c < NLF_PROF_COUNT; ++c) {
+            ms[c] += o.ms[c];
+            flops[c] += o.flops[c];
+            bytes[c] += o.bytes[c];
+            launches[c] += o.launches[c];
+        }
     }
     ~Profiler() {
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -120,6 +133,21 @@ static thread_local std::string g_last_error;
 
 using namespace nlf;
 
+// What a captured factorisation graph depends on (kernel arguments are baked into the graph).
+struct GraphKey {
+    const void* ws = nullptr;
+    int prec = -1;
+    int64_t n = 0;
+    int NZ = 0, J = 0;
+    int64_t lda = 0;
+    std::vector<const void*> A;
+    std::array<int, 4> tune{};
+    bool operator==(const GraphKey& o) const {
+        return ws == o.ws && prec == o.prec && n == o.n && NZ == o.NZ && J == o.J && lda == o.lda && A == o.A &&
+               tune == o.tune;
+    }
+};
+
 struct nlfeast_ctx {
     int64_t n = 0;
     int device = 0;
@@ -143,7 +171,23 @@ struct nlfeast_ctx {
     Profiler prof;
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};   // factorisation streams
     hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipStream_t> rstream;                      // one iteration stream per region
+    std::vector<hipEvent_t> rdone;
+    std::vector<std::unique_ptr<Profiler>> rprof;
+    hipEvent_t ev_lufork = nullptr;
+    hipStream_t gstream = nullptr;                         // capture stream of the factorisation graph
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
+    void drop_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        graph_exec = nullptr;
+    }
     ~nlfeast_ctx() {
+        drop_graph();
+        if (gstream) (void)hipStreamDestroy(gstream);
+        if (ev_lufork) (void)hipEventDestroy(ev_lufork);
+        for (hipStream_t r : rstream) (void)hipStreamDestroy(r);
+        for (hipEvent_t e : rdone) (void)hipEventDestroy(e);
         for (int i = 0; i < 4; ++i) {
             if (side[i]) (void)hipStreamDestroy(side[i]);
             if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
@@ -154,13 +198,18 @@ struct nlfeast_ctx {
 
 namespace {
 
+// Per-region iteration buffers (each region may run on its own stream and host thread).
+struct RegionLayout {
+    size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, stmp = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
+    size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0;
+    int64_t splitws_elems = 0;
+    int node0 = 0, col0 = 0;
+};
+
 struct Layout {
     size_t total = 0;
-    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, stmp = 0, ftmp = 0;
-    size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
-    size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0,
-           coef = 0;
-    int64_t splitws_elems = 0;
+    size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, ftmp = 0, coef = 0;
+    std::vector<RegionLayout> reg;
     int NZ = 0, M = 0, mmax = 0, ncmax = 0;
 };
 
@@ -184,39 +233,49 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
         return o;
     };
     const bool p32 = prec == NLF_PREC_FP32_REFINE;
-    L.fact = take(nn * L.NZ * (p32 ? 8 : 16));
+    const size_t es = p32 ? 8 : 16;
+    L.fact = take(nn * L.NZ * es);
     L.t64 = p32 ? take(nn * L.NZ * 16) : 0;
     L.ipiv = take(sizeof(int32_t) * n * L.NZ);
     L.perm = take(sizeof(int32_t) * n * L.NZ);
     L.info = take(sizeof(int32_t) * L.NZ);
     L.list = take(sizeof(int32_t) * getrf_scratch_ints(n, L.NZ));
-    L.dinv = take((size_t)lu_inverse_elems(n) * L.NZ * (p32 ? 8 : 16));
-    L.ftmp = take((size_t)getrf_tmp_elems(n) * L.NZ * (p32 ? 8 : 16));
-    const size_t blk = (size_t)n * L.mmax;
-    L.Q = take(16 * blk);
-    L.X = take(16 * blk);
-    L.W = take(16 * blk * J);
-    L.R = take(16 * blk);
-    L.Ys = take(16 * blk * L.ncmax);
-    L.QT = take(16 * blk);
-    L.stmp = take((size_t)256 * L.mmax * L.ncmax * (p32 ? 8 : 16));
-    if (p32) {
-        L.R32 = take(8 * blk);
-        L.Y32 = take(8 * blk * L.ncmax);
-        L.E = take(16 * blk * L.ncmax);
-        L.E32 = take(8 * blk * L.ncmax);
-    }
-    const size_t mm = (size_t)L.mmax * L.mmax;
-    L.Ahat = take(16 * mm * J);
-    L.G = take(16 * mm);
-    L.Ymat = take(16 * mm);
-    L.Gall = take(16 * mm * J);
-    L.rho = take(16 * L.mmax);
-    L.acoef = take(16 * (size_t)L.mmax * L.ncmax);
-    L.norms = take(8 * (size_t)(L.mmax + L.ncmax + 8));
-    L.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
-    L.splitws = take(16 * (size_t)L.splitws_elems);
+    L.dinv = take((size_t)lu_inverse_elems(n) * L.NZ * es);
+    L.ftmp = take((size_t)getrf_tmp_elems(n) * L.NZ * es);
     L.coef = take(16 * (size_t)L.NZ * J);
+    int node0 = 0, col0 = 0;
+    for (const auto& rg : h->regions) {
+        RegionLayout R;
+        const int m = rg.m0, nc = rg.nc;
+        const size_t blk = (size_t)n * m, mm = (size_t)m * m;
+        R.node0 = node0;
+        R.col0 = col0;
+        R.Q = take(16 * blk);
+        R.X = take(16 * blk);
+        R.W = take(16 * blk * J);
+        R.R = take(16 * blk);
+        R.Ys = take(16 * blk * nc);
+        R.QT = take(16 * blk);
+        R.stmp = take((size_t)256 * m * nc * es);
+        if (p32) {
+            R.R32 = take(8 * blk);
+            R.Y32 = take(8 * blk * nc);
+            R.E = take(16 * blk * nc);
+            R.E32 = take(8 * blk * nc);
+        }
+        R.Ahat = take(16 * mm * J);
+        R.G = take(16 * mm);
+        R.Ymat = take(16 * mm);
+        R.Gall = take(16 * mm * J);
+        R.rho = take(16 * (size_t)m);
+        R.acoef = take(16 * (size_t)m * nc);
+        R.norms = take(8 * (size_t)(m + nc + 8));
+        R.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
+        R.splitws = take(16 * (size_t)R.splitws_elems);
+        L.reg.push_back(R);
+        node0 += nc;
+        col0 += m;
+    }
     L.total = off;
     return L;
 }
@@ -275,6 +334,401 @@ void project(hipStream_t s, int64_t n, int m, int J, const z128* const* A, int64
     ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
     gemm<double>(s, true, m, m, n, z128(1, 0), Q, n, 0, W, n, (int64_t)n * m, z128(0, 0), Ahat, m,
                  (int64_t)m * m, J, splitws, split_elems);
+}
+
+
+// ------------------------------------------------------------------ factorisation of all nodes
+
+// LU launch parameters: panel width, trailing-update GEMM tile, node groups on separate streams.
+struct LuTuning {
+    int panel_width = 32;
+    int groups = 1;
+    int tm = 0, tn = 0;   // 0: default tile choice
+    bool operator==(const LuTuning& o) const {
+        return panel_width == o.panel_width && groups == o.groups && tm == o.tm && tn == o.tn;
+    }
+};
+
+LuTuning fixed_tuning(const nlfeast_options& o) {
+    LuTuning t;
+    if (o.panel_width) t.panel_width = o.panel_width;
+    if (o.lu_streams) t.groups = o.lu_streams;
+    return t;
+}
+
+struct TuningScope {   // applies a tuning to this thread's LU launches
+    int saved_pw;
+    GemmConfig saved_tile;
+    explicit TuningScope(const LuTuning& t) : saved_pw(lu_panel_width()), saved_tile(lu_update_tile()) {
+        lu_panel_width() = t.panel_width;
+        lu_update_tile() = GemmConfig{t.tm, t.tn};
+    }
+    ~TuningScope() {
+        lu_panel_width() = saved_pw;
+        lu_update_tile() = saved_tile;
+    }
+};
+
+// Assemble T(z_k) for every node from the coefficients in the workspace and factor them all,
+// enqueued on cs (node groups fork to the handle's side streams and join back to cs).
+void factor_all(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStream_t cs, const LuTuning& t) {
+    TuningScope ts(t);
+    const int64_t n = h->n;
+    const int J = h->J;
+    const size_t nn = (size_t)n * n;
+    if (p32)
+        assemble(cs, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.t64),
+                 at<z64>(ws, L.fact), n, (int64_t)nn);
+    else
+        assemble(cs, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.fact), nullptr,
+                 n, (int64_t)nn);
+    TrsmClassGuard tg(NLF_PROF_TRSM);
+    // groups of node matrices on separate streams: the latency-bound panels of one group run
+    // while the GEMMs of another fill the machine
+    const int groups = std::max(1, std::min({t.groups, 4, L.NZ}));
+    if (groups > 1) {
+        if (!h->ev_lufork) NLF_HIP(hipEventCreateWithFlags(&h->ev_lufork, hipEventDisableTiming));
+        NLF_HIP(hipEventRecord(h->ev_lufork, cs));
+    }
+    const int64_t dper = lu_inverse_elems(n);
+    const int64_t lper = getrf_scratch_ints(n, 1);
+    const int64_t tper = getrf_tmp_elems(n);
+    for (int g = 0; g < groups; ++g) {
+        const int q0 = (int)((int64_t)L.NZ * g / groups), q1 = (int)((int64_t)L.NZ * (g + 1) / groups);
+        if (q1 <= q0) continue;
+        hipStream_t sg = cs;
+        if (groups > 1) {
+            if (!h->side[g]) {
+                NLF_HIP(hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking));
+                NLF_HIP(hipEventCreateWithFlags(&h->ev_join[g], hipEventDisableTiming));
+            }
+            sg = h->side[g];
+            NLF_HIP(hipStreamWaitEvent(sg, h->ev_lufork, 0));
+        }
+        const int nb = q1 - q0;
+        int32_t* ipiv = at<int32_t>(ws, L.ipiv) + (size_t)q0 * n;
+        int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)q0 * n;
+        int32_t* info = at<int32_t>(ws, L.info) + q0;
+        int32_t* list = at<int32_t>(ws, L.list) + (size_t)q0 * lper;
+        if (p32)
+            getrf<float>(sg, n, nb, at<z64>(ws, L.fact) + (size_t)q0 * nn, n, (int64_t)nn, ipiv, perm, info, list,
+                         at<z64>(ws, L.dinv) + (size_t)q0 * dper, at<z64>(ws, L.ftmp) + (size_t)q0 * tper);
+        else
+            getrf<double>(sg, n, nb, at<z128>(ws, L.fact) + (size_t)q0 * nn, n, (int64_t)nn, ipiv, perm, info,
+                          list, at<z128>(ws, L.dinv) + (size_t)q0 * dper, at<z128>(ws, L.ftmp) + (size_t)q0 * tper);
+        if (groups > 1) {
+            NLF_HIP(hipEventRecord(h->ev_join[g], sg));
+            NLF_HIP(hipStreamWaitEvent(cs, h->ev_join[g], 0));
+        }
+    }
+}
+
+// Tuner: on first use of a (precision, n, node count) shape, time trial factorisations of the
+// real node matrices over the candidate launch parameters and keep the fastest for the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int>, LuTuning> g_tune_cache;
+
+LuTuning autotuned(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStream_t s, const nlfeast_options& o) {
+    const auto key = std::make_tuple(o.precision, h->n, L.NZ);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    std::vector<int> pws = o.panel_width ? std::vector<int>{o.panel_width} : std::vector<int>{16, 32};
+    std::vector<int> grs = o.lu_streams ? std::vector<int>{o.lu_streams} : std::vector<int>{1, 2};
+    std::vector<std::pair<int, int>> tiles = p32 ? std::vector<std::pair<int, int>>{{0, 0}, {2, 2}, {4, 4}}
+                                                 : std::vector<std::pair<int, int>>{{0, 0}, {4, 2}};
+    std::vector<LuTuning> cand;
+    for (int pw : pws)
+        for (int g : grs)
+            for (auto tl : tiles) {
+                LuTuning t;
+                t.panel_width = pw;
+                t.groups = g;
+                t.tm = tl.first;
+                t.tn = tl.second;
+                cand.push_back(t);
+            }
+    Profiler* saved = active_profiler();
+    active_profiler() = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    LuTuning best = fixed_tuning(o);
+    float best_ms = 0.f, total_ms = 0.f;
+    try {
+        NLF_HIP(hipEventCreate(&e0));
+        NLF_HIP(hipEventCreate(&e1));
+        factor_all(h, L, ws, p32, s, cand[0]);   // warm-up: code objects, caches
+        for (size_t c = 0; c < cand.size(); ++c) {
+            NLF_HIP(hipEventRecord(e0, s));
+            factor_all(h, L, ws, p32, s, cand[c]);
+            NLF_HIP(hipEventRecord(e1, s));
+            NLF_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            NLF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            total_ms += ms;
+            if (o.verbose)
+                fprintf(stderr, "[nlfeast] tune pw %d groups %d tile %dx%d: %.3f ms\n", cand[c].panel_width,
+                        cand[c].groups, cand[c].tm, cand[c].tn, ms);
+            if (c == 0 || ms < best_ms) {
+                best_ms = ms;
+                best = cand[c];
+            }
+        }
+    } catch (...) {
+        active_profiler() = saved;
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        throw;
+    }
+    active_profiler() = saved;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (saved) {
+        saved->ms[NLF_PROF_AUTOTUNE] += total_ms;
+        saved->launches[NLF_PROF_AUTOTUNE] += (int64_t)cand.size();
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+    return best;
+}
+
+GraphKey graph_key(const nlfeast_ctx* h, const Layout& L, const void* ws, int prec, const LuTuning& t) {
+    GraphKey k;
+    k.ws = ws;
+    k.prec = prec;
+    k.n = h->n;
+    k.NZ = L.NZ;
+    k.J = h->J;
+    k.lda = h->lda;
+    k.A.assign(h->A.begin(), h->A.end());
+    k.tune = {t.panel_width, t.groups, t.tm, t.tn};
+    return k;
+}
+
+// Record factor_all on the handle's capture stream into h->graph_exec (nothing executes).
+void capture_factorisation(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, const LuTuning& t) {
+    if (!h->gstream) NLF_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    Profiler* saved = active_profiler();
+    active_profiler() = nullptr;   // no event records inside the capture
+    hipGraph_t graph = nullptr;
+    NLF_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    try {
+        factor_all(h, L, ws, p32, h->gstream, t);
+    } catch (...) {
+        (void)hipStreamEndCapture(h->gstream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        active_profiler() = saved;
+        throw;
+    }
+    active_profiler() = saved;
+    NLF_HIP(hipStreamEndCapture(h->gstream, &graph));
+    const hipError_t e = hipGraphInstantiateWithFlags(&h->graph_exec, graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->graph_exec = nullptr;
+        throw Error{NLF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    }
+}
+
+struct RegionIO {
+    const void* X0;
+    void* Xout;
+    double* lambda;
+    double* resid;
+    int32_t* inside;
+    int32_t* m_out;
+    int32_t* iters;
+};
+
+struct RegionOutcome {
+    int status = NLF_OK;
+    std::string msg;
+};
+
+// Algorithm 1 Steps 0-5 for region ri, on stream s, with the node factorisations already in the
+// workspace.  Writes the region's slice of the outputs; never throws.
+RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, const Layout& L, int ri,
+                         hipStream_t s, Profiler* prof, const RegionIO& io) {
+    RegionOutcome res_out;
+    try {
+        ProfilerGuard pg(prof);
+        const nlfeast_options* opt = &o;
+        const int64_t n = h->n;
+        const int J = h->J;
+        const bool p32 = opt->precision == NLF_PREC_FP32_REFINE;
+        const size_t nn = (size_t)n * n;
+        const RegionLayout& RL = L.reg[ri];
+        const int node0 = RL.node0, col0 = RL.col0;
+        auto host_ms = [&](double ms) {
+            if (prof) {
+                prof->ms[NLF_PROF_HOST] += ms;
+                prof->launches[NLF_PROF_HOST] += 1;
+            }
+        };
+        const auto& reg = h->regions[ri];
+        const int m = reg.m0, nc = reg.nc;
+        z128* Q = at<z128>(ws, RL.Q);
+        z128* X = at<z128>(ws, RL.X);
+        z128* W = at<z128>(ws, RL.W);
+        z128* R = at<z128>(ws, RL.R);
+        z128* Ys = at<z128>(ws, RL.Ys);
+        z128* QT = at<z128>(ws, RL.QT);
+        z128* Ahat_d = at<z128>(ws, RL.Ahat);
+        z128* Gd = at<z128>(ws, RL.G);
+        z128* Ymat = at<z128>(ws, RL.Ymat);
+        z128* Gall = at<z128>(ws, RL.Gall);
+        z128* rho_d = at<z128>(ws, RL.rho);
+        z128* acoef_d = at<z128>(ws, RL.acoef);
+        double* norms_d = at<double>(ws, RL.norms);
+        z128* splitws = at<z128>(ws, RL.splitws);
+        const size_t blk = (size_t)n * m;
+        // Step 0
+        if (io.X0)
+            copy_block(s, n, m, (const z128*)io.X0 + (size_t)col0 * n, n, Q, n);
+        else
+            random_normal(s, n, m, opt->seed * 0x9E3779B97F4A7C15ull + ri + 1, Q, n);
+        orthonormalize(s, n, m, Q, QT, Gd, at<z128>(ws, RL.Ymat), splitws, RL.splitws_elems);
+
+        std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
+            acoef((size_t)nc * m);
+        std::vector<double> res(m), enorm(nc);
+        ReducedResult rr;
+        int it = 0, n_in = 0;
+        std::vector<int> inside(m);
+        int rstatus = NLF_OK;
+        const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
+        const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
+        const int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)node0 * n;
+        const int64_t dper = lu_inverse_elems(n);
+        const z128* D128 = at<z128>(ws, L.dinv) + (size_t)node0 * dper;
+        const z64* D64 = at<z64>(ws, L.dinv) + (size_t)node0 * dper;
+        while (true) {
+            // Step 1: projections and the reduced problem
+            project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems);
+            d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
+            const auto t0 = std::chrono::steady_clock::now();
+            std::vector<cplx> prev;
+            if (it > 0) prev = rr.lambda;
+            rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr);
+            host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+            NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
+                        "reduced eigenproblem failed (singular T at the contour centre or QR did not converge)");
+            // Step 2: X = Q Y
+            for (int i = 0; i < m; ++i) lam[i] = std::isfinite(rr.lambda[i].real()) ? rr.lambda[i] : cplx(0.0);
+            h2d(s, Ymat, rr.Y.data(), sizeof(cplx) * m * m);
+            {
+                ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m, 32.0 * n * m);
+                gemm<double>(s, false, n, m, m, z128(1, 0), Q, n, 0, Ymat, m, 0, z128(0, 0), X, n, 0, 1);
+            }
+            // Step 3: R = sum_j W_j (Y f_j(Lambda)), res_i = ||R e_i||
+            for (int j = 0; j < J; ++j)
+                for (int c = 0; c < m; ++c) {
+                    const cplx f = term_value(h->terms[j], lam[c]);
+                    for (int r = 0; r < m; ++r)
+                        Gh[(size_t)j * m + r + (size_t)c * J * m] = rr.Y[r + (size_t)c * m] * f;
+                }
+            h2d(s, Gall, Gh.data(), sizeof(cplx) * Gh.size());
+            {
+                ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
+                gemm<double>(s, false, n, m, (int64_t)J * m, z128(1, 0), W, n, 0, Gall, (int64_t)J * m, 0,
+                             z128(0, 0), R, n, 0, 1);
+                col_norms(s, n, m, R, n, norms_d);
+            }
+            d2h_sync(s, res.data(), norms_d, sizeof(double) * m);
+            n_in = 0;
+            double maxres = 0.0;
+            for (int i = 0; i < m; ++i) {
+                if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
+                inside[i] = reg.E.radius(rr.lambda[i]) < 1.0;
+                if (inside[i]) {
+                    ++n_in;
+                    maxres = std::max(maxres, res[i]);
+                }
+            }
+            if (opt->verbose)
+                fprintf(stderr, "[nlfeast] region %d it %d inside %d max_res %.3e\n", ri, it, n_in, maxres);
+            if (n_in >= m) { rstatus = NLF_ERR_M0_TOO_SMALL; break; }
+            if (it >= 1 && n_in > 0 && maxres <= opt->tol) break;
+            if (it >= 3 && n_in == 0) break;
+            if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
+            // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
+            {
+                TrsmClassGuard tg(NLF_PROF_SOLVE);
+                if (!p32) {
+                    getrs_inv<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, D128, R, n, 0, Ys, n,
+                                      (int64_t)blk, at<z128>(ws, RL.stmp));
+                } else {
+                    z64* R32 = at<z64>(ws, RL.R32);
+                    z64* Y32 = at<z64>(ws, RL.Y32);
+                    z128* E = at<z128>(ws, RL.E);
+                    z64* E32 = at<z64>(ws, RL.E32);
+                    const z128* T64 = at<z128>(ws, L.t64) + (size_t)node0 * nn;
+                    cast_128_to_64(s, n, m, 1, R, n, 0, R32, n, 0);
+                    getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, Y32, n,
+                                     (int64_t)blk, at<z64>(ws, RL.stmp));
+                    cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
+                    double rn2 = 0.0;
+                    for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
+                    for (int sweep = 0; sweep < std::min(opt->max_refine, 5); ++sweep) {
+                        TrsmClassGuard tg2(NLF_PROF_REFINE);
+                        ProfScope ps(NLF_PROF_REFINE, s, 8.0 * n * n * m * nc, 16.0 * nn * nc);
+                        // E_k = R - T(z_k) Y_k in FP64
+                        for (int q = 0; q < nc; ++q) copy_block(s, n, m, R, n, E + q * blk, n);
+                        gemm<double>(s, false, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
+                                     z128(1, 0), E, n, (int64_t)blk, nc);
+                        block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d);
+                        d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
+                        double worst = 0.0;
+                        for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);
+                        if (worst <= opt->refine_eta * opt->refine_eta * rn2) break;
+                        cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
+                        getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
+                                         Y32, n, (int64_t)blk, at<z64>(ws, RL.stmp));
+                        cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, true);
+                    }
+                }
+            }
+            // Step 4 accumulation: Q = X rho(Lambda) - sum_k omega_k Y_k (z_k - Lambda)^{-1}
+            for (int i = 0; i < m; ++i) {
+                cplx rsum = 0.0;
+                for (int q = 0; q < nc; ++q) {
+                    const cplx cq = reg.w[q] / (reg.z[q] - lam[i]);
+                    acoef[(size_t)q * m + i] = cq;
+                    rsum += cq;
+                }
+                rho[i] = rsum;
+            }
+            h2d(s, rho_d, rho.data(), sizeof(cplx) * m);
+            h2d(s, acoef_d, acoef.data(), sizeof(cplx) * acoef.size());
+            accumulate(s, n, m, nc, X, Ys, (int64_t)blk, rho_d, acoef_d, Q);
+            // Step 5
+            orthonormalize(s, n, m, Q, QT, Gd, Ymat, splitws, RL.splitws_elems);
+            ++it;
+        }
+        // outputs for this region
+        NLF_HIP(hipMemcpyAsync((z128*)io.Xout + (size_t)col0 * n, X, sizeof(z128) * blk,
+                               hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i < m; ++i) {
+            io.lambda[2 * (col0 + i)] = rr.lambda[i].real();
+            io.lambda[2 * (col0 + i) + 1] = rr.lambda[i].imag();
+            io.resid[col0 + i] = res[i];
+            io.inside[col0 + i] = inside[i];
+        }
+        io.m_out[ri] = n_in;
+        io.iters[ri] = it;
+        NLF_HIP(hipStreamSynchronize(s));
+        res_out.status = rstatus;
+        if (rstatus == NLF_ERR_M0_TOO_SMALL) res_out.msg = "m0 or more Ritz values inside a contour";
+        if (rstatus == NLF_ERR_NOT_CONVERGED) res_out.msg = "not converged within max_iter";
+    } catch (const nlf::Error& e) {
+        res_out.status = e.status;
+        res_out.msg = e.msg;
+    } catch (const std::exception& e) {
+        res_out.status = NLF_ERR_DEVICE;
+        res_out.msg = e.what();
+    }
+    return res_out;
 }
 
 }  // namespace
@@ -416,11 +870,9 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         NLF_REQUIRE(opt->lu_streams >= 0 && opt->lu_streams <= 4, NLF_ERR_ARG, "solve: lu_streams in 0..4");
         NLF_REQUIRE(opt->panel_width == 0 || (opt->panel_width >= 4 && opt->panel_width <= 32), NLF_ERR_ARG,
                     "solve: panel_width 0 or 4..32");
-        struct PanelGuard {
-            int saved;
-            explicit PanelGuard(int w) : saved(lu_panel_width()) { if (w) lu_panel_width() = w; }
-            ~PanelGuard() { lu_panel_width() = saved; }
-        } panel_guard(opt->panel_width);
+        NLF_REQUIRE((opt->region_streams == 0 || opt->region_streams == 1) && (opt->graph == 0 || opt->graph == 1) &&
+                        (opt->autotune == 0 || opt->autotune == 1),
+                    NLF_ERR_ARG, "solve: region_streams, graph and autotune are 0 or 1");
         const Layout L = make_layout(h, opt->precision);
         NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
         NLF_HIP(hipSetDevice(h->device));
@@ -430,14 +882,7 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         const bool p32 = opt->precision == NLF_PREC_FP32_REFINE;
         if (h->profiling) h->prof.reset();
         ProfilerGuard pg(h->profiling ? &h->prof : nullptr);
-        auto host_ms = [&](double ms) {
-            if (h->profiling) {
-                h->prof.ms[NLF_PROF_HOST] += ms;
-                h->prof.launches[NLF_PROF_HOST] += 1;
-            }
-        };
 
-        const size_t nn = (size_t)n * n;
         // ---- fixed shifts: assemble and factor T(z_k) once per contour
         if (!(h->factors_valid && h->factors_ws == ws && h->factors_prec == opt->precision)) {
             std::vector<cplx> coef((size_t)L.NZ * J);
@@ -446,54 +891,19 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                 for (int q = 0; q < r.nc; ++q, ++k)
                     for (int j = 0; j < J; ++j) coef[(size_t)k * J + j] = term_value(h->terms[j], r.z[q]);
             h2d(s, at<void>(ws, L.coef), coef.data(), sizeof(cplx) * coef.size());
-            if (p32)
-                assemble(s, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.t64),
-                         at<z64>(ws, L.fact), n, (int64_t)nn);
-            else
-                assemble(s, n, J, h->A.data(), h->lda, L.NZ, at<z128>(ws, L.coef), at<z128>(ws, L.fact),
-                         nullptr, n, (int64_t)nn);
-            TrsmClassGuard tg(NLF_PROF_TRSM);
-            // groups of node matrices on separate streams: the latency-bound panels of one group
-            // run while the GEMMs of another fill the machine
-            int groups = opt->lu_streams > 0 ? opt->lu_streams : 1;
-            groups = std::max(1, std::min({groups, 4, L.NZ}));
-            if (groups > 1) {
-                if (!h->ev_fork) NLF_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-                NLF_HIP(hipEventRecord(h->ev_fork, s));
-            }
-            const int64_t dper = lu_inverse_elems(n);
-            const int64_t lper = getrf_scratch_ints(n, 1);
-            for (int g = 0; g < groups; ++g) {
-                const int q0 = (int)((int64_t)L.NZ * g / groups), q1 = (int)((int64_t)L.NZ * (g + 1) / groups);
-                if (q1 <= q0) continue;
-                hipStream_t sg = s;
-                if (groups > 1) {
-                    if (!h->side[g]) {
-                        NLF_HIP(hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking));
-                        NLF_HIP(hipEventCreateWithFlags(&h->ev_join[g], hipEventDisableTiming));
-                    }
-                    sg = h->side[g];
-                    NLF_HIP(hipStreamWaitEvent(sg, h->ev_fork, 0));
+            LuTuning tune = fixed_tuning(*opt);
+            if (opt->autotune) tune = autotuned(h, L, ws, p32, s, *opt);
+            if (opt->graph) {
+                GraphKey key = graph_key(h, L, ws, opt->precision, tune);
+                if (!h->graph_exec || !(h->graph_key == key)) {
+                    h->drop_graph();
+                    capture_factorisation(h, L, ws, p32, tune);
+                    h->graph_key = key;
                 }
-                const int nb = q1 - q0;
-                int32_t* ipiv = at<int32_t>(ws, L.ipiv) + (size_t)q0 * n;
-                int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)q0 * n;
-                int32_t* info = at<int32_t>(ws, L.info) + q0;
-                int32_t* list = at<int32_t>(ws, L.list) + (size_t)q0 * lper;
-                const int64_t tper = getrf_tmp_elems(n);
-                if (p32) {
-                    z64* F = at<z64>(ws, L.fact) + (size_t)q0 * nn;
-                    getrf<float>(sg, n, nb, F, n, (int64_t)nn, ipiv, perm, info, list,
-                                 at<z64>(ws, L.dinv) + (size_t)q0 * dper, at<z64>(ws, L.ftmp) + (size_t)q0 * tper);
-                } else {
-                    z128* F = at<z128>(ws, L.fact) + (size_t)q0 * nn;
-                    getrf<double>(sg, n, nb, F, n, (int64_t)nn, ipiv, perm, info, list,
-                                  at<z128>(ws, L.dinv) + (size_t)q0 * dper, at<z128>(ws, L.ftmp) + (size_t)q0 * tper);
-                }
-                if (groups > 1) {
-                    NLF_HIP(hipEventRecord(h->ev_join[g], sg));
-                    NLF_HIP(hipStreamWaitEvent(s, h->ev_join[g], 0));
-                }
+                ProfScope ps(NLF_PROF_FACTOR_GRAPH, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
+                NLF_HIP(hipGraphLaunch(h->graph_exec, s));
+            } else {
+                factor_all(h, L, ws, p32, s, tune);
             }
             std::vector<int32_t> info(L.NZ);
             d2h_sync(s, info.data(), at<void>(ws, L.info), sizeof(int32_t) * L.NZ);
@@ -506,170 +916,77 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             h->factors_prec = opt->precision;
         }
 
-        int status = NLF_OK;
-        int node0 = 0, col0 = 0;
-        for (size_t ri = 0; ri < h->regions.size(); ++ri) {
-            const auto& reg = h->regions[ri];
-            const int m = reg.m0, nc = reg.nc;
-            z128* Q = at<z128>(ws, L.Q);
-            z128* X = at<z128>(ws, L.X);
-            z128* W = at<z128>(ws, L.W);
-            z128* R = at<z128>(ws, L.R);
-            z128* Ys = at<z128>(ws, L.Ys);
-            z128* QT = at<z128>(ws, L.QT);
-            z128* Ahat_d = at<z128>(ws, L.Ahat);
-            z128* Gd = at<z128>(ws, L.G);
-            z128* Ymat = at<z128>(ws, L.Ymat);
-            z128* Gall = at<z128>(ws, L.Gall);
-            z128* rho_d = at<z128>(ws, L.rho);
-            z128* acoef_d = at<z128>(ws, L.acoef);
-            double* norms_d = at<double>(ws, L.norms);
-            z128* splitws = at<z128>(ws, L.splitws);
-            const size_t blk = (size_t)n * m;
-            // Step 0
-            if (X0_dev)
-                copy_block(s, n, m, (const z128*)X0_dev + (size_t)col0 * n, n, Q, n);
-            else
-                random_normal(s, n, m, opt->seed * 0x9E3779B97F4A7C15ull + ri + 1, Q, n);
-            orthonormalize(s, n, m, Q, QT, Gd, at<z128>(ws, L.Ymat), splitws, L.splitws_elems);
-
-            std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
-                acoef((size_t)nc * m);
-            std::vector<double> res(m), enorm(nc);
-            ReducedResult rr;
-            int it = 0, n_in = 0;
-            std::vector<int> inside(m);
-            int rstatus = NLF_OK;
-            const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
-            const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
-            const int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)node0 * n;
-            const int64_t dper = lu_inverse_elems(n);
-            const z128* D128 = at<z128>(ws, L.dinv) + (size_t)node0 * dper;
-            const z64* D64 = at<z64>(ws, L.dinv) + (size_t)node0 * dper;
-            while (true) {
-                // Step 1: projections and the reduced problem
-                project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, L.splitws_elems);
-                d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
-                const auto t0 = std::chrono::steady_clock::now();
-                std::vector<cplx> prev;
-                if (it > 0) prev = rr.lambda;
-                rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr);
-                host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
-                NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
-                            "reduced eigenproblem failed (singular T at the contour centre or QR did not converge)");
-                // Step 2: X = Q Y
-                for (int i = 0; i < m; ++i) lam[i] = std::isfinite(rr.lambda[i].real()) ? rr.lambda[i] : cplx(0.0);
-                h2d(s, Ymat, rr.Y.data(), sizeof(cplx) * m * m);
-                {
-                    ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m, 32.0 * n * m);
-                    gemm<double>(s, false, n, m, m, z128(1, 0), Q, n, 0, Ymat, m, 0, z128(0, 0), X, n, 0, 1);
-                }
-                // Step 3: R = sum_j W_j (Y f_j(Lambda)), res_i = ||R e_i||
-                for (int j = 0; j < J; ++j)
-                    for (int c = 0; c < m; ++c) {
-                        const cplx f = term_value(h->terms[j], lam[c]);
-                        for (int r = 0; r < m; ++r)
-                            Gh[(size_t)j * m + r + (size_t)c * J * m] = rr.Y[r + (size_t)c * m] * f;
-                    }
-                h2d(s, Gall, Gh.data(), sizeof(cplx) * Gh.size());
-                {
-                    ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
-                    gemm<double>(s, false, n, m, (int64_t)J * m, z128(1, 0), W, n, 0, Gall, (int64_t)J * m, 0,
-                                 z128(0, 0), R, n, 0, 1);
-                    col_norms(s, n, m, R, n, norms_d);
-                }
-                d2h_sync(s, res.data(), norms_d, sizeof(double) * m);
-                n_in = 0;
-                double maxres = 0.0;
-                for (int i = 0; i < m; ++i) {
-                    if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
-                    inside[i] = reg.E.radius(rr.lambda[i]) < 1.0;
-                    if (inside[i]) {
-                        ++n_in;
-                        maxres = std::max(maxres, res[i]);
-                    }
-                }
-                if (opt->verbose)
-                    fprintf(stderr, "[nlfeast] region %zu it %d inside %d max_res %.3e\n", ri, it, n_in, maxres);
-                if (n_in >= m) { rstatus = NLF_ERR_M0_TOO_SMALL; break; }
-                if (it >= 1 && n_in > 0 && maxres <= opt->tol) break;
-                if (it >= 3 && n_in == 0) break;
-                if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
-                // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
-                {
-                    TrsmClassGuard tg(NLF_PROF_SOLVE);
-                    if (!p32) {
-                        getrs_inv<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, D128, R, n, 0, Ys, n,
-                                          (int64_t)blk, at<z128>(ws, L.stmp));
-                    } else {
-                        z64* R32 = at<z64>(ws, L.R32);
-                        z64* Y32 = at<z64>(ws, L.Y32);
-                        z128* E = at<z128>(ws, L.E);
-                        z64* E32 = at<z64>(ws, L.E32);
-                        const z128* T64 = at<z128>(ws, L.t64) + (size_t)node0 * nn;
-                        cast_128_to_64(s, n, m, 1, R, n, 0, R32, n, 0);
-                        getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, Y32, n,
-                                         (int64_t)blk, at<z64>(ws, L.stmp));
-                        cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
-                        double rn2 = 0.0;
-                        for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
-                        for (int sweep = 0; sweep < std::min(opt->max_refine, 5); ++sweep) {
-                            TrsmClassGuard tg2(NLF_PROF_REFINE);
-                            ProfScope ps(NLF_PROF_REFINE, s, 8.0 * n * n * m * nc, 16.0 * nn * nc);
-                            // E_k = R - T(z_k) Y_k in FP64
-                            for (int q = 0; q < nc; ++q) copy_block(s, n, m, R, n, E + q * blk, n);
-                            gemm<double>(s, false, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
-                                         z128(1, 0), E, n, (int64_t)blk, nc);
-                            block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d);
-                            d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
-                            double worst = 0.0;
-                            for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);
-                            if (worst <= opt->refine_eta * opt->refine_eta * rn2) break;
-                            cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
-                            getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
-                                             Y32, n, (int64_t)blk, at<z64>(ws, L.stmp));
-                            cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, true);
-                        }
-                    }
-                }
-                // Step 4 accumulation: Q = X rho(Lambda) - sum_k omega_k Y_k (z_k - Lambda)^{-1}
-                for (int i = 0; i < m; ++i) {
-                    cplx rsum = 0.0;
-                    for (int q = 0; q < nc; ++q) {
-                        const cplx cq = reg.w[q] / (reg.z[q] - lam[i]);
-                        acoef[(size_t)q * m + i] = cq;
-                        rsum += cq;
-                    }
-                    rho[i] = rsum;
-                }
-                h2d(s, rho_d, rho.data(), sizeof(cplx) * m);
-                h2d(s, acoef_d, acoef.data(), sizeof(cplx) * acoef.size());
-                accumulate(s, n, m, nc, X, Ys, (int64_t)blk, rho_d, acoef_d, Q);
-                // Step 5
-                orthonormalize(s, n, m, Q, QT, Gd, Ymat, splitws, L.splitws_elems);
-                ++it;
+        const int nreg = (int)h->regions.size();
+        std::vector<RegionOutcome> out(nreg);
+        RegionIO io{X0_dev, X_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out};
+        const bool concurrent = nreg > 1 && opt->region_streams == 0;
+        if (!concurrent) {
+            for (int ri = 0; ri < nreg; ++ri) {
+                out[ri] = run_region(h, *opt, ws, L, ri, s, h->profiling ? &h->prof : nullptr, io);
+                if (out[ri].status != NLF_OK && out[ri].status != NLF_ERR_NOT_CONVERGED &&
+                    out[ri].status != NLF_ERR_M0_TOO_SMALL)
+                    break;
             }
-            // outputs for this region
-            NLF_HIP(hipMemcpyAsync((z128*)X_dev_out + (size_t)col0 * n, X, sizeof(z128) * blk,
-                                   hipMemcpyDeviceToDevice, s));
-            for (int i = 0; i < m; ++i) {
-                lambda_out[2 * (col0 + i)] = rr.lambda[i].real();
-                lambda_out[2 * (col0 + i) + 1] = rr.lambda[i].imag();
-                resid_out[col0 + i] = res[i];
-                inside_out[col0 + i] = inside[i];
+        } else {
+            // every region waits for the shared factorisation, then iterates on its own stream
+            // and host thread; the caller's stream waits for all of them
+            if ((int)h->rstream.size() < nreg) {
+                for (int ri = (int)h->rstream.size(); ri < nreg; ++ri) {
+                    hipStream_t rs;
+                    hipEvent_t ev;
+                    NLF_HIP(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking));
+                    NLF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                    h->rstream.push_back(rs);
+                    h->rdone.push_back(ev);
+                    h->rprof.emplace_back(new Profiler());
+                }
             }
-            m_out[ri] = n_in;
-            iters_out[ri] = it;
-            if (rstatus != NLF_OK) status = rstatus;
-            node0 += nc;
-            col0 += m;
+            if (!h->ev_fork) NLF_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+            NLF_HIP(hipEventRecord(h->ev_fork, s));
+            for (int ri = 0; ri < nreg; ++ri) {
+                NLF_HIP(hipStreamWaitEvent(h->rstream[ri], h->ev_fork, 0));
+                h->rprof[ri]->reset();
+            }
+            std::vector<std::thread> threads;
+            threads.reserve(nreg);
+            for (int ri = 0; ri < nreg; ++ri)
+                threads.emplace_back([&, ri] {
+                    if (hipSetDevice(h->device) != hipSuccess) {
+                        out[ri].status = NLF_ERR_DEVICE;
+                        out[ri].msg = "hipSetDevice failed in a region thread";
+                        return;
+                    }
+                    out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
+                                         h->profiling ? h->rprof[ri].get() : nullptr, io);
+                });
+            for (auto& t : threads) t.join();
+            for (int ri = 0; ri < nreg; ++ri) {
+                NLF_HIP(hipEventRecord(h->rdone[ri], h->rstream[ri]));
+                NLF_HIP(hipStreamWaitEvent(s, h->rdone[ri], 0));
+            }
+            NLF_HIP(hipStreamSynchronize(s));
+            if (h->profiling)
+                for (int ri = 0; ri < nreg; ++ri) {
+                    h->rprof[ri]->collect();
+                    h->prof.merge(*h->rprof[ri]);
+                }
         }
         NLF_HIP(hipStreamSynchronize(s));
         if (h->profiling) h->prof.collect();
-        if (status != NLF_OK) {
-            h->last_error = status == NLF_ERR_M0_TOO_SMALL ? "m0 or more Ritz values inside a contour"
-                                                           : "not converged within max_iter";
+        // a hard error (device, argument) wins over the convergence statuses
+        int status = NLF_OK;
+        std::string msg;
+        for (int ri = 0; ri < nreg; ++ri) {
+            const int st = out[ri].status;
+            if (st == NLF_OK) continue;
+            const bool soft = st == NLF_ERR_NOT_CONVERGED || st == NLF_ERR_M0_TOO_SMALL;
+            const bool cur_soft = status == NLF_OK || status == NLF_ERR_NOT_CONVERGED || status == NLF_ERR_M0_TOO_SMALL;
+            if (!soft || cur_soft) {
+                status = st;
+                msg = out[ri].msg;
+            }
         }
+        if (status != NLF_OK) h->last_error = msg;
         return (nlfeast_status)status;
     })
 }

@@ -150,3 +150,98 @@ def test_node_on_eigenvalue_is_singular():
         S.solve(nl.options(tol=1e-10))
     assert e.value.status == nl.NLF_ERR_SINGULAR
     S.close()
+
+
+def test_regions_concurrent_equal_sequential():
+    # two disjoint circles on qep200: the per-region streams/threads give the same pairs as
+    # running the regions one after another on the caller's stream
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    regs = [dict(centre=c, a=r, nc=8, m0=20), dict(centre=c + 3 * r, a=r, nc=8, m0=20)]
+    X0 = wl.initial_block(200, 40, 2001)
+    outs = [gpu_solve(terms, mats, regs, X0, nl.options(tol=1e-12, region_streams=k)) for k in (0, 1)]
+    for o in outs:
+        assert o["status"] == nl.NLF_OK
+    a, b = outs
+    assert np.array_equal(a["inside"], b["inside"]) and np.array_equal(a["m"], b["m"])
+    assert np.array_equal(a["iters"], b["iters"])
+    assert np.max(np.abs(a["lam"] - b["lam"])) < 1e-13
+    # the first region alone reproduces the single-region solve
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    assert match_err(a["lam"][:20][a["inside"][:20]], brute, r) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
+def test_qep2048x8_batched_regions(prec, tol_eig):
+    # eight disjoint regions with m0 from 16 to 128 share one batched factorisation of the 128
+    # node matrices; every region's eigenvalues match the full companion spectrum
+    cfg = wl.CONFIGS["qep2048x8"]
+    terms, mats = wl.make_problem("qep2048x8")
+    gs = contours("qep2048x8")
+    regs = [dict(centre=complex(*g["centre"]), a=g["radius"], nc=cfg["nc"], m0=g["m0"]) for g in gs]
+    M = sum(g["m0"] for g in gs)
+    out = gpu_solve(terms, mats, regs, wl.initial_block(cfg["n"], M, 2000 + cfg["id"]),
+                    nl.options(tol=cfg["tol"], precision=prec))
+    assert out["status"] == nl.NLF_OK
+    col = 0
+    for ri, g in enumerate(gs):
+        sl = slice(col, col + g["m0"])
+        ins = out["inside"][sl]
+        brute = np.array([complex(*v) for v in g["eigenvalues"]])
+        assert ins.sum() == len(brute) == out["m"][ri], (ri, ins.sum(), len(brute))
+        assert match_err(out["lam"][sl][ins], brute, g["radius"]) < tol_eig
+        assert np.max(out["res"][sl][ins]) <= cfg["tol"]
+        hr = host_residuals(terms, mats, out["Xh"][:, sl][:, ins], out["lam"][sl][ins])
+        assert np.max(hr) <= 2 * cfg["tol"]
+        col += g["m0"]
+
+
+def _factor_bytes(S, n, nz, es):
+    return S.ws[: nz * n * n * es].clone()
+
+
+@pytest.mark.parametrize("prec,es", [(nl.NLF_PREC_FP64, 16), (nl.NLF_PREC_FP32_REFINE, 8)])
+def test_graph_replays_equal_eager(prec, es):
+    # the captured factorisation graph, replayed with eager work and synchronisations between
+    # the replays, leaves bit-identical factors and the same eigenpairs as the eager launches
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    regs = [dict(centre=c, a=r, nc=8, m0=20), dict(centre=c + 3 * r, a=r, nc=6, m0=12)]
+    X0 = nl.to_colmajor(wl.initial_block(200, 32, 2001))
+    S = nl.NLFEAST(200)
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    S.set_contour(regs)
+    ref = S.solve(nl.options(tol=1e-12, precision=prec), X0)
+    torch.cuda.synchronize()
+    F0 = _factor_bytes(S, 200, 14, es)
+    for rep in range(3):
+        S.set_contour(regs)                       # invalidates the factors: the graph is replayed
+        out = S.solve(nl.options(tol=1e-12, precision=prec, graph=1), X0)
+        torch.cuda.synchronize()
+        assert torch.equal(_factor_bytes(S, 200, 14, es), F0), rep
+        assert out["status"] == nl.NLF_OK
+        assert np.array_equal(out["inside"], ref["inside"])
+        assert np.max(np.abs(out["lam"] - ref["lam"])) < 1e-13
+        _ = torch.ones(1000, device="cuda").sum().item()    # eager work between replays
+    S.close()
+
+
+def test_autotuned_graph_solve_matches_brute_force():
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    S = nl.NLFEAST(200)
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    S.set_contour([dict(centre=c, a=r, nc=8, m0=20)])
+    nl.nlfeast_set_profiling(S.h, True)
+    out = S.solve(nl.options(tol=1e-12, precision=nl.NLF_PREC_FP32_REFINE, autotune=1, graph=1),
+                  nl.to_colmajor(wl.initial_block(200, 20, 2001)))
+    prof = S.profile()
+    S.close()
+    assert out["status"] == nl.NLF_OK
+    ins = out["inside"]
+    assert match_err(out["lam"][ins], brute, r) < 1e-9
+    assert prof["factor_graph"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
