@@ -33,22 +33,26 @@ def parse():
     ap.add_argument("--workload", default="damped4096")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the eight-region batched workload (qep2048x8)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
     ap.add_argument("--lu-streams", type=int, default=0,
                     help="node-matrix groups factored on separate streams (0 = library default)")
-    ap.add_argument("--probe-gemm", action="store_true",
-                    help="counter runs: one 1 GiB device copy (calibration), then the dominant "
-                         "LU trailing-update GEMM shape three times, nothing else")
+    ap.add_argument("--probe-lu", action="store_true",
+                    help="counter runs: one 1 GiB device copy (calibration), then one FP64 "
+                         "batched blocked LU of the headline shape, nothing else")
     return ap.parse_args()
 
 
-# The largest trailing update of the LU of 16 nodes at n = 4096: C -= A B with M = N = K = 2048.
-PROBE = dict(M=2048, N=2048, K=2048, batch=16)
+# The FP64 factorisation of the headline workload: 16 node matrices of n = 4096.
+PROBE = dict(n=4096, batch=16)
 
 
-def probe_gemm():
-    """Plain copy of known size (to scale HBM counters), then the dominant GEMM launch."""
+def probe_lu():
+    """Counter runs: a plain device copy of known size (to scale the HBM counters), then one
+    batched blocked LU of the headline shape, whose lu_update_kernel launches are the
+    dominant kernel's."""
     import torch
     import paper_1801_09794_amd as nl
     torch.cuda.set_device(0)
@@ -56,22 +60,24 @@ def probe_gemm():
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    M, N, K, bt = PROBE["M"], PROBE["N"], PROBE["K"], PROBE["batch"]
-    A = torch.randn((bt, K, M), dtype=torch.complex128, device="cuda")
-    B = torch.randn((bt, N, K), dtype=torch.complex128, device="cuda")
-    C = torch.randn((bt, N, M), dtype=torch.complex128, device="cuda")
-    for _ in range(3):
-        nl.nlf_gemm_batched("N", M, N, K, -1.0, A, M, M * K, B, K, K * N, 1.0, C, M, M * N, bt)
+    del a, b
+    n, bt = PROBE["n"], PROBE["batch"]
+    g = torch.Generator(device="cuda").manual_seed(7)
+    A = torch.randn((bt, n, n), dtype=torch.complex128, device="cuda", generator=g)
+    ipiv = torch.empty((bt, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty_like(ipiv)
+    info = torch.empty(bt, dtype=torch.int32, device="cuda")
+    dinv = torch.empty(bt * nl.nlf_lu_inverse_elems(n), dtype=torch.complex128, device="cuda")
+    nl.nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv)
     torch.cuda.synchronize()
-    print(json.dumps(dict(probe="gemm c128", copy_bytes=2 * a.numel() * 8,
-                          gemm_algorithmic_bytes=16.0 * bt * (M * K + K * N + 2 * M * N), **PROBE)))
+    print(json.dumps(dict(probe="blocked LU c128", copy_bytes=2 * (1 << 27) * 8, **PROBE)))
 
 
 def load_traffic():
     """HBM traffic of the probe launch from the committed counter summary, or None when the
     GEMM source changed after the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gemm_c128_2048x2048x2048_b16_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "lu_update_c128_n4096_b16_traffic.txt")
     src = os.path.join(ROOT, "paper_1801_09794_amd", "csrc", "gemm.hip")
     if not os.path.exists(path):
         return None
@@ -104,7 +110,7 @@ def load_workload(name):
     return cfg, terms, mats, regions, X0
 
 
-def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile):
+def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0, graph=0):
     import torch
     import paper_1801_09794_amd as nl
     n = cfg["n"]
@@ -114,7 +120,8 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile):
     S.set_contour(regions)
     X0d = nl.to_colmajor(X0, "cuda:0")
     opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3,
-                      lu_streams=args.lu_streams, panel_width=args.panel_width)
+                      lu_streams=args.lu_streams, panel_width=args.panel_width,
+                      autotune=autotune, graph=graph)
     for _ in range(args.warmup):
         S.set_contour(regions)
         S.solve(opts, X0d)
@@ -141,6 +148,42 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile):
     out = outs[-1]
     S.close()
     return (t1 - t0) / args.steps, out, prof
+
+
+def batched_leg(args, fp64_headline):
+    """Eight disjoint regions with uneven m0 (128 node matrices of n = 2048), FP32 LU + FP64
+    refinement with the autotuned launch parameters and the factorisation replayed as one
+    hipGraph; FP64 on the same inputs for the accuracy comparison."""
+    import numpy as np
+    import paper_1801_09794_amd as nl
+    cfg, terms, mats, regions, X0 = load_workload("qep2048x8")
+    n, nz = cfg["n"], sum(r["nc"] for r in regions)
+    t32, o32, p32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True,
+                            autotune=1, graph=1)
+    t64, o64, _ = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, False)
+    c32, c64 = converged_pairs(o32, cfg["tol"]), converged_pairs(o64, cfg["tol"])
+    err = None
+    ok = o32["inside"] & o64["inside"]
+    if np.array_equal(o32["inside"], o64["inside"]) and ok.any():
+        a, b = np.sort_complex(o32["lam"][ok]), np.sort_complex(o64["lam"][ok])
+        err = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-3)))
+    fg = p32["factor_graph"]
+    lu_ms = fg["ms"] / max(fg["launches"], 1)
+    lu_tflops = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
+    return {
+        "workload": "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%d complex Gaussian/sqrt(n), 8 disjoint "
+                    "circles, m0 %s, %d Gauss-Legendre nodes each (%d LUs), tol %.0e"
+                    % (n, [r["m0"] for r in regions], cfg["nc"], nz, cfg["tol"]),
+        "fp32_refine": {"value": c32 / t32, "unit": "eigenpairs/s", "ms_per_step": t32 * 1e3,
+                        "converged": c32, "iterations": [int(v) for v in o32["iters"]],
+                        "factor_graph_ms": lu_ms,
+                        "lu_tflops": lu_tflops,
+                        "lu_frac_fp32_peak": lu_tflops / PEAK["fp32_mfma_tflops"] if lu_tflops else None,
+                        "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p32.items()}},
+        "fp64": {"value": c64 / t64, "ms_per_step": t64 * 1e3, "converged": c64},
+        "max_rel_eig_diff_fp32_vs_fp64": err,
+        "fp32_batched_vs_fp64_headline": (c32 / t32) / fp64_headline if fp64_headline else None,
+    }
 
 
 def converged_pairs(out, tol):
@@ -188,8 +231,8 @@ def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters):
 
 def main():
     args = parse()
-    if args.probe_gemm:
-        probe_gemm()
+    if args.probe_lu:
+        probe_lu()
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -239,17 +282,17 @@ def main():
                "trailing_gemm_tflops": lu_tflops,
                "trailing_gemm_frac_fp64_peak": lu_tflops / PEAK["fp64_mfma_tflops"]},
         "roofline": {
-            "kernel": "gemm_kernel<double> (LU trailing updates)",
+            "kernel": "lu_update_kernel<double, 2, 2, 16> (rank-256 trailing updates of the blocked LU)",
             "bound": "mfma",
             "achieved": lu_tflops,
             "peak": PEAK["fp64_mfma_tflops"],
             "unit": "TFLOP/s",
             "frac": lu_tflops / PEAK["fp64_mfma_tflops"],
             "traffic": load_traffic(),
-            "traffic_note": "HBM bytes per launch of the largest trailing update (M=N=K=2048, "
-                            "16 matrices; algorithmic %.3g B) from FETCH_SIZE + WRITE_SIZE "
-                            "counters scaled by a 1 GiB copy; see profiles/" % (
-                                16.0 * 16 * (3 * 2048 * 2048 + 2048 * 2048)),
+            "traffic_note": "HBM bytes per launch, averaged over the lu_update_kernel launches "
+                            "of one FP64 factorisation of this shape, from FETCH_SIZE + "
+                            "WRITE_SIZE counters scaled by a 1 GiB copy (profiles/)",
+            "algorithmic_bytes_per_launch": lu["bytes"] / max(lu["launches"], 1),
             "launches_per_step": lu["launches"] / args.steps,
             "avg_launch_us": lu["ms"] * 1e3 / max(lu["launches"], 1),
             "flops_per_step": lu["flops"] / args.steps,
@@ -275,6 +318,8 @@ def main():
             if lu32["ms"] > 0 else None,
             "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof32.items()},
         }
+    if not args.no_batched and args.workload != "qep2048x8":
+        result["batched"] = batched_leg(args, value)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

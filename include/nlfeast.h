@@ -144,7 +144,10 @@ typedef enum {
     NLF_K_ACCUMULATE = 8, NLF_K_ORTH = 9, NLF_K_PROJECT = 10, NLF_K_HOST_REDUCED = 11,
     NLF_K_FACTOR_GRAPH = 12,     /* assembly + factorisation replayed as one hipGraph launch */
     NLF_K_AUTOTUNE = 13,         /* trial factorisations of the LU tuner (first use of a shape) */
-    NLF_K_COUNT = 14
+    NLF_K_LU_REC_GEMM = 14,      /* GEMM updates inside the recursive panel factorisation
+                                    (NLF_K_LU_GEMM: the rank-256 trailing updates of the blocked
+                                    LU, kernel symbol lu_update_kernel) */
+    NLF_K_COUNT = 15
 } nlfeast_kernel_class;
 nlfeast_status nlfeast_set_profiling(nlfeast_handle h, int32_t on);
 nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* milliseconds,

@@ -12,7 +12,8 @@ import numpy as np
 import scipy.linalg
 import scipy.sparse.linalg as spla
 
-from .reduced import companion_first
+from .problem import Problem
+from .reduced import companion_first, reduced_coeffs_about, taylor_degree
 
 
 def poly_coeffs(problem):
@@ -76,6 +77,25 @@ def companion_eigs_near(problem, sigma, k, tol=1e-13):
                    ncv=min(N - 1, max(2 * k + 1, 40)))
     lam = sigma + 1.0 / nu
     return lam[np.argsort(np.abs(lam - sigma))]
+
+
+def taylor_surrogate(problem, sigma, rho, tol=1e-16):
+    """The polynomial P(mu) = sum_q mu^q C_q, mu = lambda - sigma, that matches T(sigma + mu)
+    to a relative tail below tol on |mu| <= rho (the Taylor expansion of every f_j; exact for
+    polynomial terms), as a polynomial Problem in mu."""
+    d = taylor_degree(problem.terms, rho, tol)
+    C = reduced_coeffs_about(problem.terms, problem.mats, sigma, d)
+    return Problem([("pow", q) for q in range(d + 1)], C)
+
+
+def eigs_near(problem, sigma, k, rho):
+    """The k eigenvalues of T nearest sigma: shift-invert Arnoldi on the companion form of the
+    Taylor surrogate about sigma (valid on |lambda - sigma| <= rho; the caller checks that the
+    k-th distance stays well inside)."""
+    if problem.is_polynomial:
+        return companion_eigs_near(problem, sigma, k)
+    S = taylor_surrogate(problem, sigma, rho)
+    return sigma + companion_eigs_near(S, 0.0, k)
 
 
 def refine_eigenvalue(problem, lam, steps=3, seed=0):

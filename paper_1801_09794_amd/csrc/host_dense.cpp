@@ -2,9 +2,11 @@
 #include "host_dense.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <limits>
 #include <numeric>
+#include <thread>
 
 namespace nlf {
 
@@ -609,15 +611,16 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
     for (cplx sg : shifts) {
         deg = maxpow;
         if (!poly) {
-            // smallest d with (tau R)^{d+1} e^{tau R} / (d+1)! <= 1e-16 on the disk about the
-            // shift that covers |lambda - c| <= 1.5 max(a, b)
+            // smallest d with (tau R)^{d+1} e^{tau R} / (d+1)! <= 1e-6 on the disk about the
+            // shift that covers |lambda - c| <= 1.5 max(a, b): the truncated expansion only has
+            // to place each Ritz value in the basin of Newton's method on the exact function
             const double R = 1.5 * std::max(E.a, E.b) + std::abs(sg - E.c);
             for (const Term& t : terms) {
                 if (t.kind != 1) continue;
                 const double x = std::fabs(t.param) * R;
                 int e = 1;
                 double term = x * x / 2.0;
-                while (term * std::exp(x) > 1e-16) {
+                while (term * std::exp(x) > 1e-6) {
                     ++e;
                     term *= x / (e + 1);
                 }
@@ -695,14 +698,18 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
         for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = v[(size_t)bb * m + i] / s;
     }
     if (!poly) {
-        // Newton on F(y, l) = [T(l) y; v^H y - 1], Jacobian [[T(l), T'(l) y], [v^H, 0]]
-        std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
-        for (int q = 0; q < keep; ++q) {
+        // Newton on F(y, l) = [T(l) y; v^H y - 1], Jacobian [[T(l), T'(l) y], [v^H, 0]], for the
+        // pairs near the contour (normalised radius < 2); the pairs are independent and are
+        // spread over host threads
+        std::vector<int> todo;
+        for (int q = 0; q < keep; ++q)
+            if (std::isfinite(res.lambda[q].real()) && E.radius(res.lambda[q]) < 2.0) todo.push_back(q);
+        auto polish = [&](int q) {
+            std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
             cplx l = res.lambda[q];
-            if (!std::isfinite(l.real())) continue;
             std::vector<cplx> y(res.Y.begin() + (size_t)q * m, res.Y.begin() + (size_t)(q + 1) * m);
             const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
-            for (int it = 0; it < 3; ++it) {
+            for (int it = 0; it < 6; ++it) {
                 std::fill(Tl.begin(), Tl.end(), cplx(0.0));
                 std::fill(dT.begin(), dT.end(), cplx(0.0));
                 double scale = 0.0;
@@ -718,23 +725,19 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
                     scale += std::abs(f) * std::sqrt(an);
                 }
                 double rn = 0.0;
-                for (int r = 0; r < m; ++r) {
-                    cplx t = 0.0;
-                    for (int c = 0; c < m; ++c) t += Tl[r + (size_t)c * m] * y[c];
-                    rhs[r] = -t;
-                    rn += std::norm(t);
-                }
+                for (int r = 0; r < m; ++r) rhs[r] = 0.0;
+                for (int c = 0; c < m; ++c)
+                    for (int r = 0; r < m; ++r) rhs[r] -= Tl[r + (size_t)c * m] * y[c];
+                for (int r = 0; r < m; ++r) rn += std::norm(rhs[r]);
                 cplx vy = 0.0;
                 for (int i = 0; i < m; ++i) vy += std::conj(v0[i]) * y[i];
                 rhs[m] = -(vy - 1.0);
                 if (std::sqrt(rn) <= 1e-15 * scale && std::abs(rhs[m]) < 1e-15) break;
                 for (int c = 0; c < m; ++c)
                     for (int r = 0; r < m; ++r) Jm[r + (size_t)c * (m + 1)] = Tl[r + (size_t)c * m];
-                for (int r = 0; r < m; ++r) {
-                    cplx t = 0.0;
-                    for (int c = 0; c < m; ++c) t += dT[r + (size_t)c * m] * y[c];
-                    Jm[r + (size_t)m * (m + 1)] = t;
-                }
+                for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] = 0.0;
+                for (int c = 0; c < m; ++c)
+                    for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] += dT[r + (size_t)c * m] * y[c];
                 for (int c = 0; c < m; ++c) Jm[m + (size_t)c * (m + 1)] = std::conj(v0[c]);
                 Jm[m + (size_t)m * (m + 1)] = 0.0;
                 if (!lu_solve_small(m + 1, Jm, rhs.data(), 1)) break;
@@ -746,6 +749,19 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
             s = std::sqrt(s);
             for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = y[i] / s;
             res.lambda[q] = l;
+        };
+        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int nth = std::max(1, std::min({hw, 16, (int)todo.size() / 2}));
+        if (nth <= 1 || (size_t)m * m * todo.size() < 200000) {
+            for (int q : todo) polish(q);
+        } else {
+            std::atomic<size_t> next{0};
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nth; ++t)
+                pool.emplace_back([&] {
+                    for (size_t i; (i = next.fetch_add(1)) < todo.size();) polish(todo[i]);
+                });
+            for (auto& t : pool) t.join();
         }
     }
     res.n_finite = 0;

@@ -10,12 +10,13 @@ struct GemmConfig {
 };
 
 // C_b = alpha op(A_b) B_b + beta C_b, op(A) = A^H when conjA.  ws (optional) enables split-K
-// for small outputs with long reductions.  force overrides the tile choice.
+// for small outputs with long reductions.  force overrides the tile choice.  lu_update launches
+// the same tile program under the lu_update_kernel symbol (LU trailing updates; no split-K).
 template <typename R>
 void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alpha,
           const Cx<R>* A, int64_t lda, int64_t sA, const Cx<R>* B, int64_t ldb, int64_t sB,
           Cx<R> beta, Cx<R>* C, int64_t ldc, int64_t sC, int batch, Cx<R>* ws = nullptr,
-          int64_t ws_elems = 0, const GemmConfig* force = nullptr);
+          int64_t ws_elems = 0, const GemmConfig* force = nullptr, bool lu_update = false);
 
 // LU with partial pivoting (in place), batched over strided matrices.  With dinv and tmp
 // (getrf_tmp_elems per matrix) it runs right-looking with 256-column panels and leaves the

@@ -544,7 +544,7 @@ static void getrf_rec(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda
                        lda, sA);
     const int64_t mrest = n - (k0 + n1);
     {
-        ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * mrest * n2 * n1 * batch,
+        ProfScope ps(NLF_PROF_LU_REC_GEMM, s, 8.0 * mrest * n2 * n1 * batch,
                      sizeof(Cx<R>) * (2.0 * mrest * n2 + (double)mrest * n1 + (double)n1 * n2) * batch);
         gemm<R>(s, false, mrest, n2, n1, Cx<R>(-1, 0), A + (k0 + n1) + k0 * lda, lda, sA,
                 A + k0 + (k0 + n1) * lda, lda, sA, Cx<R>(1, 0),
@@ -606,7 +606,7 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
             ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * rest * kb * batch,
                          sizeof(Cx<R>) * (2.0 * rest * rest + 2.0 * rest * kb) * batch);
             gemm<R>(s, false, rest, rest, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
-                    A + k1 + k1 * lda, lda, sA, batch, nullptr, 0, update_tile());
+                    A + k1 + k1 * lda, lda, sA, batch, nullptr, 0, update_tile(), true);
         }
     }
 }

@@ -18,6 +18,13 @@ Recipes (contour seed 3000 + id):
               m0_r) eigenvalues each, centres drawn in the bulk |lambda| < 0.8, radius at
               the gap midpoint, rejected under a 5% gap or when two circles come closer
               than 10% of the larger radius.
+  delay512, delay8192
+              centre c = i y0, y0 ~ U(0.3, 1.5); the p + max(10, p/3) eigenvalues nearest c
+              from shift-invert Arnoldi on the companion form of the Taylor surrogate of
+              T(c + mu) (tail below 1e-16 on |mu| <= rho); the nearest p + 6 are sharpened by
+              two steps of two-sided Rayleigh functional iteration on T itself; radius =
+              midpoint between the p-th and (p+1)-th distances; rejected under a 2% relative
+              gap.  delay512 also stores the winding number of det T along the circle.
 """
 import json
 import os
@@ -30,7 +37,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import workloads as wl  # noqa: E402
-from oracle import brute, problem as pb  # noqa: E402
+from oracle import brute, problem as pb, quadrature as qd  # noqa: E402
 
 OUT = os.path.join(HERE, "contours.json")
 
@@ -98,18 +105,51 @@ def qep2048x8():
     return dict(regions=regions)
 
 
-RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8}
+def delay(name, rho):
+    cfg = wl.CONFIGS[name]
+    terms, mats = wl.make_problem(name)
+    P = pb.Problem(terms, mats)
+    rng = np.random.default_rng(3000 + cfg["id"])
+    p = cfg["inside"]
+    k = p + max(10, p // 3)
+    while True:
+        c = 1j * rng.uniform(0.3, 1.5)
+        lam = brute.eigs_near(P, c, k, rho)
+        if np.max(np.abs(lam - c)) > rho / 1.2:
+            raise RuntimeError("surrogate disk too small: raise rho")
+        _, r, gap = ring(lam, c, p)
+        if gap < 0.02:
+            continue
+        order = np.argsort(np.abs(lam - c))
+        lam = lam[order]
+        res = np.zeros(p + 6)
+        for i in range(p + 6):
+            lam[i], res[i] = brute.refine_eigenvalue(P, lam[i], steps=2, seed=i)
+        _, r, gap = ring(lam, c, p)
+        if gap >= 0.02:
+            break
+    inside = lam[np.abs(lam - c) < r]
+    out = dict(centre=[c.real, c.imag], radius=r, gap=gap, max_residual=float(res.max()),
+               eigenvalues=[[v.real, v.imag] for v in inside])
+    if cfg["n"] <= 1024:
+        out["winding_count"] = brute.winding_count(P, qd.Contour(c, r))
+    return dict(regions=[out])
+
+
+RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8,
+           "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.08)}
 
 
 def main(names):
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         t0 = time.time()
-        data[name] = RECIPES[name]()
-        data[name]["seconds"] = time.time() - t0
-        print(name, "regions", len(data[name]["regions"]),
-              "inside", [len(g["eigenvalues"]) for g in data[name]["regions"]],
-              "%.1fs" % data[name]["seconds"], flush=True)
+        entry = RECIPES[name]()
+        entry["seconds"] = time.time() - t0
+        print(name, "regions", len(entry["regions"]),
+              "inside", [len(g["eigenvalues"]) for g in entry["regions"]],
+              "%.1fs" % entry["seconds"], flush=True)
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}   # re-read: merge, not clobber
+        data[name] = entry
         json.dump(data, open(OUT, "w"), indent=1)
 
 

@@ -245,3 +245,31 @@ def test_autotuned_graph_solve_matches_brute_force():
     ins = out["inside"]
     assert match_err(out["lam"][ins], brute, r) < 1e-9
     assert prof["factor_graph"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
+
+
+@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
+def test_delay512_matches_oracle_and_surrogate(prec, tol_eig):
+    # T(l) = l^2 I + l C + K + exp(-l) E: the non-polynomial reduced problem (Taylor surrogate
+    # + Newton on the exact reduced function) on the GPU path; the count is certified by the
+    # winding number of det T along the circle
+    cfg = wl.CONFIGS["delay512"]
+    terms, mats = wl.make_problem("delay512")
+    g = contours("delay512")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    assert len(ref) == g["winding_count"] == cfg["inside"]
+    X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
+                    nl.options(tol=cfg["tol"], precision=prec))
+    assert out["status"] == nl.NLF_OK
+    ins = out["inside"]
+    assert ins.sum() == len(ref)
+    assert match_err(out["lam"][ins], ref, r) < tol_eig
+    assert np.max(out["res"][ins]) <= cfg["tol"]
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+    C = qd.Contour(c, r)
+    z, w = qd.nodes_weights(C, cfg["nc"])
+    ro = onl.solve(pb.Problem(terms, mats), C, z, w, X0, cfg["m0"], cfg["tol"])
+    assert ro.converged
+    assert match_err(out["lam"][ins], ro.eigenvalues, r) < tol_eig

@@ -112,7 +112,9 @@ CONFIGS = {
     "damped4096": dict(id=2, kind="damped_qep", n=4096, m0=64, nc=16, tol=1e-10, inside=40),
     "qep2048x8": dict(id=4, kind="random_qep", n=2048, nc=16, tol=1e-10,
                       m0s=[16, 24, 32, 48, 64, 80, 96, 128]),
-    "delay8192": dict(id=5, kind="delay_problem", n=8192, m0=160, nc=24, tol=1e-10),
+    "delay8192": dict(id=5, kind="delay_problem", n=8192, m0=160, nc=24, tol=1e-10, inside=100),
+    # the delay problem at a size the oracle iterates in seconds (parity case)
+    "delay512": dict(id=6, kind="delay_problem", n=512, m0=24, nc=16, tol=1e-11, inside=12),
 }
 
 
