@@ -37,6 +37,8 @@ def parse():
                     help="skip the eight-region batched workload (qep2048x8)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
+    ap.add_argument("--lookahead", type=int, default=0,
+                    help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
     ap.add_argument("--lu-streams", type=int, default=0,
                     help="node-matrix groups factored on separate streams (0 = library default)")
     ap.add_argument("--probe-lu", action="store_true",
@@ -121,7 +123,7 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     X0d = nl.to_colmajor(X0, "cuda:0")
     opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3,
                       lu_streams=args.lu_streams, panel_width=args.panel_width,
-                      autotune=autotune, graph=graph)
+                      autotune=autotune, graph=graph, lookahead=args.lookahead)
     for _ in range(args.warmup):
         S.set_contour(regions)
         S.solve(opts, X0d)
@@ -167,7 +169,7 @@ def batched_leg(args, fp64_headline):
     if np.array_equal(o32["inside"], o64["inside"]) and ok.any():
         a, b = np.sort_complex(o32["lam"][ok]), np.sort_complex(o64["lam"][ok])
         err = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-3)))
-    fg = p32["factor_graph"]
+    fg = p32["factor"]
     lu_ms = fg["ms"] / max(fg["launches"], 1)
     lu_tflops = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
     return {
@@ -176,7 +178,7 @@ def batched_leg(args, fp64_headline):
                     % (n, [r["m0"] for r in regions], cfg["nc"], nz, cfg["tol"]),
         "fp32_refine": {"value": c32 / t32, "unit": "eigenpairs/s", "ms_per_step": t32 * 1e3,
                         "converged": c32, "iterations": [int(v) for v in o32["iters"]],
-                        "factor_graph_ms": lu_ms,
+                        "factor_ms": lu_ms,
                         "lu_tflops": lu_tflops,
                         "lu_frac_fp32_peak": lu_tflops / PEAK["fp32_mfma_tflops"] if lu_tflops else None,
                         "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p32.items()}},
@@ -253,7 +255,8 @@ def main():
     lu_tflops = lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0
     nnodes = sum(r["nc"] for r in regions)
     lu_flops_total = 8.0 / 3.0 * n ** 3 * nnodes
-    lu_phase_ms = sum(prof[k]["ms"] for k in ("lu_gemm", "lu_panel", "lu_trsm", "lu_laswp")) / args.steps
+    # wall span of assembly + factorisation of all nodes (panels overlap the updates)
+    lu_phase_ms = prof["factor"]["ms"] / args.steps
     result = {
         "metric": "converged eigenpairs/sec + LU TFLOP/s (% MFMA peak), FP32+refine vs FP64",
         "value": value,

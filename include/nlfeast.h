@@ -89,8 +89,12 @@ typedef struct {
     int32_t graph;               /* 1: capture assembly + batched factorisation of all nodes in
                                     a hipGraph on first use and replay it on later solves with
                                     the same shapes, coefficient pointers and workspace (per-launch
-                                    profiling of those kernels is then replaced by one
-                                    NLF_K_FACTOR_GRAPH entry) */
+                                    profiling of those kernels is then replaced by the one
+                                    NLF_K_FACTOR entry) */
+    int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
+                                    the trailing update of panel k runs; -1 = one stream;
+                                    0 = library default (one stream) */
+    int32_t reserved;            /* must be 0 */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -142,7 +146,8 @@ typedef enum {
     NLF_K_ASSEMBLE = 0, NLF_K_LU_GEMM = 1, NLF_K_LU_PANEL = 2, NLF_K_LU_TRSM = 3,
     NLF_K_LU_LASWP = 4, NLF_K_SOLVE = 5, NLF_K_REFINE = 6, NLF_K_RESIDUAL = 7,
     NLF_K_ACCUMULATE = 8, NLF_K_ORTH = 9, NLF_K_PROJECT = 10, NLF_K_HOST_REDUCED = 11,
-    NLF_K_FACTOR_GRAPH = 12,     /* assembly + factorisation replayed as one hipGraph launch */
+    NLF_K_FACTOR = 12,           /* wall span of assembly + factorisation of all nodes on the
+                                    solve stream (eager launches or one graph replay) */
     NLF_K_AUTOTUNE = 13,         /* trial factorisations of the LU tuner (first use of a shape) */
     NLF_K_LU_REC_GEMM = 14,      /* GEMM updates inside the recursive panel factorisation
                                     (NLF_K_LU_GEMM: the rank-256 trailing updates of the blocked

@@ -25,7 +25,7 @@ NLF_PREC_FP64, NLF_PREC_FP32_REFINE = 0, 1
 NLF_QUAD_GAUSS_LEGENDRE, NLF_QUAD_TRAPEZOID = 0, 1
 NLF_C64, NLF_C128 = 0, 1
 KERNEL_CLASSES = ["assemble", "lu_gemm", "lu_panel", "lu_trsm", "lu_laswp", "solve", "refine",
-                  "residual", "accumulate", "orth", "project", "host_reduced", "factor_graph",
+                  "residual", "accumulate", "orth", "project", "host_reduced", "factor",
                   "autotune", "lu_rec_gemm"]
 
 STATUS_NAMES = {0: "NLF_OK", 1: "NLF_ERR_ARG", 2: "NLF_ERR_NOMEM", 3: "NLF_ERR_DEVICE",
@@ -45,14 +45,15 @@ class Options(ctypes.Structure):
                 ("refine_eta", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("autotune", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("lu_streams", ctypes.c_int32), ("panel_width", ctypes.c_int32),
-                ("region_streams", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("region_streams", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("lookahead", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def options(tol=1e-10, max_iter=50, precision=NLF_PREC_FP64, max_refine=5, refine_eta=1e-3,
             seed=2024, autotune=0, verbose=0, lu_streams=0, panel_width=0, region_streams=0,
-            graph=0):
+            graph=0, lookahead=0):
     return Options(tol, max_iter, precision, max_refine, refine_eta, seed, autotune, verbose,
-                   lu_streams, panel_width, region_streams, graph)
+                   lu_streams, panel_width, region_streams, graph, lookahead, 0)
 
 
 _lib = None

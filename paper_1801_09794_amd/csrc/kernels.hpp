@@ -27,10 +27,16 @@ int64_t getrf_tmp_elems(int64_t n);
 int& lu_panel_width();
 // Per-thread override of the LU trailing-update GEMM tile ({0, 0} = default choice).
 GemmConfig& lu_update_tile();
+// Look-ahead resources for the blocked LU: a second stream for the panel factorisations and
+// two events owned by the caller (all null: one stream).
+struct LuAux {
+    hipStream_t s = nullptr;
+    hipEvent_t panel_done = nullptr, next_ready = nullptr;
+};
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
            int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch,
-           Cx<R>* dinv = nullptr, Cx<R>* tmp = nullptr);
+           Cx<R>* dinv = nullptr, Cx<R>* tmp = nullptr, const LuAux* aux = nullptr);
 // Scratch (int32 elements) that getrf needs for its row-exchange lists.
 int64_t getrf_scratch_ints(int64_t n, int batch);
 

@@ -572,41 +572,71 @@ static void identity_pair(hipStream_t s, int batch, int64_t NB, int64_t per, Cx<
 //   left and right of it; invert the diagonal blocks L11 and U11 (kept for the solves: later
 //   exchanges only touch rows below the block, so both are final here);
 //   U12 = L11^{-1} A12 as a GEMM with the explicit inverse; A22 -= A21 U12 (rank-256 GEMM).
+// With a look-ahead stream, the panel factorisations and diagonal-block inverses run there:
+// the columns of panel k+1 are updated first, so that panel k+1 is factored while the rest of
+// the trailing matrix is updated on the main stream.  Panel k+1 only touches its own columns,
+// the trailing update only the columns after it, and the row exchanges of panel k+1 (main
+// stream) wait for both.
 // tmp holds LU_INV_NB x (n - LU_INV_NB) elements per matrix.
 template <typename R>
 static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
-                          int32_t* ipiv, int32_t* info, int32_t* list, Cx<R>* dinv, Cx<R>* tmp) {
+                          int32_t* ipiv, int32_t* info, int32_t* list, Cx<R>* dinv, Cx<R>* tmp,
+                          const LuAux* aux) {
     const int64_t NB = LU_INV_NB, per = lu_inverse_elems(n);
     const int64_t st = NB * std::max<int64_t>(n - NB, 1);
     const Cx<R> one(1, 0), mone(-1, 0), zero(0, 0);
+    const bool la = aux && aux->s && aux->panel_done && aux->next_ready;
+    hipStream_t sp = la ? aux->s : s;
+    if (la) {   // panel 0 follows the work already queued on the main stream
+        NLF_HIP(hipEventRecord(aux->next_ready, s));
+        NLF_HIP(hipStreamWaitEvent(sp, aux->next_ready, 0));
+    }
     for (int64_t k0 = 0; k0 < n; k0 += NB) {
         const int64_t kb = std::min<int64_t>(NB, n - k0), k1 = k0 + kb, rest = n - k1;
-        getrf_rec<R>(s, n, batch, A, lda, sA, k0, kb, ipiv, info, list);
-        laswp<R>(s, batch, A, lda, sA, n, k0, k1, 0, k0, ipiv, list);
-        laswp<R>(s, batch, A, lda, sA, n, k0, k1, k1, rest, ipiv, list);
         const int64_t b = k0 / NB;
         Cx<R>* Li = dinv + 2 * b * NB * NB;
         Cx<R>* Ui = Li + NB * NB;
-        identity_pair<R>(s, batch, NB, per, Li);
-        const Cx<R>* D = A + k0 + k0 * lda;
-        trsm_lower_unit<R>(s, kb, kb, batch, D, lda, sA, Li, NB, per);
-        trsm_upper<R>(s, kb, kb, batch, D, lda, sA, Ui, NB, per);
-        if (rest > 0) {
-            Cx<R>* A12 = A + k0 + k1 * lda;
+        {
+            getrf_rec<R>(sp, n, batch, A, lda, sA, k0, kb, ipiv, info, list);
+            identity_pair<R>(sp, batch, NB, per, Li);
+            const Cx<R>* D = A + k0 + k0 * lda;
+            trsm_lower_unit<R>(sp, kb, kb, batch, D, lda, sA, Li, NB, per);
+            trsm_upper<R>(sp, kb, kb, batch, D, lda, sA, Ui, NB, per);
+        }
+        if (la) {
+            NLF_HIP(hipEventRecord(aux->panel_done, sp));
+            NLF_HIP(hipStreamWaitEvent(s, aux->panel_done, 0));
+        }
+        laswp<R>(s, batch, A, lda, sA, n, k0, k1, 0, k0, ipiv, list);
+        laswp<R>(s, batch, A, lda, sA, n, k0, k1, k1, rest, ipiv, list);
+        // columns [c0, c0 + w) of the trailing matrix: U12 = L11^{-1} A12, A22 -= A21 U12
+        auto update = [&](int64_t c0, int64_t w) {
+            Cx<R>* A12 = A + k0 + c0 * lda;
             {
-                dim3 grid((unsigned)std::min<int64_t>(ceil_div(kb * rest, 256), 2048), batch);
-                hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, kb, rest,
+                dim3 grid((unsigned)std::min<int64_t>(ceil_div(kb * w, 256), 2048), batch);
+                hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, kb, w,
                                    (const Cx<R>*)A12, lda, sA, tmp, NB, st);
                 NLF_HIP(hipGetLastError());
             }
             {
-                ProfScope ps(NLF_PROF_TRSM, s, 8.0 * kb * rest * kb * batch, 0);
-                gemm<R>(s, false, kb, rest, kb, one, Li, NB, per, tmp, NB, st, zero, A12, lda, sA, batch);
+                ProfScope ps(NLF_PROF_TRSM, s, 8.0 * kb * w * kb * batch, 0);
+                gemm<R>(s, false, kb, w, kb, one, Li, NB, per, tmp, NB, st, zero, A12, lda, sA, batch);
             }
-            ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * rest * kb * batch,
-                         sizeof(Cx<R>) * (2.0 * rest * rest + 2.0 * rest * kb) * batch);
-            gemm<R>(s, false, rest, rest, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
-                    A + k1 + k1 * lda, lda, sA, batch, nullptr, 0, update_tile(), true);
+            ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * w * kb * batch,
+                         sizeof(Cx<R>) * (2.0 * rest * w + (double)rest * kb + (double)kb * w) * batch);
+            gemm<R>(s, false, rest, w, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
+                    A + k1 + c0 * lda, lda, sA, batch, nullptr, 0, update_tile(), true);
+        };
+        if (rest > 0) {
+            if (!la) {
+                update(k1, rest);
+            } else {
+                const int64_t w1 = std::min<int64_t>(NB, rest);
+                update(k1, w1);                       // the next panel's columns
+                NLF_HIP(hipEventRecord(aux->next_ready, s));
+                NLF_HIP(hipStreamWaitEvent(sp, aux->next_ready, 0));
+                if (rest > w1) update(k1 + w1, rest - w1);
+            }
         }
     }
 }
@@ -615,12 +645,13 @@ int64_t getrf_tmp_elems(int64_t n) { return LU_INV_NB * std::max<int64_t>(n - LU
 
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
-           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch, Cx<R>* dinv, Cx<R>* tmp) {
+           int32_t* ipiv, int32_t* perm, int32_t* info, int32_t* scratch, Cx<R>* dinv, Cx<R>* tmp,
+           const LuAux* aux) {
     if (n <= 0 || batch <= 0) return;
     NLF_REQUIRE(n <= 8192, 1, "getrf: n > 8192 not supported");
     fill_i32(s, info, batch, 0);
     if (dinv && tmp)
-        getrf_blocked<R>(s, n, batch, A, lda, sA, ipiv, info, scratch, dinv, tmp);
+        getrf_blocked<R>(s, n, batch, A, lda, sA, ipiv, info, scratch, dinv, tmp, aux);
     else
         getrf_rec<R>(s, n, batch, A, lda, sA, 0, n, ipiv, info, scratch);
     if (perm) {
@@ -737,9 +768,9 @@ template void getrs_inv<float>(hipStream_t, int64_t, int, int, const Cx<float>*,
                                Cx<float>*, int64_t, int64_t, Cx<float>*);
 
 template void getrf<double>(hipStream_t, int64_t, int, Cx<double>*, int64_t, int64_t, int32_t*,
-                            int32_t*, int32_t*, int32_t*, Cx<double>*, Cx<double>*);
+                            int32_t*, int32_t*, int32_t*, Cx<double>*, Cx<double>*, const LuAux*);
 template void getrf<float>(hipStream_t, int64_t, int, Cx<float>*, int64_t, int64_t, int32_t*,
-                           int32_t*, int32_t*, int32_t*, Cx<float>*, Cx<float>*);
+                           int32_t*, int32_t*, int32_t*, Cx<float>*, Cx<float>*, const LuAux*);
 template void getrs<double>(hipStream_t, int64_t, int, int, const Cx<double>*, int64_t, int64_t,
                             const int32_t*, const Cx<double>*, int64_t, int64_t, Cx<double>*,
                             int64_t, int64_t);

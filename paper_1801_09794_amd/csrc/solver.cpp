@@ -141,7 +141,7 @@ struct GraphKey {
     int NZ = 0, J = 0;
     int64_t lda = 0;
     std::vector<const void*> A;
-    std::array<int, 4> tune{};
+    std::array<int, 5> tune{};
     bool operator==(const GraphKey& o) const {
         return ws == o.ws && prec == o.prec && n == o.n && NZ == o.NZ && J == o.J && lda == o.lda && A == o.A &&
                tune == o.tune;
@@ -175,6 +175,9 @@ struct nlfeast_ctx {
     std::vector<hipEvent_t> rdone;
     std::vector<std::unique_ptr<Profiler>> rprof;
     hipEvent_t ev_lufork = nullptr;
+    hipStream_t la_stream[4] = {nullptr, nullptr, nullptr, nullptr};   // LU look-ahead streams
+    hipEvent_t la_panel[4] = {nullptr, nullptr, nullptr, nullptr}, la_next[4] = {nullptr, nullptr, nullptr, nullptr};
+
     hipStream_t gstream = nullptr;                         // capture stream of the factorisation graph
     hipGraphExec_t graph_exec = nullptr;
     GraphKey graph_key;
@@ -185,6 +188,11 @@ struct nlfeast_ctx {
     ~nlfeast_ctx() {
         drop_graph();
         if (gstream) (void)hipStreamDestroy(gstream);
+        for (int i = 0; i < 4; ++i) {
+            if (la_stream[i]) (void)hipStreamDestroy(la_stream[i]);
+            if (la_panel[i]) (void)hipEventDestroy(la_panel[i]);
+            if (la_next[i]) (void)hipEventDestroy(la_next[i]);
+        }
         if (ev_lufork) (void)hipEventDestroy(ev_lufork);
         for (hipStream_t r : rstream) (void)hipStreamDestroy(r);
         for (hipEvent_t e : rdone) (void)hipEventDestroy(e);
@@ -344,8 +352,10 @@ struct LuTuning {
     int panel_width = 32;
     int groups = 1;
     int tm = 0, tn = 0;   // 0: default tile choice
+    int lookahead = 0;
     bool operator==(const LuTuning& o) const {
-        return panel_width == o.panel_width && groups == o.groups && tm == o.tm && tn == o.tn;
+        return panel_width == o.panel_width && groups == o.groups && tm == o.tm && tn == o.tn &&
+               lookahead == o.lookahead;
     }
 };
 
@@ -353,6 +363,7 @@ LuTuning fixed_tuning(const nlfeast_options& o) {
     LuTuning t;
     if (o.panel_width) t.panel_width = o.panel_width;
     if (o.lu_streams) t.groups = o.lu_streams;
+    if (o.lookahead) t.lookahead = o.lookahead > 0 ? 1 : 0;
     return t;
 }
 
@@ -393,10 +404,24 @@ void factor_all(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStream_t
     const int64_t dper = lu_inverse_elems(n);
     const int64_t lper = getrf_scratch_ints(n, 1);
     const int64_t tper = getrf_tmp_elems(n);
+    if (t.lookahead)
+        for (int g = 0; g < groups; ++g)
+            if (!h->la_stream[g]) {
+                NLF_HIP(hipStreamCreateWithFlags(&h->la_stream[g], hipStreamNonBlocking));
+                NLF_HIP(hipEventCreateWithFlags(&h->la_panel[g], hipEventDisableTiming));
+                NLF_HIP(hipEventCreateWithFlags(&h->la_next[g], hipEventDisableTiming));
+            }
     for (int g = 0; g < groups; ++g) {
         const int q0 = (int)((int64_t)L.NZ * g / groups), q1 = (int)((int64_t)L.NZ * (g + 1) / groups);
         if (q1 <= q0) continue;
+        const int nb = q1 - q0;
         hipStream_t sg = cs;
+        LuAux aux;
+        if (t.lookahead) {
+            aux.s = h->la_stream[g];
+            aux.panel_done = h->la_panel[g];
+            aux.next_ready = h->la_next[g];
+        }
         if (groups > 1) {
             if (!h->side[g]) {
                 NLF_HIP(hipStreamCreateWithFlags(&h->side[g], hipStreamNonBlocking));
@@ -405,17 +430,17 @@ void factor_all(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStream_t
             sg = h->side[g];
             NLF_HIP(hipStreamWaitEvent(sg, h->ev_lufork, 0));
         }
-        const int nb = q1 - q0;
         int32_t* ipiv = at<int32_t>(ws, L.ipiv) + (size_t)q0 * n;
         int32_t* perm = at<int32_t>(ws, L.perm) + (size_t)q0 * n;
         int32_t* info = at<int32_t>(ws, L.info) + q0;
         int32_t* list = at<int32_t>(ws, L.list) + (size_t)q0 * lper;
         if (p32)
             getrf<float>(sg, n, nb, at<z64>(ws, L.fact) + (size_t)q0 * nn, n, (int64_t)nn, ipiv, perm, info, list,
-                         at<z64>(ws, L.dinv) + (size_t)q0 * dper, at<z64>(ws, L.ftmp) + (size_t)q0 * tper);
+                         at<z64>(ws, L.dinv) + (size_t)q0 * dper, at<z64>(ws, L.ftmp) + (size_t)q0 * tper, &aux);
         else
             getrf<double>(sg, n, nb, at<z128>(ws, L.fact) + (size_t)q0 * nn, n, (int64_t)nn, ipiv, perm, info,
-                          list, at<z128>(ws, L.dinv) + (size_t)q0 * dper, at<z128>(ws, L.ftmp) + (size_t)q0 * tper);
+                          list, at<z128>(ws, L.dinv) + (size_t)q0 * dper, at<z128>(ws, L.ftmp) + (size_t)q0 * tper,
+                          &aux);
         if (groups > 1) {
             NLF_HIP(hipEventRecord(h->ev_join[g], sg));
             NLF_HIP(hipStreamWaitEvent(cs, h->ev_join[g], 0));
@@ -436,20 +461,27 @@ LuTuning autotuned(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStrea
         if (it != g_tune_cache.end()) return it->second;
     }
     std::vector<int> pws = o.panel_width ? std::vector<int>{o.panel_width} : std::vector<int>{16, 32};
-    std::vector<int> grs = o.lu_streams ? std::vector<int>{o.lu_streams} : std::vector<int>{1, 2};
+    std::vector<int> las = o.lookahead ? std::vector<int>{o.lookahead > 0 ? 1 : 0} : std::vector<int>{0, 1};
     std::vector<std::pair<int, int>> tiles = p32 ? std::vector<std::pair<int, int>>{{0, 0}, {2, 2}, {4, 4}}
                                                  : std::vector<std::pair<int, int>>{{0, 0}, {4, 2}};
+    const int g0 = o.lu_streams ? o.lu_streams : 1;
     std::vector<LuTuning> cand;
-    for (int pw : pws)
-        for (int g : grs)
+    for (int la : las)
+        for (int pw : pws)
             for (auto tl : tiles) {
                 LuTuning t;
                 t.panel_width = pw;
-                t.groups = g;
+                t.groups = g0;
                 t.tm = tl.first;
                 t.tn = tl.second;
+                t.lookahead = la;
                 cand.push_back(t);
             }
+    if (!o.lu_streams) {   // two node groups on separate streams, other parameters at default
+        LuTuning t = cand[0];
+        t.groups = 2;
+        cand.push_back(t);
+    }
     Profiler* saved = active_profiler();
     active_profiler() = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -468,8 +500,8 @@ LuTuning autotuned(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, hipStrea
             NLF_HIP(hipEventElapsedTime(&ms, e0, e1));
             total_ms += ms;
             if (o.verbose)
-                fprintf(stderr, "[nlfeast] tune pw %d groups %d tile %dx%d: %.3f ms\n", cand[c].panel_width,
-                        cand[c].groups, cand[c].tm, cand[c].tn, ms);
+                fprintf(stderr, "[nlfeast] tune pw %d groups %d tile %dx%d lookahead %d: %.3f ms\n",
+                        cand[c].panel_width, cand[c].groups, cand[c].tm, cand[c].tn, cand[c].lookahead, ms);
             if (c == 0 || ms < best_ms) {
                 best_ms = ms;
                 best = cand[c];
@@ -502,7 +534,7 @@ GraphKey graph_key(const nlfeast_ctx* h, const Layout& L, const void* ws, int pr
     k.J = h->J;
     k.lda = h->lda;
     k.A.assign(h->A.begin(), h->A.end());
-    k.tune = {t.panel_width, t.groups, t.tm, t.tn};
+    k.tune = {t.panel_width, t.groups, t.tm, t.tn, t.lookahead};
     return k;
 }
 
@@ -873,6 +905,8 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         NLF_REQUIRE((opt->region_streams == 0 || opt->region_streams == 1) && (opt->graph == 0 || opt->graph == 1) &&
                         (opt->autotune == 0 || opt->autotune == 1),
                     NLF_ERR_ARG, "solve: region_streams, graph and autotune are 0 or 1");
+        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && opt->reserved == 0, NLF_ERR_ARG,
+                    "solve: lookahead in -1..1, reserved 0");
         const Layout L = make_layout(h, opt->precision);
         NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
         NLF_HIP(hipSetDevice(h->device));
@@ -900,9 +934,10 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                     capture_factorisation(h, L, ws, p32, tune);
                     h->graph_key = key;
                 }
-                ProfScope ps(NLF_PROF_FACTOR_GRAPH, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
+                ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
                 NLF_HIP(hipGraphLaunch(h->graph_exec, s));
             } else {
+                ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
                 factor_all(h, L, ws, p32, s, tune);
             }
             std::vector<int32_t> info(L.NZ);

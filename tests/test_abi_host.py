@@ -30,8 +30,8 @@ def test_exports_every_header_function(lib):
 
 
 def test_options_struct_layout():
-    # the C struct: double, 3 x int32, double, uint64, 6 x int32
-    assert ctypes.sizeof(nl.Options) == 64
+    # the C struct: double, 3 x int32, double, uint64, 8 x int32
+    assert ctypes.sizeof(nl.Options) == 72
     assert nl.Options.refine_eta.offset == 24 and nl.Options.seed.offset == 32
 
 

@@ -244,7 +244,7 @@ def test_autotuned_graph_solve_matches_brute_force():
     assert out["status"] == nl.NLF_OK
     ins = out["inside"]
     assert match_err(out["lam"][ins], brute, r) < 1e-9
-    assert prof["factor_graph"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
+    assert prof["factor"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
 
 
 @pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
@@ -273,3 +273,28 @@ def test_delay512_matches_oracle_and_surrogate(prec, tol_eig):
     ro = onl.solve(pb.Problem(terms, mats), C, z, w, X0, cfg["m0"], cfg["tol"])
     assert ro.converged
     assert match_err(out["lam"][ins], ro.eigenvalues, r) < tol_eig
+
+
+@pytest.mark.parametrize("prec,es", [(nl.NLF_PREC_FP64, 16), (nl.NLF_PREC_FP32_REFINE, 8)])
+def test_lookahead_factors_equal_single_stream(prec, es):
+    # n = 700: three 256-column panels, the last one ragged; look-ahead (panel k+1 on a second
+    # stream during the trailing update of panel k), eager and captured in a graph, leaves
+    # the same bits as the one-stream factorisation
+    n = 700
+    terms, mats = wl.random_qep(n, 77)
+    regs = [dict(centre=0.1 + 0.2j, a=0.08, nc=6, m0=12), dict(centre=-0.3 - 0.1j, a=0.08, nc=4, m0=12)]
+    X0 = nl.to_colmajor(wl.initial_block(n, 24, 78))
+    S = nl.NLFEAST(n)
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    facs, outs = [], []
+    for la, graph in [(-1, 0), (1, 0), (1, 1), (1, 1)]:
+        S.set_contour(regs)
+        outs.append(S.solve(nl.options(tol=1e-10, precision=prec, lookahead=la, graph=graph,
+                                       max_iter=3), X0))
+        torch.cuda.synchronize()
+        facs.append(_factor_bytes(S, n, 10, es))
+    S.close()
+    for f in facs[1:]:
+        assert torch.equal(f, facs[0])
+    for o in outs[1:]:
+        assert np.max(np.abs(o["lam"] - outs[0]["lam"])) < 1e-13
