@@ -321,62 +321,128 @@ bool eig_dense(int N, std::vector<cplx>& A, std::vector<cplx>& evals, const std:
 // eigenvectors of selected eigenvalues by inverse iteration on the Hessenberg matrix followed
 // by the Householder back-transformation.  Work ~ (10/3 + ~4) N^3 real-complex operations
 // instead of the ~25 N^3 of the full Schur form with vectors.
+// A team of host threads that run one function together and meet at barriers (spinning:
+// the phases between barriers are short).
+namespace {
+struct Team {
+    int P;
+    std::atomic<int> count{0}, gen{0};
+    explicit Team(int p) : P(p) {}
+    void barrier() {
+        const int g = gen.load(std::memory_order_acquire);
+        if (count.fetch_add(1, std::memory_order_acq_rel) == P - 1) {
+            count.store(0, std::memory_order_relaxed);
+            gen.store(g + 1, std::memory_order_release);
+        } else {
+            while (gen.load(std::memory_order_acquire) == g) std::this_thread::yield();
+        }
+    }
+    template <typename F>
+    void run(F f) {   // f(thread index) on P threads, the caller being thread 0
+        std::vector<std::thread> ts;
+        for (int t = 1; t < P; ++t) ts.emplace_back([&, t] { f(t); });
+        f(0);
+        for (auto& t : ts) t.join();
+    }
+};
+
+int host_threads(int64_t work, int64_t per_thread) {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, work / std::max<int64_t>(per_thread, 1)}));
+}
+}  // namespace
+
+// Householder reduction to Hessenberg form (the reflectors kept for the eigenvectors), then the
+// shifted QR algorithm on the active window for the eigenvalues only; the window is stored with
+// an odd leading dimension so that the row rotations do not fall into a few cache sets.  The
+// reduction's three O(N^2) updates per column are split over host threads for larger N.
 bool HessEig::compute(int N_, std::vector<cplx>& A) {
     N = N_;
     H.swap(A);
     V.assign((size_t)N * N, 0.0);
     beta.assign(N, 0.0);
     std::vector<cplx> s(N);
-    for (int k = 0; k + 2 < N; ++k) {
-        double xn2 = 0.0;
-        for (int i = k + 1; i < N; ++i) xn2 += std::norm(H[i + (size_t)k * N]);
-        if (xn2 == 0.0) continue;
-        const double xn = std::sqrt(xn2);
-        const cplx x0 = H[k + 1 + (size_t)k * N];
-        const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
-        const cplx alpha = -ph * xn;
-        cplx* v = &V[(size_t)k * N];
-        for (int i = k + 1; i < N; ++i) v[i] = H[i + (size_t)k * N];
-        v[k + 1] -= alpha;
-        double vn2 = 0.0;
-        for (int i = k + 1; i < N; ++i) vn2 += std::norm(v[i]);
-        if (vn2 == 0.0) continue;
-        const double bt = 2.0 / vn2;
-        beta[k] = bt;
-        for (int j = k + 1; j < N; ++j) {
-            cplx t = 0.0;
-            const cplx* hj = &H[(size_t)j * N];
-            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * hj[i];
-            t *= bt;
-            cplx* hw = &H[(size_t)j * N];
-            for (int i = k + 1; i < N; ++i) hw[i] -= v[i] * t;
+    const int P = N >= 96 ? host_threads((int64_t)N * N, 4096) : 1;
+    Team team(P);
+    cplx alpha_k = 0.0;
+    std::vector<char> skip(N, 0);
+    team.run([&](int t) {
+        for (int k = 0; k + 2 < N; ++k) {
+            if (t == 0) {   // reflector for column k
+                double xn2 = 0.0;
+                for (int i = k + 1; i < N; ++i) xn2 += std::norm(H[i + (size_t)k * N]);
+                cplx* v = &V[(size_t)k * N];
+                if (xn2 == 0.0) {
+                    skip[k] = 1;
+                } else {
+                    const double xn = std::sqrt(xn2);
+                    const cplx x0 = H[k + 1 + (size_t)k * N];
+                    const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
+                    alpha_k = -ph * xn;
+                    for (int i = k + 1; i < N; ++i) v[i] = H[i + (size_t)k * N];
+                    v[k + 1] -= alpha_k;
+                    double vn2 = 0.0;
+                    for (int i = k + 1; i < N; ++i) vn2 += std::norm(v[i]);
+                    if (vn2 == 0.0) skip[k] = 1;
+                    else beta[k] = 2.0 / vn2;
+                }
+            }
+            if (P > 1) team.barrier();
+            if (skip[k]) continue;
+            const cplx* v = &V[(size_t)k * N];
+            const double bt = beta[k];
+            const int cols = N - (k + 1);
+            const int j0 = k + 1 + (int)((int64_t)cols * t / P), j1 = k + 1 + (int)((int64_t)cols * (t + 1) / P);
+            // H <- (I - bt v v^H) H on rows k+1.., columns k+1..
+            for (int j = j0; j < j1; ++j) {
+                cplx* hj = &H[(size_t)j * N];
+                cplx tt = 0.0;
+                for (int i = k + 1; i < N; ++i) tt += std::conj(v[i]) * hj[i];
+                tt *= bt;
+                for (int i = k + 1; i < N; ++i) hj[i] -= v[i] * tt;
+            }
+            if (P > 1) team.barrier();
+            // s = H v over all rows (this thread's row range)
+            const int i0 = (int)((int64_t)N * t / P), i1 = (int)((int64_t)N * (t + 1) / P);
+            for (int i = i0; i < i1; ++i) s[i] = 0.0;
+            for (int j = k + 1; j < N; ++j) {
+                const cplx vj = v[j];
+                const cplx* hj = &H[(size_t)j * N];
+                for (int i = i0; i < i1; ++i) s[i] += hj[i] * vj;
+            }
+            if (P > 1) team.barrier();
+            // H <- H (I - bt v v^H) on columns k+1..
+            for (int j = j0; j < j1; ++j) {
+                const cplx cv = bt * std::conj(v[j]);
+                cplx* hj = &H[(size_t)j * N];
+                for (int i = 0; i < N; ++i) hj[i] -= s[i] * cv;
+            }
+            if (P > 1) team.barrier();
+            if (t == 0) {
+                H[k + 1 + (size_t)k * N] = alpha_k;
+                for (int i = k + 2; i < N; ++i) H[i + (size_t)k * N] = 0.0;
+            }
         }
-        std::fill(s.begin(), s.end(), cplx(0.0));
-        for (int j = k + 1; j < N; ++j) {
-            const cplx vj = v[j];
-            const cplx* hj = &H[(size_t)j * N];
-            for (int i = 0; i < N; ++i) s[i] += hj[i] * vj;
-        }
-        for (int j = k + 1; j < N; ++j) {
-            const cplx cv = bt * std::conj(v[j]);
-            cplx* hj = &H[(size_t)j * N];
-            for (int i = 0; i < N; ++i) hj[i] -= s[i] * cv;
-        }
-        H[k + 1 + (size_t)k * N] = alpha;
-        for (int i = k + 2; i < N; ++i) H[i + (size_t)k * N] = 0.0;
-    }
+    });
     H0 = H;   // Hessenberg matrix before the QR sweeps (for inverse iteration)
     norm = 0.0;
-    for (size_t e = 0; e < (size_t)N * N; ++e) norm = std::max(norm, abs1(H[e]));
+    for (size_t e = 0; e < (size_t)N * N; ++e) norm = std::max(norm, abs1(H0[e]));
     if (norm == 0.0) norm = 1.0;
+    const int LD = N + ((N % 2 == 0) ? 1 : 0);
+    {
+        std::vector<cplx> Hp((size_t)LD * N);
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) Hp[i + (size_t)j * LD] = H0[i + (size_t)j * N];
+        H.swap(Hp);
+    }
     int ihi = N - 1, its = 0, total = 0;
     while (ihi >= 0) {
         int l = ihi;
         while (l > 0) {
-            double sc = abs1(H[l - 1 + (size_t)(l - 1) * N]) + abs1(H[l + (size_t)l * N]);
+            double sc = abs1(H[l - 1 + (size_t)(l - 1) * LD]) + abs1(H[l + (size_t)l * LD]);
             if (sc == 0.0) sc = norm;
-            if (abs1(H[l + (size_t)(l - 1) * N]) <= kEps * sc) {
-                H[l + (size_t)(l - 1) * N] = 0.0;
+            if (abs1(H[l + (size_t)(l - 1) * LD]) <= kEps * sc) {
+                H[l + (size_t)(l - 1) * LD] = 0.0;
                 break;
             }
             --l;
@@ -388,8 +454,8 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
         }
         if (++its > 80 || ++total > 100 * N) return false;
         cplx mu;
-        const cplx a = H[ihi - 1 + (size_t)(ihi - 1) * N], b = H[ihi - 1 + (size_t)ihi * N];
-        const cplx c = H[ihi + (size_t)(ihi - 1) * N], d = H[ihi + (size_t)ihi * N];
+        const cplx a = H[ihi - 1 + (size_t)(ihi - 1) * LD], b = H[ihi - 1 + (size_t)ihi * LD];
+        const cplx c = H[ihi + (size_t)(ihi - 1) * LD], d = H[ihi + (size_t)ihi * LD];
         if (its == 10 || its == 20 || its == 40) {
             mu = d + std::abs(c.real()) * 0.75;
         } else {
@@ -398,28 +464,28 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
             const cplx m1 = tr2 + disc, m2 = tr2 - disc;
             mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
         }
-        cplx x = H[l + (size_t)l * N] - mu, y = H[l + 1 + (size_t)l * N];
+        cplx x = H[l + (size_t)l * LD] - mu, y = H[l + 1 + (size_t)l * LD];
         for (int k = l; k < ihi; ++k) {
             if (k > l) {
-                x = H[k + (size_t)(k - 1) * N];
-                y = H[k + 1 + (size_t)(k - 1) * N];
+                x = H[k + (size_t)(k - 1) * LD];
+                y = H[k + 1 + (size_t)(k - 1) * LD];
             }
             double cs;
             cplx sn, rho;
             givens(x, y, cs, sn, rho);
             if (k > l) {
-                H[k + (size_t)(k - 1) * N] = rho;
-                H[k + 1 + (size_t)(k - 1) * N] = 0.0;
+                H[k + (size_t)(k - 1) * LD] = rho;
+                H[k + 1 + (size_t)(k - 1) * LD] = 0.0;
             }
             const cplx csn = std::conj(sn);
             for (int j = k; j <= ihi; ++j) {            // rows k, k+1 inside the window
-                const cplx p = H[k + (size_t)j * N], q = H[k + 1 + (size_t)j * N];
-                H[k + (size_t)j * N] = cs * p + sn * q;
-                H[k + 1 + (size_t)j * N] = -csn * p + cs * q;
+                const cplx p = H[k + (size_t)j * LD], q = H[k + 1 + (size_t)j * LD];
+                H[k + (size_t)j * LD] = cs * p + sn * q;
+                H[k + 1 + (size_t)j * LD] = -csn * p + cs * q;
             }
             const int iend = std::min(k + 2, ihi);
-            cplx* ck = &H[(size_t)k * N];
-            cplx* ck1 = &H[(size_t)(k + 1) * N];
+            cplx* ck = &H[(size_t)k * LD];
+            cplx* ck1 = &H[(size_t)(k + 1) * LD];
             for (int i = l; i <= iend; ++i) {            // columns k, k+1 inside the window
                 const cplx p = ck[i], q = ck1[i];
                 ck[i] = cs * p + csn * q;
@@ -428,19 +494,21 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
         }
     }
     evals.resize(N);
-    for (int i = 0; i < N; ++i) evals[i] = H[i + (size_t)i * N];
+    for (int i = 0; i < N; ++i) evals[i] = H[i + (size_t)i * LD];
+    H.clear();
     return true;
 }
 
 void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) const {
     out.assign((size_t)N * want.size(), 0.0);
     // row-major copy of the Hessenberg matrix: the elimination below works on rows
-    std::vector<cplx> Hr((size_t)N * N), M((size_t)N * N), x(N);
+    std::vector<cplx> Hr((size_t)N * N);
     for (int j = 0; j < N; ++j)
         for (int i = 0; i < N; ++i) Hr[(size_t)i * N + j] = H0[i + (size_t)j * N];
-    std::vector<int> piv(N);
     const double smin = std::max(kEps * norm, std::numeric_limits<double>::min() * N);
-    for (size_t q = 0; q < want.size(); ++q) {
+    // the wanted vectors are independent: spread them over host threads
+    const int P = host_threads((int64_t)want.size() * N * N, (int64_t)4 * N * N);
+    auto one = [&](size_t q, std::vector<cplx>& M, std::vector<cplx>& x, std::vector<int>& piv) {
         const cplx lam = evals[want[q]];
         // LU of H0 - lam I with row exchanges between neighbours only (row i of M at M + i N)
         M = Hr;
@@ -493,6 +561,19 @@ void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) cons
         nr = std::sqrt(nr);
         cplx* o = &out[(size_t)q * N];
         for (int i = 0; i < N; ++i) o[i] = x[i] / nr;
+    };
+    std::atomic<size_t> next{0};
+    auto worker = [&] {
+        std::vector<cplx> M((size_t)N * N), x(N);
+        std::vector<int> piv(N);
+        for (size_t q; (q = next.fetch_add(1)) < want.size();) one(q, M, x, piv);
+    };
+    if (P <= 1) {
+        worker();
+    } else {
+        std::vector<std::thread> ts;
+        for (int t = 0; t < P; ++t) ts.emplace_back(worker);
+        for (auto& t : ts) t.join();
     }
 }
 
@@ -611,7 +692,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
     for (cplx sg : shifts) {
         deg = maxpow;
         if (!poly) {
-            // smallest d with (tau R)^{d+1} e^{tau R} / (d+1)! <= 1e-6 on the disk about the
+            // smallest d with (tau R)^{d+1} e^{tau R} / (d+1)! <= 1e-4 on the disk about the
             // shift that covers |lambda - c| <= 1.5 max(a, b): the truncated expansion only has
             // to place each Ritz value in the basin of Newton's method on the exact function
             const double R = 1.5 * std::max(E.a, E.b) + std::abs(sg - E.c);
@@ -620,7 +701,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
                 const double x = std::fabs(t.param) * R;
                 int e = 1;
                 double term = x * x / 2.0;
-                while (term * std::exp(x) > 1e-6) {
+                while (term * std::exp(x) > 1e-4) {
                     ++e;
                     term *= x / (e + 1);
                 }
@@ -709,7 +790,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
             cplx l = res.lambda[q];
             std::vector<cplx> y(res.Y.begin() + (size_t)q * m, res.Y.begin() + (size_t)(q + 1) * m);
             const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
-            for (int it = 0; it < 6; ++it) {
+            for (int it = 0; it < 8; ++it) {
                 std::fill(Tl.begin(), Tl.end(), cplx(0.0));
                 std::fill(dT.begin(), dT.end(), cplx(0.0));
                 double scale = 0.0;

@@ -14,10 +14,12 @@ Recipes (contour seed 3000 + id):
               T(lambda) (Arnoldi's residual test on the non-normal companion operator
               leaves eigenvalue errors near 1e-6 here); radius = midpoint between the 40th
               and 41st distances; rejected under a 2% relative gap.
-  qep2048x8   all 4096 companion eigenvalues; 8 disjoint circles with p_r = round(0.625
-              m0_r) eigenvalues each, centres drawn in the bulk |lambda| < 0.8, radius at
-              the gap midpoint, rejected under a 5% gap or when two circles come closer
-              than 10% of the larger radius.
+  qep2048x8   8 disjoint circles with p_r = round(0.625 m0_r) eigenvalues each: centre
+              uniform in the disk |c| < 0.8 (the bulk of the spectrum); the p_r + 12
+              eigenvalues nearest c from shift-invert Arnoldi on the companion pencil, the
+              nearest p_r + 4 sharpened by two steps of two-sided Rayleigh functional
+              iteration on T; radius at the gap midpoint; rejected under a 5% gap or when
+              two circles come closer than 10% of the larger radius.
   delay512, delay8192
               centre c = i y0, y0 ~ U(0.3, 1.5); the p + max(10, p/3) eigenvalues nearest c
               from shift-invert Arnoldi on the companion form of the Taylor surrogate of
@@ -86,22 +88,31 @@ def damped4096():
 def qep2048x8():
     cfg = wl.CONFIGS["qep2048x8"]
     terms, mats = wl.make_problem("qep2048x8")
-    lam = brute.companion_eigs(pb.Problem(terms, mats))
+    P = pb.Problem(terms, mats)
     rng = np.random.default_rng(3000 + cfg["id"])
-    bulk = lam[np.abs(lam) < 0.8]
     regions = []
     for m0 in cfg["m0s"]:
         p = int(round(0.625 * m0))
         while True:
-            c = bulk[rng.integers(len(bulk))]
+            c = 0.8 * np.sqrt(rng.uniform()) * np.exp(2j * np.pi * rng.uniform())
+            if any(abs(c - complex(*g["centre"])) < 1.1 * 2 * g["radius"] for g in regions):
+                continue
+            lam = brute.companion_eigs_near(P, c, p + 12)
             _, r, gap = ring(lam, c, p)
-            ok = gap >= 0.05 and all(
-                abs(c - complex(*g["centre"])) > 1.1 * (r + g["radius"]) for g in regions)
-            if ok:
+            if gap < 0.05 or any(abs(c - complex(*g["centre"])) <= 1.1 * (r + g["radius"]) for g in regions):
+                continue
+            lam = lam[np.argsort(np.abs(lam - c))]
+            res = np.zeros(p + 4)
+            for i in range(p + 4):
+                lam[i], res[i] = brute.refine_eigenvalue(P, lam[i], steps=2, seed=i)
+            _, r, gap = ring(lam, c, p)
+            if gap >= 0.05 and all(abs(c - complex(*g["centre"])) > 1.1 * (r + g["radius"]) for g in regions):
                 break
         inside = lam[np.abs(lam - c) < r]
         regions.append(dict(centre=[c.real, c.imag], radius=r, gap=gap, m0=m0,
+                            max_residual=float(res.max()),
                             eigenvalues=[[v.real, v.imag] for v in inside]))
+        print("  region m0 %d: %d inside, r %.4g, gap %.3f" % (m0, len(inside), r, gap), flush=True)
     return dict(regions=regions)
 
 
