@@ -142,30 +142,43 @@ void cast_64_to_128(hipStream_t s, int64_t rows, int64_t cols, int batch, const 
     NLF_HIP(hipGetLastError());
 }
 
-__global__ __launch_bounds__(1024) void block_sqnorm_kernel(int64_t rows, int64_t cols,
-                                                            const z128* X, int64_t ld, int64_t sX,
-                                                            double* out) {
-    __shared__ double red[16];
-    const int64_t b = blockIdx.x, total = rows * cols;
+// ||X_b||_F^2 per block in two deterministic stages: BLOCK_SQ_PARTS workgroups per block each
+// sum a strided set of columns, then one wavefront per block adds the partial sums.
+constexpr int BLOCK_SQ_PARTS = 64;
+
+__global__ __launch_bounds__(256) void block_sqnorm_part_kernel(int64_t rows, int64_t cols,
+                                                                const z128* X, int64_t ld,
+                                                                int64_t sX, double* part) {
+    __shared__ double red[4];
+    const int64_t b = blockIdx.y;
     double s = 0;
-    for (int64_t e = threadIdx.x; e < total; e += 1024) {
-        const int64_t i = e % rows, c = e / rows;
-        s += norm2(X[b * sX + i + c * ld]);
+    for (int64_t c = blockIdx.x; c < cols; c += BLOCK_SQ_PARTS) {
+        const z128* col = X + b * sX + c * ld;
+        for (int64_t i = threadIdx.x; i < rows; i += 256) s += norm2(col[i]);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0;
-        for (int q = 0; q < 16; ++q) t += red[q];
-        out[b] = t;
-    }
+    if (threadIdx.x == 0) part[b * BLOCK_SQ_PARTS + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+__global__ __launch_bounds__(64) void block_sqnorm_sum_kernel(const double* part, double* out) {
+    double s = part[blockIdx.x * BLOCK_SQ_PARTS + threadIdx.x];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+int64_t block_sqnorms_scratch(int batch) { return (int64_t)batch * BLOCK_SQ_PARTS; }
+
 void block_sqnorms(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* X,
-                   int64_t ld, int64_t sX, double* out) {
-    hipLaunchKernelGGL(block_sqnorm_kernel, dim3(batch), dim3(1024), 0, s, rows, cols, X, ld, sX, out);
+                   int64_t ld, int64_t sX, double* out, double* part) {
+    static_assert(BLOCK_SQ_PARTS == 64, "one wavefront sums the partials");
+    hipLaunchKernelGGL(block_sqnorm_part_kernel, dim3(BLOCK_SQ_PARTS, batch), dim3(256), 0, s, rows, cols,
+                       X, ld, sX, part);
+    NLF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(block_sqnorm_sum_kernel, dim3(batch), dim3(64), 0, s, (const double*)part, out);
     NLF_HIP(hipGetLastError());
 }
 

@@ -80,9 +80,11 @@ void cast_128_to_64(hipStream_t s, int64_t rows, int64_t cols, int batch, const 
                     int64_t ldi, int64_t si, z64* out, int64_t ldo, int64_t so);
 void cast_64_to_128(hipStream_t s, int64_t rows, int64_t cols, int batch, const z64* in,
                     int64_t ldi, int64_t si, z128* out, int64_t ldo, int64_t so, bool accumulate);
-// sum of squared magnitudes of each of `batch` n x m blocks into out[b] (device doubles)
+// sum of squared magnitudes of each of `batch` n x m blocks into out[b] (device doubles);
+// part: block_sqnorms_scratch(batch) doubles for the partial sums
+int64_t block_sqnorms_scratch(int batch);
 void block_sqnorms(hipStream_t s, int64_t rows, int64_t cols, int batch, const z128* X,
-                   int64_t ld, int64_t sX, double* out);
+                   int64_t ld, int64_t sX, double* out, double* part);
 // copy an n x m c128 block (ld in, ld out)
 void copy_block(hipStream_t s, int64_t rows, int64_t cols, const z128* in, int64_t ldi,
                 z128* out, int64_t ldo);

@@ -273,34 +273,47 @@ __global__ __launch_bounds__(1024) void swaplist_kernel(int64_t n, int64_t k1, i
     }
 }
 
-template <typename R, int EPT>
-__global__ __launch_bounds__(1024) void laswp_apply_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
-                                                           int64_t c0, int64_t ncols, int cw,
-                                                           const int32_t* list, int L) {
+// Row exchanges as (dst, src) lists, applied to the columns [c0a, c0a + na) and [c0b, c0b + nb)
+// (the left and right parts of a panel in one launch).  A 512-thread workgroup owns CW
+// consecutive columns of the union: every thread gathers its EPT entries of all CW columns,
+// the workgroup meets once, then every thread scatters them.
+template <typename R, int EPT, int CW>
+__global__ __launch_bounds__(512) void laswp_apply_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
+                                                          int64_t c0a, int64_t na, int64_t c0b,
+                                                          int64_t nb, const int32_t* list, int L) {
     const int64_t b = blockIdx.y;
     Cx<R>* A = A0 + b * sA;
     const int32_t* dst = list + b * 2 * (int64_t)L;
     const int32_t* src = dst + L;
-    int d[EPT], s[EPT];
+    int d[EPT], sr[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = threadIdx.x + 1024 * i;
+        const int e = threadIdx.x + 512 * i;
         d[i] = e < L ? dst[e] : -1;
-        s[i] = e < L ? src[e] : 0;
+        sr[i] = e < L ? src[e] : 0;
     }
-    const int64_t cbeg = c0 + (int64_t)blockIdx.x * cw;
-    const int64_t cend = std::min<int64_t>(cbeg + cw, c0 + ncols);
-    for (int64_t c = cbeg; c < cend; ++c) {
-        Cx<R>* col = A + c * lda;
-        Cx<R> v[EPT];
+    const int64_t total = na + nb, q0 = (int64_t)blockIdx.x * CW;
+    Cx<R> v[CW][EPT];
 #pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (d[i] >= 0) v[i] = col[s[i]];
-        __syncthreads();
+    for (int c = 0; c < CW; ++c) {
+        const int64_t q = q0 + c;
+        if (q < total) {
+            const Cx<R>* col = A + (q < na ? c0a + q : c0b + (q - na)) * lda;
 #pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (d[i] >= 0) col[d[i]] = v[i];
-        __syncthreads();
+            for (int i = 0; i < EPT; ++i)
+                if (d[i] >= 0) v[c][i] = col[sr[i]];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+        const int64_t q = q0 + c;
+        if (q < total) {
+            Cx<R>* col = A + (q < na ? c0a + q : c0b + (q - na)) * lda;
+#pragma unroll
+            for (int i = 0; i < EPT; ++i)
+                if (d[i] >= 0) col[d[i]] = v[c][i];
+        }
     }
 }
 
@@ -489,25 +502,24 @@ static void launch_panel(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_
 template <typename R>
 static void laswp(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_t sA, int64_t n,
                   int64_t k1, int64_t k2, int64_t c0, int64_t ncols, const int32_t* ipiv,
-                  int32_t* list) {
-    if (ncols <= 0 || k2 <= k1) return;
+                  int32_t* list, int64_t c0b = 0, int64_t ncolsb = 0) {
+    if (ncols + ncolsb <= 0 || k2 <= k1) return;
     const int L = (int)(2 * (k2 - k1));
-    ProfScope ps(NLF_PROF_LASWP, s, 0, 2.0 * L * ncols * sizeof(Cx<R>) * batch);
+    ProfScope ps(NLF_PROF_LASWP, s, 0, 2.0 * L * (ncols + ncolsb) * sizeof(Cx<R>) * batch);
     hipLaunchKernelGGL(swaplist_kernel, dim3(batch), dim3(1024), (size_t)(n - k1) * sizeof(int), s,
                        n, k1, k2, ipiv, list);
     NLF_HIP(hipGetLastError());
-    const int cw = 4;
-    dim3 grid((unsigned)ceil_div(ncols, cw), batch);
-    if (L <= 1024)
-        hipLaunchKernelGGL((laswp_apply_kernel<R, 1>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
-    else if (L <= 2048)
-        hipLaunchKernelGGL((laswp_apply_kernel<R, 2>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
-    else if (L <= 4096)
-        hipLaunchKernelGGL((laswp_apply_kernel<R, 4>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
-    else if (L <= 8192)
-        hipLaunchKernelGGL((laswp_apply_kernel<R, 8>), grid, dim3(1024), 0, s, A, lda, sA, c0, ncols, cw, list, L);
-    else
-        throw Error{1, "laswp: exchange range too large"};
+    const int64_t total = ncols + ncolsb;
+#define NLF_LASWP(EPT_, CW_)                                                                        \
+    hipLaunchKernelGGL((laswp_apply_kernel<R, EPT_, CW_>), dim3((unsigned)ceil_div(total, CW_), batch), \
+                       dim3(512), 0, s, A, lda, sA, c0, ncols, c0b, ncolsb, list, L)
+    if (L <= 512) NLF_LASWP(1, 16);
+    else if (L <= 1024) NLF_LASWP(2, 8);
+    else if (L <= 2048) NLF_LASWP(4, 4);
+    else if (L <= 4096) NLF_LASWP(8, 2);
+    else if (L <= 8192) NLF_LASWP(16, 1);
+    else throw Error{1, "laswp: exchange range too large"};
+#undef NLF_LASWP
     NLF_HIP(hipGetLastError());
 }
 
@@ -607,8 +619,7 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
             NLF_HIP(hipEventRecord(aux->panel_done, sp));
             NLF_HIP(hipStreamWaitEvent(s, aux->panel_done, 0));
         }
-        laswp<R>(s, batch, A, lda, sA, n, k0, k1, 0, k0, ipiv, list);
-        laswp<R>(s, batch, A, lda, sA, n, k0, k1, k1, rest, ipiv, list);
+        laswp<R>(s, batch, A, lda, sA, n, k0, k1, 0, k0, ipiv, list, k1, rest);
         // columns [c0, c0 + w) of the trailing matrix: U12 = L11^{-1} A12, A22 -= A21 U12
         auto update = [&](int64_t c0, int64_t w) {
             Cx<R>* A12 = A + k0 + c0 * lda;

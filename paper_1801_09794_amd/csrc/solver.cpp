@@ -277,7 +277,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
         R.Gall = take(16 * mm * J);
         R.rho = take(16 * (size_t)m);
         R.acoef = take(16 * (size_t)m * nc);
-        R.norms = take(8 * (size_t)(m + nc + 8));
+        R.norms = take(8 * (size_t)(m + nc + 8 + block_sqnorms_scratch(nc)));
         R.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
         R.splitws = take(16 * (size_t)R.splitws_elems);
         L.reg.push_back(R);
@@ -709,7 +709,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                         for (int q = 0; q < nc; ++q) copy_block(s, n, m, R, n, E + q * blk, n);
                         gemm<double>(s, false, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
                                      z128(1, 0), E, n, (int64_t)blk, nc);
-                        block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d);
+                        block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d, norms_d + m + nc + 8);
                         d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
                         double worst = 0.0;
                         for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);

@@ -14,12 +14,13 @@ Recipes (contour seed 3000 + id):
               T(lambda) (Arnoldi's residual test on the non-normal companion operator
               leaves eigenvalue errors near 1e-6 here); radius = midpoint between the 40th
               and 41st distances; rejected under a 2% relative gap.
-  qep2048x8   8 disjoint circles with p_r = round(0.625 m0_r) eigenvalues each: centre
-              uniform in the disk |c| < 0.8 (the bulk of the spectrum); the p_r + 12
-              eigenvalues nearest c from shift-invert Arnoldi on the companion pencil, the
-              nearest p_r + 4 sharpened by two steps of two-sided Rayleigh functional
-              iteration on T; radius at the gap midpoint; rejected under a 5% gap or when
-              two circles come closer than 10% of the larger radius.
+  qep2048x8   8 disjoint circles, region r enclosing p_r eigenvalues with p_r between
+              0.55 m0_r and 0.7 m0_r: centre uniform in the disk |c| < 0.8 (the bulk of the
+              spectrum); the nearest eigenvalues from shift-invert Arnoldi on the companion
+              pencil, sharpened by two steps of two-sided Rayleigh functional iteration on T;
+              p_r is the count in that range with the largest relative gap to the next
+              eigenvalue, the radius the gap midpoint; rejected under a 2% gap or when two
+              circles come closer than 10% of the larger radius.
   delay512, delay8192
               centre c = i y0, y0 ~ U(0.3, 1.5); the p + max(10, p/3) eigenvalues nearest c
               from shift-invert Arnoldi on the companion form of the Taylor surrogate of
@@ -92,21 +93,19 @@ def qep2048x8():
     rng = np.random.default_rng(3000 + cfg["id"])
     regions = []
     for m0 in cfg["m0s"]:
-        p = int(round(0.625 * m0))
+        plo, phi = int(round(0.55 * m0)), int(round(0.7 * m0))
         while True:
             c = 0.8 * np.sqrt(rng.uniform()) * np.exp(2j * np.pi * rng.uniform())
             if any(abs(c - complex(*g["centre"])) < 1.1 * 2 * g["radius"] for g in regions):
                 continue
-            lam = brute.companion_eigs_near(P, c, p + 12)
-            _, r, gap = ring(lam, c, p)
-            if gap < 0.05 or any(abs(c - complex(*g["centre"])) <= 1.1 * (r + g["radius"]) for g in regions):
-                continue
+            lam = brute.companion_eigs_near(P, c, phi + 8)
             lam = lam[np.argsort(np.abs(lam - c))]
-            res = np.zeros(p + 4)
-            for i in range(p + 4):
+            res = np.zeros(phi + 2)
+            for i in range(phi + 2):
                 lam[i], res[i] = brute.refine_eigenvalue(P, lam[i], steps=2, seed=i)
-            _, r, gap = ring(lam, c, p)
-            if gap >= 0.05 and all(abs(c - complex(*g["centre"])) > 1.1 * (r + g["radius"]) for g in regions):
+            best = max(range(plo, phi + 1), key=lambda k: ring(lam, c, k)[2])
+            _, r, gap = ring(lam, c, best)
+            if gap >= 0.02 and all(abs(c - complex(*g["centre"])) > 1.1 * (r + g["radius"]) for g in regions):
                 break
         inside = lam[np.abs(lam - c) < r]
         regions.append(dict(centre=[c.real, c.imag], radius=r, gap=gap, m0=m0,
