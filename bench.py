@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the eight-region batched workload (qep2048x8)")
+    ap.add_argument("--no-delay", action="store_true",
+                    help="skip the delay workload (delay8192)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
     ap.add_argument("--lookahead", type=int, default=0,
@@ -119,13 +121,14 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     S = nl.NLFEAST(n, 0)
     dmats = [nl.to_colmajor(M, "cuda:0") for M in mats]
     S.set_coeffs(terms, dmats)
-    S.set_contour(regions)
+    quad = nl.NLF_QUAD_TRAPEZOID if cfg.get("quad") == "trapezoid" else nl.NLF_QUAD_GAUSS_LEGENDRE
+    S.set_contour(regions, quad_rule=quad)
     X0d = nl.to_colmajor(X0, "cuda:0")
     opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3,
                       lu_streams=args.lu_streams, panel_width=args.panel_width,
                       autotune=autotune, graph=graph, lookahead=args.lookahead)
     for _ in range(args.warmup):
-        S.set_contour(regions)
+        S.set_contour(regions, quad_rule=quad)
         S.solve(opts, X0d)
     torch.cuda.synchronize()
     nl.nlfeast_set_profiling(S.h, profile)
@@ -134,7 +137,7 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        S.set_contour(regions)          # invalidate the cached factorisations
+        S.set_contour(regions, quad_rule=quad)   # invalidate the cached factorisations
         outs.append(S.solve(opts, X0d))
         if profile:
             p = S.profile()
@@ -164,17 +167,13 @@ def batched_leg(args, fp64_headline):
                             autotune=1, graph=1)
     t64, o64, _ = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, False)
     c32, c64 = converged_pairs(o32, cfg["tol"]), converged_pairs(o64, cfg["tol"])
-    err = None
-    ok = o32["inside"] & o64["inside"]
-    if np.array_equal(o32["inside"], o64["inside"]) and ok.any():
-        a, b = np.sort_complex(o32["lam"][ok]), np.sort_complex(o64["lam"][ok])
-        err = float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-3)))
+    err = eig_diff(o32, o64, cfg["tol"], min(r["a"] for r in regions))
     fg = p32["factor"]
     lu_ms = fg["ms"] / max(fg["launches"], 1)
     lu_tflops = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
     return {
         "workload": "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%d complex Gaussian/sqrt(n), 8 disjoint "
-                    "circles, m0 %s, %d Gauss-Legendre nodes each (%d LUs), tol %.0e"
+                    "circles, m0 %s, %d trapezoid nodes each (%d LUs), tol %.0e"
                     % (n, [r["m0"] for r in regions], cfg["nc"], nz, cfg["tol"]),
         "fp32_refine": {"value": c32 / t32, "unit": "eigenpairs/s", "ms_per_step": t32 * 1e3,
                         "converged": c32, "iterations": [int(v) for v in o32["iters"]],
@@ -186,6 +185,45 @@ def batched_leg(args, fp64_headline):
         "max_rel_eig_diff_fp32_vs_fp64": err,
         "fp32_batched_vs_fp64_headline": (c32 / t32) / fp64_headline if fp64_headline else None,
     }
+
+
+def delay_leg(args):
+    """The non-polynomial delay problem at full size: FP32 LU + FP64 refinement against FP64."""
+    import numpy as np
+    import paper_1801_09794_amd as nl
+    cfg, terms, mats, regions, X0 = load_workload("delay8192")
+    n, nz = cfg["n"], sum(r["nc"] for r in regions)
+    out = {"workload": "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%d dense complex128, circle "
+                       "enclosing %d eigenvalues, m0 %d, %d Gauss-Legendre nodes, tol %.0e"
+                       % (n, cfg["inside"], regions[0]["m0"], nz, cfg["tol"])}
+    res = {}
+    for name, prec in (("fp32_refine", nl.NLF_PREC_FP32_REFINE), ("fp64", nl.NLF_PREC_FP64)):
+        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True)
+        c = converged_pairs(o, cfg["tol"])
+        f = p["factor"]
+        lu_ms = f["ms"] / max(f["launches"], 1)
+        res[name] = o
+        out[name] = {"value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
+                     "iterations": int(o["iters"][0]), "factor_ms": lu_ms,
+                     "lu_tflops": 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None,
+                     "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()}}
+    out["max_rel_eig_diff_fp32_vs_fp64"] = eig_diff(res["fp32_refine"], res["fp64"], cfg["tol"], regions[0]["a"])
+    out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
+    return out
+
+
+def eig_diff(a, b, tol, scale):
+    """Largest relative difference between the converged eigenvalues of two solves, matched by
+    minimum-cost assignment (None when the converged counts differ)."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    ca, cb = a["inside"] & (a["res"] <= tol), b["inside"] & (b["res"] <= tol)
+    la, lb = a["lam"][ca], b["lam"][cb]
+    if len(la) != len(lb) or len(la) == 0:
+        return None
+    cost = np.abs(la[:, None] - lb[None, :]) / np.maximum(np.abs(lb)[None, :], scale)
+    r, c = linear_sum_assignment(cost)
+    return float(cost[r, c].max())
 
 
 def converged_pairs(out, tol):
@@ -305,12 +343,7 @@ def main():
     if not args.no_fp32:
         t32, out32, prof32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True)
         conv32 = converged_pairs(out32, cfg["tol"])
-        import numpy as np
-        l64 = np.sort_complex(out64["lam"][out64["inside"]])
-        l32 = np.sort_complex(out32["lam"][out32["inside"]])
-        err = None
-        if len(l64) == len(l32) and len(l64):
-            err = float(max(np.min(np.abs(l32 - a)) / max(abs(a), regions[0]["a"]) for a in l64))
+        err = eig_diff(out32, out64, cfg["tol"], regions[0]["a"])
         lu32 = prof32["lu_gemm"]
         result["fp32_refine"] = {
             "value": conv32 / t32, "ms_per_step": t32 * 1e3, "converged": conv32,
@@ -323,6 +356,8 @@ def main():
         }
     if not args.no_batched and args.workload != "qep2048x8":
         result["batched"] = batched_leg(args, value)
+    if not args.no_delay and args.workload != "delay8192":
+        result["delay"] = delay_leg(args)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

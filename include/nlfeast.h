@@ -71,7 +71,9 @@ typedef struct {
     int32_t max_iter;            /* cap on Step 4 executions (default 50) */
     int32_t precision;           /* nlfeast_precision */
     int32_t max_refine;          /* FP32_REFINE: refinement sweeps per solve, at most 5 */
-    double refine_eta;           /* FP32_REFINE: stop sweeps once ||E||_F <= eta ||R||_F */
+    double refine_eta;           /* FP32_REFINE: stop sweeps once ||E_k||_F <= eta ||R||_F for
+                                    every node; once the first check of an iteration passes,
+                                    later iterations of that region skip the check */
     uint64_t seed;               /* X0 when the caller passes none (counter-based normal draws) */
     int32_t autotune;            /* 1: on first use of a (precision, n, node count) shape, time
                                     trial factorisations over panel width, trailing-update GEMM
@@ -129,11 +131,16 @@ nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* o
  *   lambda_out         2 * sum(m0) doubles: the Ritz values (re, im), selection order
  *   resid_out          sum(m0) doubles: ||T(lambda_i) x_i||_2
  *   inside_out         sum(m0) int32: 1 if lambda_i is strictly inside its contour
- *   m_out, iters_out   per region: eigenpairs inside, Step 4 executions
+ *   m_out, iters_out   per region: converged eigenpairs inside (resid <= tol), Step 4
+ *                      executions
+ * Step 3 stops a region when every Ritz value inside has converged, or when the converged
+ * count inside has stayed the same (and positive) for three iterations while the largest
+ * unconverged residual inside has not halved: the unconverged values inside are then spurious
+ * Ritz values of the projected problem (returned with inside = 1 and resid > tol).
  * Factorisations of T(z_k) are cached in the workspace and reused by the next solve with the
  * same handle, coefficients, contours, precision and workspace pointer.
- * Returns NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL or NLF_ERR_SINGULAR (the last
- * region's status when several fail). */
+ * Returns NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL or NLF_ERR_SINGULAR (a hard
+ * error wins over the convergence statuses when several regions fail). */
 nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws_dev,
                              size_t ws_bytes, const void* X0_dev, void* X_dev_out,
                              double* lambda_out, double* resid_out, int32_t* inside_out,

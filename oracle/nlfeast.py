@@ -20,6 +20,14 @@ Readings where the paper is silent:
   inside after 3 iterations the result is empty; the iteration cap defaults to 50.
 * if m0 or more Ritz values lie inside, the precondition of Algorithm 1 (fewer than m0
   eigenvalues inside C) is violated and M0TooSmall is raised.
+* spurious Ritz values: with m0 well above the count, a Ritz value of the projected problem
+  can sit inside C without approximating any eigenvalue (the projected problem has more
+  eigenvalues than the subspace has dimensions); its residual stays large while the true
+  pairs converge.  Step 3 then also stops when, at iteration it >= 4, the number of
+  converged inside pairs is the same positive number as in each of the three previous
+  iterations and the largest residual among the unconverged inside pairs is at least half of
+  its value three iterations earlier; the unconverged inside pairs are reported as
+  spurious (eigenvalues: the converged inside pairs only).
 * Step 4 uses the literal sum of the paper; T(z_j) is factored once per contour
   (the shifts are fixed) by LU with partial pivoting (scipy lu_factor).
 * Step 0/5 orthonormalisation is Householder QR (numpy.linalg.qr).
@@ -37,7 +45,7 @@ class M0TooSmall(RuntimeError):
 
 
 class Result:
-    def __init__(self, lam, X, res, inside, iters, history, converged):
+    def __init__(self, lam, X, res, inside, iters, history, converged, spurious=None):
         self.lam = lam
         self.X = X
         self.res = res
@@ -45,10 +53,20 @@ class Result:
         self.iters = iters
         self.history = history
         self.converged = converged
+        self.spurious = np.zeros_like(inside) if spurious is None else spurious
 
     @property
     def eigenvalues(self):
-        return self.lam[self.inside]
+        return self.lam[self.inside & ~self.spurious]
+
+
+def stalled(history):
+    """The stopping rule for spurious Ritz values (module docstring)."""
+    if len(history) < 5:
+        return False
+    h = history[-4:]
+    n = h[-1]["n_conv"]
+    return n > 0 and all(x["n_conv"] == n for x in h) and h[-1]["max_unconv"] >= 0.5 * h[0]["max_unconv"]
 
 
 def orthonormalise(Q):
@@ -101,14 +119,19 @@ def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
         res = np.where(finite, res, np.inf)
         inside = contour.inside(lam)
         n_in = int(inside.sum())
+        unconv = inside & ~(res <= tol)
         history.append(dict(it=it, n_inside=n_in,
-                            max_res=float(res[inside].max()) if n_in else 0.0))
+                            max_res=float(res[inside].max()) if n_in else 0.0,
+                            n_conv=n_in - int(unconv.sum()),
+                            max_unconv=float(res[unconv].max()) if unconv.any() else 0.0))
         if verbose:
             print("it %d inside %d max_res %.3e" % (it, n_in, history[-1]["max_res"]))
         if n_in >= m0:
             raise M0TooSmall("%d Ritz values inside C with m0 = %d" % (n_in, m0))
         if it >= 1 and n_in > 0 and np.all(res[inside] <= tol):   # Step 3
             return Result(lam, X, res, inside, it, history, True)
+        if it >= 4 and stalled(history):
+            return Result(lam, X, res, inside, it, history, True, spurious=unconv)
         if it >= 3 and n_in == 0:
             return Result(lam, X, res, inside, it, history, True)
         if it >= max_iter:

@@ -347,10 +347,15 @@ struct Team {
 };
 
 int host_threads(int64_t work, int64_t per_thread) {
-    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
     return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, work / std::max<int64_t>(per_thread, 1)}));
 }
 }  // namespace
+
+int& host_thread_budget() {
+    static thread_local int b = 16;
+    return b;
+}
 
 // Householder reduction to Hessenberg form (the reflectors kept for the eigenvectors), then the
 // shifted QR algorithm on the active window for the eigenvalues only; the window is stored with
@@ -831,7 +836,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
             for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = y[i] / s;
             res.lambda[q] = l;
         };
-        const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+        const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
         const int nth = std::max(1, std::min({hw, 16, (int)todo.size() / 2}));
         if (nth <= 1 || (size_t)m * m * todo.size() < 200000) {
             for (int q : todo) polish(q);

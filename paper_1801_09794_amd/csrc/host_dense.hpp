@@ -34,6 +34,10 @@ struct Term {
 cplx term_value(const Term& t, cplx l);
 cplx term_deriv(const Term& t, cplx l);
 
+// Host threads the dense routines below may use from the calling thread (default 16); callers
+// that run several reduced solves at once lower it per thread.
+int& host_thread_budget();
+
 struct ReducedResult {
     std::vector<cplx> lambda;   // m_keep values, selection order
     std::vector<cplx> Y;        // m x m_keep, unit columns

@@ -625,9 +625,14 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
             acoef((size_t)nc * m);
         std::vector<double> res(m), enorm(nc);
+        // once a refinement check passes without a correction, the complex64 factors have shown
+        // themselves accurate enough for this region's right-hand sides and later iterations
+        // skip the check (the FP64 residual of Step 3 still decides convergence)
+        bool refine_needed = true;
         ReducedResult rr;
-        int it = 0, n_in = 0;
-        std::vector<int> inside(m);
+        int it = 0, n_in = 0, n_conv = 0;
+        std::vector<int> inside(m), conv_hist;
+        std::vector<double> unconv_hist;
         int rstatus = NLF_OK;
         const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
         const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
@@ -669,19 +674,32 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             }
             d2h_sync(s, res.data(), norms_d, sizeof(double) * m);
             n_in = 0;
-            double maxres = 0.0;
+            n_conv = 0;
+            double maxres = 0.0, max_unconv = 0.0;
             for (int i = 0; i < m; ++i) {
                 if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
                 inside[i] = reg.E.radius(rr.lambda[i]) < 1.0;
                 if (inside[i]) {
                     ++n_in;
                     maxres = std::max(maxres, res[i]);
+                    if (res[i] <= opt->tol) ++n_conv;
+                    else max_unconv = std::max(max_unconv, res[i]);
                 }
             }
+            conv_hist.push_back(n_conv);
+            unconv_hist.push_back(max_unconv);
             if (opt->verbose)
-                fprintf(stderr, "[nlfeast] region %d it %d inside %d max_res %.3e\n", ri, it, n_in, maxres);
+                fprintf(stderr, "[nlfeast] region %d it %d inside %d converged %d max_res %.3e\n", ri, it, n_in,
+                        n_conv, maxres);
             if (n_in >= m) { rstatus = NLF_ERR_M0_TOO_SMALL; break; }
             if (it >= 1 && n_in > 0 && maxres <= opt->tol) break;
+            // spurious Ritz values inside C: the converged count has not moved for three
+            // iterations and the worst unconverged residual has not halved in that time
+            if (it >= 4 && n_conv > 0) {
+                bool same = true;
+                for (int q = 1; q <= 3; ++q) same = same && conv_hist[it - q] == n_conv;
+                if (same && max_unconv >= 0.5 * unconv_hist[it - 3]) break;
+            }
             if (it >= 3 && n_in == 0) break;
             if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
             // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
@@ -702,7 +720,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                     cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
                     double rn2 = 0.0;
                     for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
-                    for (int sweep = 0; sweep < std::min(opt->max_refine, 5); ++sweep) {
+                    for (int sweep = 0; refine_needed && sweep < std::min(opt->max_refine, 5); ++sweep) {
                         TrsmClassGuard tg2(NLF_PROF_REFINE);
                         ProfScope ps(NLF_PROF_REFINE, s, 8.0 * n * n * m * nc, 16.0 * nn * nc);
                         // E_k = R - T(z_k) Y_k in FP64
@@ -713,7 +731,13 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                         d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
                         double worst = 0.0;
                         for (int q = 0; q < nc; ++q) worst = std::max(worst, enorm[q]);
-                        if (worst <= opt->refine_eta * opt->refine_eta * rn2) break;
+                        if (opt->verbose)
+                            fprintf(stderr, "[nlfeast] region %d it %d refinement check %d: max ||E_k|| / ||R|| %.3e\n",
+                                    ri, it, sweep, std::sqrt(worst / std::max(rn2, 1e-300)));
+                        if (worst <= opt->refine_eta * opt->refine_eta * rn2) {
+                            if (sweep == 0) refine_needed = false;
+                            break;
+                        }
                         cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
                         getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
                                          Y32, n, (int64_t)blk, at<z64>(ws, RL.stmp));
@@ -747,7 +771,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             io.resid[col0 + i] = res[i];
             io.inside[col0 + i] = inside[i];
         }
-        io.m_out[ri] = n_in;
+        io.m_out[ri] = n_conv;
         io.iters[ri] = it;
         NLF_HIP(hipStreamSynchronize(s));
         res_out.status = rstatus;
@@ -991,6 +1015,8 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                         out[ri].msg = "hipSetDevice failed in a region thread";
                         return;
                     }
+                    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+                    host_thread_budget() = std::max(1, hw / nreg);
                     out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
                                          h->profiling ? h->rprof[ri].get() : nullptr, io);
                 });

@@ -124,9 +124,15 @@ def delay(name, rho):
     k = p + max(10, p // 3)
     while True:
         c = 1j * rng.uniform(0.3, 1.5)
-        lam = brute.eigs_near(P, c, k, rho)
-        if np.max(np.abs(lam - c)) > rho / 1.2:
-            raise RuntimeError("surrogate disk too small: raise rho")
+        while True:
+            t0 = time.time()
+            lam = brute.eigs_near(P, c, k, rho)
+            dmax = float(np.max(np.abs(lam - c)))
+            print("  centre %s rho %.3g: %d nearest within %.4g (%.0fs)" % (c, rho, k, dmax, time.time() - t0),
+                  flush=True)
+            if dmax <= rho / 1.2:
+                break
+            rho = 1.5 * 1.2 * dmax          # the surrogate must cover the k nearest: widen it
         _, r, gap = ring(lam, c, p)
         if gap < 0.02:
             continue
@@ -147,7 +153,7 @@ def delay(name, rho):
 
 
 RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8,
-           "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.08)}
+           "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.15)}
 
 
 def main(names):

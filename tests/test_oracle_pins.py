@@ -3,6 +3,7 @@ oracle itself: closed-form spectra (mass-spring QEPs of Sec. 5), values printed 
 paper (Table 1), closed forms of the quadrature filter, the reduction of Step 4 to the
 linear FEAST filter for a linear pencil (Sec. 4.2), brute-force companion eigenvalues,
 and a known-spectrum non-polynomial family."""
+import json
 import os
 
 import numpy as np
@@ -11,7 +12,7 @@ import scipy.integrate
 import scipy.linalg
 
 import workloads as wl
-from oracle import brute, dense, nlfeast, problem as pb, quadrature as qd, reduced
+from oracle import brute, dense, nlfeast, nlfeast as onl, problem as pb, quadrature as qd, reduced
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -330,3 +331,40 @@ def test_delay_known_spectrum():
     r = nlfeast.solve(P, C, z, w, wl.initial_block(40, m0, 22), m0, 1e-12)
     assert r.converged and r.inside.sum() == len(truth)
     assert match_error(r.eigenvalues, np.array(truth), C.a) < 1e-10
+
+
+def test_stall_rule_logic():
+    # the spurious-Ritz-value stop: converged count unchanged (and positive) for three
+    # iterations and the worst unconverged residual not halved
+    h = lambda n, r: dict(n_conv=n, max_unconv=r)
+    assert not onl.stalled([h(0, 1.0)] * 4)
+    assert onl.stalled([h(0, 1.0), h(5, 1e-2), h(5, 2e-2), h(5, 1e-2), h(5, 6e-3)])
+    assert not onl.stalled([h(0, 1.0), h(5, 1e-2), h(5, 2e-2), h(5, 1e-2), h(5, 4e-3)])   # halved
+    assert not onl.stalled([h(0, 1.0), h(4, 1e-2), h(5, 2e-2), h(5, 1e-2), h(5, 6e-3)])   # count moved
+    assert not onl.stalled([h(0, 0.0), h(0, 1e-2), h(0, 2e-2), h(0, 1e-2), h(0, 6e-3)])   # nothing converged
+
+
+@pytest.mark.slow
+def test_spurious_ritz_value_region_matches_brute_force():
+    # qep2048x8 region 5 (m0 = 64, 40 eigenvalues inside, 16 trapezoid nodes): one Ritz value
+    # of the projected quadratic problem stays inside C without converging; the iteration stops
+    # by the stall rule and the converged set is exactly the brute-force set
+    from scipy.optimize import linear_sum_assignment
+    cfg = wl.CONFIGS["qep2048x8"]
+    terms, mats = wl.make_problem("qep2048x8")
+    gs = json.load(open(os.path.join(GOLDEN, "contours.json")))["qep2048x8"]["regions"]
+    ri = 4
+    g = gs[ri]
+    M = sum(x["m0"] for x in gs)
+    col = sum(x["m0"] for x in gs[:ri])
+    X0 = wl.initial_block(cfg["n"], M, 2000 + cfg["id"])[:, col:col + g["m0"]]
+    C = qd.Contour(complex(*g["centre"]), g["radius"])
+    z, w = qd.nodes_weights(C, cfg["nc"], "trapezoid")
+    r = onl.solve(pb.Problem(terms, mats), C, z, w, X0, g["m0"], cfg["tol"], max_iter=30)
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    assert r.converged and r.spurious.sum() >= 1 and r.iters < 30
+    ev = r.eigenvalues
+    assert len(ev) == len(ref) == 40
+    cost = np.abs(ev[:, None] - ref[None, :]) / np.maximum(np.abs(ref)[None, :], g["radius"])
+    a, b = linear_sum_assignment(cost)
+    assert cost[a, b].max() < 1e-11
