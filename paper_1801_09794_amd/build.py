@@ -22,6 +22,9 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# device code: MFMA accumulators in ordinary VGPRs (the loop-carried accumulators of the GEMM
+# tile otherwise bounce between VGPRs and AccVGPRs on every K step)
+DEVICE_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 # host-only numerics (the reduced eigenproblem): AVX2/FMA and Fortran complex arithmetic rules
 # (no C99 NaN recovery in complex multiply; Smith's division)
 HOST_FLAGS = ["-march=x86-64-v3", "-fcx-fortran-rules"]
@@ -30,7 +33,7 @@ HOST_ONLY_SOURCES = {"host_dense.cpp"}
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", src, "-o", obj]
     if os.path.basename(src) in HOST_ONLY_SOURCES:
         cmd = [HIPCC] + COMMON + HOST_FLAGS + ["-x", "c++", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -100,35 +100,60 @@ struct GemmTile {
     }
 };
 
+// The loads are issued here and their values are not touched until gemm_stage writes them to
+// LDS after the current step's MFMAs, so the memory latency overlaps the matrix work; lanes
+// outside the matrix read element 0 (always valid) and are zeroed at the LDS store through the
+// bit mask `ok` (bit e: A element e, bit LA + e: B element e).
 template <typename R, int TM, int TN, int BK, bool CONJA>
 __device__ __forceinline__ void gemm_fetch(int64_t M, int64_t N, int64_t lda, int64_t ldb,
                                            const Cx<R>* __restrict__ A,
                                            const Cx<R>* __restrict__ B, int64_t m0, int64_t n0,
                                            int64_t k0, int64_t kend, int tid,
                                            Cx<R> (&ra)[GemmTile<R, TM, TN, BK, CONJA>::LA],
-                                           Cx<R> (&rb)[GemmTile<R, TM, TN, BK, CONJA>::LB]) {
+                                           Cx<R> (&rb)[GemmTile<R, TM, TN, BK, CONJA>::LB],
+                                           uint32_t& ok) {
     using T = GemmTile<R, TM, TN, BK, CONJA>;
+    ok = 0;
 #pragma unroll
     for (int e = 0; e < T::LA; ++e) {
         int m, k;
         T::a_coord(tid, e, m, k);
         const int64_t gm = m0 + m, gk = k0 + k;
-        // branch-free: out-of-range lanes read element 0 (always valid here) and keep zero
-        const bool ok = gm < M && gk < kend;
-        const int64_t off = ok ? (!CONJA ? gm + gk * lda : gk + gm * lda) : 0;
-        const Cx<R> v = A[off];
-        ra[e].re = ok ? v.re : R(0);
-        ra[e].im = ok ? (CONJA ? -v.im : v.im) : R(0);
+        const bool in = gm < M && gk < kend;
+        ok |= (uint32_t)in << e;
+        ra[e] = A[in ? (!CONJA ? gm + gk * lda : gk + gm * lda) : 0];
     }
 #pragma unroll
     for (int e = 0; e < T::LB; ++e) {
         int k, n;
         T::b_coord(tid, e, k, n);
         const int64_t gn = n0 + n, gk = k0 + k;
-        const bool ok = gn < N && gk < kend;
-        const Cx<R> v = B[ok ? gk + gn * ldb : 0];
-        rb[e].re = ok ? v.re : R(0);
-        rb[e].im = ok ? v.im : R(0);
+        const bool in = gn < N && gk < kend;
+        ok |= (uint32_t)in << (T::LA + e);
+        rb[e] = B[in ? gk + gn * ldb : 0];
+    }
+}
+
+// As: one BK x (BM + 1) staging buffer, Bs: one BK x (BN + 1) buffer (row k at k * (BM + 1)).
+template <typename R, int TM, int TN, int BK, bool CONJA>
+__device__ __forceinline__ void gemm_stage(Cx<R>* As, Cx<R>* Bs, int tid, const Cx<R>* ra,
+                                           const Cx<R>* rb, uint32_t ok) {
+    using T = GemmTile<R, TM, TN, BK, CONJA>;
+    static_assert(T::PAD == 1, "stage layout");
+    static_assert(T::LA + T::LB <= 32, "mask width");
+#pragma unroll
+    for (int e = 0; e < T::LA; ++e) {
+        int m, k;
+        T::a_coord(tid, e, m, k);
+        const bool in = (ok >> e) & 1u;
+        As[k * (T::BM + 1) + m] = Cx<R>(in ? ra[e].re : R(0), in ? (CONJA ? -ra[e].im : ra[e].im) : R(0));
+    }
+#pragma unroll
+    for (int e = 0; e < T::LB; ++e) {
+        int k, n;
+        T::b_coord(tid, e, k, n);
+        const bool in = (ok >> (T::LA + e)) & 1u;
+        Bs[k * (T::BN + 1) + n] = Cx<R>(in ? rb[e].re : R(0), in ? rb[e].im : R(0));
     }
 }
 
@@ -171,18 +196,16 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
         }
 
     Cx<R> ra[LA], rb[LB];
+    uint32_t ok = 0;
     const int col = lane & 15, krow = lane >> 4;
     if (kbeg < kend) {
-        gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, kbeg, kend, tid, ra, rb);
-#pragma unroll
-        for (int e = 0; e < LA; ++e) { int m, k; T::a_coord(tid, e, m, k); As[0][k][m] = ra[e]; }
-#pragma unroll
-        for (int e = 0; e < LB; ++e) { int k, n; T::b_coord(tid, e, k, n); Bs[0][k][n] = rb[e]; }
+        gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, kbeg, kend, tid, ra, rb, ok);
+        gemm_stage<R, TM, TN, BK, CONJA>(&As[0][0][0], &Bs[0][0][0], tid, ra, rb, ok);
         __syncthreads();
         int buf = 0;
         for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             const bool more = k0 + BK < kend;
-            if (more) gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, k0 + BK, kend, tid, ra, rb);
+            if (more) gemm_fetch<R, TM, TN, BK, CONJA>(M, N, lda, ldb, A, B, m0, n0, k0 + BK, kend, tid, ra, rb, ok);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 Cx<R> a[TM], b[TN];
@@ -207,12 +230,7 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
 #pragma unroll
                     for (int j = 0; j < TN; ++j) accI[i][j] = Mfma<R>::mma(b[j].im, a[i].re, accI[i][j]);
             }
-            if (more) {
-#pragma unroll
-                for (int e = 0; e < LA; ++e) { int m, k; T::a_coord(tid, e, m, k); As[buf ^ 1][k][m] = ra[e]; }
-#pragma unroll
-                for (int e = 0; e < LB; ++e) { int k, n; T::b_coord(tid, e, k, n); Bs[buf ^ 1][k][n] = rb[e]; }
-            }
+            if (more) gemm_stage<R, TM, TN, BK, CONJA>(&As[buf ^ 1][0][0], &Bs[buf ^ 1][0][0], tid, ra, rb, ok);
             __syncthreads();
             buf ^= 1;
         }
