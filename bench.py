@@ -37,6 +37,8 @@ def parse():
                     help="skip the eight-region batched workload (qep2048x8)")
     ap.add_argument("--no-delay", action="store_true",
                     help="skip the delay workload (delay8192)")
+    ap.add_argument("--fp64-legs", action="store_true",
+                    help="also run the batched and delay workloads in FP64")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
     ap.add_argument("--lookahead", type=int, default=0,
@@ -155,60 +157,54 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     return (t1 - t0) / args.steps, out, prof
 
 
-def batched_leg(args, fp64_headline):
-    """Eight disjoint regions with uneven m0 (128 node matrices of n = 2048), FP32 LU + FP64
-    refinement with the autotuned launch parameters and the factorisation replayed as one
-    hipGraph; FP64 on the same inputs for the accuracy comparison."""
+def reference_error(name, regions, out, tol):
+    """Largest relative error of the converged eigenvalues of each region against the stored
+    brute-force reference (tests/golden/contours.json), min-cost matched; None when a region's
+    converged count differs from the reference count."""
     import numpy as np
-    import paper_1801_09794_amd as nl
-    cfg, terms, mats, regions, X0 = load_workload("qep2048x8")
-    n, nz = cfg["n"], sum(r["nc"] for r in regions)
-    t32, o32, p32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True,
-                            autotune=1, graph=1)
-    t64, o64, _ = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, False)
-    c32, c64 = converged_pairs(o32, cfg["tol"]), converged_pairs(o64, cfg["tol"])
-    err = eig_diff(o32, o64, cfg["tol"], min(r["a"] for r in regions))
-    fg = p32["factor"]
-    lu_ms = fg["ms"] / max(fg["launches"], 1)
-    lu_tflops = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
-    return {
-        "workload": "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%d complex Gaussian/sqrt(n), 8 disjoint "
-                    "circles, m0 %s, %d trapezoid nodes each (%d LUs), tol %.0e"
-                    % (n, [r["m0"] for r in regions], cfg["nc"], nz, cfg["tol"]),
-        "fp32_refine": {"value": c32 / t32, "unit": "eigenpairs/s", "ms_per_step": t32 * 1e3,
-                        "converged": c32, "iterations": [int(v) for v in o32["iters"]],
-                        "factor_ms": lu_ms,
-                        "lu_tflops": lu_tflops,
-                        "lu_frac_fp32_peak": lu_tflops / PEAK["fp32_mfma_tflops"] if lu_tflops else None,
-                        "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p32.items()}},
-        "fp64": {"value": c64 / t64, "ms_per_step": t64 * 1e3, "converged": c64},
-        "max_rel_eig_diff_fp32_vs_fp64": err,
-        "fp32_batched_vs_fp64_headline": (c32 / t32) / fp64_headline if fp64_headline else None,
-    }
+    from scipy.optimize import linear_sum_assignment
+    gs = json.load(open(os.path.join(ROOT, "tests", "golden", "contours.json")))[name]["regions"]
+    col, worst = 0, 0.0
+    for r, g in zip(regions, gs):
+        sl = slice(col, col + r["m0"])
+        conv = out["inside"][sl] & (out["res"][sl] <= tol)
+        lam = out["lam"][sl][conv]
+        ref = np.array([complex(*v) for v in g["eigenvalues"]])
+        if len(lam) != len(ref):
+            return None
+        if len(ref):
+            cost = np.abs(lam[:, None] - ref[None, :]) / np.maximum(np.abs(ref)[None, :], g["radius"])
+            i, j = linear_sum_assignment(cost)
+            worst = max(worst, float(cost[i, j].max()))
+        col += r["m0"]
+    return worst
 
 
-def delay_leg(args):
-    """The non-polynomial delay problem at full size: FP32 LU + FP64 refinement against FP64."""
-    import numpy as np
+def extra_leg(args, name, description, autotune, graph):
+    """A parity configuration beside the headline: FP32 LU + FP64 refinement (and FP64 with
+    --fp64-legs), converged eigenvalues checked against the stored brute-force reference."""
     import paper_1801_09794_amd as nl
-    cfg, terms, mats, regions, X0 = load_workload("delay8192")
+    cfg, terms, mats, regions, X0 = load_workload(name)
     n, nz = cfg["n"], sum(r["nc"] for r in regions)
-    out = {"workload": "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%d dense complex128, circle "
-                       "enclosing %d eigenvalues, m0 %d, %d Gauss-Legendre nodes, tol %.0e"
-                       % (n, cfg["inside"], regions[0]["m0"], nz, cfg["tol"])}
-    res = {}
-    for name, prec in (("fp32_refine", nl.NLF_PREC_FP32_REFINE), ("fp64", nl.NLF_PREC_FP64)):
-        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True)
+    out = {"workload": description % dict(n=n, m0=[r["m0"] for r in regions], nc=cfg["nc"], nz=nz,
+                                          tol=cfg["tol"], inside=cfg.get("inside") or 0)}
+    precs = [("fp32_refine", nl.NLF_PREC_FP32_REFINE)]
+    if args.fp64_legs:
+        precs.append(("fp64", nl.NLF_PREC_FP64))
+    for key, prec in precs:
+        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph)
         c = converged_pairs(o, cfg["tol"])
         f = p["factor"]
         lu_ms = f["ms"] / max(f["launches"], 1)
-        res[name] = o
-        out[name] = {"value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
-                     "iterations": int(o["iters"][0]), "factor_ms": lu_ms,
-                     "lu_tflops": 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None,
-                     "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()}}
-    out["max_rel_eig_diff_fp32_vs_fp64"] = eig_diff(res["fp32_refine"], res["fp64"], cfg["tol"], regions[0]["a"])
-    out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
+        tf = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
+        peak = PEAK["fp32_mfma_tflops"] if key == "fp32_refine" else PEAK["fp64_mfma_tflops"]
+        out[key] = {"value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
+                    "iterations": [int(v) for v in o["iters"]], "factor_ms": lu_ms, "lu_tflops": tf,
+                    "lu_frac_peak": tf / peak if tf else None,
+                    "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
+                    "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()}}
+    if "fp64" in out:
+        out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
     return out
 
 
@@ -355,9 +351,19 @@ def main():
             "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof32.items()},
         }
     if not args.no_batched and args.workload != "qep2048x8":
-        result["batched"] = batched_leg(args, value)
+        result["batched"] = extra_leg(
+            args, "qep2048x8",
+            "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
+            "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
+            "parameters), tol %(tol).0e", autotune=1, graph=1)
+        b32 = result["batched"]["fp32_refine"]
+        b32["vs_fp64_headline"] = b32["value"] / value if value else None
     if not args.no_delay and args.workload != "delay8192":
-        result["delay"] = delay_leg(args)
+        result["delay"] = extra_leg(
+            args, "delay8192",
+            "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%(n)d dense complex128, circle "
+            "enclosing %(inside)d eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, tol %(tol).0e",
+            autotune=0, graph=0)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {
