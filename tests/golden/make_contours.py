@@ -22,12 +22,13 @@ Recipes (contour seed 3000 + id):
               eigenvalue, the radius the gap midpoint; rejected under a 2% gap or when two
               circles come closer than 10% of the larger radius.
   delay512, delay8192
-              centre c = i y0, y0 ~ U(0.3, 1.5); the p + max(10, p/3) eigenvalues nearest c
-              from shift-invert Arnoldi on the companion form of the Taylor surrogate of
-              T(c + mu) (tail below 1e-16 on |mu| <= rho); the nearest p + 6 are sharpened by
-              two steps of two-sided Rayleigh functional iteration on T itself; radius =
-              midpoint between the p-th and (p+1)-th distances; rejected under a 2% relative
-              gap.  delay512 also stores the winding number of det T along the circle.
+              centre c = i y0, y0 ~ U(0.3, 1.5); the eigenvalues nearest c from shift-invert
+              Arnoldi on the companion form of the Taylor surrogate of T(c + mu) (tail below
+              1e-16 on |mu| <= rho, rho widened until it covers them); the count p within 10%
+              of the configured count with the largest relative gap to the next eigenvalue,
+              radius at the gap midpoint, rejected under a 1% gap; the nearest p + 2 sharpened
+              by two steps of two-sided Rayleigh functional iteration on T itself.  delay512
+              also stores the winding number of det T along the circle.
 """
 import json
 import os
@@ -120,8 +121,9 @@ def delay(name, rho):
     terms, mats = wl.make_problem(name)
     P = pb.Problem(terms, mats)
     rng = np.random.default_rng(3000 + cfg["id"])
-    p = cfg["inside"]
-    k = p + max(10, p // 3)
+    p0 = cfg["inside"]
+    plo, phi = int(round(0.9 * p0)), int(round(1.1 * p0))
+    k = phi + max(10, phi // 8)
     while True:
         c = 1j * rng.uniform(0.3, 1.5)
         while True:
@@ -133,16 +135,16 @@ def delay(name, rho):
             if dmax <= rho / 1.2:
                 break
             rho = 1.5 * 1.2 * dmax          # the surrogate must cover the k nearest: widen it
+        lam = lam[np.argsort(np.abs(lam - c))]
+        p = max(range(plo, phi + 1), key=lambda q: ring(lam, c, q)[2])
         _, r, gap = ring(lam, c, p)
-        if gap < 0.02:
+        if gap < 0.01:
             continue
-        order = np.argsort(np.abs(lam - c))
-        lam = lam[order]
-        res = np.zeros(p + 6)
-        for i in range(p + 6):
+        res = np.zeros(p + 2)
+        for i in range(p + 2):
             lam[i], res[i] = brute.refine_eigenvalue(P, lam[i], steps=2, seed=i)
         _, r, gap = ring(lam, c, p)
-        if gap >= 0.02:
+        if gap >= 0.01:
             break
     inside = lam[np.abs(lam - c) < r]
     out = dict(centre=[c.real, c.imag], radius=r, gap=gap, max_residual=float(res.max()),
