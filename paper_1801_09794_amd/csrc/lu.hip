@@ -27,10 +27,46 @@ constexpr int TRSM_NB = 64;
 constexpr int64_t LU_INV_NB = 256;   // diagonal block order of the explicit L/U block inverses
 constexpr int TRSM_CB = 8;      // right-hand-side columns per wavefront in the TRSM leaf
 
+// One step of an argmax reduction: the lane pattern CTRL (a DPP control: quad permutation or
+// row mirror) brings a partner's (value, row); the larger value wins, ties go to the lower row.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, typename R>
+__device__ __forceinline__ void argmax_dpp(R& v, int& row) {
+    R ov;
+    if constexpr (sizeof(R) == 8) {
+        const long long bits = __double_as_longlong(v);
+        const int lo = dpp_move<CTRL>((int)bits), hi = dpp_move<CTRL>((int)(bits >> 32));
+        ov = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+    } else {
+        ov = __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
+    }
+    const int orow = dpp_move<CTRL>(row);
+    if (ov > v || (ov == v && orow < row)) {
+        v = ov;
+        row = orow;
+    }
+}
+
+// Argmax within each row of 16 lanes: swap neighbours (quad_perm [1,0,3,2]), pairs
+// ([2,3,0,1]), half rows (row_half_mirror), whole row (row_mirror); afterwards every lane of a
+// row holds the row's winner.
+template <typename R>
+__device__ __forceinline__ void row16_argmax(R& v, int& row) {
+    argmax_dpp<0xB1>(v, row);
+    argmax_dpp<0x4E>(v, row);
+    argmax_dpp<0x141>(v, row);
+    argmax_dpp<0x140>(v, row);
+}
+
 template <typename R>
 __device__ __forceinline__ void wave_argmax(R& v, int& row) {
+    row16_argmax(v, row);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = 16; off < 64; off <<= 1) {
         R ov = __shfl_xor(v, off, 64);
         int orow = __shfl_xor(row, off, 64);
         if (ov > v || (ov == v && orow < row)) {
@@ -53,9 +89,13 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
 
     __shared__ Cx<R> Ltop[PANEL_WMAX][PANEL_WMAX + 1];
     __shared__ Cx<R> Utop[PANEL_WMAX][SB];
-    __shared__ R redv[NT / 64];
-    __shared__ int redr[NT / 64];
-    __shared__ Cx<R> rowJ[SB], rowP[SB];
+    // per column, double-buffered by column parity: each wave's best candidate (value, row and
+    // the row's sub-block entries) and the current row j, so one barrier per column suffices
+    constexpr int NW = NT / 64;
+    __shared__ R candv[2][NW];
+    __shared__ int candr[2][NW];
+    __shared__ Cx<R> candrow[2][NW][SB];
+    __shared__ Cx<R> rowJbuf[2][SB];
 
     Cx<R> x[RPT][SB];
 
@@ -118,7 +158,7 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
 #pragma unroll
         for (int c = 0; c < SB; ++c) {
           if (c < bw) {
-            const int j = s0 + c;
+            const int j = s0 + c, par = j & 1;
             R best = R(-1);
             int brow = INT_MAX;
 #pragma unroll
@@ -130,16 +170,34 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
                 }
             }
             wave_argmax(best, brow);
-            if (lane == 0) { redv[wave] = best; redr[wave] = brow; }
-            __syncthreads();
-            R pv = redv[0];
-            int pr = redr[0];
+            if (lane == 0) { candv[par][wave] = best; candr[par][wave] = brow; }
+            if (brow != INT_MAX && tid == brow % NT) {      // the wave's winner publishes its row
 #pragma unroll
-            for (int q = 1; q < NT / 64; ++q) {
-                const R v = redv[q];
-                const int rr = redr[q];
-                if (v > pv || (v == pv && rr < pr)) { pv = v; pr = rr; }
+                for (int i = 0; i < RPT; ++i)
+                    if (i == brow / NT)
+#pragma unroll
+                        for (int cc = 0; cc < SB; ++cc) candrow[par][wave][cc] = x[i][cc];
             }
+            const int ownJ = j % NT, iJ = j / NT;
+            if (tid == ownJ) {
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (i == iJ)
+#pragma unroll
+                        for (int cc = 0; cc < SB; ++cc) rowJbuf[par][cc] = x[i][cc];
+            }
+            __syncthreads();
+            // every wave reduces the NW = 16 candidates itself in its first row of lanes (lane q
+            // holds candidate q; the candidate index travels in the low bits of the row key)
+            static_assert(NW == 16, "one DPP row per candidate set");
+            R pv = lane < NW ? candv[par][lane] : R(-1);
+            const int cand_row = lane < NW ? candr[par][lane] : INT_MAX;
+            int key = cand_row == INT_MAX ? INT_MAX : (cand_row << 4) | (lane & 15);
+            row16_argmax(pv, key);
+            pv = __shfl(pv, 0, 64);
+            key = __shfl(key, 0, 64);
+            int pr = key == INT_MAX ? INT_MAX : (key >> 4);
+            const int pq = key == INT_MAX ? 0 : (key & 15);
             if (pr == INT_MAX || !(pv > R(0))) {   // all zero (or NaN): no exchange
                 pr = j;
                 pv = R(0);
@@ -148,36 +206,24 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
                 piv[k0 + j] = (int32_t)(k0 + pr);
                 if (pv == R(0) && info[bidx] == 0) info[bidx] = (int32_t)(k0 + j + 1);
             }
-            const int ownJ = j % NT, iJ = j / NT, ownP = pr % NT, iP = pr / NT;
-            if (tid == ownJ) {
-#pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (i == iJ)
-#pragma unroll
-                        for (int cc = 0; cc < SB; ++cc) rowJ[cc] = x[i][cc];
-            }
-            if (tid == ownP) {
-#pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (i == iP)
-#pragma unroll
-                        for (int cc = 0; cc < SB; ++cc) rowP[cc] = x[i][cc];
-            }
-            __syncthreads();
+            Cx<R> prow[SB];
             if (pr != j) {
+#pragma unroll
+                for (int cc = 0; cc < SB; ++cc) prow[cc] = candrow[par][pq][cc];
+                const int ownP = pr % NT, iP = pr / NT;
                 if (tid == ownJ) {
 #pragma unroll
                     for (int i = 0; i < RPT; ++i)
                         if (i == iJ)
 #pragma unroll
-                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = rowP[cc];
+                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = prow[cc];
                 }
                 if (tid == ownP) {
 #pragma unroll
                     for (int i = 0; i < RPT; ++i)
                         if (i == iP)
 #pragma unroll
-                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = rowJ[cc];
+                            for (int cc = 0; cc < SB; ++cc) x[i][cc] = rowJbuf[par][cc];
                 }
                 if (tid < w && (tid < s0 || tid >= s0 + bw)) {
                     Cx<R>* a = A + (int64_t)tid * lda;
@@ -185,12 +231,12 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
                     a[j] = a[pr];
                     a[pr] = t;
                 }
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < SB; ++cc) prow[cc] = rowJbuf[par][cc];
             }
             if (pv > R(0)) {
-                const Cx<R> inv = cdiv(Cx<R>(1, 0), rowP[c]);
-                Cx<R> prow[SB];
-#pragma unroll
-                for (int cc = 0; cc < SB; ++cc) prow[cc] = rowP[cc];
+                const Cx<R> inv = cdiv(Cx<R>(1, 0), prow[c]);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int r = tid + NT * i;
@@ -490,7 +536,7 @@ static void launch_panel(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_
         else throw Error{1, "getrf: matrix order above 8192 is not supported"};
     } else {
         if (mp <= 1024) NLF_PANEL(1, 16);
-        else if (mp <= 2048) NLF_PANEL(2, 16);
+        else if (mp <= 2048) NLF_PANEL(2, 8);
         else if (mp <= 4096) NLF_PANEL(4, 8);
         else if (mp <= 8192) NLF_PANEL(8, 4);
         else throw Error{1, "getrf: matrix order above 8192 is not supported"};
