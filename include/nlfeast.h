@@ -157,7 +157,7 @@ typedef enum {
                                     solve stream (eager launches or one graph replay) */
     NLF_K_AUTOTUNE = 13,         /* trial factorisations of the LU tuner (first use of a shape) */
     NLF_K_LU_REC_GEMM = 14,      /* GEMM updates inside the recursive panel factorisation
-                                    (NLF_K_LU_GEMM: the rank-256 trailing updates of the blocked
+                                    (NLF_K_LU_GEMM: the rank-512 trailing updates of the blocked
                                     LU, kernel symbol lu_update_kernel) */
     NLF_K_COUNT = 15
 } nlfeast_kernel_class;
@@ -195,11 +195,12 @@ nlfeast_status nlf_getrf_batched(int32_t dtype, int64_t n, int32_t batch, void* 
                                  int64_t lda, int64_t strideA, int32_t* ipiv_dev,
                                  int32_t* perm_dev, int32_t* info_dev, void* stream);
 
-/* The same factorisation computed right-looking with 256-column panels (each panel factored as
- * above, U12 = L11^{-1} A12 by a GEMM with the explicit inverse, rank-256 trailing updates on
- * MFMA); it also writes the diagonal-block inverses that nlf_lu_block_inverses would
- * (dinv_dev: batch * nlf_lu_inverse_elems(n) elements).  Temporary device memory of
- * 256 * (n - 256) elements per matrix is allocated on the stream for the call. */
+/* The same factorisation computed right-looking with 512-column panels (each panel factored as
+ * above; U12 = L11^{-1} A12 by GEMMs with the explicit inverses of the panel's 256 x 256
+ * diagonal blocks; rank-512 trailing updates on MFMA); it also writes the diagonal-block
+ * inverses that nlf_lu_block_inverses would (dinv_dev: batch * nlf_lu_inverse_elems(n)
+ * elements).  Temporary device memory of 512 * max(n - 512, 1) elements per matrix is
+ * allocated on the stream for the call. */
 nlfeast_status nlf_getrf_batched_blocked(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
                                          int64_t lda, int64_t strideA, int32_t* ipiv_dev,
                                          int32_t* perm_dev, int32_t* info_dev, void* dinv_dev,

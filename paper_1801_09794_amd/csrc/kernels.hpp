@@ -19,7 +19,7 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
           int64_t ws_elems = 0, const GemmConfig* force = nullptr, bool lu_update = false);
 
 // LU with partial pivoting (in place), batched over strided matrices.  With dinv and tmp
-// (getrf_tmp_elems per matrix) it runs right-looking with 256-column panels and leaves the
+// (getrf_tmp_elems per matrix) it runs right-looking with 512-column panels and leaves the
 // explicit inverses of the diagonal blocks of L and U in dinv (as lu_block_inverses does);
 // without them it is the plain column-halving recursion.
 int64_t getrf_tmp_elems(int64_t n);

@@ -25,6 +25,8 @@ constexpr int PANEL_NT = 1024;
 constexpr int PANEL_WMAX = 32;
 constexpr int TRSM_NB = 64;
 constexpr int64_t LU_INV_NB = 256;   // diagonal block order of the explicit L/U block inverses
+constexpr int64_t LU_PANEL_NB = 512; // panel width of the blocked LU (a multiple of LU_INV_NB)
+static_assert(LU_PANEL_NB % LU_INV_NB == 0, "panel = whole inverse blocks");
 constexpr int TRSM_CB = 8;      // right-hand-side columns per wavefront in the TRSM leaf
 
 // One step of an argmax reduction: the lane pattern CTRL (a DPP control: quad permutation or
@@ -625,41 +627,41 @@ static void identity_pair(hipStream_t s, int batch, int64_t NB, int64_t per, Cx<
     }
 }
 
-// Right-looking blocked LU with LU_INV_NB-column panels.  Per panel k:
-//   factor the panel (rows k0.., recursive LU above) and apply its exchanges to the columns
-//   left and right of it; invert the diagonal blocks L11 and U11 (kept for the solves: later
-//   exchanges only touch rows below the block, so both are final here);
-//   U12 = L11^{-1} A12 as a GEMM with the explicit inverse; A22 -= A21 U12 (rank-256 GEMM).
+// Right-looking blocked LU with LU_PANEL_NB-column panels (two LU_INV_NB blocks each).  Per
+// panel: factor the panel (rows k0.., recursive LU above) and apply its exchanges to the
+// columns left and right of it; invert the diagonal LU_INV_NB blocks of L and U (kept for the
+// solves: later exchanges only touch rows below a block, so both are final here); then
+// U12 = L11^{-1} A12 block by block (X_a = La^{-1} A_a, X_b = Lc^{-1} (A_b - Lb X_a)) and
+// the rank-LU_PANEL_NB trailing update A22 -= A21 U12, the dominant GEMM.
 // With a look-ahead stream, the panel factorisations and diagonal-block inverses run there:
-// the columns of panel k+1 are updated first, so that panel k+1 is factored while the rest of
-// the trailing matrix is updated on the main stream.  Panel k+1 only touches its own columns,
-// the trailing update only the columns after it, and the row exchanges of panel k+1 (main
-// stream) wait for both.
-// tmp holds LU_INV_NB x (n - LU_INV_NB) elements per matrix.
+// the columns of the next panel are updated first, so that the next panel is factored while
+// the rest of the trailing matrix is updated on the main stream.  A panel only touches its
+// own columns, the trailing update only the columns after it, and the row exchanges of the
+// next panel (main stream) wait for both.
+// tmp holds LU_PANEL_NB x (n - LU_PANEL_NB) elements per matrix (getrf_tmp_elems).
 template <typename R>
 static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
                           int32_t* ipiv, int32_t* info, int32_t* list, Cx<R>* dinv, Cx<R>* tmp,
                           const LuAux* aux) {
-    const int64_t NB = LU_INV_NB, per = lu_inverse_elems(n);
-    const int64_t st = NB * std::max<int64_t>(n - NB, 1);
+    const int64_t NB = LU_INV_NB, PB = LU_PANEL_NB, per = lu_inverse_elems(n);
+    const int64_t st = getrf_tmp_elems(n);
     const Cx<R> one(1, 0), mone(-1, 0), zero(0, 0);
     const bool la = aux && aux->s && aux->panel_done && aux->next_ready;
     hipStream_t sp = la ? aux->s : s;
-    if (la) {   // panel 0 follows the work already queued on the main stream
+    if (la) {   // the first panel follows the work already queued on the main stream
         NLF_HIP(hipEventRecord(aux->next_ready, s));
         NLF_HIP(hipStreamWaitEvent(sp, aux->next_ready, 0));
     }
-    for (int64_t k0 = 0; k0 < n; k0 += NB) {
-        const int64_t kb = std::min<int64_t>(NB, n - k0), k1 = k0 + kb, rest = n - k1;
-        const int64_t b = k0 / NB;
-        Cx<R>* Li = dinv + 2 * b * NB * NB;
-        Cx<R>* Ui = Li + NB * NB;
-        {
-            getrf_rec<R>(sp, n, batch, A, lda, sA, k0, kb, ipiv, info, list);
+    for (int64_t k0 = 0; k0 < n; k0 += PB) {
+        const int64_t kb = std::min<int64_t>(PB, n - k0), k1 = k0 + kb, rest = n - k1;
+        getrf_rec<R>(sp, n, batch, A, lda, sA, k0, kb, ipiv, info, list);
+        for (int64_t d0 = k0; d0 < k1; d0 += NB) {       // inverses of the diagonal blocks
+            const int64_t db = std::min<int64_t>(NB, k1 - d0);
+            Cx<R>* Li = dinv + 2 * (d0 / NB) * NB * NB;
             identity_pair<R>(sp, batch, NB, per, Li);
-            const Cx<R>* D = A + k0 + k0 * lda;
-            trsm_lower_unit<R>(sp, kb, kb, batch, D, lda, sA, Li, NB, per);
-            trsm_upper<R>(sp, kb, kb, batch, D, lda, sA, Ui, NB, per);
+            const Cx<R>* D = A + d0 + d0 * lda;
+            trsm_lower_unit<R>(sp, db, db, batch, D, lda, sA, Li, NB, per);
+            trsm_upper<R>(sp, db, db, batch, D, lda, sA, Li + NB * NB, NB, per);
         }
         if (la) {
             NLF_HIP(hipEventRecord(aux->panel_done, sp));
@@ -672,12 +674,17 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
             {
                 dim3 grid((unsigned)std::min<int64_t>(ceil_div(kb * w, 256), 2048), batch);
                 hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, kb, w,
-                                   (const Cx<R>*)A12, lda, sA, tmp, NB, st);
+                                   (const Cx<R>*)A12, lda, sA, tmp, PB, st);
                 NLF_HIP(hipGetLastError());
             }
-            {
-                ProfScope ps(NLF_PROF_TRSM, s, 8.0 * kb * w * kb * batch, 0);
-                gemm<R>(s, false, kb, w, kb, one, Li, NB, per, tmp, NB, st, zero, A12, lda, sA, batch);
+            for (int64_t d0 = k0; d0 < k1; d0 += NB) {
+                const int64_t db = std::min<int64_t>(NB, k1 - d0), off = d0 - k0;
+                const Cx<R>* Li = dinv + 2 * (d0 / NB) * NB * NB;
+                ProfScope ps(NLF_PROF_TRSM, s, 8.0 * db * w * (db + off) * batch, 0);
+                if (off > 0)   // subtract the contributions of the blocks above: tmp_b -= L_ba X_a
+                    gemm<R>(s, false, db, w, off, mone, A + d0 + k0 * lda, lda, sA, A12, lda, sA, one,
+                            tmp + off, PB, st, batch);
+                gemm<R>(s, false, db, w, db, one, Li, NB, per, tmp + off, PB, st, zero, A12 + off, lda, sA, batch);
             }
             ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * w * kb * batch,
                          sizeof(Cx<R>) * (2.0 * rest * w + (double)rest * kb + (double)kb * w) * batch);
@@ -688,7 +695,7 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
             if (!la) {
                 update(k1, rest);
             } else {
-                const int64_t w1 = std::min<int64_t>(NB, rest);
+                const int64_t w1 = std::min<int64_t>(PB, rest);
                 update(k1, w1);                       // the next panel's columns
                 NLF_HIP(hipEventRecord(aux->next_ready, s));
                 NLF_HIP(hipStreamWaitEvent(sp, aux->next_ready, 0));
@@ -698,7 +705,7 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
     }
 }
 
-int64_t getrf_tmp_elems(int64_t n) { return LU_INV_NB * std::max<int64_t>(n - LU_INV_NB, 1); }
+int64_t getrf_tmp_elems(int64_t n) { return LU_PANEL_NB * std::max<int64_t>(n - LU_PANEL_NB, 1); }
 
 template <typename R>
 void getrf(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t lda, int64_t sA,
