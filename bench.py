@@ -79,12 +79,20 @@ def probe_lu():
     print(json.dumps(dict(probe="blocked LU c128", copy_bytes=2 * (1 << 27) * 8, **PROBE)))
 
 
-def load_traffic():
-    """HBM traffic of the probe launch from the committed counter summary, or None when the
-    GEMM source changed after the counters were taken."""
+def source_digest():
+    """First 16 hex digits of the SHA-256 of the GEMM and LU sources (the probe's launches
+    depend on both)."""
     import hashlib
+    h = hashlib.sha256()
+    for f in ("gemm.hip", "lu.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1801_09794_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM traffic per launch of the dominant kernel from the committed counter summary, or
+    None when the GEMM or LU source changed after the counters were taken."""
     path = os.path.join(ROOT, "profiles", "lu_update_c128_n4096_b16_traffic.txt")
-    src = os.path.join(ROOT, "paper_1801_09794_amd", "csrc", "gemm.hip")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -92,8 +100,7 @@ def load_traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("gemm_source_sha256_16") != digest:
+    if kv.get("source_sha256_16", "").split()[0:1] != [source_digest()]:
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
