@@ -326,7 +326,7 @@ def main():
                "trailing_gemm_tflops": lu_tflops,
                "trailing_gemm_frac_fp64_peak": lu_tflops / PEAK["fp64_mfma_tflops"]},
         "roofline": {
-            "kernel": "lu_update_kernel<double, 2, 2, 16> (rank-512 trailing updates of the blocked LU)",
+            "kernel": "lu_update_kernel<double, 2, 2, 8> (rank-512 trailing updates of the blocked LU)",
             "bound": "mfma",
             "achieved": lu_tflops,
             "peak": PEAK["fp64_mfma_tflops"],
