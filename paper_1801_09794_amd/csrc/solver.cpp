@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <map>
 #include <mutex>
@@ -581,7 +582,8 @@ struct RegionOutcome {
 // Algorithm 1 Steps 0-5 for region ri, on stream s, with the node factorisations already in the
 // workspace.  Writes the region's slice of the outputs; never throws.
 RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, const Layout& L, int ri,
-                         hipStream_t s, Profiler* prof, const RegionIO& io) {
+                         hipStream_t s, Profiler* prof, const RegionIO& io,
+                         std::atomic<int>* active = nullptr) {
     RegionOutcome res_out;
     try {
         ProfilerGuard pg(prof);
@@ -647,6 +649,10 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             const auto t0 = std::chrono::steady_clock::now();
             std::vector<cplx> prev;
             if (it > 0) prev = rr.lambda;
+            if (active) {   // share the host threads among the regions still iterating
+                const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+                host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
+            }
             rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr);
             host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
             NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
@@ -1008,17 +1014,18 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             }
             std::vector<std::thread> threads;
             threads.reserve(nreg);
+            std::atomic<int> active{nreg};
             for (int ri = 0; ri < nreg; ++ri)
                 threads.emplace_back([&, ri] {
                     if (hipSetDevice(h->device) != hipSuccess) {
                         out[ri].status = NLF_ERR_DEVICE;
                         out[ri].msg = "hipSetDevice failed in a region thread";
+                        active.fetch_sub(1);
                         return;
                     }
-                    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-                    host_thread_budget() = std::max(1, hw / nreg);
                     out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
-                                         h->profiling ? h->rprof[ri].get() : nullptr, io);
+                                         h->profiling ? h->rprof[ri].get() : nullptr, io, &active);
+                    active.fetch_sub(1);
                 });
             for (auto& t : threads) t.join();
             for (int ri = 0; ri < nreg; ++ri) {
