@@ -122,10 +122,11 @@ def test_getrf_matches_oracle_lu(dtype, n, batch):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,batch", [(33, 2), (256, 2), (300, 2), (700, 2)])
+@pytest.mark.parametrize("n,batch", [(33, 2), (256, 2), (300, 2), (700, 2), (1100, 1)])
 def test_getrf_blocked_matches_oracle_and_inverses(dtype, n, batch):
-    # right-looking blocked LU: one partial panel, exactly one panel, a ragged second panel,
-    # three panels; the diagonal-block inverses it leaves behind are checked as well
+    # right-looking blocked LU with 512-column panels: one partial panel (one or two inverse
+    # blocks), a ragged second panel, three panels with a ragged third; the 256 x 256
+    # diagonal-block inverses it leaves behind are checked as well
     rng = np.random.default_rng(7 * n + batch)
     dt = torch.complex128 if dtype == "c128" else torch.complex64
     mats = [wl.cn(rng, (n, n)) for _ in range(batch)]

@@ -134,6 +134,16 @@ def test_m0_too_small_status():
     assert out["status"] == nl.NLF_ERR_M0_TOO_SMALL
 
 
+def test_empty_contour_returns_no_pairs():
+    # a circle far from the spectrum: no Ritz value ever falls inside, the iteration ends after
+    # three Step 4 executions with m = 0 (reading of the stop rule)
+    terms, mats = wl.make_problem("qep200")
+    out = gpu_solve(terms, mats, [dict(centre=4.0 + 4.0j, a=0.05, nc=8, m0=6)],
+                    wl.initial_block(200, 6, 9), nl.options(tol=1e-12))
+    assert out["status"] == nl.NLF_OK
+    assert out["m"][0] == 0 and out["iters"][0] == 3 and not out["inside"].any()
+
+
 def test_not_converged_status_returns_pairs():
     terms, mats = wl.make_problem("qep200")
     g = contours("qep200")[0]
