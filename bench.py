@@ -41,6 +41,8 @@ def parse():
                     help="also run the batched and delay workloads in FP64")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
+    ap.add_argument("--refine-eta", type=float, default=1e-3,
+                    help="FP32+refine: refinement target ||E_k|| <= eta ||R||")
     ap.add_argument("--lookahead", type=int, default=0,
                     help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
     ap.add_argument("--lu-streams", type=int, default=0,
@@ -133,7 +135,7 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     quad = nl.NLF_QUAD_TRAPEZOID if cfg.get("quad") == "trapezoid" else nl.NLF_QUAD_GAUSS_LEGENDRE
     S.set_contour(regions, quad_rule=quad)
     X0d = nl.to_colmajor(X0, "cuda:0")
-    opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=1e-3,
+    opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=args.refine_eta,
                       lu_streams=args.lu_streams, panel_width=args.panel_width,
                       autotune=autotune, graph=graph, lookahead=args.lookahead)
     for _ in range(args.warmup):
