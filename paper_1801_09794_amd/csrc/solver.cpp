@@ -171,13 +171,20 @@ struct nlfeast_ctx {
     bool profiling = false;
     Profiler prof;
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};   // factorisation streams
-    hipEvent_t ev_fork = nullptr, ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipStream_t> rstream;                      // one iteration stream per region
     std::vector<hipEvent_t> rdone;
     std::vector<std::unique_ptr<Profiler>> rprof;
     hipEvent_t ev_lufork = nullptr;
     hipStream_t la_stream[4] = {nullptr, nullptr, nullptr, nullptr};   // LU look-ahead streams
     hipEvent_t la_panel[4] = {nullptr, nullptr, nullptr, nullptr}, la_next[4] = {nullptr, nullptr, nullptr, nullptr};
+
+    // iteration 0 of every region (Steps 0-3 need no factors) runs while the factorisation
+    // is in flight: ev_start marks the caller's stream before the factorisation, ev_factored
+    // after it and after the pivots' info flags have reached the pinned info_host
+    hipEvent_t ev_start = nullptr, ev_factored = nullptr;
+    int32_t* info_host = nullptr;
+    int info_cap = 0;
 
     hipStream_t gstream = nullptr;                         // capture stream of the factorisation graph
     hipGraphExec_t graph_exec = nullptr;
@@ -201,7 +208,9 @@ struct nlfeast_ctx {
             if (side[i]) (void)hipStreamDestroy(side[i]);
             if (ev_join[i]) (void)hipEventDestroy(ev_join[i]);
         }
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_start) (void)hipEventDestroy(ev_start);
+        if (ev_factored) (void)hipEventDestroy(ev_factored);
+        if (info_host) (void)hipHostFree(info_host);
     }
 };
 
@@ -582,7 +591,7 @@ struct RegionOutcome {
 // Algorithm 1 Steps 0-5 for region ri, on stream s, with the node factorisations already in the
 // workspace.  Writes the region's slice of the outputs; never throws.
 RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, const Layout& L, int ri,
-                         hipStream_t s, Profiler* prof, const RegionIO& io,
+                         hipStream_t s, Profiler* prof, const RegionIO& io, hipEvent_t factored,
                          std::atomic<int>* active = nullptr) {
     RegionOutcome res_out;
     try {
@@ -708,6 +717,17 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             }
             if (it >= 3 && n_in == 0) break;
             if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
+            // the factors are needed from here on: wait for the factorisation launched before
+            // iteration 0 and reject singular node matrices of this region
+            if (factored) {
+                NLF_HIP(hipEventSynchronize(factored));
+                for (int q = 0; q < nc; ++q)
+                    NLF_REQUIRE(h->info_host[node0 + q] == 0, NLF_ERR_SINGULAR,
+                                "solve: T(z_k) is singular at node " + std::to_string(node0 + q) +
+                                    " (exact zero pivot " + std::to_string(h->info_host[node0 + q]) + ")");
+                NLF_HIP(hipStreamWaitEvent(s, factored, 0));
+                factored = nullptr;
+            }
             // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
             {
                 TrsmClassGuard tg(NLF_PROF_SOLVE);
@@ -947,8 +967,14 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         if (h->profiling) h->prof.reset();
         ProfilerGuard pg(h->profiling ? &h->prof : nullptr);
 
-        // ---- fixed shifts: assemble and factor T(z_k) once per contour
+        // ---- fixed shifts: assemble and factor T(z_k) once per contour; the regions start
+        // from ev_start (the caller's prior work) and wait for ev_factored before Step 4
+        if (!h->ev_start) NLF_HIP(hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming));
+        if (!h->ev_factored) NLF_HIP(hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming));
+        NLF_HIP(hipEventRecord(h->ev_start, s));
+        hipEvent_t factored = nullptr;
         if (!(h->factors_valid && h->factors_ws == ws && h->factors_prec == opt->precision)) {
+            h->factors_valid = false;
             std::vector<cplx> coef((size_t)L.NZ * J);
             int k = 0;
             for (const auto& r : h->regions)
@@ -970,48 +996,49 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                 ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
                 factor_all(h, L, ws, p32, s, tune);
             }
-            std::vector<int32_t> info(L.NZ);
-            d2h_sync(s, info.data(), at<void>(ws, L.info), sizeof(int32_t) * L.NZ);
-            for (int q = 0; q < L.NZ; ++q)
-                NLF_REQUIRE(info[q] == 0, NLF_ERR_SINGULAR,
-                            "solve: T(z_k) is singular at node " + std::to_string(q) +
-                                " (exact zero pivot " + std::to_string(info[q]) + ")");
-            h->factors_valid = true;
-            h->factors_ws = ws;
-            h->factors_prec = opt->precision;
+            if (h->info_cap < L.NZ) {
+                if (h->info_host) NLF_HIP(hipHostFree(h->info_host));
+                h->info_host = nullptr;
+                h->info_cap = 0;
+                NLF_HIP(hipHostMalloc((void**)&h->info_host, sizeof(int32_t) * L.NZ, hipHostMallocDefault));
+                h->info_cap = L.NZ;
+            }
+            NLF_HIP(hipMemcpyAsync(h->info_host, at<void>(ws, L.info), sizeof(int32_t) * L.NZ,
+                                   hipMemcpyDeviceToHost, s));
+            NLF_HIP(hipEventRecord(h->ev_factored, s));
+            factored = h->ev_factored;
         }
 
         const int nreg = (int)h->regions.size();
         std::vector<RegionOutcome> out(nreg);
         RegionIO io{X0_dev, X_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out};
         const bool concurrent = nreg > 1 && opt->region_streams == 0;
+        // region streams: one per region when they run concurrently, else one shared stream
+        const int nrs = concurrent ? nreg : 1;
+        for (int ri = (int)h->rstream.size(); ri < nrs; ++ri) {
+            hipStream_t rs;
+            hipEvent_t ev;
+            NLF_HIP(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking));
+            NLF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            h->rstream.push_back(rs);
+            h->rdone.push_back(ev);
+            h->rprof.emplace_back(new Profiler());
+        }
+        for (int ri = 0; ri < nrs; ++ri) NLF_HIP(hipStreamWaitEvent(h->rstream[ri], h->ev_start, 0));
         if (!concurrent) {
             for (int ri = 0; ri < nreg; ++ri) {
-                out[ri] = run_region(h, *opt, ws, L, ri, s, h->profiling ? &h->prof : nullptr, io);
+                out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[0], h->profiling ? &h->prof : nullptr, io,
+                                     factored);
                 if (out[ri].status != NLF_OK && out[ri].status != NLF_ERR_NOT_CONVERGED &&
                     out[ri].status != NLF_ERR_M0_TOO_SMALL)
                     break;
             }
+            NLF_HIP(hipEventRecord(h->rdone[0], h->rstream[0]));
+            NLF_HIP(hipStreamWaitEvent(s, h->rdone[0], 0));
         } else {
-            // every region waits for the shared factorisation, then iterates on its own stream
-            // and host thread; the caller's stream waits for all of them
-            if ((int)h->rstream.size() < nreg) {
-                for (int ri = (int)h->rstream.size(); ri < nreg; ++ri) {
-                    hipStream_t rs;
-                    hipEvent_t ev;
-                    NLF_HIP(hipStreamCreateWithFlags(&rs, hipStreamNonBlocking));
-                    NLF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-                    h->rstream.push_back(rs);
-                    h->rdone.push_back(ev);
-                    h->rprof.emplace_back(new Profiler());
-                }
-            }
-            if (!h->ev_fork) NLF_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-            NLF_HIP(hipEventRecord(h->ev_fork, s));
-            for (int ri = 0; ri < nreg; ++ri) {
-                NLF_HIP(hipStreamWaitEvent(h->rstream[ri], h->ev_fork, 0));
-                h->rprof[ri]->reset();
-            }
+            // every region iterates on its own stream and host thread (iteration 0 overlaps the
+            // shared factorisation); the caller's stream waits for all of them
+            for (int ri = 0; ri < nreg; ++ri) h->rprof[ri]->reset();
             std::vector<std::thread> threads;
             threads.reserve(nreg);
             std::atomic<int> active{nreg};
@@ -1024,7 +1051,7 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                         return;
                     }
                     out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
-                                         h->profiling ? h->rprof[ri].get() : nullptr, io, &active);
+                                         h->profiling ? h->rprof[ri].get() : nullptr, io, factored, &active);
                     active.fetch_sub(1);
                 });
             for (auto& t : threads) t.join();
@@ -1044,6 +1071,21 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         // a hard error (device, argument) wins over the convergence statuses
         int status = NLF_OK;
         std::string msg;
+        if (factored) {
+            // regions that stopped before Step 4 never looked at the pivots
+            for (int q = 0; q < L.NZ; ++q)
+                if (h->info_host[q] != 0) {
+                    status = NLF_ERR_SINGULAR;
+                    msg = "solve: T(z_k) is singular at node " + std::to_string(q) + " (exact zero pivot " +
+                          std::to_string(h->info_host[q]) + ")";
+                    break;
+                }
+            if (status == NLF_OK) {
+                h->factors_valid = true;
+                h->factors_ws = ws;
+                h->factors_prec = opt->precision;
+            }
+        }
         for (int ri = 0; ri < nreg; ++ri) {
             const int st = out[ri].status;
             if (st == NLF_OK) continue;
