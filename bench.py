@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--no-delay", action="store_true",
                     help="skip the delay workload (delay8192)")
     ap.add_argument("--fp64-legs", action="store_true",
-                    help="also run the batched and delay workloads in FP64")
+                    help="also run the batched workload in FP64 (the delay workload always runs in both)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
     ap.add_argument("--refine-eta", type=float, default=1e-3,
@@ -189,16 +189,17 @@ def reference_error(name, regions, out, tol):
     return worst
 
 
-def extra_leg(args, name, description, autotune, graph):
-    """A parity configuration beside the headline: FP32 LU + FP64 refinement (and FP64 with
-    --fp64-legs), converged eigenvalues checked against the stored brute-force reference."""
+def extra_leg(args, name, description, autotune, graph, with_fp64=False):
+    """A parity configuration beside the headline: FP32 LU + FP64 refinement (and FP64 when
+    with_fp64 or --fp64-legs), converged eigenvalues checked against the stored brute-force
+    reference."""
     import paper_1801_09794_amd as nl
     cfg, terms, mats, regions, X0 = load_workload(name)
     n, nz = cfg["n"], sum(r["nc"] for r in regions)
     out = {"workload": description % dict(n=n, m0=[r["m0"] for r in regions], nc=cfg["nc"], nz=nz,
                                           tol=cfg["tol"], inside=cfg.get("inside") or 0)}
     precs = [("fp32_refine", nl.NLF_PREC_FP32_REFINE)]
-    if args.fp64_legs:
+    if args.fp64_legs or with_fp64:
         precs.append(("fp64", nl.NLF_PREC_FP64))
     for key, prec in precs:
         t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph)
@@ -214,6 +215,23 @@ def extra_leg(args, name, description, autotune, graph):
                     "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()}}
     if "fp64" in out:
         out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
+    return out
+
+
+def hbm_kernels(prof):
+    """Achieved bandwidth of the HBM-bound steps (assembly of T(z_k), Step 4 accumulation):
+    algorithmic bytes of their launches over their summed event-timed duration."""
+    out = {}
+    for k, what in (("assemble", "T(z_k) = sum_j f_j(z_k) A_j: read each A_j once, write every node"),
+                    ("accumulate", "Q = X rho(Lambda) - sum_k omega_k Y_k (z_k - Lambda)^-1: read n_c + 1 "
+                                   "blocks, write one")):
+        v = prof.get(k)
+        if not v or v["ms"] <= 0 or v["bytes"] <= 0:
+            continue
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+        out[k] = {"what": what, "achieved": gbs, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                  "frac": gbs / PEAK["hbm_gbs"], "bytes_per_launch": v["bytes"] / max(v["launches"], 1),
+                  "avg_launch_us": v["ms"] * 1e3 / max(v["launches"], 1)}
     return out
 
 
@@ -344,6 +362,7 @@ def main():
             "flops_per_step": lu["flops"] / args.steps,
         },
         "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
+        "hbm_kernels": hbm_kernels(prof),
     }
     if not args.no_fp32:
         t32, out32, prof32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True)
@@ -372,7 +391,7 @@ def main():
             args, "delay8192",
             "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%(n)d dense complex128, circle "
             "enclosing %(inside)d eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, tol %(tol).0e",
-            autotune=0, graph=0)
+            autotune=0, graph=0, with_fp64=True)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

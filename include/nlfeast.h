@@ -270,9 +270,11 @@ nlfeast_status nlf_accumulate(int64_t n, int32_t m, int32_t nz, const void* X_de
                               const void* Y_dev, const double* z, const double* omega,
                               const double* lambda, void* Q_dev, void* stream);
 
-/* Steps 0/5: orthonormalise the columns of the c128 n x m block Q_dev (ld n) in place, by
- * Cholesky QR twice (Gram matrix on MFMA, m x m Cholesky on the host).  ws_dev: c128 scratch
- * of nlf_orth_workspace(n, m) elements.  Blocking (host Cholesky). */
+/* Steps 0/5: orthonormalise the columns of the c128 n x m block Q_dev (ld n, m <= n) in
+ * place, by Cholesky QR twice (Gram matrix on MFMA, m x m Cholesky on the host); a block whose
+ * Gram matrix is numerically singular (Cholesky fails, or a pivot falls below 1e-12 of its
+ * diagonal entry) goes through blocked Householder QR on the device instead.  ws_dev: c128
+ * scratch of nlf_orth_workspace(n, m) elements.  Blocking (host Cholesky). */
 int64_t nlf_orth_workspace(int64_t n, int32_t m);
 nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_dev, void* stream);
 

@@ -81,12 +81,14 @@ void quadrature(const Ellipse& E, int nc, int rule, std::vector<cplx>& z, std::v
     }
 }
 
-bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv) {
+bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv, double* min_pivot_ratio) {
     std::vector<cplx> R(m * m, 0.0);
+    double ratio = 1.0;
     for (int j = 0; j < m; ++j) {
         double d = G[j + j * m].real();
         for (int k = 0; k < j; ++k) d -= std::norm(R[k + j * m]);
         if (!(d > 0.0) || !std::isfinite(d)) return false;
+        ratio = std::min(ratio, d / G[j + j * m].real());
         const double rjj = std::sqrt(d);
         R[j + j * m] = rjj;
         for (int i = j + 1; i < m; ++i) {
@@ -104,6 +106,7 @@ bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv) {
             Rinv[i + (size_t)c * m] = -s / R[i + (size_t)i * m];
         }
     }
+    if (min_pivot_ratio) *min_pivot_ratio = ratio;
     return true;
 }
 
@@ -196,6 +199,9 @@ bool Schur::compute(int N_, std::vector<cplx>& A, bool vecs) {
     if (hnorm == 0.0) hnorm = 1.0;
     // shifted QR iterations (Wilkinson shift, exceptional shifts at 10 and 20 stalled steps)
     int ihi = N - 1, its = 0, total = 0;
+    std::vector<double> rc(N);
+    std::vector<cplx> rs(N);
+    std::vector<int> upto(N);
     while (ihi >= 0) {
         int l = ihi;
         while (l > 0) {
@@ -441,6 +447,9 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
         H.swap(Hp);
     }
     int ihi = N - 1, its = 0, total = 0;
+    std::vector<double> rc(N);
+    std::vector<cplx> rs(N);
+    std::vector<int> upto(N);
     while (ihi >= 0) {
         int l = ihi;
         while (l > 0) {
@@ -469,25 +478,56 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
             const cplx m1 = tr2 + disc, m2 = tr2 - disc;
             mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
         }
-        cplx x = H[l + (size_t)l * LD] - mu, y = H[l + 1 + (size_t)l * LD];
+        // One implicit single-shift sweep over [l, ihi].  Left and right rotations commute,
+        // so the row rotations are applied lazily, column by column: a column receives its
+        // pending rotations as one pass down its contiguous rows just before it is read (as
+        // the source of the next rotation or as an operand of a column rotation), and the
+        // columns ahead are brought up to date four at a time, which overlaps four independent
+        // rotation chains.  upto[c]: rotations [l, upto[c]) are applied to column c.
+        for (int c = l; c <= ihi; ++c) upto[c] = l;
+        auto flush = [&](int c0, int c1, int kend) {   // columns c0..c1 (equal upto) to kend
+            cplx* col[4];
+            const int g = c1 - c0 + 1;
+            for (int q = 0; q < g; ++q) col[q] = &H[(size_t)(c0 + q) * LD];
+            for (int j = upto[c0]; j < kend; ++j) {
+                const double cs = rc[j];
+                const cplx sn = rs[j], csn = std::conj(rs[j]);
+                for (int q = 0; q < g; ++q) {
+                    const cplx p = col[q][j], qq = col[q][j + 1];
+                    col[q][j] = cs * p + sn * qq;
+                    col[q][j + 1] = -csn * p + cs * qq;
+                }
+            }
+            for (int q = 0; q < g; ++q) upto[c0 + q] = kend;
+        };
         for (int k = l; k < ihi; ++k) {
-            if (k > l) {
+            cplx x, y;
+            if (k == l) {
+                x = H[l + (size_t)l * LD] - mu;
+                y = H[l + 1 + (size_t)l * LD];
+            } else {
+                flush(k - 1, k - 1, k);
                 x = H[k + (size_t)(k - 1) * LD];
                 y = H[k + 1 + (size_t)(k - 1) * LD];
             }
             double cs;
             cplx sn, rho;
             givens(x, y, cs, sn, rho);
+            rc[k] = cs;
+            rs[k] = sn;
             if (k > l) {
                 H[k + (size_t)(k - 1) * LD] = rho;
                 H[k + 1 + (size_t)(k - 1) * LD] = 0.0;
+                upto[k - 1] = k + 1;
+            }
+            flush(k, k, k + 1);
+            if (upto[k + 1] == l && k + 1 > l) {
+                const int c1 = std::min(k + 4, ihi);
+                flush(k + 1, c1, k + 1);
+            } else {
+                flush(k + 1, k + 1, k + 1);
             }
             const cplx csn = std::conj(sn);
-            for (int j = k; j <= ihi; ++j) {            // rows k, k+1 inside the window
-                const cplx p = H[k + (size_t)j * LD], q = H[k + 1 + (size_t)j * LD];
-                H[k + (size_t)j * LD] = cs * p + sn * q;
-                H[k + 1 + (size_t)j * LD] = -csn * p + cs * q;
-            }
             const int iend = std::min(k + 2, ihi);
             cplx* ck = &H[(size_t)k * LD];
             cplx* ck1 = &H[(size_t)(k + 1) * LD];

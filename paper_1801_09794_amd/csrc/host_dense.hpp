@@ -23,8 +23,10 @@ struct Ellipse {
 void quadrature(const Ellipse& E, int nc, int rule, std::vector<cplx>& z, std::vector<cplx>& w);
 
 // Upper-triangular R with G = R^H R (G Hermitian positive definite, m x m, column-major).
-// Returns false when a pivot is not positive.  Rinv receives R^{-1} (upper triangular).
-bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv);
+// Returns false when a pivot is not positive.  Rinv receives R^{-1} (upper triangular);
+// min_pivot_ratio (optional) the smallest R_jj^2 / G_jj, a detector of near dependence.
+bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv,
+                            double* min_pivot_ratio = nullptr);
 
 // Term of T(lambda): kind 0 = lambda^p, kind 1 = exp(-tau lambda).
 struct Term {

@@ -93,4 +93,13 @@ void fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v);
 // counter-based standard complex normal draws CN(0,1) for an n x m block
 void random_normal(hipStream_t s, int64_t rows, int64_t cols, uint64_t seed, z128* out, int64_t ld);
 
+// Householder QR of Q (n x m, ld n, m <= n), for blocks too ill-conditioned for Cholesky QR:
+// the first m columns of the orthogonal factor are written to E (n x m, ld n); Q is
+// overwritten.  V: n x m scratch (the reflectors); small: householder_scratch_elems(m)
+// elements; ws, ws_elems: split-K scratch of the GEMMs (as for the Gram matrix).
+constexpr int QR_HB = 8;   // panel width
+int64_t householder_scratch_elems(int64_t m);
+void householder_orthonormalize(hipStream_t s, int64_t n, int64_t m, z128* Q, z128* E, z128* V, z128* small,
+                                z128* ws, int64_t ws_elems);
+
 }  // namespace nlf

@@ -219,7 +219,7 @@ namespace {
 // Per-region iteration buffers (each region may run on its own stream and host thread).
 struct RegionLayout {
     size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, stmp = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
-    size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0;
+    size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0, hh = 0;
     int64_t splitws_elems = 0;
     int node0 = 0, col0 = 0;
 };
@@ -290,6 +290,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
         R.norms = take(8 * (size_t)(m + nc + 8 + block_sqnorms_scratch(nc)));
         R.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
         R.splitws = take(16 * (size_t)R.splitws_elems);
+        R.hh = take(16 * (size_t)householder_scratch_elems(m));
         L.reg.push_back(R);
         node0 += nc;
         col0 += m;
@@ -313,25 +314,30 @@ void d2h_sync(hipStream_t s, void* dst, const void* src, size_t bytes) {
 
 // Steps 0/5: Cholesky QR, twice; a diagonal shift rescues a numerically rank-deficient Gram
 // matrix (then a third pass restores orthonormality).
+// Cholesky QR twice (Step 0 and Step 5).  The filtered block of Step 4 can be numerically rank
+// deficient (components of eigenvectors far outside C are damped by rho(lambda) to rounding
+// level, and the columns of far-outside Ritz values collapse onto the inside eigenspace);
+// Cholesky QR cannot orthonormalise such a block.  When the Cholesky factor of the Gram matrix
+// fails or shows a pivot below 1e-12 of its diagonal entry (a column with less than 1e-6 of
+// its norm outside the span of the previous ones), the block goes through Householder QR
+// instead, which is orthogonal to working precision at any rank.  V: n x m scratch; hh:
+// householder_scratch_elems(m) elements.
 void orthonormalize(hipStream_t s, int64_t n, int m, z128* Q, z128* QT, z128* Gd, z128* Rd,
-                    z128* splitws, int64_t split_elems) {
+                    z128* splitws, int64_t split_elems, z128* V, z128* hh) {
     std::vector<cplx> G((size_t)m * m), Rinv;
-    int passes = 2;
-    for (int p = 0; p < passes; ++p) {
+    for (int p = 0; p < 2; ++p) {
         {
             ProfScope ps(NLF_PROF_ORTH, s, 8.0 * n * m * m, 16.0 * n * m);
             gemm<double>(s, true, m, m, n, z128(1, 0), Q, n, 0, Q, n, 0, z128(0, 0), Gd, m, 0, 1,
                          splitws, split_elems);
         }
         d2h_sync(s, G.data(), Gd, sizeof(cplx) * m * m);
-        if (!cholesky_upper_inverse(m, G.data(), Rinv)) {
-            double tr = 0.0;
-            for (int i = 0; i < m; ++i) tr += std::abs(G[i + (size_t)i * m].real());
-            const double shift = 1e-13 * std::max(tr, 1e-300);
-            for (int i = 0; i < m; ++i) G[i + (size_t)i * m] += shift;
-            NLF_REQUIRE(cholesky_upper_inverse(m, G.data(), Rinv), NLF_ERR_DEVICE,
-                        "orthonormalisation: Gram matrix is not positive definite");
-            passes = 3;
+        double ratio = 0.0;
+        if (!cholesky_upper_inverse(m, G.data(), Rinv, &ratio) || ratio < 1e-12) {
+            ProfScope ps(NLF_PROF_ORTH, s, 32.0 * n * m * m, 64.0 * n * m);
+            householder_orthonormalize(s, n, m, Q, QT, V, hh, splitws, split_elems);
+            copy_block(s, n, m, QT, n, Q, n);
+            return;
         }
         h2d(s, Rd, Rinv.data(), sizeof(cplx) * m * m);
         {
@@ -631,7 +637,8 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             copy_block(s, n, m, (const z128*)io.X0 + (size_t)col0 * n, n, Q, n);
         else
             random_normal(s, n, m, opt->seed * 0x9E3779B97F4A7C15ull + ri + 1, Q, n);
-        orthonormalize(s, n, m, Q, QT, Gd, at<z128>(ws, RL.Ymat), splitws, RL.splitws_elems);
+        orthonormalize(s, n, m, Q, QT, Gd, at<z128>(ws, RL.Ymat), splitws, RL.splitws_elems, Ys,
+                       at<z128>(ws, RL.hh));
 
         std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
             acoef((size_t)nc * m);
@@ -785,7 +792,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             h2d(s, acoef_d, acoef.data(), sizeof(cplx) * acoef.size());
             accumulate(s, n, m, nc, X, Ys, (int64_t)blk, rho_d, acoef_d, Q);
             // Step 5
-            orthonormalize(s, n, m, Q, QT, Gd, Ymat, splitws, RL.splitws_elems);
+            orthonormalize(s, n, m, Q, QT, Gd, Ymat, splitws, RL.splitws_elems, Ys, at<z128>(ws, RL.hh));
             ++it;
         }
         // outputs for this region
@@ -1363,7 +1370,8 @@ nlfeast_status nlf_accumulate(int64_t n, int32_t m, int32_t nz, const void* X_de
 }
 
 int64_t nlf_orth_workspace(int64_t n, int32_t m) {
-    return n * m + 2 * (int64_t)m * m + std::max<int64_t>(64 * (int64_t)m * m, 1 << 16);
+    return 2 * n * m + 2 * (int64_t)m * m + std::max<int64_t>(64 * (int64_t)m * m, 1 << 16) +
+           householder_scratch_elems(m);
 }
 
 nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_dev, void* stream) {
@@ -1375,8 +1383,10 @@ nlfeast_status nlf_orthonormalize(int64_t n, int32_t m, void* Q_dev, void* ws_de
         z128* G = QT + n * m;
         z128* Rd = G + (int64_t)m * m;
         z128* sp = Rd + (int64_t)m * m;
-        orthonormalize(as_stream(stream), n, m, (z128*)Q_dev, QT, G, Rd, sp,
-                       std::max<int64_t>(64 * (int64_t)m * m, 1 << 16));
+        const int64_t spn = std::max<int64_t>(64 * (int64_t)m * m, 1 << 16);
+        z128* V = sp + spn;
+        z128* hh = V + n * m;
+        orthonormalize(as_stream(stream), n, m, (z128*)Q_dev, QT, G, Rd, sp, spn, V, hh);
         NLF_HIP(hipStreamSynchronize(as_stream(stream)));
         return NLF_OK;
     })

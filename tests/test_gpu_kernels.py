@@ -297,6 +297,31 @@ def test_project_matches_oracle():
         assert rel(nl.from_colmajor(Ah[j]), ref[j]) < 1e-13
 
 
+@pytest.mark.parametrize("n,m", [(1500, 45), (300, 64)])
+def test_orthonormalize_rank_deficient_block(n, m):
+    # singular values from 1 down to 1e-20: the Gram matrix is numerically singular, so the
+    # block goes through the Householder path (ragged last panel at m = 45); the result must
+    # be orthonormal and contain every direction whose singular value is at least 1e-6
+    rng = np.random.default_rng(9)
+    U, _ = np.linalg.qr(wl.cn(rng, (n, m)))
+    Vh, _ = np.linalg.qr(wl.cn(rng, (m, m)))
+    s = np.logspace(0, -20, m)
+    Q0 = (U * s[None, :]) @ Vh
+    Q = dev(Q0)
+    ws = torch.empty(nl.nlf_orth_workspace(n, m), dtype=torch.complex128, device="cuda")
+    nl.nlf_orthonormalize(Q, ws)
+    torch.cuda.synchronize()
+    q = nl.from_colmajor(Q)
+    assert np.all(np.isfinite(q))
+    assert np.max(np.abs(q.conj().T @ q - np.eye(m))) < 1e-13
+    k = int(np.sum(s >= 1e-6))
+    Uk = U[:, :k]
+    assert np.max(np.abs(q @ (q.conj().T @ Uk) - Uk)) < 1e-8
+    # the leading columns span what the leading columns of Q0 span (a QR factorisation)
+    ref, _ = np.linalg.qr(Q0[:, :4])
+    assert np.max(np.abs(q[:, :4] @ (q[:, :4].conj().T @ ref) - ref)) < 1e-12
+
+
 def test_orthonormalize_keeps_span():
     rng = np.random.default_rng(8)
     n, m = 2000, 40
