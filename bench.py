@@ -37,11 +37,13 @@ def parse():
                     help="skip the eight-region batched workload (qep2048x8)")
     ap.add_argument("--no-delay", action="store_true",
                     help="skip the delay workload (delay8192)")
+    ap.add_argument("--no-delay-fp64", action="store_true",
+                    help="run the delay workload in FP32 + refinement only")
     ap.add_argument("--fp64-legs", action="store_true",
                     help="also run the batched workload in FP64 (the delay workload always runs in both)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
-    ap.add_argument("--refine-eta", type=float, default=1e-3,
+    ap.add_argument("--refine-eta", type=float, default=0.05,
                     help="FP32+refine: refinement target ||E_k|| <= eta ||R||")
     ap.add_argument("--lookahead", type=int, default=0,
                     help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
@@ -391,7 +393,7 @@ def main():
             args, "delay8192",
             "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%(n)d dense complex128, circle "
             "enclosing %(inside)d eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, tol %(tol).0e",
-            autotune=0, graph=0, with_fp64=True)
+            autotune=0, graph=0, with_fp64=not args.no_delay_fp64)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
                 ("lookahead", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-def options(tol=1e-10, max_iter=50, precision=NLF_PREC_FP64, max_refine=5, refine_eta=1e-3,
+def options(tol=1e-10, max_iter=50, precision=NLF_PREC_FP64, max_refine=5, refine_eta=0.05,
             seed=2024, autotune=0, verbose=0, lu_streams=0, panel_width=0, region_streams=0,
             graph=0, lookahead=0):
     return Options(tol, max_iter, precision, max_refine, refine_eta, seed, autotune, verbose,
