@@ -1,6 +1,8 @@
 // Host-side small dense routines (see host_dense.hpp).
 #include "host_dense.hpp"
 
+#include <immintrin.h>
+
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -199,9 +201,6 @@ bool Schur::compute(int N_, std::vector<cplx>& A, bool vecs) {
     if (hnorm == 0.0) hnorm = 1.0;
     // shifted QR iterations (Wilkinson shift, exceptional shifts at 10 and 20 stalled steps)
     int ihi = N - 1, its = 0, total = 0;
-    std::vector<double> rc(N);
-    std::vector<cplx> rs(N);
-    std::vector<int> upto(N);
     while (ihi >= 0) {
         int l = ihi;
         while (l > 0) {
@@ -363,6 +362,51 @@ int& host_thread_budget() {
     return b;
 }
 
+// The two rotation updates of a QR sweep with G = [[c, s], [-conj(s), c]], in AVX2.
+// Rows k, k+1 (p = row k, q = row k+1) over cnt columns with stride ld:
+//   p <- c p + s q,  q <- -conj(s) p + c q.
+// The pair (p, q) of one column is 32 contiguous bytes: one 256-bit register
+// [p.re, p.im, q.re, q.im]; with w = its halves swapped and w' = w with re/im swapped,
+//   v <- c v + [s.re, s.re, -s.re, -s.re] w + [-s.im, s.im, -s.im, s.im] w'.
+static void rotate_rows(cplx* h, int ld, int cnt, double c, cplx s) {
+    double* d = reinterpret_cast<double*>(h);
+    const __m256d vc = _mm256_set1_pd(c);
+    const __m256d vr = _mm256_setr_pd(s.real(), s.real(), -s.real(), -s.real());
+    const __m256d vi = _mm256_setr_pd(-s.imag(), s.imag(), -s.imag(), s.imag());
+    for (int j = 0; j < cnt; ++j) {
+        double* e = d + 2 * (size_t)j * ld;
+        const __m256d v = _mm256_loadu_pd(e);
+        const __m256d w = _mm256_permute4x64_pd(v, 0x4E);
+        const __m256d w2 = _mm256_permute_pd(w, 0x5);
+        _mm256_storeu_pd(e, _mm256_fmadd_pd(vc, v, _mm256_fmadd_pd(vr, w, _mm256_mul_pd(vi, w2))));
+    }
+}
+
+// Columns a (k) and b (k+1) over cnt contiguous rows:  a <- c a + conj(s) b,  b <- -s a + c b;
+// two complex numbers per register, complex products by fmaddsub.
+static void rotate_cols(cplx* a, cplx* b, int cnt, double c, cplx s) {
+    double* pa = reinterpret_cast<double*>(a);
+    double* pb = reinterpret_cast<double*>(b);
+    const __m256d vc = _mm256_set1_pd(c);
+    const __m256d sr = _mm256_set1_pd(s.real()), si = _mm256_set1_pd(s.imag());
+    int i = 0;
+    for (; i + 2 <= cnt; i += 2) {
+        const __m256d va = _mm256_loadu_pd(pa + 2 * i), vb = _mm256_loadu_pd(pb + 2 * i);
+        const __m256d sa = _mm256_permute_pd(va, 0x5), sb = _mm256_permute_pd(vb, 0x5);
+        // conj(s) b = (sr b.re + si b.im, sr b.im - si b.re): fmsubadd subtracts in odd lanes
+        const __m256d cb = _mm256_fmsubadd_pd(sr, vb, _mm256_mul_pd(si, sb));
+        // s a = (sr a.re - si a.im, sr a.im + si a.re)
+        const __m256d sa2 = _mm256_fmaddsub_pd(sr, va, _mm256_mul_pd(si, sa));
+        _mm256_storeu_pd(pa + 2 * i, _mm256_fmadd_pd(vc, va, cb));
+        _mm256_storeu_pd(pb + 2 * i, _mm256_fmsub_pd(vc, vb, sa2));
+    }
+    for (; i < cnt; ++i) {
+        const cplx p = a[i], q = b[i];
+        a[i] = c * p + std::conj(s) * q;
+        b[i] = -s * p + c * q;
+    }
+}
+
 // Householder reduction to Hessenberg form (the reflectors kept for the eigenvectors), then the
 // shifted QR algorithm on the active window for the eigenvalues only; the window is stored with
 // an odd leading dimension so that the row rotations do not fall into a few cache sets.  The
@@ -447,9 +491,6 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
         H.swap(Hp);
     }
     int ihi = N - 1, its = 0, total = 0;
-    std::vector<double> rc(N);
-    std::vector<cplx> rs(N);
-    std::vector<int> upto(N);
     while (ihi >= 0) {
         int l = ihi;
         while (l > 0) {
@@ -478,64 +519,22 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
             const cplx m1 = tr2 + disc, m2 = tr2 - disc;
             mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
         }
-        // One implicit single-shift sweep over [l, ihi].  Left and right rotations commute,
-        // so the row rotations are applied lazily, column by column: a column receives its
-        // pending rotations as one pass down its contiguous rows just before it is read (as
-        // the source of the next rotation or as an operand of a column rotation), and the
-        // columns ahead are brought up to date four at a time, which overlaps four independent
-        // rotation chains.  upto[c]: rotations [l, upto[c]) are applied to column c.
-        for (int c = l; c <= ihi; ++c) upto[c] = l;
-        auto flush = [&](int c0, int c1, int kend) {   // columns c0..c1 (equal upto) to kend
-            cplx* col[4];
-            const int g = c1 - c0 + 1;
-            for (int q = 0; q < g; ++q) col[q] = &H[(size_t)(c0 + q) * LD];
-            for (int j = upto[c0]; j < kend; ++j) {
-                const double cs = rc[j];
-                const cplx sn = rs[j], csn = std::conj(rs[j]);
-                for (int q = 0; q < g; ++q) {
-                    const cplx p = col[q][j], qq = col[q][j + 1];
-                    col[q][j] = cs * p + sn * qq;
-                    col[q][j + 1] = -csn * p + cs * qq;
-                }
-            }
-            for (int q = 0; q < g; ++q) upto[c0 + q] = kend;
-        };
+        cplx x = H[l + (size_t)l * LD] - mu, y = H[l + 1 + (size_t)l * LD];
         for (int k = l; k < ihi; ++k) {
-            cplx x, y;
-            if (k == l) {
-                x = H[l + (size_t)l * LD] - mu;
-                y = H[l + 1 + (size_t)l * LD];
-            } else {
-                flush(k - 1, k - 1, k);
+            if (k > l) {
                 x = H[k + (size_t)(k - 1) * LD];
                 y = H[k + 1 + (size_t)(k - 1) * LD];
             }
             double cs;
             cplx sn, rho;
             givens(x, y, cs, sn, rho);
-            rc[k] = cs;
-            rs[k] = sn;
             if (k > l) {
                 H[k + (size_t)(k - 1) * LD] = rho;
                 H[k + 1 + (size_t)(k - 1) * LD] = 0.0;
-                upto[k - 1] = k + 1;
             }
-            flush(k, k, k + 1);
-            if (upto[k + 1] == l && k + 1 > l) {
-                const int c1 = std::min(k + 4, ihi);
-                flush(k + 1, c1, k + 1);
-            } else {
-                flush(k + 1, k + 1, k + 1);
-            }
-            const cplx csn = std::conj(sn);
+            rotate_rows(&H[k + (size_t)k * LD], LD, ihi - k + 1, cs, sn);   // rows k, k+1 in the window
             const int iend = std::min(k + 2, ihi);
-            cplx* ck = &H[(size_t)k * LD];
-            cplx* ck1 = &H[(size_t)(k + 1) * LD];
-            for (int i = l; i <= iend; ++i) {            // columns k, k+1 inside the window
-                const cplx p = ck[i], q = ck1[i];
-                ck[i] = cs * p + csn * q;
-                ck1[i] = -sn * p + cs * q;
-            }
+            rotate_cols(&H[l + (size_t)k * LD], &H[l + (size_t)(k + 1) * LD], iend - l + 1, cs, sn);
         }
     }
     evals.resize(N);
