@@ -324,7 +324,8 @@ __global__ __launch_bounds__(1024) void swaplist_kernel(int64_t n, int64_t k1, i
 // Row exchanges as (dst, src) lists, applied to the columns [c0a, c0a + na) and [c0b, c0b + nb)
 // (the left and right parts of a panel in one launch).  A 512-thread workgroup owns CW
 // consecutive columns of the union: every thread gathers its EPT entries of all CW columns,
-// the workgroup meets once, then every thread scatters them.
+// the workgroup meets once, then every thread scatters them.  Entries whose row keeps its
+// content (dst == src: the panel rows the pivoting left in place) are skipped.
 template <typename R, int EPT, int CW>
 __global__ __launch_bounds__(512) void laswp_apply_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
                                                           int64_t c0a, int64_t na, int64_t c0b,
@@ -339,6 +340,7 @@ __global__ __launch_bounds__(512) void laswp_apply_kernel(Cx<R>* A0, int64_t lda
         const int e = threadIdx.x + 512 * i;
         d[i] = e < L ? dst[e] : -1;
         sr[i] = e < L ? src[e] : 0;
+        if (d[i] == sr[i]) d[i] = -1;   // a row that stays put moves no data
     }
     const int64_t total = na + nb, q0 = (int64_t)blockIdx.x * CW;
     Cx<R> v[CW][EPT];
