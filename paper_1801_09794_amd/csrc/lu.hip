@@ -47,10 +47,9 @@ __device__ __forceinline__ void argmax_dpp(R& v, int& row) {
         ov = __int_as_float(dpp_move<CTRL>(__float_as_int(v)));
     }
     const int orow = dpp_move<CTRL>(row);
-    if (ov > v || (ov == v && orow < row)) {
-        v = ov;
-        row = orow;
-    }
+    const bool take = (ov > v) | ((ov == v) & (orow < row));   // bitwise: no branches
+    v = take ? ov : v;
+    row = take ? orow : row;
 }
 
 // Argmax within each row of 16 lanes: swap neighbours (quad_perm [1,0,3,2]), pairs
@@ -71,10 +70,39 @@ __device__ __forceinline__ void wave_argmax(R& v, int& row) {
     for (int off = 16; off < 64; off <<= 1) {
         R ov = __shfl_xor(v, off, 64);
         int orow = __shfl_xor(row, off, 64);
-        if (ov > v || (ov == v && orow < row)) {
-            v = ov;
-            row = orow;
-        }
+        const bool take = (ov > v) | ((ov == v) & (orow < row));
+        v = take ? ov : v;
+        row = take ? orow : row;
+    }
+}
+
+// 1 / p with one real division: p is scaled by a power of two (exact) so that |p|^2 neither
+// overflows nor underflows, and 1/p = conj(p) / |p|^2.
+template <typename R>
+__device__ __forceinline__ Cx<R> crecip(Cx<R> p) {
+    const int e = ilogb(fmax(fabs(p.re), fabs(p.im)));
+    const R a = scalbn(p.re, -e), b = scalbn(p.im, -e);
+    const R d = R(1) / (a * a + b * b);
+    return Cx<R>(scalbn(a * d, -e), scalbn(-b * d, -e));
+}
+
+// Buffer descriptor of `rows` consecutive complex values (raw addressing: a load at a byte
+// offset at or beyond the length returns zero; rows <= 0 gives an empty range).
+template <typename R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const Cx<R>* col, int rows) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<Cx<R>*>(col), (short)0,
+                                             max(rows, 0) * (int)sizeof(Cx<R>), 0x00020000);
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> buffer_load_cx(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    if constexpr (sizeof(R) == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        return Cx<R>(__longlong_as_double(((long long)v[1] << 32) | v[0]),
+                     __longlong_as_double(((long long)v[3] << 32) | v[2]));
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+        return Cx<R>(__uint_as_float(v[0]), __uint_as_float(v[1]));
     }
 }
 
@@ -142,17 +170,22 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
             for (int c = 0; c < SB; ++c)
                 x[i][c] = (ok && c < bw) ? A[r + (int64_t)(s0 + c) * lda] : Cx<R>(0, 0);
         }
-        for (int u = 0; u < s0; ++u) {
-            Cx<R> ucol[SB];
+        // All RPT rows of a column of L are loaded together (one round trip per column): row
+        // block i has its own buffer descriptor, so the rows share one lane offset and rows at
+        // or beyond mp read zero; rows above s0 compute values that are never used.
+        {
+            const uint32_t loff = (uint32_t)tid * (uint32_t)sizeof(Cx<R>);
+#pragma nounroll
+            for (int u = 0; u < s0; ++u) {
+                const Cx<R>* colu = A + (int64_t)u * lda;
+                Cx<R> l[RPT];
 #pragma unroll
-            for (int c = 0; c < SB; ++c) ucol[c] = (c < bw) ? Utop[u][c] : Cx<R>(0, 0);
+                for (int i = 0; i < RPT; ++i) l[i] = buffer_load_cx<R>(column_rsrc(colu + NT * i, mp - NT * i), loff);
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int r = tid + NT * i;
-                if (r >= s0 && r < mp) {
-                    const Cx<R> l = A[r + (int64_t)u * lda];
+                for (int c = 0; c < SB; ++c) {
+                    const Cx<R> uv = (c < bw) ? Utop[u][c] : Cx<R>(0, 0);
 #pragma unroll
-                    for (int c = 0; c < SB; ++c) cfms(x[i][c], l, ucol[c]);
+                    for (int i = 0; i < RPT; ++i) cfms(x[i][c], l[i], uv);
                 }
             }
         }
@@ -238,7 +271,7 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
                 for (int cc = 0; cc < SB; ++cc) prow[cc] = rowJbuf[par][cc];
             }
             if (pv > R(0)) {
-                const Cx<R> inv = cdiv(Cx<R>(1, 0), prow[c]);
+                const Cx<R> inv = crecip(prow[c]);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int r = tid + NT * i;
