@@ -89,10 +89,12 @@ typedef struct {
                                     factorisation; 1: regions one after another on the caller's
                                     stream */
     int32_t graph;               /* 1: capture assembly + batched factorisation of all nodes in
-                                    a hipGraph on first use and replay it on later solves with
-                                    the same shapes, coefficient pointers and workspace (per-launch
-                                    profiling of those kernels is then replaced by the one
-                                    NLF_K_FACTOR entry) */
+                                    hipGraphs on first use and replay them on later solves with
+                                    the same shapes, coefficient pointers and workspace.  With one
+                                    node group and no look-ahead the capture is cut at the
+                                    trailing updates, which run eagerly between the graph segments
+                                    and stay timed (NLF_K_LU_GEMM); the other kernels of the
+                                    factorisation are then profiled only through NLF_K_FACTOR */
     int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
                                     the trailing update of panel k runs; -1 = one stream;
                                     0 = library default (one stream) */

@@ -3,6 +3,8 @@
 
 #include "common.hpp"
 
+#include <functional>
+
 namespace nlf {
 
 struct GemmConfig {
@@ -27,6 +29,16 @@ int64_t getrf_tmp_elems(int64_t n);
 int& lu_panel_width();
 // Per-thread override of the LU trailing-update GEMM tile ({0, 0} = default choice).
 GemmConfig& lu_update_tile();
+// A trailing update of the blocked LU handed to a capture hook instead of being launched:
+// launch(stream) issues it (the arguments are bound), flops and bytes are its algorithmic work.
+struct LuUpdateLaunch {
+    std::function<void(hipStream_t)> launch;
+    double flops = 0, bytes = 0;
+};
+// Per-thread hook (null: launch directly).  While a factorisation is captured into a graph,
+// the hook receives each trailing update, so the capture can be split around them and the
+// updates launched eagerly (and timed) between the graph segments.
+std::function<void(LuUpdateLaunch&&)>*& lu_update_hook();
 // Look-ahead resources for the blocked LU: a second stream for the panel factorisations and
 // two events owned by the caller (all null: one stream).
 struct LuAux {

@@ -616,6 +616,11 @@ GemmConfig& lu_update_tile() {
     return c;
 }
 
+std::function<void(LuUpdateLaunch&&)>*& lu_update_hook() {
+    static thread_local std::function<void(LuUpdateLaunch&&)>* h = nullptr;
+    return h;
+}
+
 // The tile of the trailing-update GEMMs: the override when one is set, else the default choice.
 static const GemmConfig* update_tile() {
     const GemmConfig& c = lu_update_tile();
@@ -721,10 +726,26 @@ static void getrf_blocked(hipStream_t s, int64_t n, int batch, Cx<R>* A, int64_t
                             tmp + off, PB, st, batch);
                 gemm<R>(s, false, db, w, db, one, Li, NB, per, tmp + off, PB, st, zero, A12 + off, lda, sA, batch);
             }
-            ProfScope ps(NLF_PROF_LU_GEMM, s, 8.0 * rest * w * kb * batch,
-                         sizeof(Cx<R>) * (2.0 * rest * w + (double)rest * kb + (double)kb * w) * batch);
+            const double fl = 8.0 * rest * w * kb * batch;
+            const double by = sizeof(Cx<R>) * (2.0 * rest * w + (double)rest * kb + (double)kb * w) * batch;
+            const GemmConfig* tile = update_tile();
+            if (std::function<void(LuUpdateLaunch&&)>* hook = lu_update_hook()) {
+                const GemmConfig cfg = tile ? *tile : GemmConfig{0, 0};
+                const Cx<R>* L21 = A + k1 + k0 * lda;
+                Cx<R>* A22 = A + k1 + c0 * lda;
+                LuUpdateLaunch u;
+                u.launch = [=](hipStream_t st) {
+                    gemm<R>(st, false, rest, w, kb, mone, L21, lda, sA, A12, lda, sA, one, A22, lda, sA, batch,
+                            nullptr, 0, cfg.tm > 0 ? &cfg : nullptr, true);
+                };
+                u.flops = fl;
+                u.bytes = by;
+                (*hook)(std::move(u));
+                return;
+            }
+            ProfScope ps(NLF_PROF_LU_GEMM, s, fl, by);
             gemm<R>(s, false, rest, w, kb, mone, A + k1 + k0 * lda, lda, sA, A12, lda, sA, one,
-                    A + k1 + c0 * lda, lda, sA, batch, nullptr, 0, update_tile(), true);
+                    A + k1 + c0 * lda, lda, sA, batch, nullptr, 0, tile, true);
         };
         if (rest > 0) {
             if (!la) {

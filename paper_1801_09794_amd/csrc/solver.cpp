@@ -187,11 +187,15 @@ struct nlfeast_ctx {
     int info_cap = 0;
 
     hipStream_t gstream = nullptr;                         // capture stream of the factorisation graph
-    hipGraphExec_t graph_exec = nullptr;
+    // the captured factorisation: graph segments, and between consecutive segments one
+    // trailing update launched eagerly (so that its launches stay timed by events)
+    std::vector<hipGraphExec_t> graph_segs;
+    std::vector<LuUpdateLaunch> graph_mids;
     GraphKey graph_key;
     void drop_graph() {
-        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-        graph_exec = nullptr;
+        for (hipGraphExec_t g : graph_segs) (void)hipGraphExecDestroy(g);
+        graph_segs.clear();
+        graph_mids.clear();
     }
     ~nlfeast_ctx() {
         drop_graph();
@@ -554,28 +558,73 @@ GraphKey graph_key(const nlfeast_ctx* h, const Layout& L, const void* ws, int pr
     return k;
 }
 
-// Record factor_all on the handle's capture stream into h->graph_exec (nothing executes).
+// Record factor_all on the handle's capture stream (nothing executes).  With one node group and
+// no look-ahead the capture is cut at every trailing update: h->graph_segs holds the graph
+// segments and h->graph_mids the updates that run eagerly between them; otherwise the whole
+// factorisation is one segment.
 void capture_factorisation(nlfeast_ctx* h, const Layout& L, void* ws, bool p32, const LuTuning& t) {
     if (!h->gstream) NLF_HIP(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    h->drop_graph();
     Profiler* saved = active_profiler();
     active_profiler() = nullptr;   // no event records inside the capture
-    hipGraph_t graph = nullptr;
-    NLF_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    std::function<void(LuUpdateLaunch&&)>* saved_hook = lu_update_hook();
+    std::vector<hipGraph_t> graphs;
+    std::function<void(LuUpdateLaunch&&)> cut = [&](LuUpdateLaunch&& u) {
+        hipGraph_t g = nullptr;
+        NLF_HIP(hipStreamEndCapture(h->gstream, &g));
+        graphs.push_back(g);
+        h->graph_mids.push_back(std::move(u));
+        NLF_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+    };
+    const bool segmented = !t.lookahead && t.groups <= 1;
+    auto restore = [&] {
+        active_profiler() = saved;
+        lu_update_hook() = saved_hook;
+    };
+    auto discard = [&] {
+        for (hipGraph_t g : graphs) (void)hipGraphDestroy(g);
+        graphs.clear();
+        h->graph_mids.clear();
+    };
     try {
+        NLF_HIP(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        if (segmented) lu_update_hook() = &cut;
         factor_all(h, L, ws, p32, h->gstream, t);
     } catch (...) {
-        (void)hipStreamEndCapture(h->gstream, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        active_profiler() = saved;
+        restore();
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(h->gstream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        discard();
         throw;
     }
-    active_profiler() = saved;
-    NLF_HIP(hipStreamEndCapture(h->gstream, &graph));
-    const hipError_t e = hipGraphInstantiateWithFlags(&h->graph_exec, graph, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-        h->graph_exec = nullptr;
-        throw Error{NLF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    restore();
+    hipGraph_t last = nullptr;
+    NLF_HIP(hipStreamEndCapture(h->gstream, &last));
+    graphs.push_back(last);
+    for (hipGraph_t g : graphs) {
+        hipGraphExec_t e = nullptr;
+        const hipError_t st = hipGraphInstantiateWithFlags(&e, g, 0);
+        if (st != hipSuccess) {
+            discard();
+            h->drop_graph();
+            throw Error{NLF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(st)};
+        }
+        h->graph_segs.push_back(e);
+    }
+    for (hipGraph_t g : graphs) (void)hipGraphDestroy(g);   // the instantiated segments keep what they need
+}
+
+// Replay the captured factorisation on s: the segments in order, each followed by its eager
+// trailing update (timed as NLF_K_LU_GEMM when profiling).
+void replay_factorisation(nlfeast_ctx* h, hipStream_t s) {
+    for (size_t i = 0; i < h->graph_segs.size(); ++i) {
+        NLF_HIP(hipGraphLaunch(h->graph_segs[i], s));
+        if (i < h->graph_mids.size()) {
+            const LuUpdateLaunch& u = h->graph_mids[i];
+            ProfScope ps(NLF_PROF_LU_GEMM, s, u.flops, u.bytes);
+            u.launch(s);
+        }
     }
 }
 
@@ -992,13 +1041,12 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             if (opt->autotune) tune = autotuned(h, L, ws, p32, s, *opt);
             if (opt->graph) {
                 GraphKey key = graph_key(h, L, ws, opt->precision, tune);
-                if (!h->graph_exec || !(h->graph_key == key)) {
-                    h->drop_graph();
+                if (h->graph_segs.empty() || !(h->graph_key == key)) {
                     capture_factorisation(h, L, ws, p32, tune);
                     h->graph_key = key;
                 }
                 ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
-                NLF_HIP(hipGraphLaunch(h->graph_exec, s));
+                replay_factorisation(h, s);
             } else {
                 ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
                 factor_all(h, L, ws, p32, s, tune);

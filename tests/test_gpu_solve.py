@@ -329,6 +329,35 @@ def test_graph_replays_equal_eager(prec, es):
     S.close()
 
 
+@pytest.mark.parametrize("prec,es", [(nl.NLF_PREC_FP64, 16), (nl.NLF_PREC_FP32_REFINE, 8)])
+def test_segmented_graph_replays_equal_eager(prec, es):
+    # n = 1300: three 512-column panels (the last ragged), so the capture is cut at two
+    # trailing updates that run eagerly between the graph segments; every replay leaves the
+    # eager factors bit for bit, and the updates stay timed
+    n = 1300
+    terms, mats = wl.random_qep(n, 91)
+    regs = [dict(centre=0.1 + 0.2j, a=0.08, nc=6, m0=12)]
+    X0 = nl.to_colmajor(wl.initial_block(n, 12, 92))
+    S = nl.NLFEAST(n)
+    S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    S.set_contour(regs)
+    ref = S.solve(nl.options(tol=1e-10, precision=prec, max_iter=3), X0)
+    torch.cuda.synchronize()
+    F0 = _factor_bytes(S, n, 6, es)
+    for rep in range(3):
+        S.set_contour(regs)
+        nl.nlfeast_set_profiling(S.h, rep == 2)
+        out = S.solve(nl.options(tol=1e-10, precision=prec, max_iter=3, graph=1), X0)
+        torch.cuda.synchronize()
+        assert torch.equal(_factor_bytes(S, n, 6, es), F0), rep
+        assert out["status"] == ref["status"]
+        assert np.max(np.abs(out["lam"] - ref["lam"])) < 1e-13
+        _ = torch.ones(1000, device="cuda").sum().item()    # eager work between replays
+    prof = S.profile()
+    assert prof["lu_gemm"]["launches"] == 2 and prof["lu_gemm"]["ms"] > 0
+    S.close()
+
+
 def test_autotuned_graph_solve_matches_brute_force():
     terms, mats = wl.make_problem("qep200")
     g = contours("qep200")[0]
