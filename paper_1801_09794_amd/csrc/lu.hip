@@ -418,14 +418,28 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(int nb, int64_t N, const
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t cbase = ((int64_t)blockIdx.x * 4 + wave) * CB;
     Cx<R>* xt = xts[wave];
-    for (int e = threadIdx.x; e < nb * nb; e += 256) {
-        const int i = e % nb, t = e / nb;
-        Tt[t][i] = T[i + (int64_t)t * ldt];
+    // all loads are issued before any is used (clamped in-range addresses, out-of-block
+    // elements replaced by zero afterwards), so the triangle and the right-hand sides arrive
+    // in one round trip instead of one per loop iteration
+    constexpr int PER = TRSM_NB * TRSM_NB / 256;
+    Cx<R> tv[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e % TRSM_NB, t = e / TRSM_NB;
+        tv[q] = T[min(i, nb - 1) + (int64_t)min(t, nb - 1) * ldt];
     }
     Cx<R> x[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
-        x[c] = (lane < nb && cbase + c < N) ? B[lane + (cbase + c) * ldb] : Cx<R>(0, 0);
+        x[c] = B[min(lane, nb - 1) + min(cbase + c, N - 1) * ldb];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e % TRSM_NB, t = e / TRSM_NB;
+        Tt[t][i] = (i < nb && t < nb) ? tv[q] : Cx<R>(0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        if (!(lane < nb && cbase + c < N)) x[c] = Cx<R>(0, 0);
     __syncthreads();
     if (!UPPER) {
         for (int t = 0; t + 1 < nb; ++t) {
@@ -444,9 +458,11 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(int nb, int64_t N, const
             __builtin_amdgcn_wave_barrier();
         }
     } else {
+        // every lane inverts its own diagonal entry up front, off the substitution's critical path
+        const Cx<R> dinv = lane < nb ? cdiv(Cx<R>(1, 0), Tt[lane][lane]) : Cx<R>(0, 0);
         for (int t = nb - 1; t >= 0; --t) {
             if (lane == t) {
-                const Cx<R> inv = cdiv(Cx<R>(1, 0), Tt[t][t]);
+                const Cx<R> inv = dinv;
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
                     x[c] = x[c] * inv;
