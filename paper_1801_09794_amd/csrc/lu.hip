@@ -106,11 +106,10 @@ __device__ __forceinline__ Cx<R> buffer_load_cx(__amdgpu_buffer_rsrc_t rs, uint3
     }
 }
 
-template <typename R, int RPT, int SB>
-__global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
+template <typename R, int RPT, int SB, int NT>
+__global__ __launch_bounds__(NT) void panel_kernel(Cx<R>* A0, int64_t lda, int64_t sA,
                                                         int64_t n, int64_t k0, int w,
                                                         int32_t* ipiv, int32_t* info) {
-    constexpr int NT = PANEL_NT;
     const int64_t bidx = blockIdx.x;
     Cx<R>* A = A0 + bidx * sA + k0 + k0 * lda;      // panel origin
     int32_t* piv = ipiv + bidx * n;
@@ -222,9 +221,9 @@ __global__ __launch_bounds__(PANEL_NT) void panel_kernel(Cx<R>* A0, int64_t lda,
                         for (int cc = 0; cc < SB; ++cc) rowJbuf[par][cc] = x[i][cc];
             }
             __syncthreads();
-            // every wave reduces the NW = 16 candidates itself in its first row of lanes (lane q
+            // every wave reduces the NW <= 16 candidates itself in its first row of lanes (lane q
             // holds candidate q; the candidate index travels in the low bits of the row key)
-            static_assert(NW == 16, "one DPP row per candidate set");
+            static_assert(NW <= 16, "one DPP row per candidate set");
             R pv = lane < NW ? candv[par][lane] : R(-1);
             const int cand_row = lane < NW ? candr[par][lane] : INT_MAX;
             int key = cand_row == INT_MAX ? INT_MAX : (cand_row << 4) | (lane & 15);
@@ -577,21 +576,21 @@ static void launch_panel(hipStream_t s, int batch, Cx<R>* A, int64_t lda, int64_
     const int64_t mp = n - k0;
     const double fl = 8.0 * batch * ((double)mp * w * w - (double)w * w * w / 3.0) / 2.0;
     ProfScope ps(NLF_PROF_PANEL, s, fl, 0);
-#define NLF_PANEL(RPT_, SB_) \
-    hipLaunchKernelGGL((panel_kernel<R, RPT_, SB_>), dim3(batch), dim3(PANEL_NT), 0, s, A, lda, sA, n, k0, w, ipiv, info)
-    // sub-block width SB: RPT x SB complex values per thread stay within the 128-VGPR budget
-    // of a 1024-thread workgroup
+#define NLF_PANEL(RPT_, SB_, NT_) \
+    hipLaunchKernelGGL((panel_kernel<R, RPT_, SB_, NT_>), dim3(batch), dim3(NT_), 0, s, A, lda, sA, n, k0, w, ipiv, info)
+    // RPT rows per thread (RPT x NT >= mp) and sub-block width SB: RPT x SB complex values per
+    // thread stay within the VGPR budget (128 per thread at 1024 threads, 256 at 512)
     if constexpr (sizeof(R) == 8) {
-        if (mp <= 1024) NLF_PANEL(1, 8);
-        else if (mp <= 2048) NLF_PANEL(2, 8);
-        else if (mp <= 4096) NLF_PANEL(4, 4);
-        else if (mp <= 8192) NLF_PANEL(8, 2);
+        if (mp <= 1024) NLF_PANEL(1, 8, 1024);
+        else if (mp <= 2048) NLF_PANEL(2, 8, 1024);
+        else if (mp <= 4096) NLF_PANEL(4, 4, 1024);
+        else if (mp <= 8192) NLF_PANEL(8, 2, 1024);
         else throw Error{1, "getrf: matrix order above 8192 is not supported"};
     } else {
-        if (mp <= 1024) NLF_PANEL(1, 16);
-        else if (mp <= 2048) NLF_PANEL(2, 8);
-        else if (mp <= 4096) NLF_PANEL(4, 8);
-        else if (mp <= 8192) NLF_PANEL(8, 4);
+        if (mp <= 1024) NLF_PANEL(1, 16, 1024);
+        else if (mp <= 2048) NLF_PANEL(2, 8, 1024);
+        else if (mp <= 4096) NLF_PANEL(4, 8, 1024);
+        else if (mp <= 8192) NLF_PANEL(8, 4, 1024);
         else throw Error{1, "getrf: matrix order above 8192 is not supported"};
     }
 #undef NLF_PANEL
