@@ -37,6 +37,8 @@ def parse():
                     help="skip the eight-region batched workload (qep2048x8)")
     ap.add_argument("--no-delay", action="store_true",
                     help="skip the delay workload (delay8192)")
+    ap.add_argument("--no-nc-sweep", action="store_true",
+                    help="skip the sweep over the number of quadrature nodes (quartic1024)")
     ap.add_argument("--no-delay-fp64", action="store_true",
                     help="run the delay workload in FP32 + refinement only")
     ap.add_argument("--fp64-legs", action="store_true",
@@ -224,6 +226,28 @@ def extra_leg(args, name, description, autotune, graph, with_fp64=False):
     return out
 
 
+def nc_sweep(args):
+    """Sec. 5's observation that more quadrature nodes cost fewer iterations: the quartic1024
+    workload (degree 4, n = 1024, one circle holding 15 eigenvalues, m0 = 24) in FP64 with
+    n_c = 4, 8, 16, 32 Gauss-Legendre nodes; per n_c the Step 4 executions, the converged
+    pairs and the wall time per solve and per iteration."""
+    import paper_1801_09794_amd as nl
+    cfg, terms, mats, regions, X0 = load_workload("quartic1024")
+    inside = len(json.load(open(os.path.join(ROOT, "tests", "golden", "contours.json")))["quartic1024"]
+                 ["regions"][0]["eigenvalues"])
+    out = {"workload": "quartic1024: T(l) = l^4 I + sum_{j<4} l^j A_j, A_j complex Gaussian/sqrt(n), "
+                       "n=%d, circle enclosing %d eigenvalues, m0=%d, FP64, tol %.0e"
+                       % (cfg["n"], inside, regions[0]["m0"], cfg["tol"]), "points": []}
+    for nc in (4, 8, 16, 32):
+        regs = [dict(r, nc=nc) for r in regions]
+        t, o, p = run_gpu(args, cfg, terms, mats, regs, X0, nl.NLF_PREC_FP64, True)
+        it = int(o["iters"][0])
+        out["points"].append({"nc": nc, "iterations": it, "converged": converged_pairs(o, cfg["tol"]),
+                              "ms_per_solve": t * 1e3, "factor_ms": p["factor"]["ms"] / args.steps,
+                              "ms_per_iteration": (t * 1e3 - p["factor"]["ms"] / args.steps) / max(it, 1)})
+    return out
+
+
 def hbm_kernels(prof):
     """Achieved bandwidth of the HBM-bound steps (assembly of T(z_k), Step 4 accumulation):
     algorithmic bytes of their launches over their summed event-timed duration."""
@@ -400,6 +424,8 @@ def main():
             "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%(n)d dense complex128, circle "
             "enclosing %(inside)d eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, tol %(tol).0e",
             autotune=0, graph=0, with_fp64=not args.no_delay_fp64)
+    if not args.no_nc_sweep and args.workload != "quartic1024":
+        result["nc_sweep"] = nc_sweep(args)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

@@ -21,6 +21,11 @@ Recipes (contour seed 3000 + id):
               p_r is the count in that range with the largest relative gap to the next
               eigenvalue, the radius the gap midpoint; rejected under a 2% gap or when two
               circles come closer than 10% of the larger radius.
+  quartic1024 all 4n eigenvalues of the degree-4 companion matrix (dense; shift-invert
+              Arnoldi is not accurate enough on this operator); centre = the eigenvalue nearest
+              a point uniform in |c| < 0.8; the count between 12 and 16 with the largest relative
+              gap, radius at the gap midpoint, rejected under a 2% gap; the count + 2 nearest
+              sharpened by two steps of two-sided Rayleigh functional iteration on T.
   delay512, delay8192
               centre c = i y0, y0 ~ U(0.3, 1.5); the eigenvalues nearest c from shift-invert
               Arnoldi on the companion form of the Taylor surrogate of T(c + mu) (tail below
@@ -116,6 +121,31 @@ def qep2048x8():
     return dict(regions=regions)
 
 
+def quartic1024():
+    cfg = wl.CONFIGS["quartic1024"]
+    terms, mats = wl.make_problem("quartic1024")
+    P = pb.Problem(terms, mats)
+    full = brute.companion_eigs(P)          # all 4n eigenvalues (dense companion, A_4 = I)
+    rng = np.random.default_rng(3000 + cfg["id"])
+    p0 = cfg["inside"]
+    plo, phi = p0 - 2, p0 + 2
+    while True:
+        z = 0.8 * np.sqrt(rng.uniform()) * np.exp(2j * np.pi * rng.uniform())
+        c = full[np.argmin(np.abs(full - z))]
+        best = max(range(plo, phi + 1), key=lambda k: ring(full, c, k)[2])
+        _, r, gap = ring(full, c, best)
+        if gap >= 0.02:
+            break
+    lam = full[np.argsort(np.abs(full - c))][:best + 2]
+    res = np.zeros(len(lam))
+    for i in range(len(lam)):
+        lam[i], res[i] = brute.refine_eigenvalue(P, lam[i], steps=2, seed=i)
+    _, r, gap = ring(lam, c, best)
+    inside = lam[np.abs(lam - c) < r]
+    return dict(regions=[dict(centre=[c.real, c.imag], radius=r, gap=gap, max_residual=float(res.max()),
+                              eigenvalues=[[v.real, v.imag] for v in inside])])
+
+
 def delay(name, rho):
     cfg = wl.CONFIGS[name]
     terms, mats = wl.make_problem(name)
@@ -154,7 +184,7 @@ def delay(name, rho):
     return dict(regions=[out])
 
 
-RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8,
+RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8, "quartic1024": quartic1024,
            "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.15)}
 
 

@@ -188,6 +188,27 @@ def test_cubic_pep_matches_companion(prec, tol_eig):
     assert np.max(hr) <= 2e-11
 
 
+@pytest.mark.parametrize("prec", [nl.NLF_PREC_FP64, nl.NLF_PREC_FP32_REFINE])
+def test_quartic1024_matches_brute_force(prec):
+    # degree 4, n = 1024: the circle of the stored contour holds 15 eigenvalues of the
+    # 4096 x 4096 companion matrix (dense eigenvalues sharpened on T); 16 nodes, m0 = 24.  The
+    # eigenvalues of this problem are ill-conditioned enough that residuals of 1e-10 leave
+    # eigenvalue errors near 1e-10 (the oracle: 7e-11), hence the 1e-9 bound for both forms
+    cfg = wl.CONFIGS["quartic1024"]
+    terms, mats = wl.make_problem("quartic1024")
+    g = contours("quartic1024")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
+                    wl.initial_block(cfg["n"], cfg["m0"], 2007), nl.options(tol=cfg["tol"], precision=prec))
+    assert out["status"] == nl.NLF_OK
+    ins = converged(out, cfg["tol"])
+    assert ins.sum() == len(brute) == 15 and out["m"][0] == 15
+    assert match_err(out["lam"][ins], brute, r) < 1e-9
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+
+
 @pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
 def test_damped4096_matches_brute_force(prec, tol_eig):
     cfg = wl.CONFIGS["damped4096"]

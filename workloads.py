@@ -102,6 +102,14 @@ def delay_problem(n, seed, tau=1.0):
     return terms, [np.eye(n, dtype=complex), C, K, E]
 
 
+def random_pep(n, seed, degree=4):
+    """lambda^d I + sum_{j<d} lambda^j A_j, A_j = CN(0,1)/sqrt(n) (a degree-d polynomial problem
+    with the same coefficient statistics as random_qep)."""
+    rng = np.random.default_rng(seed)
+    mats = [np.eye(n, dtype=complex)] + [cn(rng, (n, n)) / np.sqrt(n) for _ in range(degree)]
+    return [("pow", degree - q) for q in range(degree + 1)], mats
+
+
 def initial_block(n, m0, seed):
     return cn(np.random.default_rng(seed), (n, m0))
 
@@ -117,10 +125,13 @@ CONFIGS = {
     "delay8192": dict(id=5, kind="delay_problem", n=8192, m0=160, nc=24, tol=1e-10, inside=100),
     # the delay problem at a size the oracle iterates in seconds (parity case)
     "delay512": dict(id=6, kind="delay_problem", n=512, m0=24, nc=16, tol=1e-11, inside=12),
+    # a quartic problem for the sweep over the number of quadrature nodes
+    "quartic1024": dict(id=7, kind="random_pep", n=1024, m0=24, nc=16, tol=1e-10, inside=14),
 }
 
 
 def make_problem(name):
     cfg = CONFIGS[name]
-    gen = {"random_qep": random_qep, "damped_qep": damped_qep, "delay_problem": delay_problem}[cfg["kind"]]
+    gen = {"random_qep": random_qep, "damped_qep": damped_qep, "delay_problem": delay_problem,
+           "random_pep": random_pep}[cfg["kind"]]
     return gen(cfg["n"], 1000 + cfg["id"])
