@@ -37,7 +37,7 @@ import time
 import numpy as np
 import scipy.linalg
 
-from .reduced import solve_reduced, select, newton_polish
+from .reduced import solve_reduced, select, newton_polish, contour_reduced
 
 
 class M0TooSmall(RuntimeError):
@@ -86,10 +86,14 @@ def step4(factors, X, R, lam, z, omega):
 
 
 def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
-          verbose=False):
+          verbose=False, reduced="auto"):
     """Run Algorithm 1.  problem: oracle.problem.Problem; contour: quadrature.Contour;
     (z, omega): quadrature; X0: n x m0 initial guess.  Returns a Result whose arrays
-    are sorted by Step 2's selection order."""
+    are sorted by Step 2's selection order.  reduced: 'auto' (linearisation, with the
+    Taylor reading for 'exp' terms and the contour-integral reading when a term is a
+    caller-supplied function) or 'contour' (the contour-integral reading for every
+    non-polynomial problem)."""
+    use_contour = problem.has_user_terms or (reduced == "contour" and not problem.is_polynomial)
     n = problem.n
     X0 = np.asarray(X0, dtype=complex)
     if X0.shape != (n, m0):
@@ -102,14 +106,17 @@ def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
     it = 0
     while True:
         Ahat = problem.project(Q)                            # Step 1
-        lam_all, Y_all = solve_reduced(problem.terms, Ahat, contour)
-        sel = select(lam_all, contour, m0)                   # Step 2
-        lam = lam_all[sel].astype(complex)
-        Y = Y_all[:, sel]
-        if not problem.is_polynomial:
-            for i in range(m0):
-                if np.isfinite(lam[i]):
-                    lam[i], Y[:, i] = newton_polish(problem.terms, Ahat, lam[i], Y[:, i])
+        if use_contour:                                      # Steps 1-2, contour reading
+            lam, Y, _ = contour_reduced(problem.terms, Ahat, contour, m0)
+        else:
+            lam_all, Y_all = solve_reduced(problem.terms, Ahat, contour)
+            sel = select(lam_all, contour, m0)               # Step 2
+            lam = lam_all[sel].astype(complex)
+            Y = Y_all[:, sel]
+            if not problem.is_polynomial:
+                for i in range(m0):
+                    if np.isfinite(lam[i]):
+                        lam[i], Y[:, i] = newton_polish(problem.terms, Ahat, lam[i], Y[:, i])
         X = Q @ Y
         X = X / np.linalg.norm(X, axis=0)[None, :]
         finite = np.isfinite(lam)

@@ -7,6 +7,9 @@ T(lambda) = sum_j f_j(lambda) A_j with scalar functions
 
     ('pow', p)    f(lambda) = lambda**p
     ('exp', tau)  f(lambda) = exp(-tau * lambda)
+    ('fn', F)     f(lambda) = F.f(lambda), f'(lambda) = F.df(lambda): a scalar function
+                  supplied by the caller (a ScalarFunction), analytic in the region of
+                  interest; the general T(lambda) of Sec. 6
 
 and the block residual is T(X, Lambda) = sum_j A_j X f_j(Lambda) with
 f_j(Lambda) = diag(f_j(lambda_i)), the paper's sum_i A_i X Lambda^i (Sec. 4.2) for
@@ -15,12 +18,25 @@ polynomial terms.
 import numpy as np
 
 
+class ScalarFunction:
+    """A caller-supplied scalar function for a ('fn', F) term: f and its derivative df,
+    each mapping a complex numpy array to a complex numpy array of the same shape."""
+
+    def __init__(self, f, df, name="user"):
+        self.f, self.df, self.name = f, df, name
+
+    def __repr__(self):
+        return "ScalarFunction(%s)" % self.name
+
+
 def f_eval(kind, param, lam):
     lam = np.asarray(lam, dtype=complex)
     if kind == "pow":
         return lam ** int(param)
     if kind == "exp":
         return np.exp(-float(param) * lam)
+    if kind == "fn":
+        return np.asarray(param.f(lam), dtype=complex)
     raise ValueError("unknown term kind %r" % kind)
 
 
@@ -31,6 +47,8 @@ def f_deriv(kind, param, lam):
         return p * lam ** (p - 1) if p > 0 else np.zeros_like(lam)
     if kind == "exp":
         return -float(param) * np.exp(-float(param) * lam)
+    if kind == "fn":
+        return np.asarray(param.df(lam), dtype=complex)
     raise ValueError("unknown term kind %r" % kind)
 
 
@@ -65,13 +83,17 @@ class Problem:
     def __init__(self, terms, mats):
         if len(terms) != len(mats) or not terms:
             raise ValueError("need one matrix per term")
-        self.terms = [(str(k), float(p)) for k, p in terms]
+        self.terms = [(str(k), p if k == "fn" else float(p)) for k, p in terms]
         self.mats = [np.asarray(A, dtype=complex) for A in mats]
         n = self.mats[0].shape[0]
         for A in self.mats:
             if A.shape != (n, n):
                 raise ValueError("all A_j must be n x n")
         self.n = n
+
+    @property
+    def has_user_terms(self):
+        return any(k == "fn" for k, _ in self.terms)
 
     @property
     def is_polynomial(self):

@@ -15,6 +15,21 @@ degree d whose Lagrange remainder on the disk |lambda - c| <= 1.5 max(a, b) is b
 1e-16 relative, linearise that polynomial, select, then take up to 3 Newton steps per
 selected pair on the exact reduced function.
 
+Second reading for non-polynomial T, required when a term is a caller-supplied function
+(no Taylor coefficients to linearise): the projected problem is solved by a contour-integral
+method of the kind Sec. 3 reviews, applied to the small m0 x m0 function.  The moments
+(1/2 pi i) oint mu^p T_red(z)^{-1} dz (Sec. 3 eq. cauchymoments, with the normalised variable
+mu = (z - c)/L, L = 1.5 max(a, b)) are taken on the ellipse of the same shape scaled by 1.5
+(the same enlargement as the Taylor disk above), by the trapezoid rule in the ellipse
+parameter; the block Hankel matrices of moments 0..2K-1 (K = 2, or 3 when the first has full
+rank) reduce the eigenvalues inside that ellipse to a linear eigenproblem (W.-J. Beyn, "An
+integral method for solving nonlinear eigenvalue problems", Linear Algebra Appl. 436 (2012),
+with the block Hankel form of the Sakurai-Sugiura methods); each pair found then takes
+Newton steps on the exact reduced function.  When fewer than m0 pairs are found, the
+selection is completed with unit vectors orthogonal to those found, paired with values spread
+over the enlarged ellipse: outside C, so never counted, and each one still filtered into the
+wanted subspace by Step 4.
+
 Step 2 keeps the m0 pairs "closest to the interior of C" (Sec. 4.2): the reduced
 eigenvalues sorted by normalised contour radius, ascending, ties by index, infinite
 ones last.
@@ -146,3 +161,82 @@ def select(lam, contour, m0):
     r = contour.radius(lam)
     order = np.argsort(r, kind="stable")
     return order[:m0]
+
+
+CONTOUR_SCALE = 1.5      # enlargement of C for the reduced contour-integral solve
+CONTOUR_POINTS = 96      # trapezoid points on the enlarged ellipse
+CONTOUR_RANK_TOL = 1e-10  # singular values below this fraction of the largest are noise
+
+
+def contour_eigs(terms, Ahat, contour, scale=CONTOUR_SCALE, npts=CONTOUR_POINTS,
+                 rank_tol=CONTOUR_RANK_TOL):
+    """Eigenpairs of sum_j f_j(lambda) Ahat_j y = 0 inside the ellipse C scaled by `scale`,
+    by the moments of the resolvent (Sec. 3 eq. cauchymoments; Beyn's method with block
+    Hankel moments).  By Keldysh's theorem T^{-1}(z) = sum_i v_i w_i^H / (z - lambda_i) + an
+    analytic part inside the ellipse, so M_p = (1/2 pi i) oint mu(z)^p T^{-1}(z) dz equals
+    V mu(Lambda)^p W^H; the Hankel matrices H0 = [M_{i+j}], H1 = [M_{i+j+1}] then factor as
+    Vb W^H and Vb mu(Lambda) W^H with Vb = [V; V mu; ...], and the SVD H0 = U S Z^H gives
+    U^H H1 Z S^{-1} = (U^H Vb) mu(Lambda) (U^H Vb)^{-1}.  Returns (lam, Y), Y with unit columns
+    (the first block of U s_i)."""
+    m = Ahat[0].shape[0]
+    c = complex(contour.c)
+    a, b = contour.a * scale, contour.b * scale
+    L = max(a, b)
+    K_max = 3
+    M = [np.zeros((m, m), dtype=complex) for _ in range(2 * K_max)]
+    for q in range(npts):
+        th = 2.0 * np.pi * (q + 0.5) / npts
+        z = c + a * np.cos(th) + 1j * b * np.sin(th)
+        dz = -a * np.sin(th) + 1j * b * np.cos(th)
+        w = dz / (1j * npts)                 # (1/2 pi i) dz/dtheta (2 pi / npts)
+        mu = (z - c) / L
+        Tinv = np.linalg.solve(reduced_T(terms, Ahat, z), np.eye(m))
+        for p in range(2 * K_max):
+            M[p] += (w * mu ** p) * Tinv
+    for K in (2, 3):
+        H0 = np.block([[M[i + j] for j in range(K)] for i in range(K)])
+        H1 = np.block([[M[i + j + 1] for j in range(K)] for i in range(K)])
+        U, sv, Zh = np.linalg.svd(H0)
+        k = int(np.sum(sv > rank_tol * sv[0])) if sv[0] > 0 else 0
+        if k < K * m:
+            break
+    else:
+        raise RuntimeError("contour_eigs: the enlarged contour holds too many eigenvalues")
+    if k == 0:
+        return np.zeros(0, dtype=complex), np.zeros((m, 0), dtype=complex)
+    Uk = U[:, :k]
+    B = Uk.conj().T @ H1 @ Zh[:k].conj().T / sv[:k][None, :]
+    mu_e, S = np.linalg.eig(B)
+    lam = c + L * mu_e
+    Y = (Uk @ S)[:m]
+    Y = Y / np.linalg.norm(Y, axis=0)[None, :]
+    return lam, Y
+
+
+def contour_reduced(terms, Ahat, contour, m0, scale=CONTOUR_SCALE):
+    """Steps 1-2 with the contour-integral reading: the pairs found inside the enlarged
+    ellipse, Newton-polished on the exact reduced function and sorted by normalised radius
+    (the m0 closest to the interior), completed to m0 when fewer were found.  Returns
+    (lam, Y, found) with found[i] False for the completing pairs."""
+    m = Ahat[0].shape[0]
+    lam, Y = contour_eigs(terms, Ahat, contour, scale=scale)
+    keep = contour.radius(lam) < scale
+    lam, Y = lam[keep], Y[:, keep]
+    for i in range(len(lam)):
+        lam[i], y = newton_polish(terms, Ahat, lam[i], Y[:, i])
+        Y[:, i] = y / np.linalg.norm(y)
+    order = np.argsort(contour.radius(lam), kind="stable")[:m0]
+    lam, Y = lam[order], Y[:, order]
+    k = len(lam)
+    found = np.ones(m0, dtype=bool)
+    if k < m0:
+        # unit vectors orthogonal to the pairs found: the trailing columns of a Householder QR
+        # of [Y, I]
+        Qc, _ = np.linalg.qr(np.concatenate([Y, np.eye(m, dtype=complex)], axis=1))
+        pad = m0 - k
+        th = 2.0 * np.pi * (np.arange(pad) + 0.5) / pad
+        lam_pad = contour.c + scale * (contour.a * np.cos(th) + 1j * contour.b * np.sin(th))
+        lam = np.concatenate([lam, lam_pad])
+        Y = np.concatenate([Y, Qc[:, k:m0]], axis=1)
+        found[k:] = False
+    return lam, Y, found

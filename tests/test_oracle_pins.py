@@ -368,3 +368,103 @@ def test_spurious_ritz_value_region_matches_brute_force():
     cost = np.abs(ev[:, None] - ref[None, :]) / np.maximum(np.abs(ref)[None, :], g["radius"])
     a, b = linear_sum_assignment(cost)
     assert cost[a, b].max() < 1e-11
+
+
+# ---- the contour-integral reading of the reduced problem (caller-supplied functions)
+
+def _random_reduced_quadratic(m, seed):
+    rng = np.random.default_rng(seed)
+    return [np.eye(m, dtype=complex), wl.cn(rng, (m, m)) / np.sqrt(m), wl.cn(rng, (m, m)) / np.sqrt(m)]
+
+
+@pytest.mark.parametrize("shape", [(0.2 + 0.1j, 0.6, 0.6), (-0.1 + 0.0j, 0.9, 0.35)])
+def test_contour_eigs_match_companion_on_a_polynomial(shape):
+    """For a polynomial reduced problem the pairs inside the enlarged ellipse are exactly the
+    companion eigenvalues there (away from its boundary, where the trapezoid rule loses
+    accuracy), and each vector is a null vector of T(lambda)."""
+    c, a, b = shape
+    C = qd.Contour(c, a, b)
+    Ahat = _random_reduced_quadratic(12, 41)
+    terms = [("pow", 2), ("pow", 1), ("pow", 0)]
+    lam, Y = reduced.contour_eigs(terms, Ahat, C)
+    comp = brute.companion_eigs(pb.Problem(terms, Ahat))
+    rho_c = C.radius(comp)
+    want = comp[rho_c < reduced.CONTOUR_SCALE - 0.08]
+    assert len(want) >= 4
+    got = lam[C.radius(lam) < reduced.CONTOUR_SCALE - 0.08]
+    assert len(got) == len(want)
+    assert match_error(got, want, max(a, b)) < 1e-9
+    for i in np.flatnonzero(C.radius(lam) < reduced.CONTOUR_SCALE - 0.08):
+        T = reduced.reduced_T(terms, Ahat, lam[i])
+        assert np.linalg.norm(T @ Y[:, i]) < 1e-8 * np.linalg.norm(T)
+
+
+def test_contour_reduced_completes_to_m0():
+    """T(lambda) = lambda I - diag(d) with three d_i inside the enlarged circle: three pairs
+    found (the d_i, unit vectors e_i), the rest completed with vectors orthogonal to them and
+    values on the enlarged contour."""
+    m, m0 = 10, 10
+    C = qd.Contour(0.0, 1.0)
+    d = np.array([0.1, -0.5j, 0.9 + 0.3j, 3.0, -4.0, 5j, 2.5 + 2.5j, -3 - 3j, 6.0, 7.0])
+    Ahat = [np.eye(m, dtype=complex), -np.diag(d)]
+    terms = [("pow", 1), ("pow", 0)]
+    lam, Y, found = reduced.contour_reduced(terms, Ahat, C, m0)
+    assert found.sum() == 3 and found[:3].all()
+    assert match_error(lam[:3], d[:3], 1.0) < 1e-12
+    assert np.allclose(C.radius(lam[3:]), reduced.CONTOUR_SCALE)
+    assert np.allclose(Y.conj().T @ Y, np.eye(m0), atol=1e-12)
+
+
+def _as_user_terms(terms):
+    """The same problem with every 'exp' term handed over as a caller-supplied function."""
+    out = []
+    for k, p in terms:
+        if k == "exp":
+            tau = float(p)
+            out.append(("fn", pb.ScalarFunction(lambda z, t=tau: np.exp(-t * z),
+                                                lambda z, t=tau: -t * np.exp(-t * z), "exp")))
+        else:
+            out.append((k, p))
+    return out
+
+
+@pytest.mark.parametrize("route", ["user", "forced"])
+def test_contour_reading_delay_known_spectrum(route):
+    """The known-spectrum delay problem through the contour-integral reduced solve, with the
+    exponential either supplied as a caller function or kept built in and the reading forced."""
+    C = qd.Contour(0.4 + 0.6j, 0.3)
+    terms, mats, (b, c, e) = known_spectrum_delay(40, 21, C.c, C.a, 6)
+    truth = []
+    for i in range(40):
+        truth += scalar_roots_inside(b[i], c[i], e[i], C)
+    P = pb.Problem(_as_user_terms(terms) if route == "user" else terms, mats)
+    z, w = qd.nodes_weights(C, 16)
+    m0 = len(truth) + 6
+    r = nlfeast.solve(P, C, z, w, wl.initial_block(40, m0, 22), m0, 1e-12, reduced="contour")
+    assert r.converged and r.inside.sum() == len(truth)
+    assert match_error(r.eigenvalues, np.array(truth), C.a) < 1e-10
+
+
+def test_contour_reading_rational_matches_brute_force():
+    """A0 - lambda I + lambda/(lambda - sigma) C: multiplied by (lambda - sigma) it is the
+    quadratic -lambda^2 I + lambda (A0 + sigma I + C) - sigma A0, whose companion
+    eigenvalues inside the circle are the truth."""
+    n = 120
+    terms, mats = wl.rational_nep(n, 1008)
+    sig = terms[2][1]
+    F = pb.ScalarFunction(lambda z: wl.pole_value(z, sig), lambda z: wl.pole_deriv(z, sig), "pole")
+    P = pb.Problem([terms[0], terms[1], ("fn", F)], mats)
+    A0, _, Cm = mats
+    quad = pb.Problem([("pow", 2), ("pow", 1), ("pow", 0)],
+                      [-np.eye(n), A0 + sig * np.eye(n) + Cm, -sig * A0])
+    lam = brute.companion_eigs(quad)
+    c = -0.5 - 0.8j
+    d = np.sort(np.abs(lam - c))
+    r = 0.5 * (d[9] + d[10])
+    assert (d[10] - d[9]) / d[10] > 0.03
+    C = qd.Contour(c, r)
+    truth = lam[np.abs(lam - c) < r]
+    z, w = qd.nodes_weights(C, 16)
+    res = nlfeast.solve(P, C, z, w, wl.initial_block(n, 20, 2008), 20, 1e-11)
+    assert res.converged and res.inside.sum() == len(truth) == 10
+    assert match_error(res.eigenvalues, truth, r) < 1e-11

@@ -15,11 +15,16 @@ Workloads
   delay_problem(n, seed)       lambda^2 M + lambda C + K + exp(-tau lambda) E with M = I,
                                C = 0.1 CN / sqrt(n), K = tridiag(-1, 2, -1),
                                E = 0.5 CN / sqrt(n), tau = 1
+  rational_nep(n, seed, sigma) A0 - lambda I + lambda / (lambda - sigma) C with A0 = CN / sqrt(n),
+                               C = 0.3 CN / sqrt(n), sigma = 4: a rational problem whose third
+                               term is a caller-supplied function ('fn', sigma) evaluated by
+                               pole_value / pole_deriv
   initial_block(n, m0, seed)   X0 with i.i.d. CN(0, 1) entries
 
 CN(0, 1) = (N(0,1) + i N(0,1)) / sqrt(2).  Random streams: numpy default_rng(seed).
 Every matrix is returned as a complex128 numpy array in C (row-major) order; term kinds
-are ('pow', p) for lambda^p and ('exp', tau) for exp(-tau lambda).
+are ('pow', p) for lambda^p, ('exp', tau) for exp(-tau lambda) and ('fn', sigma) for the
+pole function lambda / (lambda - sigma).
 """
 import numpy as np
 
@@ -110,6 +115,25 @@ def random_pep(n, seed, degree=4):
     return [("pow", degree - q) for q in range(degree + 1)], mats
 
 
+def pole_value(z, sigma):
+    """The scalar function of a ('fn', sigma) term: lambda / (lambda - sigma)."""
+    z = np.asarray(z, dtype=complex)
+    return z / (z - sigma)
+
+
+def pole_deriv(z, sigma):
+    """Its derivative, -sigma / (lambda - sigma)^2."""
+    z = np.asarray(z, dtype=complex)
+    return -sigma / (z - sigma) ** 2
+
+
+def rational_nep(n, seed, sigma=4.0):
+    rng = np.random.default_rng(seed)
+    A0 = cn(rng, (n, n)) / np.sqrt(n)
+    C = 0.3 * cn(rng, (n, n)) / np.sqrt(n)
+    return [("pow", 0), ("pow", 1), ("fn", float(sigma))], [A0, -np.eye(n, dtype=complex), C]
+
+
 def initial_block(n, m0, seed):
     return cn(np.random.default_rng(seed), (n, m0))
 
@@ -127,11 +151,13 @@ CONFIGS = {
     "delay512": dict(id=6, kind="delay_problem", n=512, m0=24, nc=16, tol=1e-11, inside=12),
     # a quartic problem for the sweep over the number of quadrature nodes
     "quartic1024": dict(id=7, kind="random_pep", n=1024, m0=24, nc=16, tol=1e-10, inside=14),
+    # a rational problem with a caller-supplied term (the contour-integral reduced solve)
+    "rational300": dict(id=8, kind="rational_nep", n=300, m0=24, nc=16, tol=1e-11, inside=12),
 }
 
 
 def make_problem(name):
     cfg = CONFIGS[name]
     gen = {"random_qep": random_qep, "damped_qep": damped_qep, "delay_problem": delay_problem,
-           "random_pep": random_pep}[cfg["kind"]]
+           "random_pep": random_pep, "rational_nep": rational_nep}[cfg["kind"]]
     return gen(cfg["n"], 1000 + cfg["id"])
