@@ -6,7 +6,8 @@
  * for Nonlinear Eigenvalue Problems", arXiv 1801.09794: problem statement in Sec. 1 eq. nlevp
  * and Sec. 2 eq. NLEVP; the method is Algorithm 1 of Sec. 4.2), with
  *
- *     T(lambda) = sum_j f_j(lambda) A_j,   f_j(lambda) = lambda^p  or  exp(-tau lambda)
+ *     T(lambda) = sum_j f_j(lambda) A_j,   f_j(lambda) = lambda^p,  exp(-tau lambda)  or a
+ *                                          scalar function supplied by the caller
  *
  * (polynomial form of Sec. 2 eq. polynomialeig; non-polynomial form named in Sec. 6).
  *
@@ -48,8 +49,22 @@ typedef enum {
 
 typedef enum {
     NLF_F_POW = 0,               /* f(lambda) = lambda^p, param = p (integer 0..16) */
-    NLF_F_EXP = 1                /* f(lambda) = exp(-tau lambda), param = tau */
+    NLF_F_EXP = 1,               /* f(lambda) = exp(-tau lambda), param = tau */
+    NLF_F_USER = 2               /* f given by the caller's nlfeast_user_fn (set with
+                                    nlfeast_set_user_function), which receives the term's
+                                    position j and param */
 } nlfeast_fkind;
+
+/* A caller-supplied scalar function f of a term of kind NLF_F_USER (Sec. 6: T(lambda) of any
+ * form).  For the term at position `term` with parameter `param`, writes f(z_i) to
+ * f[2i], f[2i+1] and, when df is not NULL, f'(z_i) to df[2i], df[2i+1], for the `count` points
+ * z_i = z[2i] + i z[2i+1].  f must be analytic inside the contour enlarged 1.5 times (the
+ * reduced problem is solved on that enlarged ellipse) and on the contour's nodes.  Returns 0;
+ * any other value makes the computation that asked fail with NLF_ERR_ARG.  The library calls
+ * it from the calling thread and from its own host threads, possibly at the same time: it must
+ * be safe to call concurrently. */
+typedef int32_t (*nlfeast_user_fn)(void* user, int32_t term, double param, int64_t count,
+                                   const double* z, double* f, double* df);
 
 typedef enum {
     NLF_PREC_FP64 = 0,           /* LU and triangular solves in complex128 */
@@ -98,7 +113,13 @@ typedef struct {
     int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
                                     the trailing update of panel k runs; -1 = one stream;
                                     0 = library default (one stream) */
-    int32_t reserved;            /* must be 0 */
+    int32_t reduced_solver;      /* Steps 1-2 for non-polynomial T: 0 = Taylor linearisation about
+                                    the contour centre and Newton refinement for NLF_F_EXP terms;
+                                    1 = the contour-integral solve (moments of the reduced
+                                    resolvent on the contour enlarged 1.5 times, block Hankel
+                                    matrices, Newton refinement).  Problems with an NLF_F_USER
+                                    term always take the contour-integral solve; polynomial
+                                    problems always the exact companion linearisation */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -112,6 +133,12 @@ nlfeast_status nlfeast_create(nlfeast_handle* h, int64_t n, int device, void* st
  * dimension lda).  The A_j are borrowed, not copied.  Invalidates cached factorisations. */
 nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fkind,
                                   const double* fparam, const void* const* A_dev, int64_t lda);
+
+/* The function evaluated for every term of kind NLF_F_USER (see nlfeast_user_fn), with the
+ * caller's `user` pointer passed back unchanged; both stay borrowed until replaced or the
+ * handle is destroyed.  A solve with an NLF_F_USER term and no function returns NLF_ERR_STATE.
+ * Invalidates cached factorisations. */
+nlfeast_status nlfeast_set_user_function(nlfeast_handle h, nlfeast_user_fn fn, void* user);
 
 /* nreg disjoint regions (Sec. 1 and Sec. 3: independent subregions of the plane).  Region r is
  * the axis-aligned ellipse with centre (centre[2r] + i centre[2r+1]) and semi-axes
@@ -179,7 +206,8 @@ void nlfeast_destroy(nlfeast_handle h);   /* NULL is a no-op */
 /* T(z_k) = sum_j f_j(z_k) A_j for k = 0..nz-1 (the matrices whose inverses Step 4 applies).
  * A_dev[j]: c128 n x n (lda).  z: 2*nz doubles (host).  Outputs: T64_dev (c128, may be NULL)
  * and/or T32_dev (c64, rounded once from the FP64 sum, may be NULL), each a batch of nz n x n
- * matrices with leading dimension ldt and stride strideT. */
+ * matrices with leading dimension ldt and stride strideT.  Term kinds NLF_F_POW and NLF_F_EXP
+ * only (NLF_ERR_ARG otherwise: caller-supplied functions belong to a handle). */
 nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const double* fparam,
                             const void* const* A_dev, int64_t lda, int32_t nz, const double* z,
                             void* T64_dev, void* T32_dev, int64_t ldt, int64_t strideT,
@@ -257,7 +285,8 @@ nlfeast_status nlf_gemm_batched_tile(int32_t dtype, char opA, int64_t M, int64_t
 
 /* Block residual T(X, Lambda) = sum_j A_j X f_j(Lambda) (Sec. 4.2) and its column 2-norms
  * (the Step 3 quantities).  X_dev: c128 n x m (ldx); lambda: 2*m doubles (host); R_dev: c128
- * n x m (ldr); norms_dev: m doubles (device).  ws_dev: c128 scratch of n * m elements. */
+ * n x m (ldr); norms_dev: m doubles (device).  ws_dev: c128 scratch of n * m elements.
+ * Term kinds NLF_F_POW and NLF_F_EXP only. */
 nlfeast_status nlf_block_residual(int64_t n, int32_t m, int32_t J, const int32_t* fkind,
                                   const double* fparam, const void* const* A_dev, int64_t lda,
                                   const void* X_dev, int64_t ldx, const double* lambda,
@@ -305,6 +334,24 @@ nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind,
                                  double cim, double a, double b, int32_t m_keep,
                                  const double* avoid, int32_t n_avoid, double* lambda_out,
                                  double* Y_out);
+
+/* As nlf_reduced_solve, with terms of kind NLF_F_USER evaluated by fn(user, ...) and the
+ * choice `method` of nlfeast_options.reduced_solver (0 or 1).  The contour-integral solve
+ * (Sec. 3 eq. cauchymoments applied to the reduced function; taken for NLF_F_USER terms, or
+ * method 1 with any non-polynomial term) needs m_keep <= m: it returns the eigenpairs found
+ * inside the contour enlarged 1.5 times, Newton-refined and in ascending normalised radius,
+ * followed, when fewer than m_keep were found, by completing pairs (unit vectors orthogonal to
+ * those found, with values spread over the enlarged contour); found_out (m_keep int32, may be
+ * NULL) receives 1 for a found pair and 0 for a completing one.  fn may be NULL when no term
+ * is NLF_F_USER.  Errors: NLF_ERR_ARG (bad arguments, or fn reported a failure),
+ * NLF_ERR_DEVICE (a singular reduced matrix on the enlarged contour, or too many eigenvalues
+ * inside it to resolve). */
+nlfeast_status nlf_reduced_solve_ex(int32_t m, int32_t J, const int32_t* fkind,
+                                    const double* fparam, nlfeast_user_fn fn, void* user,
+                                    int32_t method, const double* Ahat, double cre, double cim,
+                                    double a, double b, int32_t m_keep, const double* avoid,
+                                    int32_t n_avoid, double* lambda_out, double* Y_out,
+                                    int32_t* found_out);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "nlfeast.h")
 
 NLF_OK, NLF_ERR_ARG, NLF_ERR_NOMEM, NLF_ERR_DEVICE, NLF_ERR_STATE = 0, 1, 2, 3, 4
 NLF_ERR_SINGULAR, NLF_ERR_M0_TOO_SMALL, NLF_ERR_NOT_CONVERGED = 5, 6, 7
-NLF_F_POW, NLF_F_EXP = 0, 1
+NLF_F_POW, NLF_F_EXP, NLF_F_USER = 0, 1, 2
 NLF_PREC_FP64, NLF_PREC_FP32_REFINE = 0, 1
 NLF_QUAD_GAUSS_LEGENDRE, NLF_QUAD_TRAPEZOID = 0, 1
 NLF_C64, NLF_C128 = 0, 1
@@ -46,14 +46,43 @@ class Options(ctypes.Structure):
                 ("autotune", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("lu_streams", ctypes.c_int32), ("panel_width", ctypes.c_int32),
                 ("region_streams", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("reduced_solver", ctypes.c_int32)]
 
 
 def options(tol=1e-10, max_iter=50, precision=NLF_PREC_FP64, max_refine=5, refine_eta=0.05,
             seed=2024, autotune=0, verbose=0, lu_streams=0, panel_width=0, region_streams=0,
-            graph=0, lookahead=0):
+            graph=0, lookahead=0, reduced_solver=0):
     return Options(tol, max_iter, precision, max_refine, refine_eta, seed, autotune, verbose,
-                   lu_streams, panel_width, region_streams, graph, lookahead, 0)
+                   lu_streams, panel_width, region_streams, graph, lookahead, reduced_solver)
+
+
+# nlfeast_user_fn: (user, term, param, count, z, f, df) -> int32
+USER_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                           ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
+
+
+def user_function(py_fn):
+    """Wraps py_fn(term, param, z, want_deriv) -> (f, df) (complex numpy arrays shaped like z;
+    df may be None when want_deriv is False) as an nlfeast_user_fn.  Keep the returned object
+    alive while the library may call it.  An exception inside py_fn is reported to the
+    library as a failure (the call that asked returns NLF_ERR_ARG)."""
+    def tramp(_user, term, param, count, z, f, df):
+        try:
+            zz = np.ctypeslib.as_array(z, shape=(2 * count,))
+            zc = zz[0::2] + 1j * zz[1::2]
+            fv, dv = py_fn(int(term), float(param), zc, bool(df))
+            fo = np.ctypeslib.as_array(f, shape=(2 * count,))
+            fv = np.broadcast_to(np.asarray(fv, dtype=complex), zc.shape)
+            fo[0::2], fo[1::2] = fv.real, fv.imag
+            if df:
+                do = np.ctypeslib.as_array(df, shape=(2 * count,))
+                dv = np.broadcast_to(np.asarray(dv, dtype=complex), zc.shape)
+                do[0::2], do[1::2] = dv.real, dv.imag
+            return 0
+        except Exception:
+            return 1
+    return USER_FN(tramp)
 
 
 _lib = None
@@ -100,6 +129,9 @@ _SIGS = {
     "nlf_quadrature": (c_i32, [c_dbl, c_dbl, c_dbl, c_dbl, c_i32, c_i32, P_dbl, P_dbl]),
     "nlf_reduced_solve": (c_i32, [c_i32, c_i32, P_i32, P_dbl, P_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
                                   c_i32, P_dbl, c_i32, P_dbl, P_dbl]),
+    "nlfeast_set_user_function": (c_i32, [c_vp, USER_FN, c_vp]),
+    "nlf_reduced_solve_ex": (c_i32, [c_i32, c_i32, P_i32, P_dbl, USER_FN, c_vp, c_i32, P_dbl, c_dbl,
+                                     c_dbl, c_dbl, c_dbl, c_i32, P_dbl, c_i32, P_dbl, P_dbl, P_i32]),
 }
 
 
@@ -173,7 +205,7 @@ def from_colmajor(t):
 def _kinds(terms):
     kinds, params = [], []
     for k, p in terms:
-        kinds.append({"pow": NLF_F_POW, "exp": NLF_F_EXP}.get(k, k))
+        kinds.append({"pow": NLF_F_POW, "exp": NLF_F_EXP, "fn": NLF_F_USER}.get(k, k))
         params.append(float(p))
     return np.array(kinds, dtype=np.int32), np.array(params, dtype=np.float64)
 
@@ -202,6 +234,11 @@ def nlfeast_set_coeffs(h, terms, mats, lda=None):
     lda = lda if lda is not None else mats[0].shape[-1]
     _check(lib().nlfeast_set_coeffs(h, len(mats), kinds.ctypes.data_as(P_i32),
                                     params.ctypes.data_as(P_dbl), ptrs, int(lda)), h)
+
+
+def nlfeast_set_user_function(h, fn):
+    """fn: a USER_FN object (see user_function) or None; the caller keeps it alive."""
+    _check(lib().nlfeast_set_user_function(h, fn if fn is not None else USER_FN(), None), h)
 
 
 def nlfeast_set_contour(h, regions, quad_rule=NLF_QUAD_GAUSS_LEGENDRE):
@@ -413,6 +450,29 @@ def nlf_reduced_solve(terms, Ahat, centre, a, b, m_keep, avoid=None):
     return lam[0::2] + 1j * lam[1::2], Yc
 
 
+def nlf_reduced_solve_ex(terms, Ahat, centre, a, b, m_keep, fn=None, method=0, avoid=None):
+    """As nlf_reduced_solve with terms ('fn', param) evaluated by fn (a USER_FN object) and the
+    reduced-solver choice `method`.  Returns (lam, Y, found)."""
+    kinds, params = _kinds(terms)
+    m = Ahat[0].shape[0]
+    A = np.concatenate([np.asfortranarray(M, dtype=complex).ravel(order="F") for M in Ahat])
+    Af = np.empty(2 * len(A))
+    Af[0::2], Af[1::2] = A.real, A.imag
+    lam = np.zeros(2 * m_keep)
+    Y = np.zeros(2 * m * m_keep)
+    found = np.zeros(m_keep, dtype=np.int32)
+    c = complex(centre)
+    av = _cplx_pairs([] if avoid is None else avoid)
+    _check(lib().nlf_reduced_solve_ex(m, len(Ahat), kinds.ctypes.data_as(P_i32),
+                                      params.ctypes.data_as(P_dbl), fn if fn is not None else USER_FN(),
+                                      None, int(method), Af.ctypes.data_as(P_dbl), c.real, c.imag,
+                                      float(a), float(b), int(m_keep), av.ctypes.data_as(P_dbl),
+                                      len(av) // 2, lam.ctypes.data_as(P_dbl), Y.ctypes.data_as(P_dbl),
+                                      found.ctypes.data_as(P_i32)))
+    Yc = (Y[0::2] + 1j * Y[1::2]).reshape(m_keep, m).T
+    return lam[0::2] + 1j * lam[1::2], Yc, found.astype(bool)
+
+
 # --------------------------------------------------------------------------- convenience
 
 class NLFEAST:
@@ -436,6 +496,11 @@ class NLFEAST:
     def set_contour(self, regions, quad_rule=NLF_QUAD_GAUSS_LEGENDRE):
         self.regions = list(regions)
         nlfeast_set_contour(self.h, regions, quad_rule)
+
+    def set_user_function(self, py_fn):
+        """py_fn(term, param, z, want_deriv) -> (f, df) for the terms of kind 'fn'."""
+        self._user_fn = user_function(py_fn)
+        nlfeast_set_user_function(self.h, self._user_fn)
 
     def solve(self, opts, X0=None):
         import torch

@@ -112,7 +112,43 @@ bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv, doubl
     return true;
 }
 
+// One call of the caller's function at count points; NaN and a recorded failure when it
+// reports one (or none is set).
+static void user_call(const Term& t, const cplx* z, int64_t count, cplx* f, cplx* df) {
+    static_assert(sizeof(cplx) == 2 * sizeof(double), "complex layout");
+    for (int64_t i = 0; i < count; ++i) {
+        f[i] = cplx(NAN, NAN);
+        if (df) df[i] = cplx(NAN, NAN);
+    }
+    if (!t.fn || !t.fn->fn) {
+        if (t.fn) t.fn->failed.store(1);
+        return;
+    }
+    if (t.fn->fn(t.fn->user, t.index, t.param, count, reinterpret_cast<const double*>(z),
+                 reinterpret_cast<double*>(f), reinterpret_cast<double*>(df)) != 0)
+        t.fn->failed.store(1);
+}
+
+void term_values(const Term& t, const cplx* z, int64_t count, cplx* f) {
+    if (t.kind == 2) {
+        user_call(t, z, count, f, nullptr);
+        return;
+    }
+    for (int64_t i = 0; i < count; ++i) f[i] = term_value(t, z[i]);
+}
+
+bool user_failed(const std::vector<Term>& terms) {
+    for (const Term& t : terms)
+        if (t.kind == 2 && (!t.fn || t.fn->failed.load())) return true;
+    return false;
+}
+
 cplx term_value(const Term& t, cplx l) {
+    if (t.kind == 2) {
+        cplx f;
+        user_call(t, &l, 1, &f, nullptr);
+        return f;
+    }
     if (t.kind == 0) {
         const int p = (int)t.param;
         cplx r = 1.0;
@@ -123,6 +159,11 @@ cplx term_value(const Term& t, cplx l) {
 }
 
 cplx term_deriv(const Term& t, cplx l) {
+    if (t.kind == 2) {
+        cplx f, d;
+        user_call(t, &l, 1, &f, &d);
+        return d;
+    }
     if (t.kind == 0) {
         const int p = (int)t.param;
         if (p == 0) return 0.0;
@@ -717,16 +758,342 @@ static std::vector<cplx> shift_candidates(const Ellipse& E, const std::vector<cp
     return out;
 }
 
+// Newton on F(y, l) = [T(l) y; v^H y - 1], Jacobian [[T(l), T'(l) y], [v^H, 0]] (v the
+// starting vector), on the exact reduced function, for the pairs (lam[q], Y[:, q]) with q in
+// todo (Y: m rows, ld m); the pairs are independent and are spread over host threads.  Each
+// refined vector is returned with unit norm.
+static void newton_polish(int m, const std::vector<Term>& terms, const cplx* Ahat, std::vector<cplx>& lam,
+                          std::vector<cplx>& Yv, const std::vector<int>& todo) {
+    const int J = (int)terms.size();
+    const size_t mm = (size_t)m * m;
+    auto polish = [&](int q) {
+        std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
+        cplx l = lam[q];
+        std::vector<cplx> y(Yv.begin() + (size_t)q * m, Yv.begin() + (size_t)(q + 1) * m);
+        const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
+        for (int it = 0; it < 8; ++it) {
+            std::fill(Tl.begin(), Tl.end(), cplx(0.0));
+            std::fill(dT.begin(), dT.end(), cplx(0.0));
+            double scale = 0.0;
+            for (int j = 0; j < J; ++j) {
+                const cplx f = term_value(terms[j], l), fd = term_deriv(terms[j], l);
+                const cplx* A = Ahat + (size_t)j * mm;
+                double an = 0.0;
+                for (size_t e = 0; e < mm; ++e) {
+                    Tl[e] += f * A[e];
+                    dT[e] += fd * A[e];
+                    an += std::norm(A[e]);
+                }
+                scale += std::abs(f) * std::sqrt(an);
+            }
+            if (!std::isfinite(scale)) break;
+            double rn = 0.0;
+            for (int r = 0; r < m; ++r) rhs[r] = 0.0;
+            for (int c = 0; c < m; ++c)
+                for (int r = 0; r < m; ++r) rhs[r] -= Tl[r + (size_t)c * m] * y[c];
+            for (int r = 0; r < m; ++r) rn += std::norm(rhs[r]);
+            cplx vy = 0.0;
+            for (int i = 0; i < m; ++i) vy += std::conj(v0[i]) * y[i];
+            rhs[m] = -(vy - 1.0);
+            if (std::sqrt(rn) <= 1e-15 * scale && std::abs(rhs[m]) < 1e-15) break;
+            for (int c = 0; c < m; ++c)
+                for (int r = 0; r < m; ++r) Jm[r + (size_t)c * (m + 1)] = Tl[r + (size_t)c * m];
+            for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] = 0.0;
+            for (int c = 0; c < m; ++c)
+                for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] += dT[r + (size_t)c * m] * y[c];
+            for (int c = 0; c < m; ++c) Jm[m + (size_t)c * (m + 1)] = std::conj(v0[c]);
+            Jm[m + (size_t)m * (m + 1)] = 0.0;
+            if (!lu_solve_small(m + 1, Jm, rhs.data(), 1)) break;
+            for (int i = 0; i < m; ++i) y[i] += rhs[i];
+            l += rhs[m];
+        }
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += std::norm(y[i]);
+        s = std::sqrt(s);
+        for (int i = 0; i < m; ++i) Yv[(size_t)q * m + i] = y[i] / s;
+        lam[q] = l;
+    };
+    const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
+    const int nth = std::max(1, std::min({hw, 16, (int)todo.size() / 2}));
+    if (nth <= 1 || (size_t)m * m * todo.size() < 200000) {
+        for (int q : todo) polish(q);
+    } else {
+        std::atomic<size_t> next{0};
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back([&] {
+                for (size_t i; (i = next.fetch_add(1)) < todo.size();) polish(todo[i]);
+            });
+        for (auto& t : pool) t.join();
+    }
+}
+
+// Householder QR with column pivoting of the N x N matrix A (column-major, overwritten: R on
+// and above the diagonal, the reflectors' tails below, LAPACK's convention H = I - tau v v^H,
+// v(0) = 1).  Column j is the remaining column of largest norm; the factorisation stops at the
+// first step whose pivot norm is at most `thresh`.  Returns that numerical rank.
+static int pivoted_qr(int N, std::vector<cplx>& A, std::vector<cplx>& tau, std::vector<int>& perm, double thresh) {
+    perm.resize(N);
+    std::iota(perm.begin(), perm.end(), 0);
+    tau.assign(N, 0.0);
+    std::vector<double> nrm2(N);
+    for (int j = 0; j < N; ++j) {
+        int p = j;
+        for (int c = j; c < N; ++c) {
+            double t = 0.0;
+            const cplx* col = &A[(size_t)c * N];
+            for (int i = j; i < N; ++i) t += std::norm(col[i]);
+            nrm2[c] = t;
+            if (t > nrm2[p]) p = c;
+        }
+        if (p != j) {
+            std::swap_ranges(A.begin() + (size_t)j * N, A.begin() + (size_t)(j + 1) * N, A.begin() + (size_t)p * N);
+            std::swap(perm[j], perm[p]);
+        }
+        const double nrm = std::sqrt(nrm2[p]);
+        if (nrm == 0.0 || nrm <= thresh) return j;
+        cplx* a = &A[(size_t)j * N];
+        const cplx alpha = a[j];
+        const double beta = alpha.real() >= 0.0 ? -nrm : nrm;
+        const cplx t = cplx((beta - alpha.real()) / beta, -alpha.imag() / beta);
+        const cplx scl = 1.0 / (alpha - beta);
+        for (int i = j + 1; i < N; ++i) a[i] *= scl;
+        a[j] = beta;
+        tau[j] = t;
+        const cplx ct = std::conj(t);
+        for (int c = j + 1; c < N; ++c) {   // column c <- (I - conj(tau) v v^H) column c
+            cplx* b = &A[(size_t)c * N];
+            cplx w = b[j];
+            for (int i = j + 1; i < N; ++i) w += std::conj(a[i]) * b[i];
+            w *= ct;
+            b[j] -= w;
+            for (int i = j + 1; i < N; ++i) b[i] -= a[i] * w;
+        }
+    }
+    return N;
+}
+
+bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                   std::vector<cplx>& lam, std::vector<cplx>& Y) {
+    const int J = (int)terms.size(), NP = CONTOUR_POINTS, KMAX = 3;
+    const size_t mm = (size_t)m * m;
+    const double a = CONTOUR_SCALE * E.a, b = CONTOUR_SCALE * E.b, L = std::max(a, b);
+    std::vector<cplx> z(NP), w(NP), mu(NP);
+    for (int q = 0; q < NP; ++q) {
+        const double th = 2.0 * kPi * (q + 0.5) / NP;
+        z[q] = E.c + cplx(a * std::cos(th), b * std::sin(th));
+        // (1/2 pi i) dz/dtheta (2 pi / NP)
+        w[q] = cplx(-a * std::sin(th), b * std::cos(th)) / cplx(0.0, (double)NP);
+        mu[q] = (z[q] - E.c) / L;
+    }
+    std::vector<cplx> fz((size_t)J * NP);   // the functions at every point, one call per term
+    for (int j = 0; j < J; ++j) term_values(terms[j], z.data(), NP, &fz[(size_t)j * NP]);
+    // M_p, p < 2 KMAX: points spread over threads, each with its own partial sums
+    const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
+    const int nth = std::max(1, std::min({hw, 16, NP / 4, (int)(mm * NP / 20000) + 1}));
+    std::vector<std::vector<cplx>> part(nth, std::vector<cplx>(2 * KMAX * mm, 0.0));
+    std::vector<double> isize(NP, 0.0);   // |w_q| ||T(z_q)^{-1}||_F, the integrand's size
+    std::atomic<int> next{0}, bad{0};
+    auto work = [&](int t) {
+        std::vector<cplx> Tz(mm), Inv(mm);
+        for (int q; (q = next.fetch_add(1)) < NP;) {
+            std::fill(Tz.begin(), Tz.end(), cplx(0.0));
+            for (int j = 0; j < J; ++j) {
+                const cplx f = fz[(size_t)j * NP + q];
+                const cplx* A = Ahat + (size_t)j * mm;
+                for (size_t e = 0; e < mm; ++e) Tz[e] += f * A[e];
+            }
+            std::fill(Inv.begin(), Inv.end(), cplx(0.0));
+            for (int i = 0; i < m; ++i) Inv[i + (size_t)i * m] = 1.0;
+            if (!lu_solve_small(m, Tz, Inv.data(), m)) {
+                bad.store(1);
+                continue;
+            }
+            double fro = 0.0;
+            for (size_t e = 0; e < mm; ++e) fro += std::norm(Inv[e]);
+            isize[q] = std::abs(w[q]) * std::sqrt(fro);
+            cplx wp = w[q];
+            for (int p = 0; p < 2 * KMAX; ++p, wp *= mu[q]) {
+                cplx* Mp = &part[t][(size_t)p * mm];
+                for (size_t e = 0; e < mm; ++e) Mp[e] += wp * Inv[e];
+            }
+        }
+    };
+    if (nth == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t) pool.emplace_back(work, t);
+        for (auto& th : pool) th.join();
+    }
+    if (bad.load()) return false;
+    std::vector<cplx> M(2 * KMAX * mm, 0.0);
+    for (int t = 0; t < nth; ++t)
+        for (size_t e = 0; e < M.size(); ++e) M[e] += part[t][e];
+    int K = 2, N = 0, k = 0;
+    std::vector<cplx> H0, tau;
+    std::vector<int> perm;
+    for (; K <= KMAX; ++K) {
+        N = K * m;
+        H0.assign((size_t)N * N, 0.0);
+        for (int bi = 0; bi < K; ++bi)
+            for (int bj = 0; bj < K; ++bj) {
+                const cplx* Mp = &M[(size_t)(bi + bj) * mm];
+                for (int c = 0; c < m; ++c)
+                    for (int r = 0; r < m; ++r)
+                        H0[(size_t)(bi * m + r) + (size_t)(bj * m + c) * N] = Mp[r + (size_t)c * m];
+            }
+        k = pivoted_qr(N, H0, tau, perm, CONTOUR_RANK_TOL * std::accumulate(isize.begin(), isize.end(), 0.0));
+        if (k < N) break;
+    }
+    if (K > KMAX) return false;
+    lam.clear();
+    Y.clear();
+    if (k == 0) return true;
+    // Q_k = H_0 ... H_{k-1} [I_k; 0]
+    std::vector<cplx> Qk((size_t)N * k, 0.0);
+    for (int i = 0; i < k; ++i) Qk[i + (size_t)i * N] = 1.0;
+    for (int j = k - 1; j >= 0; --j) {
+        const cplx* v = &H0[(size_t)j * N];
+        for (int c = 0; c < k; ++c) {
+            cplx* q = &Qk[(size_t)c * N];
+            cplx s = q[j];
+            for (int i = j + 1; i < N; ++i) s += std::conj(v[i]) * q[i];
+            s *= tau[j];
+            q[j] -= s;
+            for (int i = j + 1; i < N; ++i) q[i] -= v[i] * s;
+        }
+    }
+    // G = Q_k^H H1 P_k (k x k), with column c of H1 P_k = block column of H1 for perm[c]
+    std::vector<cplx> G((size_t)k * k, 0.0), h1(N);
+    for (int c = 0; c < k; ++c) {
+        const int col = perm[c], bj = col / m, cc = col % m;
+        for (int bi = 0; bi < K; ++bi) {
+            const cplx* Mp = &M[(size_t)(bi + bj + 1) * mm];
+            for (int r = 0; r < m; ++r) h1[bi * m + r] = Mp[r + (size_t)cc * m];
+        }
+        for (int i = 0; i < k; ++i) {
+            const cplx* q = &Qk[(size_t)i * N];
+            cplx s = 0.0;
+            for (int r = 0; r < N; ++r) s += std::conj(q[r]) * h1[r];
+            G[i + (size_t)c * k] = s;
+        }
+    }
+    // B = G R_11^{-1}: column c of B from B R_11 = G, left to right
+    std::vector<cplx> B((size_t)k * k);
+    for (int c = 0; c < k; ++c) {
+        for (int i = 0; i < k; ++i) {
+            cplx s = G[i + (size_t)c * k];
+            for (int p = 0; p < c; ++p) s -= B[i + (size_t)p * k] * H0[p + (size_t)c * N];
+            B[i + (size_t)c * k] = s / H0[c + (size_t)c * N];
+        }
+    }
+    std::vector<cplx> ev, S;
+    if (k == 1) {
+        ev.assign(1, B[0]);
+        S.assign(1, 1.0);
+    } else {
+        HessEig he;
+        if (!he.compute(k, B)) return false;
+        ev = he.evals;
+        std::vector<int> all(k);
+        std::iota(all.begin(), all.end(), 0);
+        he.vectors(all, S);
+    }
+    lam.resize(k);
+    Y.assign((size_t)m * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+        lam[i] = E.c + L * ev[i];
+        cplx* y = &Y[(size_t)i * m];
+        for (int p = 0; p < k; ++p) {
+            const cplx sp = S[p + (size_t)i * k];
+            const cplx* q = &Qk[(size_t)p * N];
+            for (int r = 0; r < m; ++r) y[r] += q[r] * sp;
+        }
+        double nn = 0.0;
+        for (int r = 0; r < m; ++r) nn += std::norm(y[r]);
+        nn = std::sqrt(nn);
+        if (nn > 0.0)
+            for (int r = 0; r < m; ++r) y[r] /= nn;
+    }
+    return true;
+}
+
+// Steps 1-2 by the contour-integral solve: the pairs inside the enlarged ellipse, refined by
+// Newton, sorted by normalised radius and completed to m_keep (see reduced_solve).
+static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                                     int m_keep) {
+    ReducedResult res;
+    std::vector<cplx> lam, Y;
+    if (m_keep > m || !contour_pairs(m, terms, Ahat, E, lam, Y)) {
+        res.ok = false;
+        return res;
+    }
+    std::vector<int> todo;
+    for (int q = 0; q < (int)lam.size(); ++q)
+        if (std::isfinite(lam[q].real()) && E.radius(lam[q]) < CONTOUR_SCALE) todo.push_back(q);
+    newton_polish(m, terms, Ahat, lam, Y, todo);
+    std::vector<double> rad(todo.size());
+    for (size_t i = 0; i < todo.size(); ++i) rad[i] = E.radius(lam[todo[i]]);
+    std::vector<int> order(todo.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return rad[p] < rad[q]; });
+    const int kf = std::min((int)order.size(), m_keep);
+    res.lambda.resize(m_keep);
+    res.Y.assign((size_t)m * m_keep, 0.0);
+    res.found.assign(m_keep, 0);
+    for (int i = 0; i < kf; ++i) {
+        const int q = todo[order[i]];
+        res.lambda[i] = lam[q];
+        std::copy(Y.begin() + (size_t)q * m, Y.begin() + (size_t)(q + 1) * m, res.Y.begin() + (size_t)i * m);
+        res.found[i] = 1;
+    }
+    // completion: unit vectors e_r orthogonalised (twice) against the columns so far, kept when
+    // at least half of the vector survives, with values spread over the enlarged ellipse
+    int col = kf;
+    std::vector<cplx> v(m);
+    for (int r = 0; r < m && col < m_keep; ++r) {
+        std::fill(v.begin(), v.end(), cplx(0.0));
+        v[r] = 1.0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int c = 0; c < col; ++c) {
+                const cplx* u = &res.Y[(size_t)c * m];
+                cplx d = 0.0;
+                for (int i = 0; i < m; ++i) d += std::conj(u[i]) * v[i];
+                for (int i = 0; i < m; ++i) v[i] -= u[i] * d;
+            }
+        double nn = 0.0;
+        for (int i = 0; i < m; ++i) nn += std::norm(v[i]);
+        nn = std::sqrt(nn);
+        if (nn < 0.5) continue;
+        for (int i = 0; i < m; ++i) res.Y[(size_t)col * m + i] = v[i] / nn;
+        ++col;
+    }
+    if (col < m_keep) {   // the found vectors are (numerically) dependent: no completion
+        res.ok = false;
+        return res;
+    }
+    const int pad = m_keep - kf;
+    for (int i = 0; i < pad; ++i) {
+        const double th = 2.0 * kPi * (i + 0.5) / pad;
+        res.lambda[kf + i] = E.c + CONTOUR_SCALE * cplx(E.a * std::cos(th), E.b * std::sin(th));
+    }
+    res.n_finite = m_keep;
+    return res;
+}
+
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
-                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid) {
+                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid, int method) {
     ReducedResult res;
     const int J = (int)terms.size();
-    bool poly = true;
+    bool poly = true, user = false;
     int maxpow = 1;
     for (const Term& t : terms) {
         if (t.kind == 0) maxpow = std::max(maxpow, (int)t.param);
         else poly = false;
+        if (t.kind == 2) user = true;
     }
+    if (user || (method == 1 && !poly)) return contour_reduced(m, terms, Ahat, E, m_keep);
     const size_t mm = (size_t)m * m;
     const std::vector<cplx> shifts = shift_candidates(E, avoid);
     int deg = maxpow, N = 0;
@@ -823,72 +1190,13 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
         for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = v[(size_t)bb * m + i] / s;
     }
     if (!poly) {
-        // Newton on F(y, l) = [T(l) y; v^H y - 1], Jacobian [[T(l), T'(l) y], [v^H, 0]], for the
-        // pairs near the contour (normalised radius < 2); the pairs are independent and are
-        // spread over host threads
+        // Newton refinement of the pairs near the contour (normalised radius < 2)
         std::vector<int> todo;
         for (int q = 0; q < keep; ++q)
             if (std::isfinite(res.lambda[q].real()) && E.radius(res.lambda[q]) < 2.0) todo.push_back(q);
-        auto polish = [&](int q) {
-            std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
-            cplx l = res.lambda[q];
-            std::vector<cplx> y(res.Y.begin() + (size_t)q * m, res.Y.begin() + (size_t)(q + 1) * m);
-            const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
-            for (int it = 0; it < 8; ++it) {
-                std::fill(Tl.begin(), Tl.end(), cplx(0.0));
-                std::fill(dT.begin(), dT.end(), cplx(0.0));
-                double scale = 0.0;
-                for (int j = 0; j < J; ++j) {
-                    const cplx f = term_value(terms[j], l), fd = term_deriv(terms[j], l);
-                    const cplx* A = Ahat + (size_t)j * mm;
-                    double an = 0.0;
-                    for (size_t e = 0; e < mm; ++e) {
-                        Tl[e] += f * A[e];
-                        dT[e] += fd * A[e];
-                        an += std::norm(A[e]);
-                    }
-                    scale += std::abs(f) * std::sqrt(an);
-                }
-                double rn = 0.0;
-                for (int r = 0; r < m; ++r) rhs[r] = 0.0;
-                for (int c = 0; c < m; ++c)
-                    for (int r = 0; r < m; ++r) rhs[r] -= Tl[r + (size_t)c * m] * y[c];
-                for (int r = 0; r < m; ++r) rn += std::norm(rhs[r]);
-                cplx vy = 0.0;
-                for (int i = 0; i < m; ++i) vy += std::conj(v0[i]) * y[i];
-                rhs[m] = -(vy - 1.0);
-                if (std::sqrt(rn) <= 1e-15 * scale && std::abs(rhs[m]) < 1e-15) break;
-                for (int c = 0; c < m; ++c)
-                    for (int r = 0; r < m; ++r) Jm[r + (size_t)c * (m + 1)] = Tl[r + (size_t)c * m];
-                for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] = 0.0;
-                for (int c = 0; c < m; ++c)
-                    for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] += dT[r + (size_t)c * m] * y[c];
-                for (int c = 0; c < m; ++c) Jm[m + (size_t)c * (m + 1)] = std::conj(v0[c]);
-                Jm[m + (size_t)m * (m + 1)] = 0.0;
-                if (!lu_solve_small(m + 1, Jm, rhs.data(), 1)) break;
-                for (int i = 0; i < m; ++i) y[i] += rhs[i];
-                l += rhs[m];
-            }
-            double s = 0.0;
-            for (int i = 0; i < m; ++i) s += std::norm(y[i]);
-            s = std::sqrt(s);
-            for (int i = 0; i < m; ++i) res.Y[(size_t)q * m + i] = y[i] / s;
-            res.lambda[q] = l;
-        };
-        const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
-        const int nth = std::max(1, std::min({hw, 16, (int)todo.size() / 2}));
-        if (nth <= 1 || (size_t)m * m * todo.size() < 200000) {
-            for (int q : todo) polish(q);
-        } else {
-            std::atomic<size_t> next{0};
-            std::vector<std::thread> pool;
-            for (int t = 0; t < nth; ++t)
-                pool.emplace_back([&] {
-                    for (size_t i; (i = next.fetch_add(1)) < todo.size();) polish(todo[i]);
-                });
-            for (auto& t : pool) t.join();
-        }
+        newton_polish(m, terms, Ahat, res.lambda, res.Y, todo);
     }
+    res.found.assign(keep, 1);
     res.n_finite = 0;
     for (int q = 0; q < keep; ++q)
         if (std::isfinite(res.lambda[q].real())) ++res.n_finite;

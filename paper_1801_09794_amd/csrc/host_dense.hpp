@@ -3,6 +3,7 @@
 // Algorithm 1, Steps 1-2.
 #pragma once
 
+#include <atomic>
 #include <complex>
 #include <cstdint>
 #include <vector>
@@ -28,13 +29,31 @@ void quadrature(const Ellipse& E, int nc, int rule, std::vector<cplx>& z, std::v
 bool cholesky_upper_inverse(int m, const cplx* G, std::vector<cplx>& Rinv,
                             double* min_pivot_ratio = nullptr);
 
-// Term of T(lambda): kind 0 = lambda^p, kind 1 = exp(-tau lambda).
+// A caller-supplied scalar function: fn(user, term, param, count, z, f, df) writes f(z_i) and,
+// when df is not null, f'(z_i), as interleaved (re, im) pairs for count points; a nonzero
+// return marks a failure.  A failure is recorded in `failed` (the evaluation then yields NaN)
+// and turned into an error by the caller once the host work that asked has finished.
+using UserFnPtr = int32_t (*)(void*, int32_t, double, int64_t, const double*, double*, double*);
+struct UserFunction {
+    UserFnPtr fn = nullptr;
+    void* user = nullptr;
+    mutable std::atomic<int> failed{0};
+};
+
+// Term of T(lambda): kind 0 = lambda^p, kind 1 = exp(-tau lambda), kind 2 = the caller's
+// function fn, called with the term's position `index` and parameter.
 struct Term {
     int kind;
     double param;
+    const UserFunction* fn = nullptr;
+    int index = 0;
 };
 cplx term_value(const Term& t, cplx l);
 cplx term_deriv(const Term& t, cplx l);
+// f(z_i) for count points (one call of a caller-supplied function).
+void term_values(const Term& t, const cplx* z, int64_t count, cplx* f);
+// True when a caller-supplied function among the terms has reported a failure.
+bool user_failed(const std::vector<Term>& terms);
 
 // Host threads the dense routines below may use from the calling thread (default 16); callers
 // that run several reduced solves at once lower it per thread.
@@ -43,18 +62,41 @@ int& host_thread_budget();
 struct ReducedResult {
     std::vector<cplx> lambda;   // m_keep values, selection order
     std::vector<cplx> Y;        // m x m_keep, unit columns
+    std::vector<int> found;     // 1 for an eigenpair of the reduced problem, 0 for a completing pair
     int n_finite = 0;
     bool ok = true;
 };
+
+// Enlargement of the contour, trapezoid points and relative rank threshold of the
+// contour-integral reduced solve.
+constexpr double CONTOUR_SCALE = 1.5;
+constexpr int CONTOUR_POINTS = 96;
+constexpr double CONTOUR_RANK_TOL = 1e-10;
 
 // All eigenpairs of sum_j f_j(lambda) Ahat_j y = 0 (Ahat: J matrices m x m, column-major,
 // consecutive), then the m_keep closest to the interior of E (ascending normalised radius,
 // stable, non-finite last).  Polynomial terms: exact companion linearisation, inverted about
 // a shift inside the contour (the centre unless a Ritz value in `avoid` is close to it);
 // exponential terms: Taylor expansion about that shift followed by Newton refinement on the
-// exact reduced function.
+// exact reduced function.  With a caller-supplied term, or method 1 and any non-polynomial
+// term: the contour-integral solve (contour_pairs), Newton refinement of every pair found, and
+// completion to m_keep pairs (requires m_keep <= m) by unit vectors orthogonal to those found,
+// paired with values spread over the enlarged ellipse.
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
-                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid = nullptr);
+                            const Ellipse& E, int m_keep, const std::vector<cplx>* avoid = nullptr,
+                            int method = 0);
+
+// Eigenpairs of sum_j f_j(lambda) Ahat_j y = 0 inside the ellipse E enlarged CONTOUR_SCALE
+// times, from the moments M_p = (1/2 pi i) oint mu^p T(z)^{-1} dz, mu = (z - c)/L (L the larger
+// enlarged semi-axis), by the trapezoid rule with CONTOUR_POINTS points: the block Hankel
+// matrices H0 = [M_{i+j}], H1 = [M_{i+j+1}] (K x K blocks, K = 2, or 3 when H0 has full rank)
+// factor as Vb W^H and Vb mu(Lambda) W^H (Keldysh), and a pivoted QR H0 P = Q R with numerical
+// rank k (pivots above CONTOUR_RANK_TOL times the integrand's size sum_q |w_q| ||T(z_q)^{-1}||_F:
+// with no eigenvalue inside, the moments are rounding noise of that size) gives the k x k matrix Q_k^H H1 P_k R_11^{-1}, similar to mu(Lambda), whose
+// eigenvectors s_i give the eigenvectors as the first block of Q_k s_i.  Returns false when
+// T(z) is singular at a point or H0 keeps full rank with K = 3.
+bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                   std::vector<cplx>& lam, std::vector<cplx>& Y);
 
 // Complex Schur decomposition A = Z T Z^H of a dense N x N matrix (column-major) by
 // Householder reduction to Hessenberg form and the shifted QR algorithm (Givens rotations,

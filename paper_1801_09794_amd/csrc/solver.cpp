@@ -156,6 +156,7 @@ struct nlfeast_ctx {
     std::string last_error;
     int J = 0;
     std::vector<Term> terms;
+    UserFunction ufn;                                      // for terms of kind NLF_F_USER
     std::vector<const z128*> A;
     int64_t lda = 0;
     struct Region {
@@ -718,10 +719,12 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                 const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
                 host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
             }
-            rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr);
+            rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
             host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+            NLF_REQUIRE(!user_failed(h->terms), NLF_ERR_ARG, "solve: the user function reported an error");
             NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
-                        "reduced eigenproblem failed (singular T at the contour centre or QR did not converge)");
+                        "reduced eigenproblem failed (singular T at the contour centre or on the enlarged "
+                        "contour, QR did not converge, or too many eigenvalues inside the enlarged contour)");
             // Step 2: X = Q Y
             for (int i = 0; i < m; ++i) lam[i] = std::isfinite(rr.lambda[i].real()) ? rr.lambda[i] : cplx(0.0);
             h2d(s, Ymat, rr.Y.data(), sizeof(cplx) * m * m);
@@ -736,6 +739,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                     for (int r = 0; r < m; ++r)
                         Gh[(size_t)j * m + r + (size_t)c * J * m] = rr.Y[r + (size_t)c * m] * f;
                 }
+            NLF_REQUIRE(!user_failed(h->terms), NLF_ERR_ARG, "solve: the user function reported an error");
             h2d(s, Gall, Gh.data(), sizeof(cplx) * Gh.size());
             {
                 ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
@@ -919,12 +923,14 @@ nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fk
                     "set_coeffs: need 1 <= J <= 8, non-null arrays, lda >= n");
         std::vector<Term> terms(J);
         for (int j = 0; j < J; ++j) {
-            NLF_REQUIRE(fkind[j] == NLF_F_POW || fkind[j] == NLF_F_EXP, NLF_ERR_ARG, "set_coeffs: bad kind");
+            NLF_REQUIRE(fkind[j] == NLF_F_POW || fkind[j] == NLF_F_EXP || fkind[j] == NLF_F_USER, NLF_ERR_ARG,
+                        "set_coeffs: bad kind");
             if (fkind[j] == NLF_F_POW)
                 NLF_REQUIRE(fparam[j] >= 0 && fparam[j] <= 16 && fparam[j] == std::floor(fparam[j]),
                             NLF_ERR_ARG, "set_coeffs: power must be an integer in 0..16");
+            NLF_REQUIRE(std::isfinite(fparam[j]), NLF_ERR_ARG, "set_coeffs: parameter not finite");
             NLF_REQUIRE(A_dev[j], NLF_ERR_ARG, "set_coeffs: null matrix");
-            terms[j] = Term{fkind[j], fparam[j]};
+            terms[j] = Term{fkind[j], fparam[j], fkind[j] == NLF_F_USER ? &h->ufn : nullptr, j};
         }
         h->J = J;
         h->terms = terms;
@@ -932,6 +938,18 @@ nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fk
         for (int j = 0; j < J; ++j) h->A[j] = (const z128*)A_dev[j];
         h->lda = lda;
         h->factors_valid = false;
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlfeast_set_user_function(nlfeast_handle h, nlfeast_user_fn fn, void* user) {
+    NLF_TRY(h, {
+        NLF_REQUIRE(h, NLF_ERR_ARG, "null handle");
+        h->ufn.fn = fn;
+        h->ufn.user = user;
+        h->ufn.failed.store(0);
+        h->factors_valid = false;
+        h->drop_graph();
         return NLF_OK;
     })
 }
@@ -1011,8 +1029,13 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         NLF_REQUIRE((opt->region_streams == 0 || opt->region_streams == 1) && (opt->graph == 0 || opt->graph == 1) &&
                         (opt->autotune == 0 || opt->autotune == 1),
                     NLF_ERR_ARG, "solve: region_streams, graph and autotune are 0 or 1");
-        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && opt->reserved == 0, NLF_ERR_ARG,
-                    "solve: lookahead in -1..1, reserved 0");
+        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && (opt->reduced_solver == 0 || opt->reduced_solver == 1),
+                    NLF_ERR_ARG, "solve: lookahead in -1..1, reduced_solver 0 or 1");
+        bool has_user = false;
+        for (const Term& t : h->terms) has_user = has_user || t.kind == NLF_F_USER;
+        NLF_REQUIRE(!has_user || h->ufn.fn, NLF_ERR_STATE,
+                    "solve: a term of kind NLF_F_USER needs nlfeast_set_user_function first");
+        h->ufn.failed.store(0);
         const Layout L = make_layout(h, opt->precision);
         NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
         NLF_HIP(hipSetDevice(h->device));
@@ -1036,6 +1059,7 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
             for (const auto& r : h->regions)
                 for (int q = 0; q < r.nc; ++q, ++k)
                     for (int j = 0; j < J; ++j) coef[(size_t)k * J + j] = term_value(h->terms[j], r.z[q]);
+            NLF_REQUIRE(!user_failed(h->terms), NLF_ERR_ARG, "solve: the user function reported an error");
             h2d(s, at<void>(ws, L.coef), coef.data(), sizeof(cplx) * coef.size());
             LuTuning tune = fixed_tuning(*opt);
             if (opt->autotune) tune = autotuned(h, L, ws, p32, s, *opt);
@@ -1160,6 +1184,13 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
 
 static hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// The step-level calls take built-in terms only: a caller-supplied function lives on a handle.
+static void require_builtin_kinds(int J, const int32_t* fkind, const char* who) {
+    for (int j = 0; j < J; ++j)
+        NLF_REQUIRE(fkind[j] == NLF_F_POW || fkind[j] == NLF_F_EXP, NLF_ERR_ARG,
+                    std::string(who) + ": term kinds are NLF_F_POW or NLF_F_EXP");
+}
+
 nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const double* fparam,
                             const void* const* A_dev, int64_t lda, int32_t nz, const double* z,
                             void* T64_dev, void* T32_dev, int64_t ldt, int64_t strideT, void* stream) {
@@ -1168,6 +1199,7 @@ nlfeast_status nlf_assemble(int64_t n, int32_t J, const int32_t* fkind, const do
         NLF_REQUIRE(n > 0 && J >= 1 && J <= 8 && fkind && fparam && A_dev && lda >= n && nz >= 1 && z &&
                         (T64_dev || T32_dev) && ldt >= n && strideT >= ldt * n,
                     NLF_ERR_ARG, "nlf_assemble: bad arguments");
+        require_builtin_kinds(J, fkind, "nlf_assemble");
         std::vector<cplx> coef((size_t)nz * J);
         for (int k = 0; k < nz; ++k)
             for (int j = 0; j < J; ++j)
@@ -1362,6 +1394,7 @@ nlfeast_status nlf_block_residual(int64_t n, int32_t m, int32_t J, const int32_t
         NLF_REQUIRE(n > 0 && m >= 1 && J >= 1 && J <= 8 && fkind && fparam && A_dev && lda >= n && X_dev &&
                         ldx >= n && lambda && R_dev && ldr >= n && norms_dev && ws_dev,
                     NLF_ERR_ARG, "nlf_block_residual: bad arguments");
+        require_builtin_kinds(J, fkind, "nlf_block_residual");
         hipStream_t s = as_stream(stream);
         z128* XF = (z128*)ws_dev;     // X f_j(Lambda), one term at a time
         std::vector<cplx> f((size_t)m);
@@ -1474,28 +1507,66 @@ nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_
     })
 }
 
+// Shared body of nlf_reduced_solve and nlf_reduced_solve_ex.
+static void reduced_solve_c(int32_t m, int32_t J, const int32_t* fkind, const double* fparam, const UserFunction* uf,
+                            int32_t method, const double* Ahat, double cre, double cim, double a, double b,
+                            int32_t m_keep, const double* avoid, int32_t n_avoid, double* lambda_out, double* Y_out,
+                            int32_t* found_out, const char* who) {
+    NLF_REQUIRE(m >= 1 && J >= 1 && J <= 8 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
+                    lambda_out && Y_out && (method == 0 || method == 1),
+                NLF_ERR_ARG, std::string(who) + ": bad arguments");
+    std::vector<Term> terms(J);
+    bool user = false;
+    for (int j = 0; j < J; ++j) {
+        NLF_REQUIRE(fkind[j] == NLF_F_POW || fkind[j] == NLF_F_EXP || (uf && fkind[j] == NLF_F_USER), NLF_ERR_ARG,
+                    std::string(who) + ": bad term kind");
+        terms[j] = Term{fkind[j], fparam[j], fkind[j] == NLF_F_USER ? uf : nullptr, j};
+        user = user || fkind[j] == NLF_F_USER;
+    }
+    NLF_REQUIRE(!user || uf->fn, NLF_ERR_ARG, std::string(who) + ": NLF_F_USER terms need a function");
+    bool poly = true;
+    for (const Term& t : terms) poly = poly && t.kind == NLF_F_POW;
+    NLF_REQUIRE(!(user || (method == 1 && !poly)) || m_keep <= m, NLF_ERR_ARG,
+                std::string(who) + ": the contour-integral solve needs m_keep <= m");
+    std::vector<cplx> av;
+    for (int i = 0; avoid && i < n_avoid; ++i) av.push_back(cplx(avoid[2 * i], avoid[2 * i + 1]));
+    ReducedResult rr = reduced_solve(m, terms, (const cplx*)Ahat, Ellipse{cplx(cre, cim), a, b}, m_keep,
+                                     av.empty() ? nullptr : &av, method);
+    NLF_REQUIRE(!user_failed(terms), NLF_ERR_ARG, std::string(who) + ": the user function reported an error");
+    NLF_REQUIRE(rr.ok, NLF_ERR_DEVICE, std::string(who) + ": eigen-decomposition failed");
+    const int keep = (int)rr.lambda.size();
+    for (int q = 0; q < keep; ++q) {
+        lambda_out[2 * q] = rr.lambda[q].real();
+        lambda_out[2 * q + 1] = rr.lambda[q].imag();
+        if (found_out) found_out[q] = rr.found[q];
+    }
+    std::memcpy(Y_out, rr.Y.data(), sizeof(cplx) * rr.Y.size());
+}
+
 nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind, const double* fparam,
                                  const double* Ahat, double cre, double cim, double a, double b,
                                  int32_t m_keep, const double* avoid, int32_t n_avoid,
                                  double* lambda_out, double* Y_out) {
     nlfeast_ctx* h = nullptr;
     NLF_TRY(h, {
-        NLF_REQUIRE(m >= 1 && J >= 1 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
-                        lambda_out && Y_out,
-                    NLF_ERR_ARG, "nlf_reduced_solve: bad arguments");
-        std::vector<Term> terms(J);
-        for (int j = 0; j < J; ++j) terms[j] = Term{fkind[j], fparam[j]};
-        std::vector<cplx> av;
-        for (int i = 0; avoid && i < n_avoid; ++i) av.push_back(cplx(avoid[2 * i], avoid[2 * i + 1]));
-        ReducedResult rr = reduced_solve(m, terms, (const cplx*)Ahat, Ellipse{cplx(cre, cim), a, b}, m_keep,
-                                         av.empty() ? nullptr : &av);
-        NLF_REQUIRE(rr.ok, NLF_ERR_DEVICE, "nlf_reduced_solve: eigen-decomposition failed");
-        const int keep = (int)rr.lambda.size();
-        for (int q = 0; q < keep; ++q) {
-            lambda_out[2 * q] = rr.lambda[q].real();
-            lambda_out[2 * q + 1] = rr.lambda[q].imag();
-        }
-        std::memcpy(Y_out, rr.Y.data(), sizeof(cplx) * rr.Y.size());
+        reduced_solve_c(m, J, fkind, fparam, nullptr, 0, Ahat, cre, cim, a, b, m_keep, avoid, n_avoid, lambda_out,
+                        Y_out, nullptr, "nlf_reduced_solve");
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_reduced_solve_ex(int32_t m, int32_t J, const int32_t* fkind, const double* fparam,
+                                    nlfeast_user_fn fn, void* user, int32_t method, const double* Ahat,
+                                    double cre, double cim, double a, double b, int32_t m_keep,
+                                    const double* avoid, int32_t n_avoid, double* lambda_out, double* Y_out,
+                                    int32_t* found_out) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        UserFunction uf;
+        uf.fn = fn;
+        uf.user = user;
+        reduced_solve_c(m, J, fkind, fparam, &uf, method, Ahat, cre, cim, a, b, m_keep, avoid, n_avoid, lambda_out,
+                        Y_out, found_out, "nlf_reduced_solve_ex");
         return NLF_OK;
     })
 }

@@ -34,6 +34,9 @@ Recipes (contour seed 3000 + id):
               radius at the gap midpoint, rejected under a 1% gap; the nearest p + 2 sharpened
               by two steps of two-sided Rayleigh functional iteration on T itself.  delay512
               also stores the winding number of det T along the circle.
+  rational300 A0 - l I + l/(l - sigma) C: all 2n companion eigenvalues of the quadratic
+              (l - sigma) T(l); centre = a seeded pick among them with |c| <= 0.9; radius =
+              midpoint between the 12th and 13th distances, rejected under a 5% gap.
 """
 import json
 import os
@@ -146,6 +149,33 @@ def quartic1024():
                               eigenvalues=[[v.real, v.imag] for v in inside])])
 
 
+def rational300():
+    """Brute force for the rational problem A0 - l I + l/(l - sigma) C: multiplied by
+    (l - sigma) it is the quadratic -l^2 I + l (A0 + sigma I + C) - sigma A0 (no eigenvalue at
+    sigma while C is non-singular), whose 2n companion eigenvalues are the truth.  The centre is
+    a seeded eigenvalue of the cluster around the unit disk (away from the pole's cluster)."""
+    cfg = wl.CONFIGS["rational300"]
+    terms, mats = wl.make_problem("rational300")
+    n, sig = cfg["n"], terms[2][1]
+    A0, _, Cm = mats
+    quad = pb.Problem([("pow", 2), ("pow", 1), ("pow", 0)], [-np.eye(n), A0 + sig * np.eye(n) + Cm, -sig * A0])
+    full = brute.companion_eigs(quad)
+    rng = np.random.default_rng(3000 + cfg["id"])
+    k = cfg["inside"]
+    while True:
+        c = full[rng.integers(len(full))]
+        if abs(c) > 0.9:
+            continue
+        _, r, gap = ring(full, c, k)
+        if gap >= 0.05:
+            break
+    inside = full[np.abs(full - c) < r]
+    res = [np.linalg.norm(np.linalg.svd(quad.T(v), compute_uv=False)[-1:]) for v in inside]
+    return dict(regions=[dict(centre=[c.real, c.imag], radius=r, gap=gap, pole=sig,
+                              max_smallest_singular_value=float(max(res)),
+                              eigenvalues=[[v.real, v.imag] for v in inside])])
+
+
 def delay(name, rho):
     cfg = wl.CONFIGS[name]
     terms, mats = wl.make_problem(name)
@@ -185,7 +215,8 @@ def delay(name, rho):
 
 
 RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8, "quartic1024": quartic1024,
-           "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.15)}
+           "delay512": lambda: delay("delay512", 0.4), "delay8192": lambda: delay("delay8192", 0.15),
+           "rational300": rational300}
 
 
 def main(names):

@@ -86,3 +86,82 @@ def test_argument_errors_are_reported(lib):
     assert e.value.status == nl.NLF_ERR_ARG
     with pytest.raises(nl.NLFError):
         nl.nlf_reduced_solve(wl.QUADRATIC, [np.eye(3)] * 3, 0.0, 1.0, 0.0, 2)
+
+
+# ---- the contour-integral reduced solve (caller-supplied functions), host side
+
+def _exp_fn():
+    return nl.user_function(lambda j, p, z, d: (np.exp(-p * z), -p * np.exp(-p * z) if d else None))
+
+
+def _pow_fn():
+    """Every term handed over as a caller function z -> z^p."""
+    def f(j, p, z, d):
+        q = int(p)
+        return z ** q, (q * z ** (q - 1) if q > 0 else np.zeros_like(z)) if d else None
+    return nl.user_function(f)
+
+
+def _oracle_exp(tau):
+    from oracle import problem as pb
+    return pb.ScalarFunction(lambda z: np.exp(-tau * z), lambda z: -tau * np.exp(-tau * z), "exp")
+
+
+@pytest.mark.parametrize("route", ["user", "forced"])
+@pytest.mark.parametrize("shape,m,seed", [((0.2 + 0.1j, 0.6, 0.6), 12, 41), ((-0.1 + 0.3j, 0.7, 0.3), 30, 42)])
+def test_contour_reduced_matches_oracle(lib, route, shape, m, seed):
+    """Library (pivoted QR of the Hankel matrix) and oracle (SVD) on the same reduced delay
+    problem: the same eigenvalues well inside the enlarged ellipse, each a null vector."""
+    rng = np.random.default_rng(seed)
+    A = [np.eye(m, dtype=complex), wl.cn(rng, (m, m)) / np.sqrt(m), wl.cn(rng, (m, m)) / np.sqrt(m),
+         0.3 * wl.cn(rng, (m, m)) / np.sqrt(m)]
+    C = qd.Contour(*shape)
+    if route == "user":
+        terms, fn, method = [("pow", 2), ("pow", 1), ("pow", 0), ("fn", 1.0)], _exp_fn(), 0
+    else:
+        terms, fn, method = wl.DELAY, None, 1
+    lam, Y, found = nl.nlf_reduced_solve_ex(terms, A, C.c, C.a, C.b, m, fn=fn, method=method)
+    lam0, _, found0 = reduced.contour_reduced(wl.DELAY[:3] + [("fn", _oracle_exp(1.0))], A, C, m)
+    well = lambda l: l[C.radius(l) < 1.2]
+    a, b = np.sort_complex(well(lam[found])), np.sort_complex(well(lam0[found0]))
+    assert len(a) == len(b) >= 3
+    assert np.max(np.abs(a - b)) < 1e-12
+    for l, y in zip(lam[found], Y[:, found].T):
+        if C.radius(l) < 1.2:
+            T = sum(f * Aj for f, Aj in zip([l * l, l, 1.0, np.exp(-l)], A))
+            assert np.linalg.norm(T @ y) < 1e-12 * np.linalg.norm(T)
+    assert np.linalg.norm(np.linalg.norm(Y, axis=0) - 1) < 1e-12
+
+
+def test_contour_reduced_completion(lib):
+    """lambda I - diag(d) through caller functions: three eigenvalues inside the enlarged
+    circle are found (e_i vectors), seven completing pairs sit on the enlarged circle with
+    vectors orthogonal to everything before them."""
+    m = 10
+    d = np.array([0.1, -0.5j, 0.9 + 0.3j, 3.0, -4.0, 5j, 2.5 + 2.5j, -3 - 3j, 6.0, 7.0])
+    A = [np.eye(m, dtype=complex), -np.diag(d)]
+    C = qd.Contour(0.0, 1.0)
+    lam, Y, found = nl.nlf_reduced_solve_ex([("fn", 1), ("fn", 0)], A, C.c, C.a, C.b, m, fn=_pow_fn())
+    assert found.sum() == 3 and found[:3].all()
+    assert np.max(np.abs(np.sort_complex(lam[:3]) - np.sort_complex(d[:3]))) < 1e-13
+    assert np.allclose(C.radius(lam[3:]), 1.5)
+    assert np.allclose(Y.conj().T @ Y, np.eye(m), atol=1e-12)
+
+
+def test_user_function_errors(lib):
+    A = [np.eye(4, dtype=complex), -np.diag([0.1, 0.2, 3.0, 4.0])]
+    C = qd.Contour(0.0, 1.0)
+    def boom(j, p, z, d):
+        raise ValueError("no")
+    with pytest.raises(nl.NLFError) as e:
+        nl.nlf_reduced_solve_ex([("fn", 1), ("pow", 0)], A, C.c, C.a, C.b, 4, fn=nl.user_function(boom))
+    assert e.value.status == nl.NLF_ERR_ARG
+    with pytest.raises(nl.NLFError) as e:        # a user term with no function
+        nl.nlf_reduced_solve_ex([("fn", 1), ("pow", 0)], A, C.c, C.a, C.b, 4)
+    assert e.value.status == nl.NLF_ERR_ARG
+    with pytest.raises(nl.NLFError) as e:        # the plain entry point takes built-in kinds only
+        nl.nlf_reduced_solve([("fn", 1), ("pow", 0)], A, C.c, C.a, C.b, 4)
+    assert e.value.status == nl.NLF_ERR_ARG
+    with pytest.raises(nl.NLFError) as e:        # the contour solve completes to at most m pairs
+        nl.nlf_reduced_solve_ex([("fn", 1), ("pow", 0)], A, C.c, C.a, C.b, 5, fn=_pow_fn())
+    assert e.value.status == nl.NLF_ERR_ARG

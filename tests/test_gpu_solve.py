@@ -41,9 +41,11 @@ def match_err(a, b, scale):
     return float(cost[r, c].max())
 
 
-def gpu_solve(terms, mats, regions, X0, opts, quad_rule=nl.NLF_QUAD_GAUSS_LEGENDRE):
+def gpu_solve(terms, mats, regions, X0, opts, quad_rule=nl.NLF_QUAD_GAUSS_LEGENDRE, user_fn=None):
     S = nl.NLFEAST(mats[0].shape[0])
     S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+    if user_fn is not None:
+        S.set_user_function(user_fn)
     S.set_contour(regions, quad_rule=quad_rule)
     out = S.solve(opts, None if X0 is None else nl.to_colmajor(X0))
     torch.cuda.synchronize()
@@ -471,3 +473,97 @@ def test_delay8192_full_size(prec, tol_eig):
     assert np.max(out["res"][ins]) <= cfg["tol"]
     hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
     assert np.max(hr) <= 2 * cfg["tol"]
+
+
+# ---- caller-supplied functions: the contour-integral reduced solve on the GPU path
+
+def _pole_fn(j, sigma, z, want_deriv):
+    return wl.pole_value(z, sigma), (wl.pole_deriv(z, sigma) if want_deriv else None)
+
+
+def _exp_fn(j, tau, z, want_deriv):
+    e = np.exp(-tau * z)
+    return e, (-tau * e if want_deriv else None)
+
+
+@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
+def test_rational300_user_function_matches_brute_force(prec, tol_eig):
+    # A0 - l I + l/(l - 4) C with the pole term supplied as a caller function: the 12
+    # eigenvalues inside the stored circle are the brute-force companion eigenvalues of the
+    # quadratic (l - 4) T(l); the oracle (contour-integral reading too) agrees
+    cfg = wl.CONFIGS["rational300"]
+    terms, mats = wl.make_problem("rational300")
+    g = contours("rational300")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
+                    nl.options(tol=cfg["tol"], precision=prec), user_fn=_pole_fn)
+    assert out["status"] == nl.NLF_OK
+    ins = converged(out, cfg["tol"])
+    assert ins.sum() == len(ref) == 12 and out["m"][0] == 12
+    assert match_err(out["lam"][ins], ref, r) < tol_eig
+    sig = terms[2][1]
+    P = pb.Problem([terms[0], terms[1], ("fn", pb.ScalarFunction(lambda z: wl.pole_value(z, sig),
+                                                                 lambda z: wl.pole_deriv(z, sig)))], mats)
+    hr = np.linalg.norm(P.block_residual(out["Xh"][:, ins], out["lam"][ins]), axis=0)
+    assert np.max(hr) <= 2 * cfg["tol"]
+    C = qd.Contour(c, r)
+    z, w = qd.nodes_weights(C, cfg["nc"])
+    ro = onl.solve(P, C, z, w, X0, cfg["m0"], cfg["tol"])
+    assert ro.converged
+    assert match_err(out["lam"][ins], ro.eigenvalues, r) < tol_eig
+
+
+@pytest.mark.parametrize("route", ["user", "forced"])
+def test_delay512_contour_reduced_solve(route):
+    # the delay problem with Steps 1-2 by the contour-integral solve: the exponential handed
+    # over as a caller function, or kept built in with reduced_solver = 1; same eigenvalues as
+    # the stored (surrogate + Rayleigh-refined, winding-certified) reference
+    cfg = wl.CONFIGS["delay512"]
+    terms, mats = wl.make_problem("delay512")
+    g = contours("delay512")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
+    if route == "user":
+        t = [(k, p) if k != "exp" else ("fn", p) for k, p in terms]
+        out = gpu_solve(t, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
+                        nl.options(tol=cfg["tol"]), user_fn=_exp_fn)
+    else:
+        out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
+                        nl.options(tol=cfg["tol"], reduced_solver=1))
+    assert out["status"] == nl.NLF_OK
+    ins = converged(out, cfg["tol"])
+    assert ins.sum() == len(ref) == cfg["inside"]
+    assert match_err(out["lam"][ins], ref, r) < 1e-10
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+
+
+def test_user_function_status_codes():
+    # a term of kind 'fn' without a function is a state error; a function that fails is an
+    # argument error; both are detected on the host before any launch
+    terms, mats = wl.make_problem("rational300")
+    g = contours("rational300")[0]
+    region = [dict(centre=complex(*g["centre"]), a=g["radius"], nc=8, m0=24)]
+    S = nl.NLFEAST(mats[0].shape[0])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour(region)
+        with pytest.raises(nl.NLFError) as e:
+            S.solve(nl.options())
+        assert e.value.status == nl.NLF_ERR_STATE
+
+        def broken(j, p, z, d):
+            raise RuntimeError("not defined here")
+        S.set_user_function(broken)
+        with pytest.raises(nl.NLFError) as e:
+            S.solve(nl.options())
+        assert e.value.status == nl.NLF_ERR_ARG
+        S.set_user_function(_pole_fn)
+        out = S.solve(nl.options(tol=1e-11))
+        assert out["status"] == nl.NLF_OK and out["m"][0] == 12
+    finally:
+        torch.cuda.synchronize()
+        S.close()
