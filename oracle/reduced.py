@@ -165,7 +165,7 @@ def select(lam, contour, m0):
 
 CONTOUR_SCALE = 1.5      # enlargement of C for the reduced contour-integral solve
 CONTOUR_POINTS = 96      # trapezoid points on the enlarged ellipse
-CONTOUR_RANK_TOL = 1e-10  # singular values below this fraction of the largest are noise
+CONTOUR_RANK_TOL = 1e-10  # singular values below this fraction of the integrand's size are noise
 
 
 def contour_eigs(terms, Ahat, contour, scale=CONTOUR_SCALE, npts=CONTOUR_POINTS,
@@ -177,13 +177,16 @@ def contour_eigs(terms, Ahat, contour, scale=CONTOUR_SCALE, npts=CONTOUR_POINTS,
     V mu(Lambda)^p W^H; the Hankel matrices H0 = [M_{i+j}], H1 = [M_{i+j+1}] then factor as
     Vb W^H and Vb mu(Lambda) W^H with Vb = [V; V mu; ...], and the SVD H0 = U S Z^H gives
     U^H H1 Z S^{-1} = (U^H Vb) mu(Lambda) (U^H Vb)^{-1}.  Returns (lam, Y), Y with unit columns
-    (the first block of U s_i)."""
+    (the first block of U s_i).  The numerical rank counts the singular values above
+    rank_tol times the size of the integrand, sum_q |w_q| ||T^{-1}(z_q)||_F (with no eigenvalue
+    inside, the moments are rounding noise of that size times the machine epsilon)."""
     m = Ahat[0].shape[0]
     c = complex(contour.c)
     a, b = contour.a * scale, contour.b * scale
     L = max(a, b)
     K_max = 3
     M = [np.zeros((m, m), dtype=complex) for _ in range(2 * K_max)]
+    size = 0.0
     for q in range(npts):
         th = 2.0 * np.pi * (q + 0.5) / npts
         z = c + a * np.cos(th) + 1j * b * np.sin(th)
@@ -191,13 +194,14 @@ def contour_eigs(terms, Ahat, contour, scale=CONTOUR_SCALE, npts=CONTOUR_POINTS,
         w = dz / (1j * npts)                 # (1/2 pi i) dz/dtheta (2 pi / npts)
         mu = (z - c) / L
         Tinv = np.linalg.solve(reduced_T(terms, Ahat, z), np.eye(m))
+        size += abs(w) * np.linalg.norm(Tinv)
         for p in range(2 * K_max):
             M[p] += (w * mu ** p) * Tinv
     for K in (2, 3):
         H0 = np.block([[M[i + j] for j in range(K)] for i in range(K)])
         H1 = np.block([[M[i + j + 1] for j in range(K)] for i in range(K)])
         U, sv, Zh = np.linalg.svd(H0)
-        k = int(np.sum(sv > rank_tol * sv[0])) if sv[0] > 0 else 0
+        k = int(np.sum(sv > rank_tol * size))
         if k < K * m:
             break
     else:
