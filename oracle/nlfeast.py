@@ -147,6 +147,37 @@ def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
         it += 1
 
 
+def adjoint_problem(problem):
+    """S(mu) = T(conj mu)^H = sum_j conj(f_j(conj mu)) A_j^H: y^H T(lambda) = 0 (the left
+    eigenvectors of Sec. 2 eq. NLEVP) is S(conj lambda) y = 0.  For 'pow' and 'exp' terms,
+    whose parameters are real, conj(f(conj mu)) = f(mu)."""
+    from .problem import Problem, ScalarFunction
+    terms = []
+    for k, p in problem.terms:
+        if k == "fn":
+            terms.append(("fn", ScalarFunction(lambda mu, F=p: np.conj(F.f(np.conj(mu))),
+                                               lambda mu, F=p: np.conj(F.df(np.conj(mu))),
+                                               "adjoint of %s" % p.name)))
+        else:
+            terms.append((k, p))
+    return Problem(terms, [A.conj().T for A in problem.mats])
+
+
+def solve_left(problem, contour, nc, Y0, m0, tol, rule="gauss", max_iter=50, reduced="auto",
+               verbose=False):
+    """Left eigenpairs of T inside C: Algorithm 1 applied to the adjoint function S on the
+    conjugate contour, with that contour's own quadrature, and the eigenvalues conjugated back
+    (so they are T's).  Returns a Result whose X holds the left eigenvectors y (unit norm),
+    res the values ||T(lambda_i)^H y_i||."""
+    from .quadrature import Contour, nodes_weights
+    Cc = Contour(np.conj(contour.c), contour.a, contour.b)
+    z, w = nodes_weights(Cc, nc, rule)
+    r = solve(adjoint_problem(problem), Cc, z, w, Y0, m0, tol, max_iter=max_iter, verbose=verbose,
+              reduced=reduced)
+    r.lam = np.conj(r.lam)
+    return r
+
+
 def timed_solve(*args, **kw):
     t0 = time.perf_counter()
     r = solve(*args, **kw)

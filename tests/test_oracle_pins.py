@@ -468,3 +468,74 @@ def test_contour_reading_rational_matches_brute_force():
     res = nlfeast.solve(P, C, z, w, wl.initial_block(n, 20, 2008), 20, 1e-11)
     assert res.converged and res.inside.sum() == len(truth) == 10
     assert match_error(res.eigenvalues, truth, r) < 1e-11
+
+
+# ---- left eigenvectors (eigentriples): Algorithm 1 on the adjoint function
+
+def test_left_solve_matches_brute_force_left_null_vectors():
+    """Random quadratic problem: the left solve returns the same eigenvalues as the right solve
+    and the companion, and each y spans the left null space of T(lambda) (the left singular
+    vector of its smallest singular value, by an independent SVD); every simple eigenvalue has
+    y^H T'(lambda) x != 0."""
+    n, m0 = 60, 14
+    terms, mats = wl.random_qep(n, 77)
+    P = pb.Problem(terms, mats)
+    lam = brute.companion_eigs(P)
+    c = lam[np.argmin(np.abs(lam - 0.3j))]
+    d = np.sort(np.abs(lam - c))
+    r = 0.5 * (d[7] + d[8])
+    assert (d[8] - d[7]) / d[8] > 0.02
+    C = qd.Contour(c, r)
+    z, w = qd.nodes_weights(C, 16)
+    right = nlfeast.solve(P, C, z, w, wl.initial_block(n, m0, 78), m0, 1e-12)
+    left = nlfeast.solve_left(P, C, 16, wl.initial_block(n, m0, 79), m0, 1e-12)
+    truth = lam[np.abs(lam - c) < r]
+    # spurious Ritz values inside (reading of the stop rule) occur on both sides here; the
+    # converged sets are compared
+    good = left.inside & ~left.spurious
+    assert left.converged and good.sum() == len(truth) == 8
+    assert match_error(left.eigenvalues, truth, r) < 1e-11
+    assert match_error(left.eigenvalues, right.eigenvalues, r) < 1e-11
+    for l, y in zip(left.lam[good], left.X[:, good].T):
+        T = P.T(l)
+        U, sv, _ = np.linalg.svd(T)
+        assert sv[-1] < 1e-11 * sv[0] and sv[-2] > 1e-6 * sv[0]
+        assert abs(abs(np.vdot(U[:, -1], y)) - 1.0) < 1e-10
+        assert np.linalg.norm(y.conj() @ T) < 1e-12 * sv[0]
+        i = np.argmin(np.abs(right.lam - l))
+        assert abs(np.vdot(y, P.dT(l) @ right.X[:, i])) > 1e-6
+
+
+def test_left_vectors_of_a_real_symmetric_problem_are_conjugate_right_vectors():
+    """Example 2's A_j are real symmetric, so T(lambda)^T = T(lambda) and y = conj(x) up to a
+    phase (Sec. 5: the right and left eigenvectors coincide for real A_j)."""
+    n = 50
+    terms, mats = wl.mass_spring(n, 10.0, 5.0)
+    P = pb.Problem(terms, mats)
+    C = qd.Contour(-20.5, 9.5)
+    right = nlfeast.solve(P, C, *qd.nodes_weights(C, 8), wl.initial_block(n, 25, 5), 25, 1e-10)
+    left = nlfeast.solve_left(P, C, 8, wl.initial_block(n, 25, 6), 25, 1e-10)
+    good = left.inside & ~left.spurious
+    assert good.sum() == len(right.eigenvalues) == 19
+    for l, y in zip(left.lam[good], left.X[:, good].T):
+        i = np.argmin(np.abs(right.lam - l))
+        assert abs(right.lam[i] - l) < 1e-10 * abs(l)
+        assert abs(abs(np.vdot(right.X[:, i].conj(), y)) - 1.0) < 1e-9
+
+
+def test_left_solve_of_a_user_function_problem():
+    """The adjoint of a caller-supplied term is conj(f(conj mu)): the rational problem's left
+    eigenvectors annihilate T(lambda) from the left."""
+    n = 80
+    terms, mats = wl.rational_nep(n, 1008)
+    sig = terms[2][1]
+    F = pb.ScalarFunction(lambda z: wl.pole_value(z, sig), lambda z: wl.pole_deriv(z, sig), "pole")
+    P = pb.Problem([terms[0], terms[1], ("fn", F)], mats)
+    C = qd.Contour(-0.3 + 0.4j, 0.35)
+    left = nlfeast.solve_left(P, C, 16, wl.initial_block(n, 16, 7), 16, 1e-12)
+    right = nlfeast.solve(P, C, *qd.nodes_weights(C, 16), wl.initial_block(n, 16, 8), 16, 1e-12)
+    good = left.inside & ~left.spurious
+    assert left.converged and good.sum() == len(right.eigenvalues) >= 3
+    assert match_error(left.eigenvalues, right.eigenvalues, C.a) < 1e-11
+    for l, y in zip(left.lam[good], left.X[:, good].T):
+        assert np.linalg.norm(y.conj() @ P.T(l)) < 1e-11
