@@ -175,6 +175,21 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                              double* lambda_out, double* resid_out, int32_t* inside_out,
                              int32_t* m_out, int32_t* iters_out);
 
+/* Left eigenvectors (Sec. 2 eq. NLEVP: y^* T(lambda) = 0; (lambda, x, y) an eigentriple):
+ * Algorithm 1 applied to the adjoint function S(mu) = T(conj mu)^H = sum_j conj(f_j(conj mu))
+ * A_j^H on the conjugate of every contour, whose eigenpairs (conj lambda, y) are the left
+ * eigenpairs of T.  The quadrature nodes of the conjugate contour are conj z_k with weights
+ * conj omega_k, and S(conj z_k) = T(z_k)^H, so the cached LU factors of T(z_k) serve through
+ * adjoint triangular solves (U^H, then L^H, then the row permutation); the factorisation is
+ * done here first when no valid one is cached.  Arguments and statuses as nlfeast_solve, with
+ * Y0_dev the initial blocks (or NULL), Y_dev_out the left eigenvectors y (unit 2-norm),
+ * lambda_out the eigenvalues of T (conjugated back, so they match nlfeast_solve's), resid_out
+ * ||T(lambda_i)^H y_i||_2 and inside_out relative to the caller's contours. */
+nlfeast_status nlfeast_solve_left(nlfeast_handle h, const nlfeast_options* opt, void* ws_dev,
+                                  size_t ws_bytes, const void* Y0_dev, void* Y_dev_out,
+                                  double* lambda_out, double* resid_out, int32_t* inside_out,
+                                  int32_t* m_out, int32_t* iters_out);
+
 /* Per-kernel-class device time of the last solve, measured with HIP events on the solve's
  * stream when profiling is on (nlfeast_set_profiling).  For class c (see nlfeast_kernel_class):
  * launches[c], milliseconds[c], and the algorithmic flops[c] / bytes[c] of those launches. */
@@ -263,6 +278,18 @@ nlfeast_status nlf_getrs_batched_inv(int32_t dtype, int64_t n, int32_t nrhs, int
                                      const int32_t* perm_dev, const void* dinv_dev,
                                      const void* B_dev, int64_t ldb, int64_t strideB, void* X_dev,
                                      int64_t ldx, int64_t strideX, void* tmp_dev, void* stream);
+
+/* As nlf_getrs_batched_inv for the conjugate-transposed matrices: X_b = A_b^{-H} B_b from the
+ * same factors and inverses (the solves of the adjoint problem behind nlfeast_solve_left).
+ * Z_dev: scratch of the same dtype, n x nrhs per matrix (ld n, stride n * nrhs); it may be B_dev
+ * when B has exactly that layout (B is then overwritten); X_dev must not overlap Z_dev
+ * (NLF_ERR_ARG). */
+nlfeast_status nlf_getrs_batched_inv_adjoint(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                             const void* LU_dev, int64_t lda, int64_t strideA,
+                                             const int32_t* perm_dev, const void* dinv_dev,
+                                             const void* B_dev, int64_t ldb, int64_t strideB,
+                                             void* Z_dev, void* X_dev, int64_t ldx, int64_t strideX,
+                                             void* tmp_dev, void* stream);
 
 /* C_b = alpha op(A_b) op(B_b) + beta C_b, complex (dtype c128 or c64), op 'N' or 'C'
  * (conjugate transpose); alpha, beta: 2 doubles each (host).  The MFMA GEMM used by every

@@ -130,6 +130,10 @@ _SIGS = {
     "nlf_reduced_solve": (c_i32, [c_i32, c_i32, P_i32, P_dbl, P_dbl, c_dbl, c_dbl, c_dbl, c_dbl,
                                   c_i32, P_dbl, c_i32, P_dbl, P_dbl]),
     "nlfeast_set_user_function": (c_i32, [c_vp, USER_FN, c_vp]),
+    "nlfeast_solve_left": (c_i32, [c_vp, ctypes.POINTER(Options), c_vp, ctypes.c_size_t, c_vp, c_vp,
+                                   P_dbl, P_dbl, P_i32, P_i32, P_i32]),
+    "nlf_getrs_batched_inv_adjoint": (c_i32, [c_i32, c_i64, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp,
+                                              c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_i64, c_vp, c_vp]),
     "nlf_reduced_solve_ex": (c_i32, [c_i32, c_i32, P_i32, P_dbl, USER_FN, c_vp, c_i32, P_dbl, c_dbl,
                                      c_dbl, c_dbl, c_dbl, c_i32, P_dbl, c_i32, P_dbl, P_dbl, P_i32]),
 }
@@ -271,10 +275,11 @@ def nlfeast_get_profile(h):
             for i, c in enumerate(KERNEL_CLASSES)}
 
 
-def nlfeast_solve(h, opts, ws, n, m_total, nreg, X0=None, X_out=None):
+def nlfeast_solve(h, opts, ws, n, m_total, nreg, X0=None, X_out=None, left=False):
     """Runs Algorithm 1 on every region.  ws: device tensor of at least workspace_size bytes;
     X0: column-major device tensor (sum m0, n) or None.  Returns a dict with status,
-    lam (complex), res, inside (bool), m and iters per region, and X (device tensor)."""
+    lam (complex), res, inside (bool), m and iters per region, and X (device tensor).
+    left=True calls nlfeast_solve_left: X then holds the left eigenvectors."""
     import torch
     if X_out is None:
         X_out = torch.empty((m_total, n), dtype=torch.complex128, device=ws.device)
@@ -283,10 +288,11 @@ def nlfeast_solve(h, opts, ws, n, m_total, nreg, X0=None, X_out=None):
     ins = np.zeros(m_total, dtype=np.int32)
     mo = np.zeros(nreg, dtype=np.int32)
     it = np.zeros(nreg, dtype=np.int32)
-    st = lib().nlfeast_solve(h, ctypes.byref(opts), _ptr(ws), ws.numel() * ws.element_size(),
-                             _ptr(X0), _ptr(X_out), lam.ctypes.data_as(P_dbl),
-                             res.ctypes.data_as(P_dbl), ins.ctypes.data_as(P_i32),
-                             mo.ctypes.data_as(P_i32), it.ctypes.data_as(P_i32))
+    fn = lib().nlfeast_solve_left if left else lib().nlfeast_solve
+    st = fn(h, ctypes.byref(opts), _ptr(ws), ws.numel() * ws.element_size(),
+            _ptr(X0), _ptr(X_out), lam.ctypes.data_as(P_dbl),
+            res.ctypes.data_as(P_dbl), ins.ctypes.data_as(P_i32),
+            mo.ctypes.data_as(P_i32), it.ctypes.data_as(P_i32))
     if st not in (NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL):
         _check(st, h)
     return dict(status=st, lam=lam[0::2] + 1j * lam[1::2], res=res, inside=ins.astype(bool),
@@ -357,6 +363,19 @@ def nlf_getrs_batched_inv(LU, perm, dinv, B, X, tmp, shared_rhs=False, stream=No
     _check(lib().nlf_getrs_batched_inv(dtype, n, nrhs, batch, _ptr(LU), n, n * n, _ptr(perm),
                                        _ptr(dinv), _ptr(B), n, sB, _ptr(X), n, n * nrhs, _ptr(tmp),
                                        _stream(stream)))
+
+
+def nlf_getrs_batched_inv_adjoint(LU, perm, dinv, B, Z, X, tmp, shared_rhs=False, stream=None):
+    """X_b = A_b^{-H} B_b from the factors; Z: scratch shaped like X (may be B when B is not
+    shared)."""
+    import torch
+    dtype = NLF_C128 if LU.dtype == torch.complex128 else NLF_C64
+    batch, n = LU.shape[0], LU.shape[-1]
+    nrhs = X.shape[-2]
+    sB = 0 if shared_rhs else n * nrhs
+    _check(lib().nlf_getrs_batched_inv_adjoint(dtype, n, nrhs, batch, _ptr(LU), n, n * n, _ptr(perm),
+                                               _ptr(dinv), _ptr(B), n, sB, _ptr(Z), _ptr(X), n, n * nrhs,
+                                               _ptr(tmp), _stream(stream)))
 
 
 def nlf_gemm_batched(opA, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch,
@@ -502,14 +521,16 @@ class NLFEAST:
         self._user_fn = user_function(py_fn)
         nlfeast_set_user_function(self.h, self._user_fn)
 
-    def solve(self, opts, X0=None):
+    def solve(self, opts, X0=None, left=False):
+        """Right eigenpairs (nlfeast_solve), or with left=True the left eigenvectors
+        (nlfeast_solve_left; X then holds y with y^H T(lambda) = 0)."""
         import torch
         need = nlfeast_workspace_size(self.h, opts)
         if self.ws is None or self.ws.numel() < need:
             self.ws = None
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         m_total = sum(r["m0"] for r in self.regions)
-        return nlfeast_solve(self.h, opts, self.ws, self.n, m_total, len(self.regions), X0)
+        return nlfeast_solve(self.h, opts, self.ws, self.n, m_total, len(self.regions), X0, left=left)
 
     def profile(self):
         return nlfeast_get_profile(self.h)

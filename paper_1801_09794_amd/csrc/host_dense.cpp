@@ -124,9 +124,20 @@ static void user_call(const Term& t, const cplx* z, int64_t count, cplx* f, cplx
         if (t.fn) t.fn->failed.store(1);
         return;
     }
+    std::vector<cplx> zc;
+    if (t.conj) {   // conj(f(conj z)) and its derivative conj(f'(conj z))
+        zc.assign(z, z + count);
+        for (cplx& v : zc) v = std::conj(v);
+        z = zc.data();
+    }
     if (t.fn->fn(t.fn->user, t.index, t.param, count, reinterpret_cast<const double*>(z),
                  reinterpret_cast<double*>(f), reinterpret_cast<double*>(df)) != 0)
         t.fn->failed.store(1);
+    if (t.conj)
+        for (int64_t i = 0; i < count; ++i) {
+            f[i] = std::conj(f[i]);
+            if (df) df[i] = std::conj(df[i]);
+        }
 }
 
 void term_values(const Term& t, const cplx* z, int64_t count, cplx* f) {

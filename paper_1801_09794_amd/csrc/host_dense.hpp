@@ -41,12 +41,15 @@ struct UserFunction {
 };
 
 // Term of T(lambda): kind 0 = lambda^p, kind 1 = exp(-tau lambda), kind 2 = the caller's
-// function fn, called with the term's position `index` and parameter.
+// function fn, called with the term's position `index` and parameter.  conj: the term of the
+// adjoint function T(conj mu)^H, i.e. conj(f(conj mu)) (the same function for kinds 0 and 1,
+// whose parameters are real).
 struct Term {
     int kind;
     double param;
     const UserFunction* fn = nullptr;
     int index = 0;
+    bool conj = false;
 };
 cplx term_value(const Term& t, cplx l);
 cplx term_deriv(const Term& t, cplx l);

@@ -68,6 +68,12 @@ template <typename R>
 void getrs_inv(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
                int64_t sA, const int32_t* perm, const Cx<R>* dinv, const Cx<R>* B, int64_t ldb,
                int64_t sB, Cx<R>* X, int64_t ldx, int64_t sX, Cx<R>* tmp);   // tmp: 256 x nrhs per matrix
+// X = A^{-H} B with the same factors (the solves of the adjoint problem): Z is n x nrhs scratch
+// per matrix (ld n, stride n * nrhs; may equal B with those strides), X must not overlap Z.
+template <typename R>
+void getrs_inv_adjoint(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+                       int64_t sA, const int32_t* perm, const Cx<R>* dinv, const Cx<R>* B, int64_t ldb,
+                       int64_t sB, Cx<R>* Z, Cx<R>* X, int64_t ldx, int64_t sX, Cx<R>* tmp);
 
 // In-place triangular solves B <- L^{-1} B (unit lower) and B <- U^{-1} B (upper).
 template <typename R>

@@ -501,6 +501,23 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(int64_t n, int64_t nco
     }
 }
 
+// X[perm[i]] = Z[i] per matrix: the row permutation P^T that ends a solve with (P A)^H.
+template <typename R>
+__global__ __launch_bounds__(256) void scatter_rows_kernel(int64_t n, int64_t ncols,
+                                                           const int32_t* perm, const Cx<R>* Z0,
+                                                           int64_t ldz, int64_t sZ, Cx<R>* X0,
+                                                           int64_t ldx, int64_t sX) {
+    const int64_t b = blockIdx.y;
+    const int32_t* p = perm + b * n;
+    const Cx<R>* Z = Z0 + b * sZ;
+    Cx<R>* X = X0 + b * sX;
+    const int64_t total = n * ncols;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % n, c = e / n;
+        X[p[i] + c * ldx] = Z[i + c * ldz];
+    }
+}
+
 // Identity in every s x s block of a strided set (the right-hand sides of the block inversion).
 template <typename R>
 __global__ __launch_bounds__(256) void identity_blocks_kernel(int64_t s, int64_t ld, int64_t count,
@@ -890,6 +907,71 @@ void getrs_inv(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, i
         }
     }
 }
+
+// X_b = A_b^{-H} B_b with the factors P A = L U and the block inverses: A^H = U^H L^H P, so
+// U^H V = B is solved forwards block by block (V_q = (U_qq^{-1})^H V_q, then the rows below
+// lose (U_{q, below})^H V_q), L^H W = V backwards (W_q = (L_qq^{-1})^H W_q, the rows above
+// lose (L_{q, above})^H W_q), and X = P^T W.  Every step is a batched MFMA GEMM on the
+// conjugate transpose of a stored block.  Z (n x nrhs per matrix, ld n, stride n * nrhs) holds
+// B and then W; Z == B (same strides) skips the copy; X must not overlap Z.
+template <typename R>
+void getrs_inv_adjoint(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
+                       int64_t sA, const int32_t* perm, const Cx<R>* dinv, const Cx<R>* B, int64_t ldb,
+                       int64_t sB, Cx<R>* Z, Cx<R>* X, int64_t ldx, int64_t sX, Cx<R>* tmp) {
+    if (n <= 0 || nrhs <= 0 || batch <= 0) return;
+    const int64_t NB = LU_INV_NB, nblk = ceil_div(n, NB), per = lu_inverse_elems(n);
+    const int64_t st = NB * nrhs, sZ = n * nrhs;
+    const Cx<R> one(1, 0), mone(-1, 0), zero(0, 0);
+    if (B != Z || ldb != n || sB != sZ) {
+        ProfScope ps(trsm_class(), s, 0, 2.0 * n * nrhs * sizeof(Cx<R>) * batch);
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(n * nrhs, 256), 2048), batch);
+        hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, n, (int64_t)nrhs, B, ldb, sB, Z, n, sZ);
+        NLF_HIP(hipGetLastError());
+    }
+    auto solve_block = [&](int64_t b, bool upper) {   // Z_b <- (D_bb^{-1})^H Z_b
+        const int64_t s0 = b * NB, sb = std::min<int64_t>(NB, n - s0);
+        const Cx<R>* Dinv = dinv + (2 * b + (upper ? 1 : 0)) * NB * NB;
+        ProfScope ps(trsm_class(), s, 8.0 * sb * sb * nrhs * batch, 0);
+        gemm<R>(s, true, sb, nrhs, sb, one, Dinv, NB, per, Z + s0, n, sZ, zero, tmp, NB, st, batch);
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(sb * nrhs, 256), 1024), batch);
+        hipLaunchKernelGGL((copy_batched_kernel<R>), grid, dim3(256), 0, s, sb, (int64_t)nrhs,
+                           (const Cx<R>*)tmp, NB, st, Z + s0, n, sZ);
+        NLF_HIP(hipGetLastError());
+    };
+    for (int64_t b = 0; b < nblk; ++b) {          // U^H V = B, forwards
+        solve_block(b, true);
+        const int64_t s0 = b * NB, s1 = s0 + NB;
+        if (s1 < n) {
+            const int64_t sb = std::min<int64_t>(NB, n - s0);
+            ProfScope ps(trsm_class(), s, 8.0 * (n - s1) * nrhs * sb * batch, 0);
+            gemm<R>(s, true, n - s1, nrhs, sb, mone, LU + s0 + s1 * lda, lda, sA, Z + s0, n, sZ, one, Z + s1, n,
+                    sZ, batch);
+        }
+    }
+    for (int64_t b = nblk - 1; b >= 0; --b) {     // L^H W = V, backwards
+        solve_block(b, false);
+        const int64_t s0 = b * NB;
+        if (s0 > 0) {
+            const int64_t sb = std::min<int64_t>(NB, n - s0);
+            ProfScope ps(trsm_class(), s, 8.0 * s0 * nrhs * sb * batch, 0);
+            gemm<R>(s, true, s0, nrhs, sb, mone, LU + s0, lda, sA, Z + s0, n, sZ, one, Z, n, sZ, batch);
+        }
+    }
+    {
+        ProfScope ps(trsm_class(), s, 0, 2.0 * n * nrhs * sizeof(Cx<R>) * batch);
+        dim3 grid((unsigned)std::min<int64_t>(ceil_div(n * nrhs, 256), 2048), batch);
+        hipLaunchKernelGGL((scatter_rows_kernel<R>), grid, dim3(256), 0, s, n, (int64_t)nrhs, perm,
+                           (const Cx<R>*)Z, n, sZ, X, ldx, sX);
+        NLF_HIP(hipGetLastError());
+    }
+}
+
+template void getrs_inv_adjoint<double>(hipStream_t, int64_t, int, int, const Cx<double>*, int64_t, int64_t,
+                                        const int32_t*, const Cx<double>*, const Cx<double>*, int64_t, int64_t,
+                                        Cx<double>*, Cx<double>*, int64_t, int64_t, Cx<double>*);
+template void getrs_inv_adjoint<float>(hipStream_t, int64_t, int, int, const Cx<float>*, int64_t, int64_t,
+                                       const int32_t*, const Cx<float>*, const Cx<float>*, int64_t, int64_t,
+                                       Cx<float>*, Cx<float>*, int64_t, int64_t, Cx<float>*);
 
 template void lu_block_inverses<double>(hipStream_t, int64_t, int, const Cx<double>*, int64_t, int64_t,
                                         Cx<double>*);

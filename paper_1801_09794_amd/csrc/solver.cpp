@@ -280,10 +280,10 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
         R.Ys = take(16 * blk * nc);
         R.QT = take(16 * blk);
         R.stmp = take((size_t)256 * m * nc * es);
+        R.E = take(16 * blk * nc);   // refinement residuals; the FP64 adjoint solves' scratch
         if (p32) {
             R.R32 = take(8 * blk);
             R.Y32 = take(8 * blk * nc);
-            R.E = take(16 * blk * nc);
             R.E32 = take(8 * blk * nc);
         }
         R.Ahat = take(16 * mm * J);
@@ -353,11 +353,12 @@ void orthonormalize(hipStream_t s, int64_t n, int m, z128* Q, z128* QT, z128* Gd
     }
 }
 
+// W_j = op(A_j) Q and Ahat_j = Q^H W_j, with op(A) = A^H for the adjoint problem.
 void project(hipStream_t s, int64_t n, int m, int J, const z128* const* A, int64_t lda,
-             const z128* Q, z128* W, z128* Ahat, z128* splitws, int64_t split_elems) {
+             const z128* Q, z128* W, z128* Ahat, z128* splitws, int64_t split_elems, bool adj = false) {
     for (int j = 0; j < J; ++j) {
         ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * n * m, 16.0 * ((double)n * n + 2.0 * n * m));
-        gemm<double>(s, false, n, m, n, z128(1, 0), A[j], lda, 0, Q, n, 0, z128(0, 0),
+        gemm<double>(s, adj, n, m, n, z128(1, 0), A[j], lda, 0, Q, n, 0, z128(0, 0),
                      W + (size_t)j * n * m, n, 0, 1, splitws, split_elems);
     }
     ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
@@ -646,9 +647,13 @@ struct RegionOutcome {
 
 // Algorithm 1 Steps 0-5 for region ri, on stream s, with the node factorisations already in the
 // workspace.  Writes the region's slice of the outputs; never throws.
+// Algorithm 1 for region ri.  adj: the adjoint problem S(mu) = T(conj mu)^H on the conjugate
+// contour (nodes conj z_k, weights conj omega_k, whose matrices T(z_k)^H reuse the factors of
+// T(z_k) through adjoint solves): its eigenvectors are the left eigenvectors of T, its
+// eigenvalues the conjugates of T's (returned conjugated back).
 RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, const Layout& L, int ri,
                          hipStream_t s, Profiler* prof, const RegionIO& io, hipEvent_t factored,
-                         std::atomic<int>* active = nullptr) {
+                         std::atomic<int>* active = nullptr, bool adj = false) {
     RegionOutcome res_out;
     try {
         ProfilerGuard pg(prof);
@@ -667,6 +672,15 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         };
         const auto& reg = h->regions[ri];
         const int m = reg.m0, nc = reg.nc;
+        std::vector<Term> terms = h->terms;
+        std::vector<cplx> zn = reg.z, wn = reg.w;
+        Ellipse E = reg.E;
+        if (adj) {
+            for (Term& t : terms) t.conj = true;
+            for (cplx& v : zn) v = std::conj(v);
+            for (cplx& v : wn) v = std::conj(v);
+            E.c = std::conj(E.c);
+        }
         z128* Q = at<z128>(ws, RL.Q);
         z128* X = at<z128>(ws, RL.X);
         z128* W = at<z128>(ws, RL.W);
@@ -710,7 +724,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         const z64* D64 = at<z64>(ws, L.dinv) + (size_t)node0 * dper;
         while (true) {
             // Step 1: projections and the reduced problem
-            project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems);
+            project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems, adj);
             d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
             const auto t0 = std::chrono::steady_clock::now();
             std::vector<cplx> prev;
@@ -719,9 +733,9 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                 const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
                 host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
             }
-            rr = reduced_solve(m, h->terms, Ahat.data(), reg.E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
+            rr = reduced_solve(m, terms, Ahat.data(), E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
             host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
-            NLF_REQUIRE(!user_failed(h->terms), NLF_ERR_ARG, "solve: the user function reported an error");
+            NLF_REQUIRE(!user_failed(terms), NLF_ERR_ARG, "solve: the user function reported an error");
             NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
                         "reduced eigenproblem failed (singular T at the contour centre or on the enlarged "
                         "contour, QR did not converge, or too many eigenvalues inside the enlarged contour)");
@@ -735,11 +749,11 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             // Step 3: R = sum_j W_j (Y f_j(Lambda)), res_i = ||R e_i||
             for (int j = 0; j < J; ++j)
                 for (int c = 0; c < m; ++c) {
-                    const cplx f = term_value(h->terms[j], lam[c]);
+                    const cplx f = term_value(terms[j], lam[c]);
                     for (int r = 0; r < m; ++r)
                         Gh[(size_t)j * m + r + (size_t)c * J * m] = rr.Y[r + (size_t)c * m] * f;
                 }
-            NLF_REQUIRE(!user_failed(h->terms), NLF_ERR_ARG, "solve: the user function reported an error");
+            NLF_REQUIRE(!user_failed(terms), NLF_ERR_ARG, "solve: the user function reported an error");
             h2d(s, Gall, Gh.data(), sizeof(cplx) * Gh.size());
             {
                 ProfScope ps(NLF_PROF_RESIDUAL, s, 8.0 * n * m * m * J, 16.0 * n * m * (J + 1));
@@ -753,7 +767,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             double maxres = 0.0, max_unconv = 0.0;
             for (int i = 0; i < m; ++i) {
                 if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
-                inside[i] = reg.E.radius(rr.lambda[i]) < 1.0;
+                inside[i] = E.radius(rr.lambda[i]) < 1.0;
                 if (inside[i]) {
                     ++n_in;
                     maxres = std::max(maxres, res[i]);
@@ -791,7 +805,10 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             // Step 4: Y_k = T(z_k)^{-1} R for the region's nodes
             {
                 TrsmClassGuard tg(NLF_PROF_SOLVE);
-                if (!p32) {
+                if (!p32 && adj) {
+                    getrs_inv_adjoint<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, D128, R, n, 0,
+                                              at<z128>(ws, RL.E), Ys, n, (int64_t)blk, at<z128>(ws, RL.stmp));
+                } else if (!p32) {
                     getrs_inv<double>(s, n, m, nc, LU128, n, (int64_t)nn, perm, D128, R, n, 0, Ys, n,
                                       (int64_t)blk, at<z128>(ws, RL.stmp));
                 } else {
@@ -801,17 +818,21 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                     z64* E32 = at<z64>(ws, RL.E32);
                     const z128* T64 = at<z128>(ws, L.t64) + (size_t)node0 * nn;
                     cast_128_to_64(s, n, m, 1, R, n, 0, R32, n, 0);
-                    getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, Y32, n,
-                                     (int64_t)blk, at<z64>(ws, RL.stmp));
+                    if (adj)
+                        getrs_inv_adjoint<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, E32, Y32, n,
+                                                 (int64_t)blk, at<z64>(ws, RL.stmp));
+                    else
+                        getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, R32, n, 0, Y32, n,
+                                         (int64_t)blk, at<z64>(ws, RL.stmp));
                     cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, false);
                     double rn2 = 0.0;
                     for (int i = 0; i < m; ++i) rn2 += std::isfinite(res[i]) ? res[i] * res[i] : 0.0;
                     for (int sweep = 0; refine_needed && sweep < std::min(opt->max_refine, 5); ++sweep) {
                         TrsmClassGuard tg2(NLF_PROF_REFINE);
                         ProfScope ps(NLF_PROF_REFINE, s, 8.0 * n * n * m * nc, 16.0 * nn * nc);
-                        // E_k = R - T(z_k) Y_k in FP64
+                        // E_k = R - T(z_k) Y_k (adjoint: R - T(z_k)^H Y_k) in FP64
                         for (int q = 0; q < nc; ++q) copy_block(s, n, m, R, n, E + q * blk, n);
-                        gemm<double>(s, false, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
+                        gemm<double>(s, adj, n, m, n, z128(-1, 0), T64, n, (int64_t)nn, Ys, n, (int64_t)blk,
                                      z128(1, 0), E, n, (int64_t)blk, nc);
                         block_sqnorms(s, n, m, nc, E, n, (int64_t)blk, norms_d, norms_d + m + nc + 8);
                         d2h_sync(s, enorm.data(), norms_d, sizeof(double) * nc);
@@ -825,8 +846,12 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                             break;
                         }
                         cast_128_to_64(s, n, m, nc, E, n, (int64_t)blk, E32, n, (int64_t)blk);
-                        getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
-                                         Y32, n, (int64_t)blk, at<z64>(ws, RL.stmp));
+                        if (adj)
+                            getrs_inv_adjoint<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n,
+                                                     (int64_t)blk, E32, Y32, n, (int64_t)blk, at<z64>(ws, RL.stmp));
+                        else
+                            getrs_inv<float>(s, n, m, nc, LU64, n, (int64_t)nn, perm, D64, E32, n, (int64_t)blk,
+                                             Y32, n, (int64_t)blk, at<z64>(ws, RL.stmp));
                         cast_64_to_128(s, n, m, nc, Y32, n, (int64_t)blk, Ys, n, (int64_t)blk, true);
                     }
                 }
@@ -835,7 +860,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             for (int i = 0; i < m; ++i) {
                 cplx rsum = 0.0;
                 for (int q = 0; q < nc; ++q) {
-                    const cplx cq = reg.w[q] / (reg.z[q] - lam[i]);
+                    const cplx cq = wn[q] / (zn[q] - lam[i]);
                     acoef[(size_t)q * m + i] = cq;
                     rsum += cq;
                 }
@@ -852,8 +877,9 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         NLF_HIP(hipMemcpyAsync((z128*)io.Xout + (size_t)col0 * n, X, sizeof(z128) * blk,
                                hipMemcpyDeviceToDevice, s));
         for (int i = 0; i < m; ++i) {
-            io.lambda[2 * (col0 + i)] = rr.lambda[i].real();
-            io.lambda[2 * (col0 + i) + 1] = rr.lambda[i].imag();
+            const cplx l = adj ? std::conj(rr.lambda[i]) : rr.lambda[i];   // eigenvalues of T
+            io.lambda[2 * (col0 + i)] = l.real();
+            io.lambda[2 * (col0 + i) + 1] = l.imag();
             io.resid[col0 + i] = res[i];
             io.inside[col0 + i] = inside[i];
         }
@@ -1010,10 +1036,10 @@ nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* 
     return NLF_OK;
 }
 
-nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws,
-                             size_t ws_bytes, const void* X0_dev, void* X_dev_out,
-                             double* lambda_out, double* resid_out, int32_t* inside_out,
-                             int32_t* m_out, int32_t* iters_out) {
+// nlfeast_solve (adj = false) and nlfeast_solve_left (adj = true).
+static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, void* ws, size_t ws_bytes,
+                                 const void* X0_dev, void* X_dev_out, double* lambda_out, double* resid_out,
+                                 int32_t* inside_out, int32_t* m_out, int32_t* iters_out, bool adj) {
     NLF_TRY(h, {
         NLF_REQUIRE(h && opt, NLF_ERR_ARG, "solve: null argument");
         NLF_REQUIRE(!h->regions.empty() && h->J > 0, NLF_ERR_STATE,
@@ -1107,7 +1133,7 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         if (!concurrent) {
             for (int ri = 0; ri < nreg; ++ri) {
                 out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[0], h->profiling ? &h->prof : nullptr, io,
-                                     factored);
+                                     factored, nullptr, adj);
                 if (out[ri].status != NLF_OK && out[ri].status != NLF_ERR_NOT_CONVERGED &&
                     out[ri].status != NLF_ERR_M0_TOO_SMALL)
                     break;
@@ -1130,7 +1156,7 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
                         return;
                     }
                     out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
-                                         h->profiling ? h->rprof[ri].get() : nullptr, io, factored, &active);
+                                         h->profiling ? h->rprof[ri].get() : nullptr, io, factored, &active, adj);
                     active.fetch_sub(1);
                 });
             for (auto& t : threads) t.join();
@@ -1178,6 +1204,22 @@ nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void*
         if (status != NLF_OK) h->last_error = msg;
         return (nlfeast_status)status;
     })
+}
+
+nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws,
+                             size_t ws_bytes, const void* X0_dev, void* X_dev_out,
+                             double* lambda_out, double* resid_out, int32_t* inside_out,
+                             int32_t* m_out, int32_t* iters_out) {
+    return solve_impl(h, opt, ws, ws_bytes, X0_dev, X_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out,
+                      false);
+}
+
+nlfeast_status nlfeast_solve_left(nlfeast_handle h, const nlfeast_options* opt, void* ws,
+                                  size_t ws_bytes, const void* Y0_dev, void* Y_dev_out,
+                                  double* lambda_out, double* resid_out, int32_t* inside_out,
+                                  int32_t* m_out, int32_t* iters_out) {
+    return solve_impl(h, opt, ws, ws_bytes, Y0_dev, Y_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out,
+                      true);
 }
 
 // ------------------------------------------------------------------ step-level entry points
@@ -1323,6 +1365,36 @@ nlfeast_status nlf_getrs_batched_inv(int32_t dtype, int64_t n, int32_t nrhs, int
             getrs_inv<float>(as_stream(stream), n, nrhs, batch, (const z64*)LU_dev, lda, strideA, perm_dev,
                              (const z64*)dinv_dev, (const z64*)B_dev, ldb, strideB, (z64*)X_dev, ldx, strideX,
                              (z64*)tmp_dev);
+        return NLF_OK;
+    })
+}
+
+nlfeast_status nlf_getrs_batched_inv_adjoint(int32_t dtype, int64_t n, int32_t nrhs, int32_t batch,
+                                             const void* LU_dev, int64_t lda, int64_t strideA,
+                                             const int32_t* perm_dev, const void* dinv_dev, const void* B_dev,
+                                             int64_t ldb, int64_t strideB, void* Z_dev, void* X_dev, int64_t ldx,
+                                             int64_t strideX, void* tmp_dev, void* stream) {
+    nlfeast_ctx* h = nullptr;
+    NLF_TRY(h, {
+        NLF_REQUIRE(n > 0 && nrhs >= 1 && batch >= 1 && LU_dev && perm_dev && dinv_dev && B_dev && Z_dev && X_dev &&
+                        tmp_dev && lda >= n && ldb >= n && ldx >= n && strideB >= 0 && strideX >= ldx * nrhs &&
+                        (dtype == NLF_C64 || dtype == NLF_C128),
+                    NLF_ERR_ARG, "nlf_getrs_batched_inv_adjoint: bad arguments");
+        const size_t es = dtype == NLF_C128 ? 16 : 8;
+        const char* z0 = (const char*)Z_dev;
+        const char* z1 = z0 + es * (size_t)n * nrhs * batch;
+        const char* x0 = (const char*)X_dev;
+        const char* x1 = x0 + es * ((size_t)(batch - 1) * strideX + (size_t)ldx * nrhs);
+        NLF_REQUIRE(x1 <= z0 || z1 <= x0, NLF_ERR_ARG, "nlf_getrs_batched_inv_adjoint: X overlaps Z");
+        TrsmClassGuard tg(NLF_PROF_SOLVE);
+        if (dtype == NLF_C128)
+            getrs_inv_adjoint<double>(as_stream(stream), n, nrhs, batch, (const z128*)LU_dev, lda, strideA, perm_dev,
+                                      (const z128*)dinv_dev, (const z128*)B_dev, ldb, strideB, (z128*)Z_dev,
+                                      (z128*)X_dev, ldx, strideX, (z128*)tmp_dev);
+        else
+            getrs_inv_adjoint<float>(as_stream(stream), n, nrhs, batch, (const z64*)LU_dev, lda, strideA, perm_dev,
+                                     (const z64*)dinv_dev, (const z64*)B_dev, ldb, strideB, (z64*)Z_dev,
+                                     (z64*)X_dev, ldx, strideX, (z64*)tmp_dev);
         return NLF_OK;
     })
 }

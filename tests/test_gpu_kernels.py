@@ -222,6 +222,51 @@ def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
         assert rel(nl.from_colmajor(X[b]), ref) < tol
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,nrhs,batch,inplace", [(100, 7, 2, False), (300, 64, 3, True), (700, 20, 2, False),
+                                                  (1000, 33, 1, True)])
+def test_getrs_adjoint_matches_solve(dtype, n, nrhs, batch, inplace):
+    # X = A^{-H} B from the factors of A (the adjoint problem's solves): B shared by the batch
+    # with a separate scratch Z, or one B per matrix used as Z itself
+    rng = np.random.default_rng(n + 5 * nrhs)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    mats = [wl.cn(rng, (n, n)) + 3 * np.eye(n) for _ in range(batch)]
+    Bs = [wl.cn(rng, (n, nrhs)) for _ in range(batch)]
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    nl.nlf_getrf_batched(A, ipiv, perm, info)
+    dinv = torch.empty(batch * nl.nlf_lu_inverse_elems(n), dtype=dt, device="cuda")
+    nl.nlf_lu_block_inverses(A, dinv)
+    X = torch.empty((batch, nrhs, n), dtype=dt, device="cuda")
+    tmp = torch.empty(batch * 256 * nrhs, dtype=dt, device="cuda")
+    if inplace:
+        B = torch.stack([dev(b, dt) for b in Bs])
+        nl.nlf_getrs_batched_inv_adjoint(A, perm, dinv, B, B, X, tmp)
+        refs = [np.linalg.solve(M.conj().T, b) for M, b in zip(mats, Bs)]
+    else:
+        Z = torch.empty((batch, nrhs, n), dtype=dt, device="cuda")
+        nl.nlf_getrs_batched_inv_adjoint(A, perm, dinv, dev(Bs[0], dt), Z, X, tmp, shared_rhs=True)
+        refs = [np.linalg.solve(M.conj().T, Bs[0]) for M in mats]
+    torch.cuda.synchronize()
+    tol = 1e-11 if dtype == "c128" else 2e-3
+    for b in range(batch):
+        assert rel(nl.from_colmajor(X[b]), refs[b]) < tol
+
+
+def test_getrs_adjoint_rejects_overlap():
+    n, nrhs = 64, 4
+    A = torch.zeros((1, n, n), dtype=torch.complex128, device="cuda")
+    perm = torch.zeros((1, n), dtype=torch.int32, device="cuda")
+    dinv = torch.zeros(nl.nlf_lu_inverse_elems(n), dtype=torch.complex128, device="cuda")
+    Z = torch.zeros((1, nrhs, n), dtype=torch.complex128, device="cuda")
+    tmp = torch.zeros(256 * nrhs, dtype=torch.complex128, device="cuda")
+    with pytest.raises(nl.NLFError) as e:
+        nl.nlf_getrs_batched_inv_adjoint(A, perm, dinv, Z, Z, Z, tmp)
+    assert e.value.status == nl.NLF_ERR_ARG
+
+
 def test_getrf_large_backward_error():
     # n = 4096: several recursion levels, 4 rows per panel thread, full-size panels
     n, batch = 4096, 2

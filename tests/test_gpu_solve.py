@@ -567,3 +567,103 @@ def test_user_function_status_codes():
     finally:
         torch.cuda.synchronize()
         S.close()
+
+
+# ---- left eigenvectors: Algorithm 1 on the adjoint function with the cached factors
+
+def _left_checks(terms_or_problem, mats, out, tol, r, lam_ref):
+    P = terms_or_problem if isinstance(terms_or_problem, pb.Problem) else pb.Problem(terms_or_problem, mats)
+    ins = converged(out, tol)
+    assert ins.sum() == len(lam_ref)
+    assert match_err(out["lam"][ins], lam_ref, r) < 1e-9
+    Y = out["Xh"][:, ins]
+    for l, y in zip(out["lam"][ins], Y.T):
+        T = P.T(l)
+        assert abs(np.linalg.norm(y) - 1) < 1e-12
+        assert np.linalg.norm(y.conj() @ T) <= 2 * tol      # y^H T(lambda) = 0
+    return ins
+
+
+@pytest.mark.parametrize("prec", [nl.NLF_PREC_FP64, nl.NLF_PREC_FP32_REFINE])
+def test_qep200_left_eigenvectors(prec):
+    # right solve, then the left solve on the same handle and workspace (factors reused): the
+    # same eigenvalues, each y the left null vector of T(lambda) (independent SVD), and the
+    # oracle's left solve agrees
+    cfg = wl.CONFIGS["qep200"]
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    S = nl.NLFEAST(cfg["n"])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour([dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])])
+        opts = nl.options(tol=cfg["tol"], precision=prec)
+        right = S.solve(opts, nl.to_colmajor(wl.initial_block(cfg["n"], cfg["m0"], 2001)))
+        nl.nlfeast_set_profiling(S.h, True)
+        Y0 = wl.initial_block(cfg["n"], cfg["m0"], 2101)
+        left = S.solve(opts, nl.to_colmajor(Y0), left=True)
+        prof = S.profile()
+        torch.cuda.synchronize()
+        left["Xh"] = nl.from_colmajor(left["X"])
+        right["Xh"] = nl.from_colmajor(right["X"])
+    finally:
+        S.close()
+    assert right["status"] == left["status"] == nl.NLF_OK
+    assert prof["factor"]["launches"] == 0          # the cached factors were reused
+    ins = _left_checks(terms, mats, left, cfg["tol"], r, brute)
+    P = pb.Problem(terms, mats)
+    rin = converged(right, cfg["tol"])
+    for l, y in zip(left["lam"][ins], left["Xh"][:, ins].T):
+        U, sv, _ = np.linalg.svd(P.T(l))
+        assert abs(abs(np.vdot(U[:, -1], y)) - 1) < 1e-8
+        i = np.flatnonzero(rin)[np.argmin(np.abs(right["lam"][rin] - l))]
+        assert abs(np.vdot(y, P.dT(l) @ right["Xh"][:, i])) > 1e-6   # a simple eigenvalue
+    C = qd.Contour(c, r)
+    ro = onl.solve_left(P, C, cfg["nc"], Y0, cfg["m0"], cfg["tol"])
+    assert match_err(left["lam"][ins], ro.eigenvalues, r) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [nl.NLF_PREC_FP64, nl.NLF_PREC_FP32_REFINE])
+def test_delay512_left_eigenvectors(prec):
+    cfg = wl.CONFIGS["delay512"]
+    terms, mats = wl.make_problem("delay512")
+    g = contours("delay512")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    S = nl.NLFEAST(cfg["n"])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour([dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])])
+        left = S.solve(nl.options(tol=cfg["tol"], precision=prec),
+                       nl.to_colmajor(wl.initial_block(cfg["n"], cfg["m0"], 2106)), left=True)
+        torch.cuda.synchronize()
+        left["Xh"] = nl.from_colmajor(left["X"])
+    finally:
+        S.close()
+    assert left["status"] == nl.NLF_OK
+    _left_checks(terms, mats, left, cfg["tol"], r, ref)
+
+
+def test_rational300_left_eigenvectors_user_function():
+    cfg = wl.CONFIGS["rational300"]
+    terms, mats = wl.make_problem("rational300")
+    g = contours("rational300")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    S = nl.NLFEAST(cfg["n"])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_user_function(_pole_fn)
+        S.set_contour([dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])])
+        left = S.solve(nl.options(tol=cfg["tol"]), nl.to_colmajor(wl.initial_block(cfg["n"], cfg["m0"], 2108)),
+                       left=True)
+        torch.cuda.synchronize()
+        left["Xh"] = nl.from_colmajor(left["X"])
+    finally:
+        S.close()
+    assert left["status"] == nl.NLF_OK
+    sig = terms[2][1]
+    P = pb.Problem([terms[0], terms[1], ("fn", pb.ScalarFunction(lambda z: wl.pole_value(z, sig),
+                                                                 lambda z: wl.pole_deriv(z, sig)))], mats)
+    _left_checks(P, mats, left, cfg["tol"], r, ref)
