@@ -462,7 +462,7 @@ static void rotate_cols(cplx* a, cplx* b, int cnt, double c, cplx s) {
 // Householder reduction to Hessenberg form (the reflectors kept for the eigenvectors), then the
 // shifted QR algorithm on the active window for the eigenvalues only; the window is stored with
 // an odd leading dimension so that the row rotations do not fall into a few cache sets.  The
-// reduction's three O(N^2) updates per column are split over two host threads from N = 192.
+// reduction's three O(N^2) updates per column are split over host threads from N = 192.
 bool HessEig::compute(int N_, std::vector<cplx>& A) {
     N = N_;
     H.swap(A);
@@ -470,8 +470,10 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
     beta.assign(N, 0.0);
     std::vector<cplx> s(N);
     // each reduction step ends in barriers, so threads only pay off on large matrices: measured
-    // on the MI355X hosts, one thread is fastest up to N = 128 and two from N = 192 to 256
-    const int P = N >= 192 ? std::min(2, host_threads((int64_t)N * N, 4096)) : 1;
+    // on the MI355X hosts, one thread is fastest up to N = 128 and two from N = 192 to 256; the
+    // delay problem's N = 480 runs best on the full count
+    const int P = N < 192 ? 1 : N < 384 ? std::min(2, host_threads((int64_t)N * N, 4096))
+                                        : host_threads((int64_t)N * N, 4096);
     Team team(P);
     cplx alpha_k = 0.0;
     std::vector<char> skip(N, 0);

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <memory>
 #include <string>
 #include <thread>
@@ -171,6 +172,7 @@ struct nlfeast_ctx {
     int factors_prec = -1;
     bool profiling = false;
     Profiler prof;
+    Profiler fprof;                                        // the factorisation thread's launches
     hipStream_t side[4] = {nullptr, nullptr, nullptr, nullptr};   // factorisation streams
     hipEvent_t ev_join[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<hipStream_t> rstream;                      // one iteration stream per region
@@ -638,6 +640,9 @@ struct RegionIO {
     int32_t* inside;
     int32_t* m_out;
     int32_t* iters;
+    // set once the factorisation has been enqueued by its host thread (the event passed to the
+    // regions is recorded then); holds that thread's error if it failed.  Null: nothing to wait for
+    const std::shared_future<void>* enqueued = nullptr;
 };
 
 struct RegionOutcome {
@@ -794,6 +799,10 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             // the factors are needed from here on: wait for the factorisation launched before
             // iteration 0 and reject singular node matrices of this region
             if (factored) {
+                if (io.enqueued) {   // the event must be recorded before it can be waited on
+                    std::shared_future<void> f = *io.enqueued;
+                    f.get();
+                }
                 NLF_HIP(hipEventSynchronize(factored));
                 for (int q = 0; q < nc; ++q)
                     NLF_REQUIRE(h->info_host[node0 + q] == 0, NLF_ERR_SINGULAR,
@@ -1078,6 +1087,13 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         if (!h->ev_factored) NLF_HIP(hipEventCreateWithFlags(&h->ev_factored, hipEventDisableTiming));
         NLF_HIP(hipEventRecord(h->ev_start, s));
         hipEvent_t factored = nullptr;
+        std::shared_future<void> enqueued;
+        struct Joiner {   // joins the factorisation thread on every exit path
+            std::thread t;
+            ~Joiner() {
+                if (t.joinable()) t.join();
+            }
+        } fthread;
         if (!(h->factors_valid && h->factors_ws == ws && h->factors_prec == opt->precision)) {
             h->factors_valid = false;
             std::vector<cplx> coef((size_t)L.NZ * J);
@@ -1095,11 +1111,6 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
                     capture_factorisation(h, L, ws, p32, tune);
                     h->graph_key = key;
                 }
-                ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
-                replay_factorisation(h, s);
-            } else {
-                ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)n * n * n * L.NZ, 0);
-                factor_all(h, L, ws, p32, s, tune);
             }
             if (h->info_cap < L.NZ) {
                 if (h->info_host) NLF_HIP(hipHostFree(h->info_host));
@@ -1108,15 +1119,36 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
                 NLF_HIP(hipHostMalloc((void**)&h->info_host, sizeof(int32_t) * L.NZ, hipHostMallocDefault));
                 h->info_cap = L.NZ;
             }
-            NLF_HIP(hipMemcpyAsync(h->info_host, at<void>(ws, L.info), sizeof(int32_t) * L.NZ,
-                                   hipMemcpyDeviceToHost, s));
-            NLF_HIP(hipEventRecord(h->ev_factored, s));
+            // the factorisation is enqueued from a thread of its own: enqueuing blocks the host
+            // (a graph launch waits for the GPU, and so do eager launches once the queue is full),
+            // and Steps 0-3 of every region need no factors, so they run meanwhile
+            if (h->profiling) h->fprof.reset();
+            std::shared_ptr<std::promise<void>> done = std::make_shared<std::promise<void>>();
+            enqueued = done->get_future().share();
             factored = h->ev_factored;
+            fthread.t = std::thread([h, &L, ws, p32, s, tune, opt, done] {
+                try {
+                    NLF_HIP(hipSetDevice(h->device));
+                    ProfilerGuard fpg(h->profiling ? &h->fprof : nullptr);
+                    {
+                        ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)h->n * h->n * h->n * L.NZ, 0);
+                        if (opt->graph) replay_factorisation(h, s);
+                        else factor_all(h, L, ws, p32, s, tune);
+                    }
+                    NLF_HIP(hipMemcpyAsync(h->info_host, at<void>(ws, L.info), sizeof(int32_t) * L.NZ,
+                                           hipMemcpyDeviceToHost, s));
+                    NLF_HIP(hipEventRecord(h->ev_factored, s));
+                    done->set_value();
+                } catch (...) {
+                    done->set_exception(std::current_exception());
+                }
+            });
         }
 
         const int nreg = (int)h->regions.size();
         std::vector<RegionOutcome> out(nreg);
-        RegionIO io{X0_dev, X_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out};
+        RegionIO io{X0_dev, X_dev_out, lambda_out, resid_out, inside_out, m_out, iters_out,
+                    enqueued.valid() ? &enqueued : nullptr};
         const bool concurrent = nreg > 1 && opt->region_streams == 0;
         // region streams: one per region when they run concurrently, else one shared stream
         const int nrs = concurrent ? nreg : 1;
@@ -1171,8 +1203,18 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
                     h->prof.merge(*h->rprof[ri]);
                 }
         }
+        if (fthread.t.joinable()) {
+            fthread.t.join();
+            enqueued.get();   // rethrows the factorisation thread's error
+        }
         NLF_HIP(hipStreamSynchronize(s));
-        if (h->profiling) h->prof.collect();
+        if (h->profiling) {
+            h->prof.collect();
+            if (factored) {
+                h->fprof.collect();
+                h->prof.merge(h->fprof);
+            }
+        }
         // a hard error (device, argument) wins over the convergence statuses
         int status = NLF_OK;
         std::string msg;
