@@ -1063,28 +1063,46 @@ static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, cons
         std::copy(Y.begin() + (size_t)q * m, Y.begin() + (size_t)(q + 1) * m, res.Y.begin() + (size_t)i * m);
         res.found[i] = 1;
     }
-    // completion: unit vectors e_r orthogonalised (twice) against the columns so far, kept when
-    // at least half of the vector survives, with values spread over the enlarged ellipse
+    // completion: an orthonormal basis B of the found vectors' span (Gram-Schmidt, twice), then
+    // unit vectors e_r orthogonalised (twice) against B and the completions so far, kept when a
+    // part of norm >= 0.5/sqrt(m) survives (the projections of all e_r onto a complement of
+    // dimension d have squared norms summing to d, so enough e_r always pass), with values spread
+    // over the enlarged ellipse
+    std::vector<cplx> B((size_t)m * m, 0.0), v(m);
+    int nb = 0;
+    auto orthogonalise = [&](std::vector<cplx>& x) {
+        for (int pass = 0; pass < 2; ++pass)
+            for (int c = 0; c < nb; ++c) {
+                const cplx* u = &B[(size_t)c * m];
+                cplx d = 0.0;
+                for (int i = 0; i < m; ++i) d += std::conj(u[i]) * x[i];
+                for (int i = 0; i < m; ++i) x[i] -= u[i] * d;
+            }
+        double nn = 0.0;
+        for (int i = 0; i < m; ++i) nn += std::norm(x[i]);
+        return std::sqrt(nn);
+    };
+    for (int c = 0; c < kf; ++c) {
+        std::copy(res.Y.begin() + (size_t)c * m, res.Y.begin() + (size_t)(c + 1) * m, v.begin());
+        const double nn = orthogonalise(v);
+        if (nn < 1e-8) continue;   // numerically inside the span already
+        for (int i = 0; i < m; ++i) B[(size_t)nb * m + i] = v[i] / nn;
+        ++nb;
+    }
     int col = kf;
-    std::vector<cplx> v(m);
     for (int r = 0; r < m && col < m_keep; ++r) {
         std::fill(v.begin(), v.end(), cplx(0.0));
         v[r] = 1.0;
-        for (int pass = 0; pass < 2; ++pass)
-            for (int c = 0; c < col; ++c) {
-                const cplx* u = &res.Y[(size_t)c * m];
-                cplx d = 0.0;
-                for (int i = 0; i < m; ++i) d += std::conj(u[i]) * v[i];
-                for (int i = 0; i < m; ++i) v[i] -= u[i] * d;
-            }
-        double nn = 0.0;
-        for (int i = 0; i < m; ++i) nn += std::norm(v[i]);
-        nn = std::sqrt(nn);
-        if (nn < 0.5) continue;
-        for (int i = 0; i < m; ++i) res.Y[(size_t)col * m + i] = v[i] / nn;
+        const double nn = orthogonalise(v);
+        if (nn < 0.5 / std::sqrt((double)m)) continue;
+        for (int i = 0; i < m; ++i) {
+            B[(size_t)nb * m + i] = v[i] / nn;
+            res.Y[(size_t)col * m + i] = v[i] / nn;
+        }
+        ++nb;
         ++col;
     }
-    if (col < m_keep) {   // the found vectors are (numerically) dependent: no completion
+    if (col < m_keep) {   // not reached for m_keep <= m (see above); kept as a guard
         res.ok = false;
         return res;
     }

@@ -148,6 +148,26 @@ def test_contour_reduced_completion(lib):
     assert np.allclose(Y.conj().T @ Y, np.eye(m), atol=1e-12)
 
 
+def test_contour_reduced_completion_is_orthogonal_to_a_non_normal_span(lib):
+    """lambda I - A with A = S diag(d) S^{-1} (S far from unitary): the three eigenvectors found
+    are not orthogonal to each other, and every completing vector is orthogonal to their span."""
+    m = 12
+    rng = np.random.default_rng(31)
+    d = np.array([0.1, -0.4j, 0.5 + 0.2j] + list(3.0 + 2.0 * rng.uniform(size=m - 3)))
+    S = np.eye(m) + 0.8 * wl.cn(rng, (m, m))
+    A = [np.eye(m, dtype=complex), -(S * d[None, :]) @ np.linalg.inv(S)]
+    C = qd.Contour(0.0, 1.0)
+    lam, Y, found = nl.nlf_reduced_solve_ex([("fn", 1), ("fn", 0)], A, C.c, C.a, C.b, m, fn=_pow_fn())
+    assert found.sum() == 3
+    assert np.max(np.abs(np.sort_complex(lam[found]) - np.sort_complex(d[:3]))) < 1e-12
+    F = Y[:, found]
+    assert abs(np.vdot(F[:, 0], F[:, 1])) > 1e-3           # not an orthogonal set
+    Qf, _ = np.linalg.qr(F)
+    P = Y[:, ~found]
+    assert np.linalg.norm(Qf.conj().T @ P) < 1e-12
+    assert np.allclose(P.conj().T @ P, np.eye(m - 3), atol=1e-12)
+
+
 def test_user_function_errors(lib):
     A = [np.eye(4, dtype=complex), -np.diag([0.1, 0.2, 3.0, 4.0])]
     C = qd.Contour(0.0, 1.0)
