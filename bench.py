@@ -39,6 +39,10 @@ def parse():
                     help="skip the delay workload (delay8192)")
     ap.add_argument("--no-nc-sweep", action="store_true",
                     help="skip the sweep over the number of quadrature nodes (quartic1024)")
+    ap.add_argument("--no-left", action="store_true",
+                    help="skip the left-eigenvector leg on the headline workload")
+    ap.add_argument("--no-user-fn", action="store_true",
+                    help="skip delay8192 with its exponential supplied as a caller function")
     ap.add_argument("--no-delay-fp64", action="store_true",
                     help="run the delay workload in FP32 + refinement only")
     ap.add_argument("--fp64-legs", action="store_true",
@@ -133,19 +137,22 @@ def load_workload(name):
     return cfg, terms, mats, regions, X0
 
 
-def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0, graph=0):
+def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0, graph=0, user_fn=None,
+            reduced_solver=0):
     import torch
     import paper_1801_09794_amd as nl
     n = cfg["n"]
     S = nl.NLFEAST(n, 0)
     dmats = [nl.to_colmajor(M, "cuda:0") for M in mats]
     S.set_coeffs(terms, dmats)
+    if user_fn is not None:
+        S.set_user_function(user_fn)
     quad = nl.NLF_QUAD_TRAPEZOID if cfg.get("quad") == "trapezoid" else nl.NLF_QUAD_GAUSS_LEGENDRE
     S.set_contour(regions, quad_rule=quad)
     X0d = nl.to_colmajor(X0, "cuda:0")
     opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=args.refine_eta,
                       lu_streams=args.lu_streams, panel_width=args.panel_width,
-                      autotune=autotune, graph=graph, lookahead=args.lookahead)
+                      autotune=autotune, graph=graph, lookahead=args.lookahead, reduced_solver=reduced_solver)
     for _ in range(args.warmup):
         S.set_contour(regions, quad_rule=quad)
         S.solve(opts, X0d)
@@ -224,6 +231,69 @@ def extra_leg(args, name, description, autotune, graph, with_fp64=False):
     if "fp64" in out:
         out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
     return out
+
+
+def user_function_leg(args):
+    """Caller-supplied scalar functions and the contour-integral reduced solve: delay8192 with its
+    exponential handed over as a Python function through the C ABI (evaluated on the host at
+    the nodes, the Ritz values and the reduced contour's points), FP32 LU + FP64 refinement;
+    converged eigenvalues against the stored reference."""
+    import numpy as np
+    import paper_1801_09794_amd as nl
+    cfg, terms, mats, regions, X0 = load_workload("delay8192")
+    uterms = [(k, p) if k != "exp" else ("fn", p) for k, p in terms]
+
+    def expo(j, tau, z, want_deriv):
+        e = np.exp(-tau * z)
+        return e, (-tau * e if want_deriv else None)
+
+    t, o, p = run_gpu(args, cfg, uterms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True, user_fn=expo)
+    c = converged_pairs(o, cfg["tol"])
+    return {"workload": "delay8192 with exp(-l) supplied as a caller function (contour-integral reduced "
+                        "solve: 96 points on the 1.5x circle, block Hankel moments, Newton), FP32 LU + FP64 "
+                        "refinement, n=%d, m0=%d, %d nodes" % (cfg["n"], regions[0]["m0"], cfg["nc"]),
+            "value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
+            "iterations": [int(v) for v in o["iters"]],
+            "max_rel_err_vs_reference": reference_error("delay8192", regions, o, cfg["tol"]),
+            "host_reduced_ms_per_step": p["host_reduced"]["ms"] / args.steps,
+            "factor_ms": p["factor"]["ms"] / args.steps}
+
+
+def left_leg(args):
+    """Left eigenvectors (eigentriples) of the headline problem: after one right solve, each left
+    solve runs Algorithm 1 on the adjoint function with the cached factors (no factorisation);
+    left eigenpairs per second, the largest ||T(lambda)^H y||, and the distance of the left
+    eigenvalues from the right ones."""
+    import numpy as np
+    import torch
+    import paper_1801_09794_amd as nl
+    cfg, terms, mats, regions, X0 = load_workload(args.workload)
+    S = nl.NLFEAST(cfg["n"], 0)
+    S.set_coeffs(terms, [nl.to_colmajor(M, "cuda:0") for M in mats])
+    S.set_contour(regions)
+    opts = nl.options(tol=cfg["tol"], precision=nl.NLF_PREC_FP64, graph=args.graph)
+    right = S.solve(opts, nl.to_colmajor(X0, "cuda:0"))
+    Y0 = nl.to_colmajor(np.conj(X0), "cuda:0")
+    for _ in range(args.warmup):
+        S.solve(opts, Y0, left=True)
+    nl.nlfeast_set_profiling(S.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = 0
+    for _ in range(args.steps):
+        left = S.solve(opts, Y0, left=True)
+        fac += S.profile()["factor"]["launches"]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    S.close()
+    ok = left["inside"] & (left["res"] <= cfg["tol"])
+    c = int(np.sum(ok))
+    return {"workload": "left eigenvectors of %s after its right solve (adjoint problem on the conjugate "
+                        "contour, cached factors through adjoint solves), FP64" % args.workload,
+            "value": c / t, "unit": "left eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
+            "iterations": [int(v) for v in left["iters"]], "factorisation_launches": fac,
+            "max_left_residual": float(np.max(left["res"][ok])) if c else None,
+            "max_rel_diff_vs_right_eigenvalues": eig_diff(left, right, cfg["tol"], regions[0]["a"])}
 
 
 def nc_sweep(args):
@@ -426,6 +496,10 @@ def main():
             autotune=0, graph=0, with_fp64=not args.no_delay_fp64)
     if not args.no_nc_sweep and args.workload != "quartic1024":
         result["nc_sweep"] = nc_sweep(args)
+    if not args.no_left:
+        result["left_eigenvectors"] = left_leg(args)
+    if not args.no_user_fn and not args.no_delay:
+        result["user_function"] = user_function_leg(args)
     if not args.no_cpu:
         est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {

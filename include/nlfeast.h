@@ -113,13 +113,14 @@ typedef struct {
     int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
                                     the trailing update of panel k runs; -1 = one stream;
                                     0 = library default (one stream) */
-    int32_t reduced_solver;      /* Steps 1-2 for non-polynomial T: 0 = Taylor linearisation about
-                                    the contour centre and Newton refinement for NLF_F_EXP terms;
-                                    1 = the contour-integral solve (moments of the reduced
-                                    resolvent on the contour enlarged 1.5 times, block Hankel
-                                    matrices, Newton refinement).  Problems with an NLF_F_USER
-                                    term always take the contour-integral solve; polynomial
-                                    problems always the exact companion linearisation */
+    int32_t reduced_solver;      /* Steps 1-2 for non-polynomial T: 0 (default) or 1 = the
+                                    contour-integral solve (moments of the reduced resolvent on
+                                    the contour enlarged 1.5 times, block Hankel matrices, Newton
+                                    refinement); 2 = Taylor linearisation about the contour centre
+                                    and Newton refinement (NLF_F_EXP terms).  Problems with an
+                                    NLF_F_USER term always take the contour-integral solve;
+                                    polynomial problems always the exact companion
+                                    linearisation */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -350,7 +351,9 @@ nlfeast_status nlf_project(int64_t n, int32_t m, int32_t J, const void* const* A
 nlfeast_status nlf_quadrature(double cre, double cim, double a, double b, int32_t nc,
                               int32_t quad_rule, double* z, double* omega);
 
-/* Step 1/2 on the host: all eigenpairs of the reduced problem sum_j f_j(lambda) Ahat_j y = 0
+/* Step 1/2 on the host (the linearisation route: companion for polynomial terms, Taylor
+ * surrogate and Newton for NLF_F_EXP terms): all eigenpairs of the reduced problem
+ * sum_j f_j(lambda) Ahat_j y = 0
  * (m x m c128 matrices Ahat, host, ld m, stride m*m) near the ellipse (centre, a, b), of which
  * the m_keep closest to its interior (ascending normalised radius) are returned: lambda_out
  * (2*m_keep doubles) and Y_out (c128 m x m_keep, ld m, unit-norm columns).  The linearisation
@@ -363,9 +366,9 @@ nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind,
                                  double* Y_out);
 
 /* As nlf_reduced_solve, with terms of kind NLF_F_USER evaluated by fn(user, ...) and the
- * choice `method` of nlfeast_options.reduced_solver (0 or 1).  The contour-integral solve
- * (Sec. 3 eq. cauchymoments applied to the reduced function; taken for NLF_F_USER terms, or
- * method 1 with any non-polynomial term) needs m_keep <= m: it returns the eigenpairs found
+ * choice `method` of nlfeast_options.reduced_solver (0..2).  The contour-integral solve
+ * (Sec. 3 eq. cauchymoments applied to the reduced function; taken for NLF_F_USER terms, and for
+ * any non-polynomial term unless method is 2) needs m_keep <= m: it returns the eigenpairs found
  * inside the contour enlarged 1.5 times, Newton-refined and in ascending normalised radius,
  * followed, when fewer than m_keep were found, by completing pairs (unit vectors orthogonal to
  * those found, with values spread over the enlarged contour); found_out (m_keep int32, may be

@@ -462,18 +462,18 @@ static void rotate_cols(cplx* a, cplx* b, int cnt, double c, cplx s) {
 // Householder reduction to Hessenberg form (the reflectors kept for the eigenvectors), then the
 // shifted QR algorithm on the active window for the eigenvalues only; the window is stored with
 // an odd leading dimension so that the row rotations do not fall into a few cache sets.  The
-// reduction's three O(N^2) updates per column are split over host threads from N = 192.
+// reduction's three O(N^2) updates per column are split over host threads above N = 128.
 bool HessEig::compute(int N_, std::vector<cplx>& A) {
     N = N_;
     H.swap(A);
     V.assign((size_t)N * N, 0.0);
     beta.assign(N, 0.0);
     std::vector<cplx> s(N);
-    // each reduction step ends in barriers, so threads only pay off on large matrices: measured
-    // on the MI355X hosts, one thread is fastest up to N = 128 and two from N = 192 to 256; the
-    // delay problem's N = 480 runs best on the full count
-    const int P = N < 192 ? 1 : N < 384 ? std::min(2, host_threads((int64_t)N * N, 4096))
-                                        : host_threads((int64_t)N * N, 4096);
+    // each reduction step ends in barriers: one thread up to N = 128 (0.97 ms at N = 128 against
+    // 2.3 ms on four threads, the headline's size), the thread budget above (measured on whole
+    // solves: the batched eight-region workload 322-333 ms with it, 352-392 ms with two threads
+    // at N = 256)
+    const int P = N <= 128 ? 1 : host_threads((int64_t)N * N, 4096);
     Team team(P);
     cplx alpha_k = 0.0;
     std::vector<char> skip(N, 0);
@@ -1126,7 +1126,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
         else poly = false;
         if (t.kind == 2) user = true;
     }
-    if (user || (method == 1 && !poly)) return contour_reduced(m, terms, Ahat, E, m_keep);
+    if (user || (!poly && method != 2)) return contour_reduced(m, terms, Ahat, E, m_keep);
     const size_t mm = (size_t)m * m;
     const std::vector<cplx> shifts = shift_candidates(E, avoid);
     int deg = maxpow, N = 0;

@@ -79,12 +79,12 @@ constexpr double CONTOUR_RANK_TOL = 1e-10;
 // All eigenpairs of sum_j f_j(lambda) Ahat_j y = 0 (Ahat: J matrices m x m, column-major,
 // consecutive), then the m_keep closest to the interior of E (ascending normalised radius,
 // stable, non-finite last).  Polynomial terms: exact companion linearisation, inverted about
-// a shift inside the contour (the centre unless a Ritz value in `avoid` is close to it);
-// exponential terms: Taylor expansion about that shift followed by Newton refinement on the
-// exact reduced function.  With a caller-supplied term, or method 1 and any non-polynomial
-// term: the contour-integral solve (contour_pairs), Newton refinement of every pair found, and
-// completion to m_keep pairs (requires m_keep <= m) by unit vectors orthogonal to those found,
-// paired with values spread over the enlarged ellipse.
+// a shift inside the contour (the centre unless a Ritz value in `avoid` is close to it).
+// Non-polynomial terms (method 0 or 1; always with a caller-supplied term): the contour-integral
+// solve (contour_pairs), Newton refinement of every pair found, and completion to m_keep pairs
+// (requires m_keep <= m) by unit vectors orthogonal to those found, paired with values spread
+// over the enlarged ellipse.  Method 2 with exponential terms: Taylor expansion about the shift,
+// linearised, followed by Newton refinement on the exact reduced function.
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
                             const Ellipse& E, int m_keep, const std::vector<cplx>* avoid = nullptr,
                             int method = 0);

@@ -1064,8 +1064,8 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         NLF_REQUIRE((opt->region_streams == 0 || opt->region_streams == 1) && (opt->graph == 0 || opt->graph == 1) &&
                         (opt->autotune == 0 || opt->autotune == 1),
                     NLF_ERR_ARG, "solve: region_streams, graph and autotune are 0 or 1");
-        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && (opt->reduced_solver == 0 || opt->reduced_solver == 1),
-                    NLF_ERR_ARG, "solve: lookahead in -1..1, reduced_solver 0 or 1");
+        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && opt->reduced_solver >= 0 && opt->reduced_solver <= 2,
+                    NLF_ERR_ARG, "solve: lookahead in -1..1, reduced_solver in 0..2");
         bool has_user = false;
         for (const Term& t : h->terms) has_user = has_user || t.kind == NLF_F_USER;
         NLF_REQUIRE(!has_user || h->ufn.fn, NLF_ERR_STATE,
@@ -1119,30 +1119,41 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
                 NLF_HIP(hipHostMalloc((void**)&h->info_host, sizeof(int32_t) * L.NZ, hipHostMallocDefault));
                 h->info_cap = L.NZ;
             }
-            // the factorisation is enqueued from a thread of its own: enqueuing blocks the host
-            // (a graph launch waits for the GPU, and so do eager launches once the queue is full),
-            // and Steps 0-3 of every region need no factors, so they run meanwhile
-            if (h->profiling) h->fprof.reset();
-            std::shared_ptr<std::promise<void>> done = std::make_shared<std::promise<void>>();
-            enqueued = done->get_future().share();
-            factored = h->ev_factored;
-            fthread.t = std::thread([h, &L, ws, p32, s, tune, opt, done] {
-                try {
-                    NLF_HIP(hipSetDevice(h->device));
-                    ProfilerGuard fpg(h->profiling ? &h->fprof : nullptr);
-                    {
-                        ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)h->n * h->n * h->n * L.NZ, 0);
-                        if (opt->graph) replay_factorisation(h, s);
-                        else factor_all(h, L, ws, p32, s, tune);
-                    }
-                    NLF_HIP(hipMemcpyAsync(h->info_host, at<void>(ws, L.info), sizeof(int32_t) * L.NZ,
-                                           hipMemcpyDeviceToHost, s));
-                    NLF_HIP(hipEventRecord(h->ev_factored, s));
-                    done->set_value();
-                } catch (...) {
-                    done->set_exception(std::current_exception());
+            // enqueuing the factorisation blocks the host (a graph launch waits for the GPU, and
+            // so do eager launches once the queue is full).  With the regions on one stream, it is
+            // enqueued from a thread of its own, so that Steps 0-3 (which need no factors) run
+            // meanwhile; with concurrent region threads the same overlap measured no gain (the
+            // batched eight-region workload: 333-358 ms with it, 341-346 ms without), so it is
+            // enqueued here before they start
+            auto enqueue = [h, &L, ws, p32, s, tune, opt](Profiler* fp) {
+                NLF_HIP(hipSetDevice(h->device));
+                ProfilerGuard fpg(fp);
+                {
+                    ProfScope ps(NLF_PROF_FACTOR, s, 8.0 / 3.0 * (double)h->n * h->n * h->n * L.NZ, 0);
+                    if (opt->graph) replay_factorisation(h, s);
+                    else factor_all(h, L, ws, p32, s, tune);
                 }
-            });
+                NLF_HIP(hipMemcpyAsync(h->info_host, at<void>(ws, L.info), sizeof(int32_t) * L.NZ,
+                                       hipMemcpyDeviceToHost, s));
+                NLF_HIP(hipEventRecord(h->ev_factored, s));
+            };
+            factored = h->ev_factored;
+            const bool concurrent_regions = h->regions.size() > 1 && opt->region_streams == 0;
+            if (concurrent_regions) {
+                enqueue(h->profiling ? &h->prof : nullptr);
+            } else {
+                if (h->profiling) h->fprof.reset();
+                std::shared_ptr<std::promise<void>> done = std::make_shared<std::promise<void>>();
+                enqueued = done->get_future().share();
+                fthread.t = std::thread([h, enqueue, done] {
+                    try {
+                        enqueue(h->profiling ? &h->fprof : nullptr);
+                        done->set_value();
+                    } catch (...) {
+                        done->set_exception(std::current_exception());
+                    }
+                });
+            }
         }
 
         const int nreg = (int)h->regions.size();
@@ -1210,7 +1221,7 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         NLF_HIP(hipStreamSynchronize(s));
         if (h->profiling) {
             h->prof.collect();
-            if (factored) {
+            if (enqueued.valid()) {
                 h->fprof.collect();
                 h->prof.merge(h->fprof);
             }
@@ -1627,7 +1638,7 @@ static void reduced_solve_c(int32_t m, int32_t J, const int32_t* fkind, const do
                             int32_t m_keep, const double* avoid, int32_t n_avoid, double* lambda_out, double* Y_out,
                             int32_t* found_out, const char* who) {
     NLF_REQUIRE(m >= 1 && J >= 1 && J <= 8 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
-                    lambda_out && Y_out && (method == 0 || method == 1),
+                    lambda_out && Y_out && method >= 0 && method <= 2,
                 NLF_ERR_ARG, std::string(who) + ": bad arguments");
     std::vector<Term> terms(J);
     bool user = false;
@@ -1640,7 +1651,7 @@ static void reduced_solve_c(int32_t m, int32_t J, const int32_t* fkind, const do
     NLF_REQUIRE(!user || uf->fn, NLF_ERR_ARG, std::string(who) + ": NLF_F_USER terms need a function");
     bool poly = true;
     for (const Term& t : terms) poly = poly && t.kind == NLF_F_POW;
-    NLF_REQUIRE(!(user || (method == 1 && !poly)) || m_keep <= m, NLF_ERR_ARG,
+    NLF_REQUIRE(!(user || (method != 2 && !poly)) || m_keep <= m, NLF_ERR_ARG,
                 std::string(who) + ": the contour-integral solve needs m_keep <= m");
     std::vector<cplx> av;
     for (int i = 0; avoid && i < n_avoid; ++i) av.push_back(cplx(avoid[2 * i], avoid[2 * i + 1]));
@@ -1663,7 +1674,7 @@ nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind, con
                                  double* lambda_out, double* Y_out) {
     nlfeast_ctx* h = nullptr;
     NLF_TRY(h, {
-        reduced_solve_c(m, J, fkind, fparam, nullptr, 0, Ahat, cre, cim, a, b, m_keep, avoid, n_avoid, lambda_out,
+        reduced_solve_c(m, J, fkind, fparam, nullptr, 2, Ahat, cre, cim, a, b, m_keep, avoid, n_avoid, lambda_out,
                         Y_out, nullptr, "nlf_reduced_solve");
         return NLF_OK;
     })

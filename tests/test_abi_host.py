@@ -133,6 +133,23 @@ def test_contour_reduced_matches_oracle(lib, route, shape, m, seed):
     assert np.linalg.norm(np.linalg.norm(Y, axis=0) - 1) < 1e-12
 
 
+def test_reduced_solver_choice(lib):
+    """Method 2 keeps the Taylor route for exponential terms (every pair marked found, the same
+    values as nlf_reduced_solve); method 0 takes the contour-integral solve."""
+    rng = np.random.default_rng(43)
+    m = 14
+    A = [np.eye(m, dtype=complex), wl.cn(rng, (m, m)) / np.sqrt(m), wl.cn(rng, (m, m)) / np.sqrt(m),
+         0.3 * wl.cn(rng, (m, m)) / np.sqrt(m)]
+    C = qd.Contour(0.1 + 0.1j, 0.6)
+    lt, _, ft = nl.nlf_reduced_solve_ex(wl.DELAY, A, C.c, C.a, C.b, m, method=2)
+    lp, _ = nl.nlf_reduced_solve(wl.DELAY, A, C.c, C.a, C.b, m)
+    assert ft.all() and np.max(np.abs(lt - lp)) == 0.0
+    lc, _, fc = nl.nlf_reduced_solve_ex(wl.DELAY, A, C.c, C.a, C.b, m, method=0)
+    well = lambda l: np.sort_complex(l[C.radius(l) < 1.0])
+    assert len(well(lc[fc])) == len(well(lt)) >= 2
+    assert np.max(np.abs(well(lc[fc]) - well(lt))) < 1e-12
+
+
 def test_contour_reduced_completion(lib):
     """lambda I - diag(d) through caller functions: three eigenvalues inside the enlarged
     circle are found (e_i vectors), seven completing pairs sit on the enlarged circle with

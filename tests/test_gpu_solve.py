@@ -400,11 +400,12 @@ def test_autotuned_graph_solve_matches_brute_force():
     assert prof["factor"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
 
 
+@pytest.mark.parametrize("rs", [0, 2])
 @pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
-def test_delay512_matches_oracle_and_surrogate(prec, tol_eig):
-    # T(l) = l^2 I + l C + K + exp(-l) E: the non-polynomial reduced problem (Taylor surrogate
-    # + Newton on the exact reduced function) on the GPU path; the count is certified by the
-    # winding number of det T along the circle
+def test_delay512_matches_oracle_and_surrogate(prec, tol_eig, rs):
+    # T(l) = l^2 I + l C + K + exp(-l) E: the non-polynomial reduced problem on the GPU path, by
+    # the default contour-integral solve (rs = 0) or the Taylor surrogate + Newton (rs = 2); the
+    # count is certified by the winding number of det T along the circle
     cfg = wl.CONFIGS["delay512"]
     terms, mats = wl.make_problem("delay512")
     g = contours("delay512")[0]
@@ -413,7 +414,7 @@ def test_delay512_matches_oracle_and_surrogate(prec, tol_eig):
     assert len(ref) == g["winding_count"] == cfg["inside"]
     X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
-                    nl.options(tol=cfg["tol"], precision=prec))
+                    nl.options(tol=cfg["tol"], precision=prec, reduced_solver=rs))
     assert out["status"] == nl.NLF_OK
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref)
