@@ -110,6 +110,30 @@ def test_example1_table1_on_gpu():
     assert out["iters"][0] <= 6
 
 
+def test_example1_left_vectors_are_conjugate_right_vectors():
+    # Example 1's A_j are real symmetric, so T(lambda)^T = T(lambda): the left solve on the same
+    # ellipse (its conjugate is itself) gives the same eigenvalues, and y = conj(x) up to a phase
+    terms, mats = wl.mass_spring(1000, 0.6202, 0.4807)
+    S = nl.NLFEAST(1000)
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour([dict(centre=-1.55, a=0.05, b=0.0035, nc=16, m0=22)])
+        opts = nl.options(tol=1e-10)
+        right = S.solve(opts, nl.to_colmajor(wl.initial_block(1000, 22, 2101)))
+        left = S.solve(opts, nl.to_colmajor(wl.initial_block(1000, 22, 2102)), left=True)
+        torch.cuda.synchronize()
+        Xr, Yl = nl.from_colmajor(right["X"]), nl.from_colmajor(left["X"])
+    finally:
+        S.close()
+    assert right["status"] == left["status"] == nl.NLF_OK
+    ri, li = converged(right, 1e-10), converged(left, 1e-10)
+    assert ri.sum() == li.sum() == 20
+    assert match_err(left["lam"][li], right["lam"][ri], 0.05) < 1e-12
+    for l, y in zip(left["lam"][li], Yl[:, li].T):
+        i = np.flatnonzero(ri)[np.argmin(np.abs(right["lam"][ri] - l))]
+        assert abs(abs(np.vdot(Xr[:, i].conj(), y)) - 1.0) < 1e-8
+
+
 def mass_spring_eigs(n, tau, kappa):
     """Closed form for lambda^2 I + lambda tau T3 + kappa T3, T3 = tridiag(-1, 3, -1): the
     coefficients share T3's eigenvectors, so each eigenvalue mu_j = 3 - 2 cos(j pi / (n + 1))
@@ -454,11 +478,13 @@ def test_lookahead_factors_equal_single_stream(prec, es):
         assert np.max(np.abs(o["lam"] - outs[0]["lam"])) < 1e-13
 
 
-@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP32_REFINE, 1e-9), (nl.NLF_PREC_FP64, 1e-10)])
-def test_delay8192_full_size(prec, tol_eig):
-    # the delay problem at full size (24 nodes of n = 8192, m0 = 160): every eigenvalue inside
-    # the circle against the surrogate + Rayleigh-refined reference, residuals recomputed on
-    # the host
+@pytest.mark.parametrize("prec,tol_eig,rs", [(nl.NLF_PREC_FP32_REFINE, 1e-9, 0), (nl.NLF_PREC_FP64, 1e-10, 0),
+                                             (nl.NLF_PREC_FP32_REFINE, 1e-9, 2)])
+def test_delay8192_full_size(prec, tol_eig, rs):
+    # the delay problem at full size (24 nodes of n = 8192, m0 = 160), reduced problem by the
+    # default contour-integral solve (rs = 0) or the Taylor route (rs = 2): every eigenvalue
+    # inside the circle against the surrogate + Rayleigh-refined reference, residuals
+    # recomputed on the host
     cfg = wl.CONFIGS["delay8192"]
     terms, mats = wl.make_problem("delay8192")
     g = contours("delay8192")[0]
@@ -466,7 +492,7 @@ def test_delay8192_full_size(prec, tol_eig):
     ref = np.array([complex(*v) for v in g["eigenvalues"]])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
                     wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"]),
-                    nl.options(tol=cfg["tol"], precision=prec))
+                    nl.options(tol=cfg["tol"], precision=prec, reduced_solver=rs))
     assert out["status"] == nl.NLF_OK
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref)
