@@ -345,6 +345,40 @@ def test_qep2048x8_batched_regions(prec, tol_eig):
         col += g["m0"]
 
 
+def test_qep2048x8_left_eigenvectors_concurrent_regions():
+    # the left solve over eight concurrent regions (adjoint problem, conjugate contours, FP32
+    # factors with FP64 refinement): every region's converged left eigenvalues are the
+    # brute-force set, and each y annihilates T(lambda) from the left
+    cfg = wl.CONFIGS["qep2048x8"]
+    terms, mats = wl.make_problem("qep2048x8")
+    gs = contours("qep2048x8")
+    regs = [dict(centre=complex(*g["centre"]), a=g["radius"], nc=cfg["nc"], m0=g["m0"]) for g in gs]
+    M = sum(g["m0"] for g in gs)
+    S = nl.NLFEAST(cfg["n"])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(Mx) for Mx in mats])
+        S.set_contour(regs, quad_rule=nl.NLF_QUAD_TRAPEZOID)
+        out = S.solve(nl.options(tol=cfg["tol"], precision=nl.NLF_PREC_FP32_REFINE),
+                      nl.to_colmajor(wl.initial_block(cfg["n"], M, 2104)), left=True)
+        torch.cuda.synchronize()
+        Y = nl.from_colmajor(out["X"])
+    finally:
+        S.close()
+    assert out["status"] == nl.NLF_OK
+    P = pb.Problem(terms, mats)
+    col = 0
+    for ri, g in enumerate(gs):
+        sl = slice(col, col + g["m0"])
+        ins = out["inside"][sl] & (out["res"][sl] <= cfg["tol"])
+        assert out["inside"][sl].sum() - ins.sum() <= 2
+        brute = np.array([complex(*v) for v in g["eigenvalues"]])
+        assert ins.sum() == len(brute), (ri, ins.sum(), len(brute))
+        assert match_err(out["lam"][sl][ins], brute, g["radius"]) < 1e-9
+        for l, y in zip(out["lam"][sl][ins], Y[:, sl][:, ins].T):
+            assert np.linalg.norm(y.conj() @ P.T(l)) <= 2 * cfg["tol"]
+        col += g["m0"]
+
+
 def _factor_bytes(S, n, nz, es):
     return S.ws[: nz * n * n * es].clone()
 
