@@ -62,11 +62,12 @@ USER_FN = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctyp
                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
 
-def user_function(py_fn):
+def user_function(py_fn, errors=None):
     """Wraps py_fn(term, param, z, want_deriv) -> (f, df) (complex numpy arrays shaped like z;
     df may be None when want_deriv is False) as an nlfeast_user_fn.  Keep the returned object
     alive while the library may call it.  An exception inside py_fn is reported to the
-    library as a failure (the call that asked returns NLF_ERR_ARG)."""
+    library as a failure (the call that asked returns NLF_ERR_ARG) and, when `errors` is a
+    list, appended to it."""
     def tramp(_user, term, param, count, z, f, df):
         try:
             zz = np.ctypeslib.as_array(z, shape=(2 * count,))
@@ -80,7 +81,9 @@ def user_function(py_fn):
                 dv = np.broadcast_to(np.asarray(dv, dtype=complex), zc.shape)
                 do[0::2], do[1::2] = dv.real, dv.imag
             return 0
-        except Exception:
+        except Exception as e:   # noqa: BLE001 - reported to the library as a failure
+            if errors is not None:
+                errors.append(e)
             return 1
     return USER_FN(tramp)
 
@@ -517,8 +520,11 @@ class NLFEAST:
         nlfeast_set_contour(self.h, regions, quad_rule)
 
     def set_user_function(self, py_fn):
-        """py_fn(term, param, z, want_deriv) -> (f, df) for the terms of kind 'fn'."""
-        self._user_fn = user_function(py_fn)
+        """py_fn(term, param, z, want_deriv) -> (f, df) for the terms of kind 'fn'.  An exception
+        raised by py_fn makes solve() raise NLFError(NLF_ERR_ARG) with that exception as its
+        cause."""
+        self._user_errors = []
+        self._user_fn = user_function(py_fn, self._user_errors)
         nlfeast_set_user_function(self.h, self._user_fn)
 
     def solve(self, opts, X0=None, left=False):
@@ -530,7 +536,15 @@ class NLFEAST:
             self.ws = None
             self.ws = torch.empty(need, dtype=torch.uint8, device=self.device)
         m_total = sum(r["m0"] for r in self.regions)
-        return nlfeast_solve(self.h, opts, self.ws, self.n, m_total, len(self.regions), X0, left=left)
+        errors = getattr(self, "_user_errors", None)
+        if errors:
+            errors.clear()
+        try:
+            return nlfeast_solve(self.h, opts, self.ws, self.n, m_total, len(self.regions), X0, left=left)
+        except NLFError as e:
+            if errors:
+                raise e from errors[0]
+            raise
 
     def profile(self):
         return nlfeast_get_profile(self.h)

@@ -622,6 +622,7 @@ def test_user_function_status_codes():
         with pytest.raises(nl.NLFError) as e:
             S.solve(nl.options())
         assert e.value.status == nl.NLF_ERR_ARG
+        assert isinstance(e.value.__cause__, RuntimeError)   # the function's own exception
         S.set_user_function(_pole_fn)
         out = S.solve(nl.options(tol=1e-11))
         assert out["status"] == nl.NLF_OK and out["m"][0] == 12
