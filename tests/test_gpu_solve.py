@@ -254,6 +254,31 @@ def test_damped4096_matches_brute_force(prec, tol_eig):
     assert np.max(hr) <= 2 * cfg["tol"]
 
 
+def test_restart_from_previous_ritz_vectors():
+    # Algorithm 1 accepts any X0: restarting from a converged solve's Ritz vectors (the
+    # checkpoint is X) needs a single Step 4 and returns the same eigenvalues
+    cfg = wl.CONFIGS["qep200"]
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    S = nl.NLFEAST(cfg["n"])
+    try:
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour([dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])])
+        opts = nl.options(tol=cfg["tol"])
+        first = S.solve(opts, nl.to_colmajor(wl.initial_block(cfg["n"], cfg["m0"], 2001)))
+        X = first["X"].clone()
+        again = S.solve(opts, X)
+        torch.cuda.synchronize()
+    finally:
+        S.close()
+    assert first["status"] == again["status"] == nl.NLF_OK
+    assert first["iters"][0] > 1 and again["iters"][0] == 1
+    a, b = converged(first, cfg["tol"]), converged(again, cfg["tol"])
+    assert a.sum() == b.sum() == len(g["eigenvalues"])
+    assert match_err(again["lam"][b], first["lam"][a], r) < 1e-12
+
+
 def test_m0_too_small_status():
     terms, mats = wl.mass_spring(50, 10.0, 5.0)      # r = 19 encloses 34 > m0 = 25
     out = gpu_solve(terms, mats, [dict(centre=-20.5, a=19.0, nc=8, m0=25)],
