@@ -903,15 +903,16 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
     }
     std::vector<cplx> fz((size_t)J * NP);   // the functions at every point, one call per term
     for (int j = 0; j < J; ++j) term_values(terms[j], z.data(), NP, &fz[(size_t)j * NP]);
-    // M_p, p < 2 KMAX: points spread over threads, each with its own partial sums
+    // M_p, p < 2 KMAX: points dealt to threads in a fixed pattern (q = t, t + nth, ...), each
+    // thread with its own partial sums, added in thread order: the sums do not depend on timing
     const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
     const int nth = std::max(1, std::min({hw, 16, NP / 4, (int)(mm * NP / 20000) + 1}));
     std::vector<std::vector<cplx>> part(nth, std::vector<cplx>(2 * KMAX * mm, 0.0));
     std::vector<double> isize(NP, 0.0);   // |w_q| ||T(z_q)^{-1}||_F, the integrand's size
-    std::atomic<int> next{0}, bad{0};
+    std::atomic<int> bad{0};
     auto work = [&](int t) {
         std::vector<cplx> Tz(mm), Inv(mm);
-        for (int q; (q = next.fetch_add(1)) < NP;) {
+        for (int q = t; q < NP; q += nth) {
             std::fill(Tz.begin(), Tz.end(), cplx(0.0));
             for (int j = 0; j < J; ++j) {
                 const cplx f = fz[(size_t)j * NP + q];

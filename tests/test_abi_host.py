@@ -150,6 +150,20 @@ def test_reduced_solver_choice(lib):
     assert np.max(np.abs(well(lc[fc]) - well(lt))) < 1e-12
 
 
+def test_contour_reduced_solve_is_reproducible(lib):
+    """The moments are summed in an order fixed by the point index and the thread count, so
+    repeated calls give bitwise-identical pairs (iteration counts do not vary between runs)."""
+    rng = np.random.default_rng(42)
+    m = 40
+    A = [np.eye(m, dtype=complex), wl.cn(rng, (m, m)) / np.sqrt(m), wl.cn(rng, (m, m)) / np.sqrt(m),
+         0.3 * wl.cn(rng, (m, m)) / np.sqrt(m)]
+    C = qd.Contour(0.1 + 0.1j, 0.6)
+    runs = [nl.nlf_reduced_solve_ex(wl.DELAY, A, C.c, C.a, C.b, m, method=0) for _ in range(5)]
+    for lam, Y, found in runs[1:]:
+        assert np.array_equal(lam, runs[0][0]) and np.array_equal(Y, runs[0][1])
+        assert np.array_equal(found, runs[0][2])
+
+
 def test_contour_reduced_completion(lib):
     """lambda I - diag(d) through caller functions: three eigenvalues inside the enlarged
     circle are found (e_i vectors), seven completing pairs sit on the enlarged circle with
