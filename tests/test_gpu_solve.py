@@ -627,6 +627,31 @@ def test_delay512_contour_reduced_solve(route):
     assert np.max(hr) <= 2 * cfg["tol"]
 
 
+@pytest.mark.parametrize("rs", [0, 2])
+def test_delay512_ellipse_region(rs):
+    # an ellipse inside the stored circle (a = r, b = r/2): its eigenvalues are the reference
+    # values it contains (6, none within 10% of its boundary), by the default contour-integral
+    # reduced solve on the enlarged ellipse and by the Taylor route
+    cfg = wl.CONFIGS["delay512"]
+    terms, mats = wl.make_problem("delay512")
+    g = contours("delay512")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    E = qd.Contour(c, r, 0.5 * r)
+    rho = E.radius(ref)
+    assert np.min(np.abs(rho - 1.0)) > 0.1
+    want = ref[rho < 1.0]
+    out = gpu_solve(terms, mats, [dict(centre=c, a=r, b=0.5 * r, nc=cfg["nc"], m0=16)],
+                    wl.initial_block(cfg["n"], 16, 2306), nl.options(tol=cfg["tol"], reduced_solver=rs))
+    assert out["status"] == nl.NLF_OK
+    ins = converged(out, cfg["tol"])
+    assert ins.sum() == len(want) == 6
+    # residuals <= tol = 1e-11 and eigenvalue condition numbers up to ~1e2 here: 1e-9
+    assert match_err(out["lam"][ins], want, r) < 1e-9
+    hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
+    assert np.max(hr) <= 2 * cfg["tol"]
+
+
 def test_user_function_status_codes():
     # a term of kind 'fn' without a function is a state error; a function that fails is an
     # argument error; both are detected on the host before any launch
