@@ -652,6 +652,33 @@ def test_delay512_ellipse_region(rs):
     assert np.max(hr) <= 2 * cfg["tol"]
 
 
+def test_option_and_state_validation():
+    # every option is checked on the host before any launch: out-of-range values return
+    # NLF_ERR_ARG, solving before set_coeffs/set_contour NLF_ERR_STATE, and a valid call after
+    # the rejected ones still solves
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    S = nl.NLFEAST(200)
+    try:
+        with pytest.raises(nl.NLFError) as e:
+            S.solve(nl.options())
+        assert e.value.status == nl.NLF_ERR_STATE
+        S.set_coeffs(terms, [nl.to_colmajor(M) for M in mats])
+        S.set_contour([dict(centre=complex(*g["centre"]), a=g["radius"], nc=8, m0=20)])
+        bad = [dict(reduced_solver=3), dict(reduced_solver=-1), dict(lookahead=2), dict(precision=7),
+               dict(tol=0.0), dict(max_iter=0), dict(lu_streams=5), dict(panel_width=3), dict(graph=2),
+               dict(region_streams=2), dict(autotune=2)]
+        for kw in bad:
+            with pytest.raises(nl.NLFError) as e:
+                S.solve(nl.options(**kw))
+            assert e.value.status == nl.NLF_ERR_ARG, kw
+        out = S.solve(nl.options(tol=1e-12))
+        assert out["status"] == nl.NLF_OK and out["m"][0] == len(g["eigenvalues"])
+    finally:
+        torch.cuda.synchronize()
+        S.close()
+
+
 def test_user_function_status_codes():
     # a term of kind 'fn' without a function is a state error; a function that fails is an
     # argument error; both are detected on the host before any launch
