@@ -227,7 +227,8 @@ def extra_leg(args, name, description, autotune, graph, with_fp64=False):
                     "iterations": [int(v) for v in o["iters"]], "factor_ms": lu_ms, "lu_tflops": tf,
                     "lu_frac_peak": tf / peak if tf else None,
                     "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
-                    "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()}}
+                    "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()},
+                    "hbm_kernels": hbm_kernels(p)}
     if "fp64" in out:
         out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
     return out
