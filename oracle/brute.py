@@ -101,18 +101,35 @@ def eigs_near(problem, sigma, k, rho):
     return sigma + companion_eigs_near(S, 0.0, k)
 
 
+def eigen_residual(problem, lam, seed=0, steps=2):
+    """Certificate that lam is an eigenvalue of T: ||T(lam) x|| with ||x|| = 1, x taken by
+    `steps` inverse-iteration steps x <- T(lam)^{-1} x from a seeded random vector (one LU of
+    T(lam)).  Since ||T(lam) x|| >= sigma_min(T(lam)) for every unit x, a small value bounds the
+    smallest singular value of T(lam), i.e. T(lam) is within that distance of a singular
+    matrix (Sec. 2: the eigenvalues are the points where T is singular)."""
+    rng = np.random.default_rng(seed)
+    n = problem.n
+    x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    T = problem.T(complex(lam))
+    lu = scipy.linalg.lu_factor(T, check_finite=False)
+    for _ in range(max(1, steps)):
+        x = scipy.linalg.lu_solve(lu, x / np.linalg.norm(x), check_finite=False)
+    x /= np.linalg.norm(x)
+    return float(np.linalg.norm(T @ x))
+
+
 def refine_eigenvalue(problem, lam, steps=3, seed=0):
     """Two-sided Rayleigh functional iteration on T itself: with x = T(l)^{-1} b and
     y = T(l)^{-H} c (one LU of T(l) per step), l <- l - (y^H T(l) x) / (y^H T'(l) x).
     Used to sharpen eigenvalues from the companion operator, whose non-normality lets
-    Arnoldi's residual test leave errors far above the residual.  Returns (l, ||T(l) x||)
-    with ||x|| = 1 from the last step."""
+    Arnoldi's residual test leave errors far above the residual.  Returns (l, res) with
+    res = eigen_residual(problem, l): the residual of a unit vector taken at the final l,
+    not at the l of the last step."""
     rng = np.random.default_rng(seed)
     n = problem.n
     b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
     l = complex(lam)
-    res = np.inf
     for _ in range(steps):
         T = problem.T(l)
         lu = scipy.linalg.lu_factor(T, check_finite=False)
@@ -120,14 +137,12 @@ def refine_eigenvalue(problem, lam, steps=3, seed=0):
         x /= np.linalg.norm(x)
         y = scipy.linalg.lu_solve(lu, c, trans=2, check_finite=False)
         y /= np.linalg.norm(y)
-        res = float(np.linalg.norm(T @ x))
         num = np.vdot(y, T @ x)
         den = np.vdot(y, problem.dT(l) @ x)
         if den == 0:
             break
         l = l - num / den
-    res = float(np.linalg.norm(problem.T(l) @ x))
-    return l, res
+    return l, eigen_residual(problem, l, seed=seed + 1)
 
 
 def logdet(M):
@@ -138,16 +153,26 @@ def logdet(M):
     return np.sum(np.log(d.astype(complex))) + (0 if sign > 0 else 1j * np.pi)
 
 
-def winding_count(problem, contour, npts=256, max_step=0.5):
+def winding_count(problem, contour, npts=256, max_step=0.5, deflate=None):
     """Number of eigenvalues of T inside C: (1/2 pi) times the total change of
-    arg det T(z) around C.  The sampling is refined until every step of the unwrapped
-    phase is below max_step radians."""
+    arg det T(z) around C (argument principle).  The sampling is refined until every step of
+    the unwrapped phase is below max_step radians.
+
+    deflate (optional): points mu_i, e.g. eigenvalues found by another method.  The phase
+    followed is then that of g(z) = det T(z) / prod_i (z - mu_i), and the count is the winding
+    number of g plus the number of mu_i inside C.  This is exact whatever the mu_i are (a
+    wrong or missing mu_i changes the winding of g by the same amount); it only makes the
+    phase vary slowly where the mu_i sit next to true eigenvalues, so far fewer samples are
+    needed when many eigenvalues lie inside."""
+    mu = np.asarray([] if deflate is None else deflate, dtype=complex)
     theta = np.linspace(0.0, 2 * np.pi, npts + 1)
     vals = {}
 
     def phase(t):
         if t not in vals:
-            vals[t] = np.angle(np.exp(1j * logdet(problem.T(contour.point(t))).imag))
+            z = contour.point(t)
+            ph = logdet(problem.T(z)).imag - np.sum(np.angle(z - mu))
+            vals[t] = np.angle(np.exp(1j * ph))
         return vals[t]
 
     pts = list(theta)
@@ -161,4 +186,4 @@ def winding_count(problem, contour, npts=256, max_step=0.5):
             continue
         total += d
         i += 1
-    return int(round(total / (2 * np.pi)))
+    return int(round(total / (2 * np.pi))) + int(np.sum(contour.inside(mu)))

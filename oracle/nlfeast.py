@@ -1,36 +1,34 @@
-"""Algorithm 1 (NLFEAST for T(lambda) x = 0), literally, in complex128 (oracle; test
-infrastructure only).
+"""Algorithm 1 of Sec. 4.2 (NLFEAST for T(lambda) x = 0) in complex128: the oracle, test
+infrastructure only.  `solve` runs the algorithm's Steps 0-5 in their order with the block
+contour integral of eq. nlfeast_int evaluated by the quadrature sum of Step 4.
 
-    Step 0  Q = X0, orthonormalise its columns.
-    Step 1  solve the projected problem Q^H T(lambda) Q y = 0.
-    Step 2  keep the m0 pairs closest to the interior of C: Lambda = diag(lambda_i),
-            X = [Q y_1, ..., Q y_m0].
-    Step 3  stop if ||T(lambda_i) Q y_i|| <= eps for every lambda_i inside C.
-    Step 4  Q = sum_j omega_j (X - T(z_j)^{-1} T(X, Lambda)) (z_j I - Lambda)^{-1}.
-    Step 5  orthonormalise Q (QR) and go to Step 1.
-
-(Sec. 4.2, Algorithm 1 and the block contour integral eq. nlfeast_int.)
-
-Readings where the paper is silent:
-* Ritz vectors are normalised, ||x_i||_2 = 1, so the Step 3 residual is absolute and
-  relative at once.
-* "inside C" is strictly inside (normalised radius < 1).
-* Step 3 is checked only after at least one Step 4 (iterations = number of Step 4
-  executions, as in "converges in three iterations" of Example 1); with no Ritz value
-  inside after 3 iterations the result is empty; the iteration cap defaults to 50.
-* if m0 or more Ritz values lie inside, the precondition of Algorithm 1 (fewer than m0
-  eigenvalues inside C) is violated and M0TooSmall is raised.
-* spurious Ritz values: with m0 well above the count, a Ritz value of the projected problem
-  can sit inside C without approximating any eigenvalue (the projected problem has more
-  eigenvalues than the subspace has dimensions); its residual stays large while the true
-  pairs converge.  Step 3 then also stops when, at iteration it >= 4, the number of
-  converged inside pairs is the same positive number as in each of the three previous
-  iterations and the largest residual among the unconverged inside pairs is at least half of
-  its value three iterations earlier; the unconverged inside pairs are reported as
-  spurious (eigenvalues: the converged inside pairs only).
-* Step 4 uses the literal sum of the paper; T(z_j) is factored once per contour
-  (the shifts are fixed) by LU with partial pivoting (scipy lu_factor).
-* Step 0/5 orthonormalisation is Householder QR (numpy.linalg.qr).
+Choices where the paper leaves room:
+* Ritz vectors are scaled to unit 2-norm, so the Step 3 residual is absolute and relative
+  at once.
+* A Ritz value counts as inside C when its normalised radius is below 1.
+* Step 3 may stop only after Step 4 has run at least once, so the iteration count is the
+  number of Step 4 executions (Example 1 converges "in three iterations" in this sense).
+  The iteration cap defaults to 50; with no Ritz value inside after 3 iterations the result
+  is empty.
+* When m0 or more Ritz values are inside, the algorithm's precondition (fewer than m0
+  eigenvalues inside C) does not hold and M0TooSmall is raised.
+* Spurious Ritz values (Sec. 4.2 calls them Ritz pairs that match no eigenpair of the full
+  problem): the projected problem has more eigenvalues than the subspace has dimensions, and
+  an extra one can land inside C.  Its residual does not shrink from one iteration to the
+  next, whereas the residual of a genuine pair shrinks by about the filter ratio
+  |rho(lambda_out)| / |rho(lambda_i)| per iteration, rho(l) = sum_k omega_k / (z_k - l)
+  being the rational filter of the quadrature and lambda_out the first eigenvalue the
+  subspace leaves out.  From iteration 2 on, every Ritz value is paired with one of the
+  previous iteration's (`match_previous`); an unconverged value inside is *stagnant* when its
+  residual exceeds theta_i times its partner's (`stagnant`), with
+  theta_i = min(0.97, max(0.25, (rho_min / |rho(lambda_i)|)^(1/3))), rho_min the smallest
+  |rho| over the selected values (the farthest selected value bounds |rho(lambda_out)| from
+  above; the cube root and the bounds leave a margin for a genuine pair).  Step 3 then stops
+  when at least one pair inside has converged and every other value inside is stagnant; the
+  stagnant ones are returned flagged as spurious.
+* Step 4 uses the quadrature sum exactly as the paper writes it; every T(z_j) is factored
+  once (the shifts are fixed) by LU with partial pivoting (scipy lu_factor).
+* Steps 0 and 5 orthonormalise by Householder QR (numpy.linalg.qr).
 """
 import time
 
@@ -60,13 +58,40 @@ class Result:
         return self.lam[self.inside & ~self.spurious]
 
 
-def stalled(history):
-    """The stopping rule for spurious Ritz values (module docstring)."""
-    if len(history) < 5:
-        return False
-    h = history[-4:]
-    n = h[-1]["n_conv"]
-    return n > 0 and all(x["n_conv"] == n for x in h) and h[-1]["max_unconv"] >= 0.5 * h[0]["max_unconv"]
+def match_previous(lam, prev):
+    """Pair each current Ritz value with at most one of the previous iteration's: repeatedly
+    take the closest unpaired pair (ties: lower current index, then lower previous index).
+    Returns, per current value, the index of its partner or -1."""
+    lam = np.asarray(lam, dtype=complex)
+    prev = np.asarray(prev, dtype=complex)
+    with np.errstate(invalid="ignore"):
+        d = np.abs(lam[:, None] - prev[None, :])
+    d = np.where(np.isfinite(d), d, np.inf)
+    partner = -np.ones(len(lam), dtype=np.int64)
+    used = np.zeros(len(prev), dtype=bool)
+    for f in np.argsort(d, axis=None, kind="stable"):
+        i, j = divmod(int(f), len(prev))
+        if not np.isfinite(d[i, j]):
+            break
+        if partner[i] < 0 and not used[j]:
+            partner[i] = j
+            used[j] = True
+    return partner
+
+
+def stagnant(lam, res, unconv, rho, prev_lam, prev_res):
+    """Mask of the unconverged values inside C (`unconv`) whose residual did not shrink by
+    the factor a genuine pair reaches (module docstring).  rho: |rho(lambda_i)| of every
+    selected value (0 for infinite ones)."""
+    finite = np.isfinite(lam)
+    rho_min = float(np.min(rho[finite])) if finite.any() else 0.0
+    partner = match_previous(lam, prev_lam)
+    out = np.zeros(len(lam), dtype=bool)
+    for i in np.flatnonzero(unconv):
+        theta = min(0.97, max(0.25, (rho_min / max(rho[i], 1e-300)) ** (1.0 / 3.0)))
+        before = prev_res[partner[i]] if partner[i] >= 0 else 0.0
+        out[i] = not (res[i] <= theta * before)
+    return out
 
 
 def orthonormalise(Q):
@@ -103,6 +128,7 @@ def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
         factors = [scipy.linalg.lu_factor(problem.T(zj), check_finite=False) for zj in z]
     Q = orthonormalise(X0)                                   # Step 0
     history = []
+    prev = None
     it = 0
     while True:
         Ahat = problem.project(Q)                            # Step 1
@@ -137,8 +163,13 @@ def solve(problem, contour, z, omega, X0, m0, tol, max_iter=50, factors=None,
             raise M0TooSmall("%d Ritz values inside C with m0 = %d" % (n_in, m0))
         if it >= 1 and n_in > 0 and np.all(res[inside] <= tol):   # Step 3
             return Result(lam, X, res, inside, it, history, True)
-        if it >= 4 and stalled(history):
-            return Result(lam, X, res, inside, it, history, True, spurious=unconv)
+        if it >= 2 and prev is not None and n_in > n_in - int(unconv.sum()) > 0:
+            rho = np.array([abs(np.sum(omega / (z - l))) if np.isfinite(l) else 0.0 for l in lam])
+            stag = stagnant(lam, res, unconv, rho, prev[0], prev[1])
+            history[-1]["n_stagnant"] = int(stag.sum())
+            if np.all(stag[unconv]):
+                return Result(lam, X, res, inside, it, history, True, spurious=stag)
+        prev = (lam.copy(), res.copy())
         if it >= 3 and n_in == 0:
             return Result(lam, X, res, inside, it, history, True)
         if it >= max_iter:

@@ -34,6 +34,15 @@ Recipes (contour seed 3000 + id):
               radius at the gap midpoint, rejected under a 1% gap; the nearest p + 2 sharpened
               by two steps of two-sided Rayleigh functional iteration on T itself.  delay512
               also stores the winding number of det T along the circle.
+
+Certificates added to a stored entry without redoing its search (the reference values stay as
+they are):
+  --certify NAME   max_residual = the largest eigen_residual over the stored eigenvalues: the
+                   residual of a unit vector taken by inverse iteration at each eigenvalue
+                   itself, an upper bound of the smallest singular value of T there.
+  --winding NAME   winding_count = the number of eigenvalues inside the circle by the argument
+                   principle (det T from LU factors along the circle), with the stored values
+                   deflated from the phase only to keep the number of samples small.
   rational300 A0 - l I + l/(l - sigma) C: all 2n companion eigenvalues of the quadratic
               (l - sigma) T(l); centre = a seeded pick among them with |c| <= 0.9; radius =
               midpoint between the 12th and 13th distances, rejected under a 5% gap.
@@ -219,6 +228,39 @@ RECIPES = {"qep200": qep200, "damped4096": damped4096, "qep2048x8": qep2048x8, "
            "rational300": rational300}
 
 
+def certify(name):
+    terms, mats = wl.make_problem(name)
+    P = pb.Problem(terms, mats)
+    data = json.load(open(OUT))
+    for g in data[name]["regions"]:
+        t0 = time.time()
+        res = [brute.eigen_residual(P, complex(*v), seed=i) for i, v in enumerate(g["eigenvalues"])]
+        g["max_residual"] = float(max(res))
+        print("  %s: %d certified, max residual %.3g (%.0fs)" % (name, len(res), max(res), time.time() - t0),
+              flush=True)
+    return data[name]
+
+
+def winding(name):
+    terms, mats = wl.make_problem(name)
+    P = pb.Problem(terms, mats)
+    data = json.load(open(OUT))
+    for g in data[name]["regions"]:
+        t0 = time.time()
+        C = qd.Contour(complex(*g["centre"]), g["radius"])
+        mu = [complex(*v) for v in g["eigenvalues"]]
+        g["winding_count"] = brute.winding_count(P, C, npts=128, max_step=0.8, deflate=mu)
+        print("  %s: winding count %d, %d stored (%.0fs)" % (name, g["winding_count"], len(mu), time.time() - t0),
+              flush=True)
+    return data[name]
+
+
+def store(name, entry):
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}   # re-read: merge, not clobber
+    data[name] = entry
+    json.dump(data, open(OUT, "w"), indent=1)
+
+
 def main(names):
     for name in names:
         t0 = time.time()
@@ -227,10 +269,12 @@ def main(names):
         print(name, "regions", len(entry["regions"]),
               "inside", [len(g["eigenvalues"]) for g in entry["regions"]],
               "%.1fs" % entry["seconds"], flush=True)
-        data = json.load(open(OUT)) if os.path.exists(OUT) else {}   # re-read: merge, not clobber
-        data[name] = entry
-        json.dump(data, open(OUT, "w"), indent=1)
+        store(name, entry)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(RECIPES))
+    if len(sys.argv) == 3 and sys.argv[1] in ("--certify", "--winding"):
+        name = sys.argv[2]
+        store(name, (certify if sys.argv[1] == "--certify" else winding)(name))
+    else:
+        main(sys.argv[1:] or list(RECIPES))
