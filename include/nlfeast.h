@@ -44,7 +44,11 @@ typedef enum {
     NLF_ERR_SINGULAR = 5,        /* exact zero pivot: a quadrature node sits on an eigenvalue */
     NLF_ERR_M0_TOO_SMALL = 6,    /* m0 or more Ritz values inside a contour (Algorithm 1
                                     requires fewer than m0 eigenvalues inside C) */
-    NLF_ERR_NOT_CONVERGED = 7    /* max_iter reached; outputs hold the last iterate */
+    NLF_ERR_NOT_CONVERGED = 7,   /* max_iter reached; outputs hold the last iterate */
+    NLF_SPURIOUS = 8             /* not an error: every eigenpair inside converged, and some
+                                    Ritz values inside were identified as spurious (Sec. 4.2:
+                                    Ritz pairs that match no eigenpair of the full problem);
+                                    they are flagged with inside_out = 2 */
 } nlfeast_status;
 
 typedef enum {
@@ -160,17 +164,25 @@ nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* o
  *   X_dev_out          c128 n x sum(m0): the Ritz vectors (unit 2-norm), region by region
  *   lambda_out         2 * sum(m0) doubles: the Ritz values (re, im), selection order
  *   resid_out          sum(m0) doubles: ||T(lambda_i) x_i||_2
- *   inside_out         sum(m0) int32: 1 if lambda_i is strictly inside its contour
+ *   inside_out         sum(m0) int32: 0 outside its contour, 1 strictly inside, 2 strictly
+ *                      inside and identified as a spurious Ritz value (see below)
  *   m_out, iters_out   per region: converged eigenpairs inside (resid <= tol), Step 4
  *                      executions
- * Step 3 stops a region when every Ritz value inside has converged, or when the converged
- * count inside has stayed the same (and positive) for three iterations while the largest
- * unconverged residual inside has not halved: the unconverged values inside are then spurious
- * Ritz values of the projected problem (returned with inside = 1 and resid > tol).
+ * Step 3 stops a region when every Ritz value inside has converged.  Spurious Ritz values
+ * (Sec. 4.2) are identified by their residuals: from iteration 2 on, each Ritz value is paired
+ * with the nearest unpaired one of the previous iteration (nearest pairs first), and an
+ * unconverged value inside is stagnant when its residual exceeds theta times its partner's,
+ * theta = min(0.97, max(0.25, (rho_min / |rho(lambda)|)^(1/3))), where
+ * rho(l) = sum_k omega_k / (z_k - l) is the quadrature filter and rho_min its smallest modulus
+ * over the selected Ritz values (a genuine pair's residual falls by about that filter ratio per
+ * iteration).  When at least one pair inside has converged and every other value inside is
+ * stagnant, the region stops, those values are returned with inside_out = 2 and the status is
+ * NLF_SPURIOUS.
  * Factorisations of T(z_k) are cached in the workspace and reused by the next solve with the
  * same handle, coefficients, contours, precision and workspace pointer.
- * Returns NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL or NLF_ERR_SINGULAR (a hard
- * error wins over the convergence statuses when several regions fail). */
+ * Returns NLF_OK, NLF_SPURIOUS, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL or NLF_ERR_SINGULAR
+ * (with several regions: a hard error first, then NOT_CONVERGED / M0_TOO_SMALL, then
+ * NLF_SPURIOUS). */
 nlfeast_status nlfeast_solve(nlfeast_handle h, const nlfeast_options* opt, void* ws_dev,
                              size_t ws_bytes, const void* X0_dev, void* X_dev_out,
                              double* lambda_out, double* resid_out, int32_t* inside_out,

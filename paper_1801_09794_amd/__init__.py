@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnlfeast.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "nlfeast.h")
 
 NLF_OK, NLF_ERR_ARG, NLF_ERR_NOMEM, NLF_ERR_DEVICE, NLF_ERR_STATE = 0, 1, 2, 3, 4
-NLF_ERR_SINGULAR, NLF_ERR_M0_TOO_SMALL, NLF_ERR_NOT_CONVERGED = 5, 6, 7
+NLF_ERR_SINGULAR, NLF_ERR_M0_TOO_SMALL, NLF_ERR_NOT_CONVERGED, NLF_SPURIOUS = 5, 6, 7, 8
 NLF_F_POW, NLF_F_EXP, NLF_F_USER = 0, 1, 2
 NLF_PREC_FP64, NLF_PREC_FP32_REFINE = 0, 1
 NLF_QUAD_GAUSS_LEGENDRE, NLF_QUAD_TRAPEZOID = 0, 1
@@ -30,7 +30,7 @@ KERNEL_CLASSES = ["assemble", "lu_gemm", "lu_panel", "lu_trsm", "lu_laswp", "sol
 
 STATUS_NAMES = {0: "NLF_OK", 1: "NLF_ERR_ARG", 2: "NLF_ERR_NOMEM", 3: "NLF_ERR_DEVICE",
                 4: "NLF_ERR_STATE", 5: "NLF_ERR_SINGULAR", 6: "NLF_ERR_M0_TOO_SMALL",
-                7: "NLF_ERR_NOT_CONVERGED"}
+                7: "NLF_ERR_NOT_CONVERGED", 8: "NLF_SPURIOUS"}
 
 
 class NLFError(RuntimeError):
@@ -281,7 +281,8 @@ def nlfeast_get_profile(h):
 def nlfeast_solve(h, opts, ws, n, m_total, nreg, X0=None, X_out=None, left=False):
     """Runs Algorithm 1 on every region.  ws: device tensor of at least workspace_size bytes;
     X0: column-major device tensor (sum m0, n) or None.  Returns a dict with status,
-    lam (complex), res, inside (bool), m and iters per region, and X (device tensor).
+    lam (complex), res, inside (bool: strictly inside the contour), spurious (bool: inside and
+    identified as a spurious Ritz value), m and iters per region, and X (device tensor).
     left=True calls nlfeast_solve_left: X then holds the left eigenvectors."""
     import torch
     if X_out is None:
@@ -296,10 +297,10 @@ def nlfeast_solve(h, opts, ws, n, m_total, nreg, X0=None, X_out=None, left=False
             _ptr(X0), _ptr(X_out), lam.ctypes.data_as(P_dbl),
             res.ctypes.data_as(P_dbl), ins.ctypes.data_as(P_i32),
             mo.ctypes.data_as(P_i32), it.ctypes.data_as(P_i32))
-    if st not in (NLF_OK, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL):
+    if st not in (NLF_OK, NLF_SPURIOUS, NLF_ERR_NOT_CONVERGED, NLF_ERR_M0_TOO_SMALL):
         _check(st, h)
-    return dict(status=st, lam=lam[0::2] + 1j * lam[1::2], res=res, inside=ins.astype(bool),
-                m=mo, iters=it, X=X_out)
+    return dict(status=st, lam=lam[0::2] + 1j * lam[1::2], res=res, inside=ins != 0,
+                spurious=ins == 2, m=mo, iters=it, X=X_out)
 
 
 # --------------------------------------------------------------------------- step-level API

@@ -632,6 +632,65 @@ void replay_factorisation(nlfeast_ctx* h, hipStream_t s) {
     }
 }
 
+// Spurious Ritz values (Sec. 4.2: Ritz pairs that match no eigenpair of the full problem).
+// Each current Ritz value is paired with at most one of the previous iteration's, nearest pairs
+// first (ties: lower current index, then lower previous index); -1 = unpaired.
+std::vector<int> match_previous(const std::vector<cplx>& cur, const std::vector<cplx>& prev) {
+    const int m = (int)cur.size(), p = (int)prev.size();
+    std::vector<std::pair<double, int64_t>> d;
+    d.reserve((size_t)m * p);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < p; ++j) {
+            const double v = std::abs(cur[i] - prev[j]);
+            if (std::isfinite(v)) d.emplace_back(v, (int64_t)i * p + j);
+        }
+    std::stable_sort(d.begin(), d.end(),
+                     [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) {
+                         return a.first < b.first || (a.first == b.first && a.second < b.second);
+                     });
+    std::vector<int> partner(m, -1);
+    std::vector<char> used(p, 0);
+    for (const auto& e : d) {
+        const int i = (int)(e.second / p), j = (int)(e.second % p);
+        if (partner[i] < 0 && !used[j]) {
+            partner[i] = j;
+            used[j] = 1;
+        }
+    }
+    return partner;
+}
+
+// The unconverged Ritz values inside C whose residual did not shrink by the filter's
+// contraction bound: a genuine pair's residual falls by about |rho(lambda_out)| / |rho(lambda_i)|
+// per iteration (rho the quadrature filter, lambda_out the first eigenvalue the subspace leaves
+// out, bounded by the farthest selected value, rho_min); stagnant means res_i > theta_i times its
+// partner's, theta_i = min(0.97, max(0.25, (rho_min / |rho(lambda_i)|)^(1/3))).
+std::vector<char> stagnant(const std::vector<cplx>& lam, const std::vector<double>& res,
+                           const std::vector<char>& unconv, const std::vector<cplx>& z,
+                           const std::vector<cplx>& w, const std::vector<cplx>& prev_lam,
+                           const std::vector<double>& prev_res) {
+    const int m = (int)lam.size();
+    std::vector<double> rho(m, 0.0);
+    double rho_min = INFINITY;
+    for (int i = 0; i < m; ++i) {
+        if (!std::isfinite(lam[i].real()) || !std::isfinite(lam[i].imag())) continue;
+        cplx sum = 0.0;
+        for (size_t k = 0; k < z.size(); ++k) sum += w[k] / (z[k] - lam[i]);
+        rho[i] = std::abs(sum);
+        rho_min = std::min(rho_min, rho[i]);
+    }
+    if (!std::isfinite(rho_min)) rho_min = 0.0;
+    const std::vector<int> partner = match_previous(lam, prev_lam);
+    std::vector<char> out(m, 0);
+    for (int i = 0; i < m; ++i) {
+        if (!unconv[i]) continue;
+        const double theta = std::min(0.97, std::max(0.25, std::cbrt(rho_min / std::max(rho[i], 1e-300))));
+        const double before = partner[i] >= 0 ? prev_res[partner[i]] : 0.0;
+        out[i] = !(res[i] <= theta * before);
+    }
+    return out;
+}
+
 struct RegionIO {
     const void* X0;
     void* Xout;
@@ -718,8 +777,10 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         bool refine_needed = true;
         ReducedResult rr;
         int it = 0, n_in = 0, n_conv = 0;
-        std::vector<int> inside(m), conv_hist;
-        std::vector<double> unconv_hist;
+        std::vector<int> inside(m);
+        std::vector<char> spurious(m, 0);
+        std::vector<cplx> prev_lam;
+        std::vector<double> prev_res;
         int rstatus = NLF_OK;
         const z128* LU128 = at<z128>(ws, L.fact) + (size_t)node0 * nn;
         const z64* LU64 = at<z64>(ws, L.fact) + (size_t)node0 * nn;
@@ -769,7 +830,8 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             d2h_sync(s, res.data(), norms_d, sizeof(double) * m);
             n_in = 0;
             n_conv = 0;
-            double maxres = 0.0, max_unconv = 0.0;
+            double maxres = 0.0;
+            std::vector<char> unconv(m, 0);
             for (int i = 0; i < m; ++i) {
                 if (!std::isfinite(rr.lambda[i].real())) res[i] = INFINITY;
                 inside[i] = E.radius(rr.lambda[i]) < 1.0;
@@ -777,23 +839,35 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                     ++n_in;
                     maxres = std::max(maxres, res[i]);
                     if (res[i] <= opt->tol) ++n_conv;
-                    else max_unconv = std::max(max_unconv, res[i]);
+                    else unconv[i] = 1;
                 }
             }
-            conv_hist.push_back(n_conv);
-            unconv_hist.push_back(max_unconv);
             if (opt->verbose)
                 fprintf(stderr, "[nlfeast] region %d it %d inside %d converged %d max_res %.3e\n", ri, it, n_in,
                         n_conv, maxres);
             if (n_in >= m) { rstatus = NLF_ERR_M0_TOO_SMALL; break; }
             if (it >= 1 && n_in > 0 && maxres <= opt->tol) break;
-            // spurious Ritz values inside C: the converged count has not moved for three
-            // iterations and the worst unconverged residual has not halved in that time
-            if (it >= 4 && n_conv > 0) {
-                bool same = true;
-                for (int q = 1; q <= 3; ++q) same = same && conv_hist[it - q] == n_conv;
-                if (same && max_unconv >= 0.5 * unconv_hist[it - 3]) break;
+            // spurious Ritz values inside C: stop once every inside value that has not
+            // converged is stagnant
+            if (it >= 2 && !prev_lam.empty() && n_conv > 0 && n_conv < n_in) {
+                const std::vector<char> st = stagnant(rr.lambda, res, unconv, zn, wn, prev_lam, prev_res);
+                bool all = true;
+                int n_st = 0;
+                for (int i = 0; i < m; ++i) {
+                    if (unconv[i] && !st[i]) all = false;
+                    n_st += st[i];
+                }
+                if (opt->verbose)
+                    fprintf(stderr, "[nlfeast] region %d it %d stagnant %d of %d unconverged inside\n", ri, it, n_st,
+                            n_in - n_conv);
+                if (all) {
+                    spurious = st;
+                    rstatus = NLF_SPURIOUS;
+                    break;
+                }
             }
+            prev_lam = rr.lambda;
+            prev_res = res;
             if (it >= 3 && n_in == 0) break;
             if (it >= opt->max_iter) { rstatus = NLF_ERR_NOT_CONVERGED; break; }
             // the factors are needed from here on: wait for the factorisation launched before
@@ -890,7 +964,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             io.lambda[2 * (col0 + i)] = l.real();
             io.lambda[2 * (col0 + i) + 1] = l.imag();
             io.resid[col0 + i] = res[i];
-            io.inside[col0 + i] = inside[i];
+            io.inside[col0 + i] = spurious[i] ? 2 : inside[i];
         }
         io.m_out[ri] = n_conv;
         io.iters[ri] = it;
@@ -898,6 +972,7 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         res_out.status = rstatus;
         if (rstatus == NLF_ERR_M0_TOO_SMALL) res_out.msg = "m0 or more Ritz values inside a contour";
         if (rstatus == NLF_ERR_NOT_CONVERGED) res_out.msg = "not converged within max_iter";
+        if (rstatus == NLF_SPURIOUS) res_out.msg = "spurious Ritz values inside a contour (inside_out = 2)";
     } catch (const nlf::Error& e) {
         res_out.status = e.status;
         res_out.msg = e.msg;
@@ -1244,12 +1319,17 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
                 h->factors_prec = opt->precision;
             }
         }
+        // precedence: hard errors, then NOT_CONVERGED / M0_TOO_SMALL, then SPURIOUS, then OK
+        auto rank = [](int st) {
+            if (st == NLF_OK) return 0;
+            if (st == NLF_SPURIOUS) return 1;
+            if (st == NLF_ERR_NOT_CONVERGED || st == NLF_ERR_M0_TOO_SMALL) return 2;
+            return 3;
+        };
         for (int ri = 0; ri < nreg; ++ri) {
             const int st = out[ri].status;
-            if (st == NLF_OK) continue;
-            const bool soft = st == NLF_ERR_NOT_CONVERGED || st == NLF_ERR_M0_TOO_SMALL;
-            const bool cur_soft = status == NLF_OK || status == NLF_ERR_NOT_CONVERGED || status == NLF_ERR_M0_TOO_SMALL;
-            if (!soft || cur_soft) {
+            const bool keep_hard = rank(status) == 3;
+            if (rank(st) > rank(status) || (rank(st) == 2 && rank(status) == 2 && !keep_hard)) {
                 status = st;
                 msg = out[ri].msg;
             }

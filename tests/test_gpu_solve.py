@@ -54,11 +54,18 @@ def gpu_solve(terms, mats, regions, X0, opts, quad_rule=nl.NLF_QUAD_GAUSS_LEGEND
     return out
 
 
+def status_ok(out):
+    """NLF_OK, or NLF_SPURIOUS exactly when some Ritz value inside is flagged spurious."""
+    sp = out["spurious"]
+    assert out["status"] == (nl.NLF_SPURIOUS if sp.any() else nl.NLF_OK), (out["status"], int(sp.sum()))
+    return True
+
+
 def converged(out, tol):
-    """Converged pairs inside the contour; a spurious Ritz value of the projected problem may
-    remain inside unconverged (at most two are tolerated)."""
+    """Converged pairs inside the contour.  Every Ritz value inside that has not converged
+    must be flagged as spurious, and no converged one may be."""
     ins = out["inside"] & (out["res"] <= tol)
-    assert out["inside"].sum() - ins.sum() <= 2
+    assert np.array_equal(out["inside"] & ~ins, out["spurious"])
     return ins
 
 
@@ -77,7 +84,7 @@ def test_qep200_matches_oracle_and_brute_force(prec, tol_eig):
     X0 = wl.initial_block(200, 20, 2001)
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=8, m0=20)], X0,
                     nl.options(tol=cfg["tol"], precision=prec))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(brute) == 10 and out["m"][0] == 10
     assert match_err(out["lam"][ins], brute, r) < tol_eig
@@ -101,7 +108,7 @@ def test_example1_table1_on_gpu():
                     if l.strip() and not l.startswith("#")])
     out = gpu_solve(terms, mats, [dict(centre=-1.55, a=0.05, b=0.0035, nc=16, m0=22)],
                     wl.initial_block(1000, 22, 2101), nl.options(tol=1e-10))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, 1e-10)
     assert ins.sum() == 20
     assert np.max(np.abs(np.sort(out["lam"][ins].real) - np.sort(tab))) < 6e-11
@@ -125,7 +132,7 @@ def test_example1_left_vectors_are_conjugate_right_vectors():
         Xr, Yl = nl.from_colmajor(right["X"]), nl.from_colmajor(left["X"])
     finally:
         S.close()
-    assert right["status"] == left["status"] == nl.NLF_OK
+    assert status_ok(right) and status_ok(left)
     ri, li = converged(right, 1e-10), converged(left, 1e-10)
     assert ri.sum() == li.sum() == 20
     assert match_err(left["lam"][li], right["lam"][ri], 0.05) < 1e-12
@@ -155,7 +162,7 @@ def test_example2_overdamped_on_gpu(prec, tol_eig):
     assert len(want) == 19
     out = gpu_solve(terms, mats, [dict(centre=-20.5, a=9.5, nc=8, m0=25)],
                     wl.initial_block(50, 25, 2102), nl.options(tol=1e-10, precision=prec))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, 1e-10)
     assert ins.sum() == 19 and out["m"][0] == 19
     assert match_err(out["lam"][ins], want, 20.5) < tol_eig
@@ -177,7 +184,7 @@ def test_example3_scattering_matches_companion(prec, tol_eig):
     assert len(want) == 42
     out = gpu_solve(terms, mats, [dict(centre=0.0, a=15.5, nc=16, m0=60)],
                     wl.initial_block(n, 60, 2103), nl.options(tol=1e-10, precision=prec))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, 1e-10)
     assert ins.sum() == 42 and out["m"][0] == 42
     assert match_err(out["lam"][ins], want, 15.5) < tol_eig
@@ -206,8 +213,8 @@ def test_cubic_pep_matches_companion(prec, tol_eig):
     assert len(want) == 14
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=16, m0=32)],
                     wl.initial_block(n, 32, 2107), nl.options(tol=1e-11, precision=prec))
-    assert out["status"] == nl.NLF_OK
-    ins = out["inside"] & (out["res"] <= 1e-11)
+    assert status_ok(out)
+    ins = converged(out, 1e-11)
     assert ins.sum() == 14 and out["m"][0] == 14
     assert match_err(out["lam"][ins], want, r) < tol_eig
     hr = host_residuals(terms, mats, out["Xh"][:, ins], out["lam"][ins])
@@ -227,7 +234,7 @@ def test_quartic1024_matches_brute_force(prec):
     brute = np.array([complex(*v) for v in g["eigenvalues"]])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
                     wl.initial_block(cfg["n"], cfg["m0"], 2007), nl.options(tol=cfg["tol"], precision=prec))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(brute) == 15 and out["m"][0] == 15
     assert match_err(out["lam"][ins], brute, r) < 1e-9
@@ -235,8 +242,12 @@ def test_quartic1024_matches_brute_force(prec):
     assert np.max(hr) <= 2 * cfg["tol"]
 
 
-@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
-def test_damped4096_matches_brute_force(prec, tol_eig):
+@pytest.mark.parametrize("prec,tol_eig,graph", [(nl.NLF_PREC_FP64, 1e-10, 0), (nl.NLF_PREC_FP64, 1e-10, 1),
+                                                (nl.NLF_PREC_FP32_REFINE, 1e-9, 0), (nl.NLF_PREC_FP32_REFINE, 1e-9, 1)])
+def test_damped4096_matches_brute_force(prec, tol_eig, graph):
+    # the mass-spring-damper problem at full size (16 nodes of n = 4096), eager or with the
+    # factorisation captured and replayed as graph segments (the benchmarked launch
+    # configuration): the 40 eigenvalues inside against the certified reference set
     cfg = wl.CONFIGS["damped4096"]
     terms, mats = wl.make_problem("damped4096")
     g = contours("damped4096")[0]
@@ -244,8 +255,8 @@ def test_damped4096_matches_brute_force(prec, tol_eig):
     brute = np.array([complex(*v) for v in g["eigenvalues"]])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
                     wl.initial_block(4096, cfg["m0"], 2002),
-                    nl.options(tol=cfg["tol"], precision=prec))
-    assert out["status"] == nl.NLF_OK
+                    nl.options(tol=cfg["tol"], precision=prec, graph=graph))
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(brute) == 40
     assert match_err(out["lam"][ins], brute, r) < tol_eig
@@ -272,7 +283,7 @@ def test_restart_from_previous_ritz_vectors():
         torch.cuda.synchronize()
     finally:
         S.close()
-    assert first["status"] == again["status"] == nl.NLF_OK
+    assert status_ok(first) and status_ok(again)
     assert first["iters"][0] > 1 and again["iters"][0] == 1
     a, b = converged(first, cfg["tol"]), converged(again, cfg["tol"])
     assert a.sum() == b.sum() == len(g["eigenvalues"])
@@ -292,7 +303,7 @@ def test_empty_contour_returns_no_pairs():
     terms, mats = wl.make_problem("qep200")
     out = gpu_solve(terms, mats, [dict(centre=4.0 + 4.0j, a=0.05, nc=8, m0=6)],
                     wl.initial_block(200, 6, 9), nl.options(tol=1e-12))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     assert out["m"][0] == 0 and out["iters"][0] == 3 and not out["inside"].any()
 
 
@@ -332,7 +343,7 @@ def test_regions_concurrent_equal_sequential():
     X0 = wl.initial_block(200, 40, 2001)
     outs = [gpu_solve(terms, mats, regs, X0, nl.options(tol=1e-12, region_streams=k)) for k in (0, 1)]
     for o in outs:
-        assert o["status"] == nl.NLF_OK
+        assert status_ok(o)
     a, b = outs
     assert np.array_equal(a["inside"], b["inside"]) and np.array_equal(a["m"], b["m"])
     assert np.array_equal(a["iters"], b["iters"])
@@ -354,13 +365,13 @@ def test_qep2048x8_batched_regions(prec, tol_eig):
     M = sum(g["m0"] for g in gs)
     out = gpu_solve(terms, mats, regs, wl.initial_block(cfg["n"], M, 2000 + cfg["id"]),
                     nl.options(tol=cfg["tol"], precision=prec), quad_rule=nl.NLF_QUAD_TRAPEZOID)
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     col = 0
     for ri, g in enumerate(gs):
         sl = slice(col, col + g["m0"])
-        # converged pairs inside; a spurious Ritz value inside C (never converging) may remain
+        # converged pairs inside; every other value inside is flagged spurious
         ins = out["inside"][sl] & (out["res"][sl] <= cfg["tol"])
-        assert out["inside"][sl].sum() - ins.sum() <= 2
+        assert np.array_equal(out["inside"][sl] & ~ins, out["spurious"][sl])
         brute = np.array([complex(*v) for v in g["eigenvalues"]])
         assert ins.sum() == len(brute) == out["m"][ri], (ri, ins.sum(), len(brute))
         assert match_err(out["lam"][sl][ins], brute, g["radius"]) < tol_eig
@@ -389,13 +400,13 @@ def test_qep2048x8_left_eigenvectors_concurrent_regions():
         Y = nl.from_colmajor(out["X"])
     finally:
         S.close()
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     P = pb.Problem(terms, mats)
     col = 0
     for ri, g in enumerate(gs):
         sl = slice(col, col + g["m0"])
         ins = out["inside"][sl] & (out["res"][sl] <= cfg["tol"])
-        assert out["inside"][sl].sum() - ins.sum() <= 2
+        assert np.array_equal(out["inside"][sl] & ~ins, out["spurious"][sl])
         brute = np.array([complex(*v) for v in g["eigenvalues"]])
         assert ins.sum() == len(brute), (ri, ins.sum(), len(brute))
         assert match_err(out["lam"][sl][ins], brute, g["radius"]) < 1e-9
@@ -428,7 +439,7 @@ def test_graph_replays_equal_eager(prec, es):
         out = S.solve(nl.options(tol=1e-12, precision=prec, graph=1), X0)
         torch.cuda.synchronize()
         assert torch.equal(_factor_bytes(S, 200, 14, es), F0), rep
-        assert out["status"] == nl.NLF_OK
+        assert status_ok(out)
         assert np.array_equal(out["inside"], ref["inside"])
         assert np.max(np.abs(out["lam"] - ref["lam"])) < 1e-13
         _ = torch.ones(1000, device="cuda").sum().item()    # eager work between replays
@@ -477,7 +488,7 @@ def test_autotuned_graph_solve_matches_brute_force():
                   nl.to_colmajor(wl.initial_block(200, 20, 2001)))
     prof = S.profile()
     S.close()
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, 1e-12)
     assert match_err(out["lam"][ins], brute, r) < 1e-9
     assert prof["factor"]["launches"] == 1 and prof["lu_gemm"]["launches"] == 0
@@ -498,7 +509,7 @@ def test_delay512_matches_oracle_and_surrogate(prec, tol_eig, rs):
     X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
                     nl.options(tol=cfg["tol"], precision=prec, reduced_solver=rs))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref)
     assert match_err(out["lam"][ins], ref, r) < tol_eig
@@ -552,7 +563,7 @@ def test_delay8192_full_size(prec, tol_eig, rs):
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
                     wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"]),
                     nl.options(tol=cfg["tol"], precision=prec, reduced_solver=rs))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref)
     assert match_err(out["lam"][ins], ref, r) < tol_eig
@@ -585,7 +596,7 @@ def test_rational300_user_function_matches_brute_force(prec, tol_eig):
     X0 = wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"])
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
                     nl.options(tol=cfg["tol"], precision=prec), user_fn=_pole_fn)
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref) == 12 and out["m"][0] == 12
     assert match_err(out["lam"][ins], ref, r) < tol_eig
@@ -619,7 +630,7 @@ def test_delay512_contour_reduced_solve(route):
     else:
         out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])], X0,
                         nl.options(tol=cfg["tol"], reduced_solver=1))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(ref) == cfg["inside"]
     assert match_err(out["lam"][ins], ref, r) < 1e-10
@@ -643,7 +654,7 @@ def test_delay512_ellipse_region(rs):
     want = ref[rho < 1.0]
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, b=0.5 * r, nc=cfg["nc"], m0=16)],
                     wl.initial_block(cfg["n"], 16, 2306), nl.options(tol=cfg["tol"], reduced_solver=rs))
-    assert out["status"] == nl.NLF_OK
+    assert status_ok(out)
     ins = converged(out, cfg["tol"])
     assert ins.sum() == len(want) == 6
     # residuals <= tol = 1e-11 and eigenvalue condition numbers up to ~1e2 here: 1e-9
@@ -673,7 +684,7 @@ def test_option_and_state_validation():
                 S.solve(nl.options(**kw))
             assert e.value.status == nl.NLF_ERR_ARG, kw
         out = S.solve(nl.options(tol=1e-12))
-        assert out["status"] == nl.NLF_OK and out["m"][0] == len(g["eigenvalues"])
+        assert status_ok(out) and out["m"][0] == len(g["eigenvalues"])
     finally:
         torch.cuda.synchronize()
         S.close()
@@ -702,7 +713,7 @@ def test_user_function_status_codes():
         assert isinstance(e.value.__cause__, RuntimeError)   # the function's own exception
         S.set_user_function(_pole_fn)
         out = S.solve(nl.options(tol=1e-11))
-        assert out["status"] == nl.NLF_OK and out["m"][0] == 12
+        assert status_ok(out) and out["m"][0] == 12
     finally:
         torch.cuda.synchronize()
         S.close()
@@ -748,7 +759,7 @@ def test_qep200_left_eigenvectors(prec):
         right["Xh"] = nl.from_colmajor(right["X"])
     finally:
         S.close()
-    assert right["status"] == left["status"] == nl.NLF_OK
+    assert status_ok(right) and status_ok(left)
     assert prof["factor"]["launches"] == 0          # the cached factors were reused
     ins = _left_checks(terms, mats, left, cfg["tol"], r, brute)
     P = pb.Problem(terms, mats)
@@ -780,7 +791,7 @@ def test_delay512_left_eigenvectors(prec):
         left["Xh"] = nl.from_colmajor(left["X"])
     finally:
         S.close()
-    assert left["status"] == nl.NLF_OK
+    assert status_ok(left)
     _left_checks(terms, mats, left, cfg["tol"], r, ref)
 
 
@@ -801,7 +812,7 @@ def test_rational300_left_eigenvectors_user_function():
         left["Xh"] = nl.from_colmajor(left["X"])
     finally:
         S.close()
-    assert left["status"] == nl.NLF_OK
+    assert status_ok(left)
     sig = terms[2][1]
     P = pb.Problem([terms[0], terms[1], ("fn", pb.ScalarFunction(lambda z: wl.pole_value(z, sig),
                                                                  lambda z: wl.pole_deriv(z, sig)))], mats)
