@@ -6,12 +6,17 @@ triangular solves against the residual block, accumulation, orthonormalisation) 
 coefficient matrices and X0 already resident in HBM.  The factorisation cache is invalidated
 before every step so each step pays the LU.
 
-Prints one JSON line with the headline FP64 figure, the FP32-LU + FP64-refinement form on the
-same problem, the roofline of the dominant kernel (the complex GEMMs of the LU trailing
-updates, timed with HIP events on the solve stream inside the timed region), and the CPU
-oracle timed on a bounded sample of the same workload.
+The headline is the largest single-GPU workload, delay8192 (T(l) = l^2 I + l C + K +
+exp(-l) E, n = 8192, 24 nodes, m0 = 160) in FP64, with the FP32-LU + FP64-refinement form of
+the same problem beside it, the roofline of the dominant kernel (the complex GEMMs of the LU
+trailing updates at n = 8192 x 24 nodes, timed with HIP events on the solve stream inside the
+timed region), and the CPU oracle timed on a bounded sample of the same workload.  Further
+legs: damped4096 (the FP64 mass-spring-damper problem, graph-replayed factorisation), the
+eight-region batched qep2048x8 in FP64 and in FP32 + refinement, the node-count sweep,
+left eigenvectors and a caller-supplied function.  Every leg reports its converged eigenvalues'
+largest relative error against the stored reference set.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu] [--no-fp32]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu] [--headline-only]
 """
 import argparse
 import json
@@ -30,31 +35,27 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="damped4096")
+    ap.add_argument("--workload", default="delay8192")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload in FP64 (the profiled command)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the eight-region batched workload (qep2048x8)")
-    ap.add_argument("--no-delay", action="store_true",
-                    help="skip the delay workload (delay8192)")
+                    help="skip the damped4096 and eight-region batched (qep2048x8) legs")
     ap.add_argument("--no-nc-sweep", action="store_true",
                     help="skip the sweep over the number of quadrature nodes (quartic1024)")
     ap.add_argument("--no-left", action="store_true",
                     help="skip the left-eigenvector leg on the headline workload")
     ap.add_argument("--no-user-fn", action="store_true",
                     help="skip delay8192 with its exponential supplied as a caller function")
-    ap.add_argument("--no-delay-fp64", action="store_true",
-                    help="run the delay workload in FP32 + refinement only")
-    ap.add_argument("--fp64-legs", action="store_true",
-                    help="also run the batched workload in FP64 (the delay workload always runs in both)")
     ap.add_argument("--panel-width", type=int, default=0,
                     help="LU panel width per workgroup, 4..32 (0 = library default)")
     ap.add_argument("--refine-eta", type=float, default=0.05,
                     help="FP32+refine: refinement target ||E_k|| <= eta ||R||")
     ap.add_argument("--graph", type=int, default=1,
-                    help="damped4096 legs: 1 (default) replays the factorisation as captured "
-                         "hipGraph segments with the trailing updates launched (and timed) between "
-                         "them; 0 launches every kernel eagerly")
+                    help="headline and damped4096 legs: 1 (default) replays the factorisation as "
+                         "captured hipGraph segments with the trailing updates launched (and timed) "
+                         "between them; 0 launches every kernel eagerly")
     ap.add_argument("--lookahead", type=int, default=0,
                     help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
     ap.add_argument("--lu-streams", type=int, default=0,
@@ -62,17 +63,15 @@ def parse():
     ap.add_argument("--probe-lu", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration), then one FP64 "
                          "batched blocked LU of the headline shape, nothing else")
+    ap.add_argument("--probe-n", type=int, default=8192)
+    ap.add_argument("--probe-batch", type=int, default=24)
     return ap.parse_args()
 
 
-# The FP64 factorisation of the headline workload: 16 node matrices of n = 4096.
-PROBE = dict(n=4096, batch=16)
-
-
-def probe_lu():
+def probe_lu(n, bt):
     """Counter runs: a plain device copy of known size (to scale the HBM counters), then one
-    batched blocked LU of the headline shape, whose lu_update_kernel launches are the
-    dominant kernel's."""
+    batched blocked LU of n x n complex128 matrices (the headline: 24 of n = 8192), whose
+    lu_update_kernel launches are the dominant kernel's."""
     import torch
     import paper_1801_09794_amd as nl
     torch.cuda.set_device(0)
@@ -81,7 +80,6 @@ def probe_lu():
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    n, bt = PROBE["n"], PROBE["batch"]
     g = torch.Generator(device="cuda").manual_seed(7)
     A = torch.randn((bt, n, n), dtype=torch.complex128, device="cuda", generator=g)
     ipiv = torch.empty((bt, n), dtype=torch.int32, device="cuda")
@@ -90,7 +88,7 @@ def probe_lu():
     dinv = torch.empty(bt * nl.nlf_lu_inverse_elems(n), dtype=torch.complex128, device="cuda")
     nl.nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv)
     torch.cuda.synchronize()
-    print(json.dumps(dict(probe="blocked LU c128", copy_bytes=2 * (1 << 27) * 8, **PROBE)))
+    print(json.dumps(dict(probe="blocked LU c128", copy_bytes=2 * (1 << 27) * 8, n=n, batch=bt)))
 
 
 def source_digest():
@@ -103,10 +101,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM traffic per launch of the dominant kernel from the committed counter summary, or
-    None when the GEMM or LU source changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "lu_update_c128_n4096_b16_traffic.txt")
+def load_traffic(n, batch):
+    """HBM traffic per launch of the dominant kernel from the committed counter summary of
+    that shape, or None when there is none or the GEMM or LU source changed after the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", "lu_update_c128_n%d_b%d_traffic.txt" % (n, batch))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -204,33 +203,38 @@ def reference_error(name, regions, out, tol):
     return worst
 
 
-def extra_leg(args, name, description, autotune, graph, with_fp64=False):
-    """A parity configuration beside the headline: FP32 LU + FP64 refinement (and FP64 when
-    with_fp64 or --fp64-legs), converged eigenvalues checked against the stored brute-force
-    reference."""
+def leg_stats(args, name, key, n, nz, regions, cfg, t, o, p):
+    c = converged_pairs(o, cfg["tol"])
+    f = p["factor"]
+    lu_ms = f["ms"] / max(f["launches"], 1)
+    tf = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
+    peak = PEAK["fp32_mfma_tflops"] if key == "fp32_refine" else PEAK["fp64_mfma_tflops"]
+    g = p["lu_gemm"]
+    gt = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
+    return {"value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
+            "spurious_flagged": int(o["spurious"].sum()), "status": int(o["status"]),
+            "iterations": [int(v) for v in o["iters"]], "factor_ms": lu_ms, "lu_tflops": tf,
+            "lu_frac_peak": tf / peak if tf else None,
+            "trailing_gemm_tflops": gt, "trailing_gemm_frac_peak": gt / peak if gt else None,
+            "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
+            "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()},
+            "hbm_kernels": hbm_kernels(p)}
+
+
+def extra_leg(args, name, description, autotune, graph):
+    """A workload beside the headline in FP64 and in FP32 LU + FP64 refinement (same inputs,
+    same tolerance), with the speedup of the precision form over FP64 on this workload and the
+    converged eigenvalues checked against the stored reference."""
     import paper_1801_09794_amd as nl
     cfg, terms, mats, regions, X0 = load_workload(name)
     n, nz = cfg["n"], sum(r["nc"] for r in regions)
     out = {"workload": description % dict(n=n, m0=[r["m0"] for r in regions], nc=cfg["nc"], nz=nz,
                                           tol=cfg["tol"], inside=cfg.get("inside") or 0)}
-    precs = [("fp32_refine", nl.NLF_PREC_FP32_REFINE)]
-    if args.fp64_legs or with_fp64:
-        precs.append(("fp64", nl.NLF_PREC_FP64))
-    for key, prec in precs:
+    for key, prec in (("fp64", nl.NLF_PREC_FP64), ("fp32_refine", nl.NLF_PREC_FP32_REFINE)):
         t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph)
-        c = converged_pairs(o, cfg["tol"])
-        f = p["factor"]
-        lu_ms = f["ms"] / max(f["launches"], 1)
-        tf = 8.0 / 3.0 * n ** 3 * nz / (lu_ms * 1e-3) / 1e12 if lu_ms > 0 else None
-        peak = PEAK["fp32_mfma_tflops"] if key == "fp32_refine" else PEAK["fp64_mfma_tflops"]
-        out[key] = {"value": c / t, "unit": "eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
-                    "iterations": [int(v) for v in o["iters"]], "factor_ms": lu_ms, "lu_tflops": tf,
-                    "lu_frac_peak": tf / peak if tf else None,
-                    "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
-                    "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()},
-                    "hbm_kernels": hbm_kernels(p)}
-    if "fp64" in out:
-        out["fp32_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
+        out[key] = leg_stats(args, name, key, n, nz, regions, cfg, t, o, p)
+    out["fp32_refine_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
+    out["fp32_refine_vs_fp64_eigenpairs_per_s"] = out["fp32_refine"]["value"] / out["fp64"]["value"]
     return out
 
 
@@ -261,14 +265,14 @@ def user_function_leg(args):
 
 
 def left_leg(args):
-    """Left eigenvectors (eigentriples) of the headline problem: after one right solve, each left
+    """Left eigenvectors (eigentriples) of damped4096: after one right solve, each left
     solve runs Algorithm 1 on the adjoint function with the cached factors (no factorisation);
     left eigenpairs per second, the largest ||T(lambda)^H y||, and the distance of the left
     eigenvalues from the right ones."""
     import numpy as np
     import torch
     import paper_1801_09794_amd as nl
-    cfg, terms, mats, regions, X0 = load_workload(args.workload)
+    cfg, terms, mats, regions, X0 = load_workload("damped4096")
     S = nl.NLFEAST(cfg["n"], 0)
     S.set_coeffs(terms, [nl.to_colmajor(M, "cuda:0") for M in mats])
     S.set_contour(regions)
@@ -290,7 +294,7 @@ def left_leg(args):
     ok = left["inside"] & (left["res"] <= cfg["tol"])
     c = int(np.sum(ok))
     return {"workload": "left eigenvectors of %s after its right solve (adjoint problem on the conjugate "
-                        "contour, cached factors through adjoint solves), FP64" % args.workload,
+                        "contour, cached factors through adjoint solves), FP64" % "damped4096",
             "value": c / t, "unit": "left eigenpairs/s", "ms_per_step": t * 1e3, "converged": c,
             "iterations": [int(v) for v in left["iters"]], "factorisation_launches": fac,
             "max_left_residual": float(np.max(left["res"][ok])) if c else None,
@@ -356,9 +360,13 @@ def converged_pairs(out, tol):
     return int(np.sum(ok))
 
 
-def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters):
-    """The oracle on a bounded sample: LU of 4 of the n_c node matrices and one full
-    iteration (Steps 1-5 with every node's solve), extrapolated to the whole solve."""
+def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters, sample_nodes=2):
+    """The oracle (numpy/scipy complex128, as it stands) on a bounded sample of the headline
+    workload, extrapolated to the whole solve: the assembly + LU of `sample_nodes` of the n_c
+    node matrices, one pass of Steps 1-3 (projections, the reduced problem by the oracle's own
+    route, Ritz vectors, block residual), the Step 4 solves against the residual block at the
+    sampled nodes, and the Step 5 QR.  Whole solve = n_c LUs + iterations x (Steps 1-3 +
+    n_c solves + QR) + one final Steps 1-3."""
     import numpy as np
     import scipy.linalg
     from oracle import nlfeast as onl, problem as pb, quadrature as qd, reduced
@@ -372,31 +380,52 @@ def cpu_baseline(cfg, terms, mats, regions, X0, gpu_iters):
     C = qd.Contour(g["centre"], g["a"])
     z, w = qd.nodes_weights(C, g["nc"])
     m0 = g["m0"]
-    nsample = 4
     t0 = time.perf_counter()
-    facs = [scipy.linalg.lu_factor(P.T(zk), check_finite=False) for zk in z[:nsample]]
-    t_lu = (time.perf_counter() - t0) / nsample
-    # one iteration of Steps 1-5 (solves re-use the sampled factors cyclically)
+    facs = [scipy.linalg.lu_factor(P.T(zk), check_finite=False) for zk in z[:sample_nodes]]
+    t_lu = (time.perf_counter() - t0) / sample_nodes
     Q = onl.orthonormalise(X0[:, :m0])
     t0 = time.perf_counter()
     Ahat = P.project(Q)
     lam_all, Y_all = reduced.solve_reduced(P.terms, Ahat, C)
     sel = reduced.select(lam_all, C, m0)
-    lam = lam_all[sel]
-    X = Q @ Y_all[:, sel]
+    lam, Y = lam_all[sel].astype(complex), Y_all[:, sel]
+    if not P.is_polynomial:
+        for i in range(m0):
+            if np.isfinite(lam[i]):
+                lam[i], Y[:, i] = reduced.newton_polish(P.terms, Ahat, lam[i], Y[:, i])
+    lam = np.where(np.isfinite(lam), lam, 0.0)
+    X = Q @ Y
     X /= np.linalg.norm(X, axis=0)
     R = P.block_residual(X, lam)
-    facs_all = [facs[k % nsample] for k in range(len(z))]
-    Q = onl.orthonormalise(onl.step4(facs_all, X, R, lam, z, w))
-    t_it = time.perf_counter() - t0
-    est = t_lu * len(z) + t_it * (gpu_iters + 1)
-    return est, cores, dict(t_lu=t_lu, t_iter=t_it, nodes=len(z), sample_lus=nsample)
+    t_123 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Qn = onl.step4(facs, X, R, lam, z[:sample_nodes], w[:sample_nodes])
+    t_solve = (time.perf_counter() - t0) / sample_nodes
+    t0 = time.perf_counter()
+    onl.orthonormalise(Qn)
+    t_qr = time.perf_counter() - t0
+    nodes = len(z)
+    est = t_lu * nodes + gpu_iters * (t_123 + nodes * t_solve + t_qr) + t_123
+    return est, cores, dict(t_lu=t_lu, t_123=t_123, t_solve=t_solve, t_qr=t_qr, nodes=nodes,
+                            sample_lus=sample_nodes, iters=gpu_iters)
+
+
+def oracle_full_run(name):
+    """The oracle's complete run on this workload, if one is stored (tests/golden/oracle_runs.json:
+    written once by tests/golden/make_oracle_runs.py on the build host, whose cores it states)."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_runs.json")
+    if not os.path.exists(path):
+        return None
+    e = json.load(open(path)).get(name)
+    if not e:
+        return None
+    return {k: e[k] for k in ("seconds", "converged", "iterations", "cores", "host") if k in e}
 
 
 def main():
     args = parse()
     if args.probe_lu:
-        probe_lu()
+        probe_lu(args.probe_n, args.probe_batch)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -407,18 +436,20 @@ def main():
     nl.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg, terms, mats, regions, X0 = load_workload(args.workload)
+    name = args.workload
+    cfg, terms, mats, regions, X0 = load_workload(name)
     n = cfg["n"]
+    nnodes = sum(r["nc"] for r in regions)
 
     t64, out64, prof = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, True, graph=args.graph)
     conv64 = converged_pairs(out64, cfg["tol"])
     value = conv64 / t64
     lu = prof["lu_gemm"]
     lu_tflops = lu["flops"] / (lu["ms"] * 1e-3) / 1e12 if lu["ms"] > 0 else 0.0
-    nnodes = sum(r["nc"] for r in regions)
     lu_flops_total = 8.0 / 3.0 * n ** 3 * nnodes
     # wall span of assembly + factorisation of all nodes (panels overlap the updates)
     lu_phase_ms = prof["factor"]["ms"] / args.steps
+    kinds = ", ".join({"pow": "l^%d", "exp": "exp(-%gl)"}[k] % p for k, p in terms)
     result = {
         "metric": "converged eigenpairs/sec + LU TFLOP/s (% MFMA peak), FP32+refine vs FP64",
         "value": value,
@@ -433,28 +464,34 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: quadratic mass-spring-damper T(l) = l^2 A2 + l A1 + A0, n=%d dense "
-                        "complex128, circle enclosing %d eigenvalues, m0=%d, %d Gauss-Legendre "
-                        "nodes, tol %.0e, FP64 LU" % (args.workload, n, conv64, regions[0]["m0"],
-                                                      regions[0]["nc"], cfg["tol"]),
+            "workload": "%s: T(l) = sum_j f_j(l) A_j with f_j in {%s}, n=%d dense complex128, %d "
+                        "region(s), circle enclosing %d eigenvalues, m0=%d, %d Gauss-Legendre nodes, "
+                        "tol %.0e, FP64 LU" % (name, kinds, n, len(regions), conv64, regions[0]["m0"],
+                                               regions[0]["nc"], cfg["tol"]),
             "n": n, "m0": regions[0]["m0"], "nodes": nnodes, "regions": len(regions),
             "parallelism": "single GPU, nodes batched",
             "launch": "factorisation replayed as hipGraph segments" if args.graph else "eager launches",
         },
         "converged": conv64,
+        "spurious_flagged": int(out64["spurious"].sum()),
+        "status": int(out64["status"]),
         "iterations": int(out64["iters"][0]),
+        "max_rel_err_vs_reference": reference_error(name, regions, out64, cfg["tol"]),
         "lu": {"tflops_phase": lu_flops_total / (lu_phase_ms * 1e-3) / 1e12 if lu_phase_ms > 0 else None,
                "phase_ms": lu_phase_ms,
+               "phase_frac_fp64_peak": (lu_flops_total / (lu_phase_ms * 1e-3) / 1e12) / PEAK["fp64_mfma_tflops"]
+               if lu_phase_ms > 0 else None,
                "trailing_gemm_tflops": lu_tflops,
                "trailing_gemm_frac_fp64_peak": lu_tflops / PEAK["fp64_mfma_tflops"]},
         "roofline": {
-            "kernel": "lu_update_kernel<double, 2, 2, 8> (rank-512 trailing updates of the blocked LU)",
+            "kernel": "lu_update_kernel<double, 2, 2, 8> (rank-512 trailing updates of the blocked LU, "
+                      "%d complex128 matrices of n = %d)" % (nnodes, n),
             "bound": "mfma",
             "achieved": lu_tflops if lu["ms"] > 0 else None,
             "peak": PEAK["fp64_mfma_tflops"],
             "unit": "TFLOP/s",
             "frac": lu_tflops / PEAK["fp64_mfma_tflops"] if lu["ms"] > 0 else None,
-            "traffic": load_traffic(),
+            "traffic": load_traffic(n, nnodes),
             "traffic_note": "HBM bytes per launch, averaged over the lu_update_kernel launches "
                             "of one FP64 factorisation of this shape, from FETCH_SIZE + "
                             "WRITE_SIZE counters scaled by a 1 GiB copy (profiles/)",
@@ -466,51 +503,47 @@ def main():
         "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof.items()},
         "hbm_kernels": hbm_kernels(prof),
     }
-    if not args.no_fp32:
+    if not args.headline_only and not args.no_fp32:
         t32, out32, prof32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True,
                                      graph=args.graph)
-        conv32 = converged_pairs(out32, cfg["tol"])
-        err = eig_diff(out32, out64, cfg["tol"], regions[0]["a"])
-        lu32 = prof32["lu_gemm"]
-        result["fp32_refine"] = {
-            "value": conv32 / t32, "ms_per_step": t32 * 1e3, "converged": conv32,
-            "iterations": int(out32["iters"][0]), "speedup_vs_fp64": t64 / t32,
-            "max_rel_eig_diff_vs_fp64": err,
-            "trailing_gemm_tflops": lu32["flops"] / (lu32["ms"] * 1e-3) / 1e12 if lu32["ms"] > 0 else None,
-            "trailing_gemm_frac_fp32_peak": (lu32["flops"] / (lu32["ms"] * 1e-3) / 1e12) / PEAK["fp32_mfma_tflops"]
-            if lu32["ms"] > 0 else None,
-            "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in prof32.items()},
-        }
-    if not args.no_batched and args.workload != "qep2048x8":
-        result["batched"] = extra_leg(
-            args, "qep2048x8",
-            "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
-            "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
-            "parameters), tol %(tol).0e", autotune=1, graph=1)
-        b32 = result["batched"]["fp32_refine"]
-        b32["vs_fp64_headline"] = b32["value"] / value if value else None
-    if not args.no_delay and args.workload != "delay8192":
-        result["delay"] = extra_leg(
-            args, "delay8192",
-            "delay8192: T(l) = l^2 I + l C + K + exp(-l) E, n=%(n)d dense complex128, circle "
-            "enclosing %(inside)d eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, tol %(tol).0e",
-            autotune=0, graph=0, with_fp64=not args.no_delay_fp64)
-    if not args.no_nc_sweep and args.workload != "quartic1024":
-        result["nc_sweep"] = nc_sweep(args)
-    if not args.no_left:
-        result["left_eigenvectors"] = left_leg(args)
-    if not args.no_user_fn and not args.no_delay:
-        result["user_function"] = user_function_leg(args)
-    if not args.no_cpu:
-        est, cores, detail = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
+        st = leg_stats(args, name, "fp32_refine", n, nnodes, regions, cfg, t32, out32, prof32)
+        st["speedup_vs_fp64"] = t64 / t32
+        st["max_rel_eig_diff_vs_fp64"] = eig_diff(out32, out64, cfg["tol"], regions[0]["a"])
+        result["fp32_refine"] = st
+    if not args.headline_only and not args.no_cpu:
+        est, cores, d = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
         result["cpu_baseline"] = {
             "value": conv64 / est, "unit": "eigenpairs/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle (numpy/scipy complex128) on the same workload: LU of %d of the %d "
-                      "node matrices (%.2f s each) and one full NLFEAST iteration (%.2f s), "
-                      "extrapolated to %d LUs + %d iterations = %.1f s per solve"
-                      % (detail["sample_lus"], detail["nodes"], detail["t_lu"], detail["t_iter"],
-                         detail["nodes"], int(out64["iters"][0]) + 1, est),
+            "sample": "oracle (numpy/scipy complex128) on %s: assembly + LU of %d of the %d node matrices "
+                      "(%.2f s each), one pass of Steps 1-3 (%.2f s), the Step 4 solves at the sampled "
+                      "nodes (%.2f s per node) and the Step 5 QR (%.2f s); extrapolated to %d LUs + %d "
+                      "iterations (the GPU solve's count) + the final Steps 1-3 = %.1f s per solve"
+                      % (name, d["sample_lus"], d["nodes"], d["t_lu"], d["t_123"], d["t_solve"], d["t_qr"],
+                         d["nodes"], d["iters"], est),
         }
+        full = oracle_full_run(name)
+        if full:
+            result["cpu_baseline"]["full_run_build_host"] = full
+    del mats
+    if not args.headline_only:
+        if not args.no_batched and name != "damped4096":
+            result["damped4096"] = extra_leg(
+                args, "damped4096",
+                "damped4096: quadratic mass-spring-damper T(l) = l^2 A2 + l A1 + A0, n=%(n)d dense "
+                "complex128, circle enclosing 40 eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, "
+                "factorisation replayed as hipGraph segments, tol %(tol).0e", autotune=0, graph=args.graph)
+        if not args.no_batched and name != "qep2048x8":
+            result["batched"] = extra_leg(
+                args, "qep2048x8",
+                "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
+                "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
+                "parameters), tol %(tol).0e", autotune=1, graph=1)
+        if not args.no_nc_sweep and name != "quartic1024":
+            result["nc_sweep"] = nc_sweep(args)
+        if not args.no_left:
+            result["left_eigenvectors"] = left_leg(args)
+        if not args.no_user_fn:
+            result["user_function"] = user_function_leg(args)
     print(json.dumps(result))
 
 

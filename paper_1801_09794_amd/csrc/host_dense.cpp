@@ -4,6 +4,7 @@
 #include <immintrin.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <limits>
@@ -777,10 +778,11 @@ static std::vector<cplx> shift_candidates(const Ellipse& E, const std::vector<cp
 // starting vector), on the exact reduced function, for the pairs (lam[q], Y[:, q]) with q in
 // todo (Y: m rows, ld m); the pairs are independent and are spread over host threads.  Each
 // refined vector is returned with unit norm.
-static void newton_polish(int m, const std::vector<Term>& terms, const cplx* Ahat, std::vector<cplx>& lam,
-                          std::vector<cplx>& Yv, const std::vector<int>& todo) {
+static int newton_polish(int m, const std::vector<Term>& terms, const cplx* Ahat, std::vector<cplx>& lam,
+                         std::vector<cplx>& Yv, const std::vector<int>& todo) {
     const int J = (int)terms.size();
     const size_t mm = (size_t)m * m;
+    std::atomic<int> steps{0};
     auto polish = [&](int q) {
         std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
         cplx l = lam[q];
@@ -819,6 +821,7 @@ static void newton_polish(int m, const std::vector<Term>& terms, const cplx* Aha
             for (int c = 0; c < m; ++c) Jm[m + (size_t)c * (m + 1)] = std::conj(v0[c]);
             Jm[m + (size_t)m * (m + 1)] = 0.0;
             if (!lu_solve_small(m + 1, Jm, rhs.data(), 1)) break;
+            steps.fetch_add(1);
             for (int i = 0; i < m; ++i) y[i] += rhs[i];
             l += rhs[m];
         }
@@ -841,6 +844,7 @@ static void newton_polish(int m, const std::vector<Term>& terms, const cplx* Aha
             });
         for (auto& t : pool) t.join();
     }
+    return steps.load();
 }
 
 // Householder QR with column pivoting of the N x N matrix A (column-major, overwritten: R on
@@ -889,7 +893,8 @@ static int pivoted_qr(int N, std::vector<cplx>& A, std::vector<cplx>& tau, std::
 }
 
 bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
-                   std::vector<cplx>& lam, std::vector<cplx>& Y) {
+                   std::vector<cplx>& lam, std::vector<cplx>& Y, double* ms_points, double* ms_rank_eig) {
+    const auto t_start = std::chrono::steady_clock::now();
     const int J = (int)terms.size(), NP = CONTOUR_POINTS, KMAX = 3;
     const size_t mm = (size_t)m * m;
     const double a = CONTOUR_SCALE * E.a, b = CONTOUR_SCALE * E.b, L = std::max(a, b);
@@ -946,6 +951,8 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
     std::vector<cplx> M(2 * KMAX * mm, 0.0);
     for (int t = 0; t < nth; ++t)
         for (size_t e = 0; e < M.size(); ++e) M[e] += part[t][e];
+    const auto t_mid = std::chrono::steady_clock::now();
+    if (ms_points) *ms_points = std::chrono::duration<double, std::milli>(t_mid - t_start).count();
     int K = 2, N = 0, k = 0;
     std::vector<cplx> H0, tau;
     std::vector<int> perm;
@@ -1032,6 +1039,8 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
         if (nn > 0.0)
             for (int r = 0; r < m; ++r) y[r] /= nn;
     }
+    if (ms_rank_eig)
+        *ms_rank_eig = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_mid).count();
     return true;
 }
 
@@ -1041,14 +1050,18 @@ static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, cons
                                      int m_keep) {
     ReducedResult res;
     std::vector<cplx> lam, Y;
-    if (m_keep > m || !contour_pairs(m, terms, Ahat, E, lam, Y)) {
+    if (m_keep > m || !contour_pairs(m, terms, Ahat, E, lam, Y, &res.ms_points, &res.ms_rank_eig)) {
         res.ok = false;
         return res;
     }
+    res.rank = (int)lam.size();
     std::vector<int> todo;
     for (int q = 0; q < (int)lam.size(); ++q)
         if (std::isfinite(lam[q].real()) && E.radius(lam[q]) < CONTOUR_SCALE) todo.push_back(q);
-    newton_polish(m, terms, Ahat, lam, Y, todo);
+    const auto t0 = std::chrono::steady_clock::now();
+    res.newton_steps = newton_polish(m, terms, Ahat, lam, Y, todo);
+    res.newton_pairs = (int)todo.size();
+    res.ms_newton = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     std::vector<double> rad(todo.size());
     for (size_t i = 0; i < todo.size(); ++i) rad[i] = E.radius(lam[todo[i]]);
     std::vector<int> order(todo.size());

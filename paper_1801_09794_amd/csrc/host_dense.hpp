@@ -68,6 +68,10 @@ struct ReducedResult {
     std::vector<int> found;     // 1 for an eigenpair of the reduced problem, 0 for a completing pair
     int n_finite = 0;
     bool ok = true;
+    // host milliseconds of the parts of the contour-integral solve: resolvent points and moments,
+    // rank-revealing QR + small eigenproblem, Newton refinement; and the Newton pairs and steps
+    double ms_points = 0, ms_rank_eig = 0, ms_newton = 0;
+    int newton_pairs = 0, newton_steps = 0, rank = 0;
 };
 
 // Enlargement of the contour, trapezoid points and relative rank threshold of the
@@ -99,7 +103,8 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
 // eigenvectors s_i give the eigenvectors as the first block of Q_k s_i.  Returns false when
 // T(z) is singular at a point or H0 keeps full rank with K = 3.
 bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
-                   std::vector<cplx>& lam, std::vector<cplx>& Y);
+                   std::vector<cplx>& lam, std::vector<cplx>& Y, double* ms_points = nullptr,
+                   double* ms_rank_eig = nullptr);
 
 // Complex Schur decomposition A = Z T Z^H of a dense N x N matrix (column-major) by
 // Householder reduction to Hessenberg form and the shifted QR algorithm (Givens rotations,

@@ -800,7 +800,14 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                 host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
             }
             rr = reduced_solve(m, terms, Ahat.data(), E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
-            host_ms(std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+            const double hms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            host_ms(hms);
+            if (opt->verbose)
+                fprintf(stderr,
+                        "[nlfeast] region %d it %d host reduced %.1f ms (points+moments %.1f, rank+eig %.1f, "
+                        "newton %.1f: %d pairs %d steps, rank %d)\n",
+                        ri, it, hms, rr.ms_points, rr.ms_rank_eig, rr.ms_newton, rr.newton_pairs, rr.newton_steps,
+                        rr.rank);
             NLF_REQUIRE(!user_failed(terms), NLF_ERR_ARG, "solve: the user function reported an error");
             NLF_REQUIRE(rr.ok && (int)rr.lambda.size() == m, NLF_ERR_DEVICE,
                         "reduced eigenproblem failed (singular T at the contour centre or on the enlarged "
