@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--workload", default="delay8192")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload in FP64 (the profiled command)")
+    ap.add_argument("--leg-steps", type=int, default=5,
+                    help="timed steps of every leg beside the headline (at most --steps; one "
+                         "warm-up step each), so that the whole run stays within a few minutes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
@@ -526,6 +529,11 @@ def main():
             result["cpu_baseline"]["full_run_build_host"] = full
     del mats
     if not args.headline_only:
+        import copy
+        args = copy.copy(args)
+        args.steps = max(1, min(args.steps, args.leg_steps))
+        args.warmup = min(args.warmup, 1)
+        result["legs_steps"] = {"steps": args.steps, "warmup": args.warmup}
         if not args.no_batched and name != "damped4096":
             result["damped4096"] = extra_leg(
                 args, "damped4096",

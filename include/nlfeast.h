@@ -129,8 +129,12 @@ typedef struct {
 
 typedef struct nlfeast_ctx* nlfeast_handle;
 
-/* Library-owned context for problems of size n on HIP device `device`, enqueuing on
- * `stream`.  The handle owns only small host/device arrays (quadrature, pivots' book-keeping). */
+/* Library mechanics, not a step of the paper's method: a library-owned context for problems
+ * of size n (the order of T(lambda), Sec. 1 eq. nlevp) on HIP device `device`, enqueuing on
+ * `stream`.  The handle owns only host state, small device arrays (quadrature book-keeping) and
+ * its own streams and events; all large device memory is the caller's workspace.  Host threads
+ * it starts during a solve are joined before the solve returns.  Errors: NLF_ERR_ARG for
+ * n outside 1..8192 or a bad device index. */
 nlfeast_status nlfeast_create(nlfeast_handle* h, int64_t n, int device, void* stream);
 
 /* The coefficients of T (Sec. 2 eq. polynomialeig; Sec. 4.2 block residual): J terms, term j
@@ -154,7 +158,10 @@ nlfeast_status nlfeast_set_contour(nlfeast_handle h, int32_t nreg, const double*
                                    const double* semi_axes, const int32_t* n_nodes,
                                    const int32_t* m0, int32_t quad_rule);
 
-/* Device workspace bytes that nlfeast_solve needs for these options. */
+/* Library mechanics: the device workspace bytes that nlfeast_solve (or nlfeast_solve_left) needs
+ * for these options, the coefficients and the contours (the node factors of T(z_k), Algorithm 1
+ * Step 4, dominate: n^2 per node in the LU precision, plus n^2 complex128 per node in the FP32 +
+ * refinement form).  NLF_ERR_STATE before set_coeffs / set_contour. */
 nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* opt, size_t* bytes);
 
 /* Algorithm 1 for every region.  Blocks until the outputs are valid.
@@ -216,19 +223,30 @@ typedef enum {
     NLF_K_LU_REC_GEMM = 14,      /* GEMM updates inside the recursive panel factorisation
                                     (NLF_K_LU_GEMM: the rank-512 trailing updates of the blocked
                                     LU, kernel symbol lu_update_kernel) */
-    NLF_K_COUNT = 15
+    NLF_K_REDUCED = 15,          /* device part of the contour-integral reduced solve: the reduced
+                                    matrices at the enlarged contour's points, their batched LU
+                                    and inverses, and the moment sums */
+    NLF_K_COUNT = 16
 } nlfeast_kernel_class;
 nlfeast_status nlfeast_set_profiling(nlfeast_handle h, int32_t on);
 nlfeast_status nlfeast_get_profile(nlfeast_handle h, int64_t* launches, double* milliseconds,
                                    double* flops, double* bytes);
 
+/* Library mechanics: the message of the last failed call on h (or, with h = NULL, of the last
+ * failed call without a handle on this thread); valid until the next call. */
 const char* nlfeast_last_error(nlfeast_handle h);
-void nlfeast_destroy(nlfeast_handle h);   /* NULL is a no-op */
+/* Library mechanics: releases the handle, its streams and events (after the work it enqueued has
+ * been synchronised by the caller); caller-owned memory is untouched.  NULL is a no-op. */
+void nlfeast_destroy(nlfeast_handle h);
 
 /* ------------------------------------------------------------------------------------------
  * Step-level entry points: each performs one step of Algorithm 1's hot path on caller-owned
  * device buffers, enqueued on `stream` (asynchronous).  The solver above is built from the
- * same kernels.
+ * same kernels.  Unlike the solver, some of these allocate small temporary device memory on
+ * the stream for the duration of the call (hipMallocAsync / hipFreeAsync: nlf_assemble its
+ * coefficient table, nlf_getrf_batched and nlf_getrf_batched_blocked their row-exchange lists and
+ * staging, nlf_block_residual a diagonal m x m block per term, nlf_accumulate its coefficient
+ * table).
  * ---------------------------------------------------------------------------------------- */
 
 /* T(z_k) = sum_j f_j(z_k) A_j for k = 0..nz-1 (the matrices whose inverses Step 4 applies).

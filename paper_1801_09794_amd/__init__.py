@@ -26,7 +26,7 @@ NLF_QUAD_GAUSS_LEGENDRE, NLF_QUAD_TRAPEZOID = 0, 1
 NLF_C64, NLF_C128 = 0, 1
 KERNEL_CLASSES = ["assemble", "lu_gemm", "lu_panel", "lu_trsm", "lu_laswp", "solve", "refine",
                   "residual", "accumulate", "orth", "project", "host_reduced", "factor",
-                  "autotune", "lu_rec_gemm"]
+                  "autotune", "lu_rec_gemm", "reduced"]
 
 STATUS_NAMES = {0: "NLF_OK", 1: "NLF_ERR_ARG", 2: "NLF_ERR_NOMEM", 3: "NLF_ERR_DEVICE",
                 4: "NLF_ERR_STATE", 5: "NLF_ERR_SINGULAR", 6: "NLF_ERR_M0_TOO_SMALL",

@@ -86,7 +86,8 @@ enum ProfClass {
     NLF_PROF_ASSEMBLE = 0, NLF_PROF_LU_GEMM = 1, NLF_PROF_PANEL = 2, NLF_PROF_TRSM = 3,
     NLF_PROF_LASWP = 4, NLF_PROF_SOLVE = 5, NLF_PROF_REFINE = 6, NLF_PROF_RESIDUAL = 7,
     NLF_PROF_ACCUMULATE = 8, NLF_PROF_ORTH = 9, NLF_PROF_PROJECT = 10, NLF_PROF_HOST = 11,
-    NLF_PROF_FACTOR = 12, NLF_PROF_AUTOTUNE = 13, NLF_PROF_LU_REC_GEMM = 14, NLF_PROF_COUNT = 15
+    NLF_PROF_FACTOR = 12, NLF_PROF_AUTOTUNE = 13, NLF_PROF_LU_REC_GEMM = 14, NLF_PROF_REDUCED = 15,
+    NLF_PROF_COUNT = 16
 };
 // Class charged for triangular-solve launches (TRSM inside the factorisation, SOLVE inside
 // the per-iteration solves); set by the caller around a group of launches.

@@ -19,28 +19,62 @@ static inline unsigned grid_for(int64_t total, int64_t cap = 8192) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), cap));
 }
 
+// Rows per thread and rows per workgroup of the two-dimensional launches below: workgroup
+// (x, y) covers rows [x EW_ROWS, (x + 1) EW_ROWS) of column y; thread t handles rows
+// x EW_ROWS + t + 256 r, r < EW_RPT, so each load or store instruction of a wavefront touches
+// 64 consecutive elements (1 KB of complex128) and every thread has EW_RPT independent
+// accesses in flight per stream.
+constexpr int EW_RPT = 4;
+constexpr int EW_ROWS = 256 * EW_RPT;
+
+// Streaming accesses: the node matrices are written once here and read again only by the LU,
+// long after they have left the caches; the A_j are read once per assembly.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ z128 ld_stream(const z128* p) {
+    const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+    return z128(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(z128* p, z128 v) {
+    const v2d w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2d*>(p));
+}
+__device__ __forceinline__ void st_stream(z64* p, z128 v) {
+    const v2f w = {(float)v.re, (float)v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2f*>(p));
+}
+
 // T_k(i, c) = sum_j coef[k J + j] A_j(i, c): each A_j element is read once and all nz
-// outputs are written from registers.
+// outputs are written from registers (one FP64 sum, rounded once for the complex64 copy).
 __global__ __launch_bounds__(256) void assemble_kernel(int64_t n, int J, APtrs A, int64_t lda,
                                                        int nz, const z128* __restrict__ coef,
                                                        z128* T64, z64* T32, int64_t ldt,
                                                        int64_t sT) {
-    const int64_t total = n * n;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * 256) {
-        const int64_t i = e % n, c = e / n;
-        z128 a[MAXJ];
+    const int64_t c = blockIdx.y;
+    const int64_t r0 = (int64_t)blockIdx.x * EW_ROWS + threadIdx.x;
+    z128 a[EW_RPT][MAXJ];
+#pragma unroll
+    for (int r = 0; r < EW_RPT; ++r) {
+        const int64_t i = r0 + 256 * r;
 #pragma unroll
         for (int j = 0; j < MAXJ; ++j)
-            if (j < J) a[j] = A.p[j][i + c * lda];
-        const int64_t off = i + c * ldt;
-        for (int k = 0; k < nz; ++k) {
+            if (j < J && i < n) a[r][j] = ld_stream(A.p[j] + i + c * lda);
+    }
+    const int64_t off = r0 + c * ldt;
+    for (int k = 0; k < nz; ++k) {
+        z128 w[MAXJ];
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j)
+            if (j < J) w[j] = coef[k * J + j];
+#pragma unroll
+        for (int r = 0; r < EW_RPT; ++r) {
+            if (r0 + 256 * r >= n) continue;
             z128 acc(0, 0);
 #pragma unroll
             for (int j = 0; j < MAXJ; ++j)
-                if (j < J) cfma(acc, coef[k * J + j], a[j]);
-            if (T64) T64[k * sT + off] = acc;
-            if (T32) T32[k * sT + off] = z64((float)acc.re, (float)acc.im);
+                if (j < J) cfma(acc, w[j], a[r][j]);
+            if (T64) st_stream(T64 + k * sT + off + 256 * r, acc);
+            if (T32) st_stream(T32 + k * sT + off + 256 * r, acc);
         }
     }
 }
@@ -48,12 +82,13 @@ __global__ __launch_bounds__(256) void assemble_kernel(int64_t n, int J, APtrs A
 void assemble(hipStream_t s, int64_t n, int J, const z128* const* A, int64_t lda, int nz,
               const z128* coef_dev, z128* T64, z64* T32, int64_t ldt, int64_t sT) {
     NLF_REQUIRE(J >= 1 && J <= MAXJ, 1, "assemble: 1 <= J <= 8 terms");
+    NLF_REQUIRE(n <= 65535, 1, "assemble: n <= 65535");
     APtrs ap{};
     for (int j = 0; j < J; ++j) ap.p[j] = A[j];
     const double bytes = (double)n * n * (16.0 * J + nz * ((T64 ? 16.0 : 0) + (T32 ? 8.0 : 0)));
     ProfScope ps(NLF_PROF_ASSEMBLE, s, 8.0 * n * n * J * nz, bytes);
-    hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n * n, 16384)), dim3(256), 0, s, n, J, ap,
-                       lda, nz, coef_dev, T64, T32, ldt, sT);
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)ceil_div(n, EW_ROWS), (unsigned)n), dim3(256), 0, s, n, J,
+                       ap, lda, nz, coef_dev, T64, T32, ldt, sT);
     NLF_HIP(hipGetLastError());
 }
 
@@ -77,27 +112,40 @@ void col_norms(hipStream_t s, int64_t n, int m, const z128* X, int64_t ld, doubl
     NLF_HIP(hipGetLastError());
 }
 
-// Q = X diag(rho) - sum_k Y_k diag(c_k)
+// Q = X diag(rho) - sum_k Y_k diag(c_k): column c of Q from column c of X and of every Y_k
+// (the coefficients of the column are uniform across the workgroup).
 __global__ __launch_bounds__(256) void accumulate_kernel(int64_t n, int m, int nz,
                                                          const z128* __restrict__ X,
                                                          const z128* __restrict__ Y, int64_t sY,
                                                          const z128* __restrict__ rho,
                                                          const z128* __restrict__ coef, z128* Q) {
-    const int64_t total = n * m;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * 256) {
-        const int c = (int)(e / n);
-        z128 q = rho[c] * X[e];
-        for (int k = 0; k < nz; ++k) cfms(q, coef[(int64_t)k * m + c], Y[k * sY + e]);
-        Q[e] = q;
+    const int64_t c = blockIdx.y;
+    const int64_t e0 = (int64_t)blockIdx.x * EW_ROWS + threadIdx.x + c * n;
+    const int64_t end = (c + 1) * n;
+    const z128 rc = rho[c];
+    z128 q[EW_RPT];
+#pragma unroll
+    for (int r = 0; r < EW_RPT; ++r) q[r] = e0 + 256 * r < end ? rc * ld_stream(X + e0 + 256 * r) : z128(0, 0);
+    for (int k = 0; k < nz; ++k) {
+        const z128 w = coef[(int64_t)k * m + c];
+        const z128* Yk = Y + k * sY;
+        z128 y[EW_RPT];
+#pragma unroll
+        for (int r = 0; r < EW_RPT; ++r) y[r] = e0 + 256 * r < end ? ld_stream(Yk + e0 + 256 * r) : z128(0, 0);
+#pragma unroll
+        for (int r = 0; r < EW_RPT; ++r) cfms(q[r], w, y[r]);
     }
+#pragma unroll
+    for (int r = 0; r < EW_RPT; ++r)
+        if (e0 + 256 * r < end) Q[e0 + 256 * r] = q[r];
 }
 
 void accumulate(hipStream_t s, int64_t n, int m, int nz, const z128* X, const z128* Y,
                 int64_t sY, const z128* rho, const z128* c, z128* Q) {
+    if (n <= 0 || m <= 0) return;
     ProfScope ps(NLF_PROF_ACCUMULATE, s, 8.0 * n * m * nz, 16.0 * n * m * (nz + 2));
-    hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(n * m)), dim3(256), 0, s, n, m, nz, X, Y,
-                       sY, rho, c, Q);
+    hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)ceil_div(n, EW_ROWS), (unsigned)m), dim3(256), 0, s, n,
+                       m, nz, X, Y, sY, rho, c, Q);
     NLF_HIP(hipGetLastError());
 }
 

@@ -855,50 +855,77 @@ static int pivoted_qr(int N, std::vector<cplx>& A, std::vector<cplx>& tau, std::
     perm.resize(N);
     std::iota(perm.begin(), perm.end(), 0);
     tau.assign(N, 0.0);
-    std::vector<double> nrm2(N);
-    for (int j = 0; j < N; ++j) {
-        int p = j;
-        for (int c = j; c < N; ++c) {
-            double t = 0.0;
-            const cplx* col = &A[(size_t)c * N];
-            for (int i = j; i < N; ++i) t += std::norm(col[i]);
-            nrm2[c] = t;
-            if (t > nrm2[p]) p = c;
+    // squared norms of the remaining parts of the columns, downdated after every step and
+    // recomputed when the downdate has cancelled most of the value
+    std::vector<double> nrm2(N), ref(N);
+    auto colnorm = [&](int c, int from) {
+        double t = 0.0;
+        const cplx* col = &A[(size_t)c * N];
+        for (int i = from; i < N; ++i) t += std::norm(col[i]);
+        return t;
+    };
+    const int nth = host_threads((int64_t)N * N, 1 << 14);
+    std::atomic<int> rank{N};
+    Team team(nth);
+    team.run([&](int t) {
+        for (int c = t; c < N; c += nth) nrm2[c] = ref[c] = colnorm(c, 0);
+        team.barrier();
+        for (int j = 0; j < N; ++j) {
+            if (t == 0) {
+                int p = j;
+                for (int c = j + 1; c < N; ++c)
+                    if (nrm2[c] > nrm2[p]) p = c;
+                if (p != j) {
+                    std::swap_ranges(A.begin() + (size_t)j * N, A.begin() + (size_t)(j + 1) * N,
+                                     A.begin() + (size_t)p * N);
+                    std::swap(perm[j], perm[p]);
+                    std::swap(nrm2[j], nrm2[p]);
+                    std::swap(ref[j], ref[p]);
+                }
+                const double nrm = std::sqrt(colnorm(j, j));
+                if (nrm == 0.0 || nrm <= thresh) {
+                    rank.store(j);
+                } else {
+                    cplx* a = &A[(size_t)j * N];
+                    const cplx alpha = a[j];
+                    const double beta = alpha.real() >= 0.0 ? -nrm : nrm;
+                    const cplx tj = cplx((beta - alpha.real()) / beta, -alpha.imag() / beta);
+                    const cplx scl = 1.0 / (alpha - beta);
+                    for (int i = j + 1; i < N; ++i) a[i] *= scl;
+                    a[j] = beta;
+                    tau[j] = tj;
+                }
+            }
+            team.barrier();
+            if (rank.load() <= j) return;
+            const cplx* a = &A[(size_t)j * N];
+            const cplx ct = std::conj(tau[j]);
+            for (int c = j + 1 + t; c < N; c += nth) {   // column c <- (I - conj(tau) v v^H) column c
+                cplx* b = &A[(size_t)c * N];
+                cplx w = b[j];
+                for (int i = j + 1; i < N; ++i) w += std::conj(a[i]) * b[i];
+                w *= ct;
+                b[j] -= w;
+                for (int i = j + 1; i < N; ++i) b[i] -= a[i] * w;
+                const double d = nrm2[c] - std::norm(b[j]);
+                if (d <= 1e-6 * ref[c]) {
+                    nrm2[c] = ref[c] = colnorm(c, j + 1);
+                } else {
+                    nrm2[c] = d;
+                }
+            }
+            team.barrier();
         }
-        if (p != j) {
-            std::swap_ranges(A.begin() + (size_t)j * N, A.begin() + (size_t)(j + 1) * N, A.begin() + (size_t)p * N);
-            std::swap(perm[j], perm[p]);
-        }
-        const double nrm = std::sqrt(nrm2[p]);
-        if (nrm == 0.0 || nrm <= thresh) return j;
-        cplx* a = &A[(size_t)j * N];
-        const cplx alpha = a[j];
-        const double beta = alpha.real() >= 0.0 ? -nrm : nrm;
-        const cplx t = cplx((beta - alpha.real()) / beta, -alpha.imag() / beta);
-        const cplx scl = 1.0 / (alpha - beta);
-        for (int i = j + 1; i < N; ++i) a[i] *= scl;
-        a[j] = beta;
-        tau[j] = t;
-        const cplx ct = std::conj(t);
-        for (int c = j + 1; c < N; ++c) {   // column c <- (I - conj(tau) v v^H) column c
-            cplx* b = &A[(size_t)c * N];
-            cplx w = b[j];
-            for (int i = j + 1; i < N; ++i) w += std::conj(a[i]) * b[i];
-            w *= ct;
-            b[j] -= w;
-            for (int i = j + 1; i < N; ++i) b[i] -= a[i] * w;
-        }
-    }
-    return N;
+    });
+    return rank.load();
 }
 
-bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
-                   std::vector<cplx>& lam, std::vector<cplx>& Y, double* ms_points, double* ms_rank_eig) {
-    const auto t_start = std::chrono::steady_clock::now();
-    const int J = (int)terms.size(), NP = CONTOUR_POINTS, KMAX = 3;
-    const size_t mm = (size_t)m * m;
+void contour_points(const Ellipse& E, std::vector<cplx>& z, std::vector<cplx>& w, std::vector<cplx>& mu) {
+    const int NP = CONTOUR_POINTS;
     const double a = CONTOUR_SCALE * E.a, b = CONTOUR_SCALE * E.b, L = std::max(a, b);
-    std::vector<cplx> z(NP), w(NP), mu(NP);
+    z.resize(NP);
+    w.resize(NP);
+    mu.resize(NP);
     for (int q = 0; q < NP; ++q) {
         const double th = 2.0 * kPi * (q + 0.5) / NP;
         z[q] = E.c + cplx(a * std::cos(th), b * std::sin(th));
@@ -906,14 +933,23 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
         w[q] = cplx(-a * std::sin(th), b * std::cos(th)) / cplx(0.0, (double)NP);
         mu[q] = (z[q] - E.c) / L;
     }
+}
+
+// The moments on the host: T(z_q) assembled, inverted by LU (points dealt to threads in a fixed
+// pattern q = t, t + nth, ..., each thread with its own partial sums, added in thread order, so
+// the sums do not depend on timing).
+static bool contour_moments_host(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                                 std::vector<cplx>& M, std::vector<double>& isize) {
+    const int J = (int)terms.size(), NP = CONTOUR_POINTS, NM = CONTOUR_MOMENTS;
+    const size_t mm = (size_t)m * m;
+    std::vector<cplx> z, w, mu;
+    contour_points(E, z, w, mu);
     std::vector<cplx> fz((size_t)J * NP);   // the functions at every point, one call per term
     for (int j = 0; j < J; ++j) term_values(terms[j], z.data(), NP, &fz[(size_t)j * NP]);
-    // M_p, p < 2 KMAX: points dealt to threads in a fixed pattern (q = t, t + nth, ...), each
-    // thread with its own partial sums, added in thread order: the sums do not depend on timing
     const int hw = std::min((int)std::max(1u, std::thread::hardware_concurrency()), host_thread_budget());
     const int nth = std::max(1, std::min({hw, 16, NP / 4, (int)(mm * NP / 20000) + 1}));
-    std::vector<std::vector<cplx>> part(nth, std::vector<cplx>(2 * KMAX * mm, 0.0));
-    std::vector<double> isize(NP, 0.0);   // |w_q| ||T(z_q)^{-1}||_F, the integrand's size
+    std::vector<std::vector<cplx>> part(nth, std::vector<cplx>(NM * mm, 0.0));
+    isize.assign(NP, 0.0);   // |w_q| ||T(z_q)^{-1}||_F, the integrand's size
     std::atomic<int> bad{0};
     auto work = [&](int t) {
         std::vector<cplx> Tz(mm), Inv(mm);
@@ -934,7 +970,7 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
             for (size_t e = 0; e < mm; ++e) fro += std::norm(Inv[e]);
             isize[q] = std::abs(w[q]) * std::sqrt(fro);
             cplx wp = w[q];
-            for (int p = 0; p < 2 * KMAX; ++p, wp *= mu[q]) {
+            for (int p = 0; p < NM; ++p, wp *= mu[q]) {
                 cplx* Mp = &part[t][(size_t)p * mm];
                 for (size_t e = 0; e < mm; ++e) Mp[e] += wp * Inv[e];
             }
@@ -948,15 +984,21 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
         for (auto& th : pool) th.join();
     }
     if (bad.load()) return false;
-    std::vector<cplx> M(2 * KMAX * mm, 0.0);
+    M.assign(NM * mm, 0.0);
     for (int t = 0; t < nth; ++t)
         for (size_t e = 0; e < M.size(); ++e) M[e] += part[t][e];
-    const auto t_mid = std::chrono::steady_clock::now();
-    if (ms_points) *ms_points = std::chrono::duration<double, std::milli>(t_mid - t_start).count();
+    return true;
+}
+
+bool contour_pairs_from_moments(int m, const Ellipse& E, const std::vector<cplx>& M,
+                                const std::vector<double>& isize, std::vector<cplx>& lam,
+                                std::vector<cplx>& Y) {
+    const size_t mm = (size_t)m * m;
+    const double L = CONTOUR_SCALE * std::max(E.a, E.b);
     int K = 2, N = 0, k = 0;
     std::vector<cplx> H0, tau;
     std::vector<int> perm;
-    for (; K <= KMAX; ++K) {
+    for (; K <= CONTOUR_KMAX; ++K) {
         N = K * m;
         H0.assign((size_t)N * N, 0.0);
         for (int bi = 0; bi < K; ++bi)
@@ -969,48 +1011,55 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
         k = pivoted_qr(N, H0, tau, perm, CONTOUR_RANK_TOL * std::accumulate(isize.begin(), isize.end(), 0.0));
         if (k < N) break;
     }
-    if (K > KMAX) return false;
+    if (K > CONTOUR_KMAX) return false;
     lam.clear();
     Y.clear();
     if (k == 0) return true;
-    // Q_k = H_0 ... H_{k-1} [I_k; 0]
+    const int nth = host_threads((int64_t)N * k * k, 1 << 18);
+    // Q_k = H_0 ... H_{k-1} [I_k; 0], column by column (columns are independent)
     std::vector<cplx> Qk((size_t)N * k, 0.0);
     for (int i = 0; i < k; ++i) Qk[i + (size_t)i * N] = 1.0;
-    for (int j = k - 1; j >= 0; --j) {
-        const cplx* v = &H0[(size_t)j * N];
-        for (int c = 0; c < k; ++c) {
-            cplx* q = &Qk[(size_t)c * N];
-            cplx s = q[j];
-            for (int i = j + 1; i < N; ++i) s += std::conj(v[i]) * q[i];
-            s *= tau[j];
-            q[j] -= s;
-            for (int i = j + 1; i < N; ++i) q[i] -= v[i] * s;
-        }
-    }
     // G = Q_k^H H1 P_k (k x k), with column c of H1 P_k = block column of H1 for perm[c]
-    std::vector<cplx> G((size_t)k * k, 0.0), h1(N);
-    for (int c = 0; c < k; ++c) {
-        const int col = perm[c], bj = col / m, cc = col % m;
-        for (int bi = 0; bi < K; ++bi) {
-            const cplx* Mp = &M[(size_t)(bi + bj + 1) * mm];
-            for (int r = 0; r < m; ++r) h1[bi * m + r] = Mp[r + (size_t)cc * m];
+    std::vector<cplx> G((size_t)k * k, 0.0);
+    Team(nth).run([&](int t) {
+        for (int c = t; c < k; c += nth) {
+            cplx* q = &Qk[(size_t)c * N];
+            for (int j = std::min(c, k - 1); j >= 0; --j) {   // H_j leaves e_c alone for j > c
+                const cplx* v = &H0[(size_t)j * N];
+                cplx s = q[j];
+                for (int i = j + 1; i < N; ++i) s += std::conj(v[i]) * q[i];
+                s *= tau[j];
+                q[j] -= s;
+                for (int i = j + 1; i < N; ++i) q[i] -= v[i] * s;
+            }
         }
-        for (int i = 0; i < k; ++i) {
-            const cplx* q = &Qk[(size_t)i * N];
-            cplx s = 0.0;
-            for (int r = 0; r < N; ++r) s += std::conj(q[r]) * h1[r];
-            G[i + (size_t)c * k] = s;
+    });
+    Team(nth).run([&](int t) {
+        std::vector<cplx> h1(N);
+        for (int c = t; c < k; c += nth) {
+            const int col = perm[c], bj = col / m, cc = col % m;
+            for (int bi = 0; bi < K; ++bi) {
+                const cplx* Mp = &M[(size_t)(bi + bj + 1) * mm];
+                for (int r = 0; r < m; ++r) h1[bi * m + r] = Mp[r + (size_t)cc * m];
+            }
+            for (int i = 0; i < k; ++i) {
+                const cplx* q = &Qk[(size_t)i * N];
+                cplx s = 0.0;
+                for (int r = 0; r < N; ++r) s += std::conj(q[r]) * h1[r];
+                G[i + (size_t)c * k] = s;
+            }
         }
-    }
-    // B = G R_11^{-1}: column c of B from B R_11 = G, left to right
+    });
+    // B = G R_11^{-1}: row i of B from B R_11 = G, left to right (rows are independent)
     std::vector<cplx> B((size_t)k * k);
-    for (int c = 0; c < k; ++c) {
-        for (int i = 0; i < k; ++i) {
-            cplx s = G[i + (size_t)c * k];
-            for (int p = 0; p < c; ++p) s -= B[i + (size_t)p * k] * H0[p + (size_t)c * N];
-            B[i + (size_t)c * k] = s / H0[c + (size_t)c * N];
-        }
-    }
+    Team(nth).run([&](int t) {
+        for (int i = t; i < k; i += nth)
+            for (int c = 0; c < k; ++c) {
+                cplx s = G[i + (size_t)c * k];
+                for (int p = 0; p < c; ++p) s -= B[i + (size_t)p * k] * H0[p + (size_t)c * N];
+                B[i + (size_t)c * k] = s / H0[c + (size_t)c * N];
+            }
+    });
     std::vector<cplx> ev, S;
     if (k == 1) {
         ev.assign(1, B[0]);
@@ -1039,21 +1088,28 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
         if (nn > 0.0)
             for (int r = 0; r < m; ++r) y[r] /= nn;
     }
-    if (ms_rank_eig)
-        *ms_rank_eig = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_mid).count();
     return true;
+}
+
+bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                   std::vector<cplx>& lam, std::vector<cplx>& Y, double* ms_points, double* ms_rank_eig) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<cplx> M;
+    std::vector<double> isize;
+    if (!contour_moments_host(m, terms, Ahat, E, M, isize)) return false;
+    const auto t1 = std::chrono::steady_clock::now();
+    const bool ok = contour_pairs_from_moments(m, E, M, isize, lam, Y);
+    if (ms_points) *ms_points = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (ms_rank_eig)
+        *ms_rank_eig = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+    return ok;
 }
 
 // Steps 1-2 by the contour-integral solve: the pairs inside the enlarged ellipse, refined by
 // Newton, sorted by normalised radius and completed to m_keep (see reduced_solve).
-static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
-                                     int m_keep) {
-    ReducedResult res;
-    std::vector<cplx> lam, Y;
-    if (m_keep > m || !contour_pairs(m, terms, Ahat, E, lam, Y, &res.ms_points, &res.ms_rank_eig)) {
-        res.ok = false;
-        return res;
-    }
+// The pairs found (lam, Y), refined by Newton, sorted by normalised radius and completed to m_keep.
+static ReducedResult contour_finish(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                                    int m_keep, std::vector<cplx>& lam, std::vector<cplx>& Y, ReducedResult res) {
     res.rank = (int)lam.size();
     std::vector<int> todo;
     for (int q = 0; q < (int)lam.size(); ++q)
@@ -1127,6 +1183,40 @@ static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, cons
     }
     res.n_finite = m_keep;
     return res;
+}
+
+static ReducedResult contour_reduced(int m, const std::vector<Term>& terms, const cplx* Ahat, const Ellipse& E,
+                                     int m_keep) {
+    ReducedResult res;
+    std::vector<cplx> lam, Y;
+    if (m_keep > m || !contour_pairs(m, terms, Ahat, E, lam, Y, &res.ms_points, &res.ms_rank_eig)) {
+        res.ok = false;
+        return res;
+    }
+    return contour_finish(m, terms, Ahat, E, m_keep, lam, Y, res);
+}
+
+ReducedResult contour_reduced_from_moments(int m, const std::vector<Term>& terms, const cplx* Ahat,
+                                           const Ellipse& E, int m_keep, const std::vector<cplx>& M,
+                                           const std::vector<double>& isize) {
+    ReducedResult res;
+    std::vector<cplx> lam, Y;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (m_keep > m || !contour_pairs_from_moments(m, E, M, isize, lam, Y)) {
+        res.ok = false;
+        return res;
+    }
+    res.ms_rank_eig = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return contour_finish(m, terms, Ahat, E, m_keep, lam, Y, res);
+}
+
+bool takes_contour_route(const std::vector<Term>& terms, int method) {
+    bool poly = true, user = false;
+    for (const Term& t : terms) {
+        if (t.kind != 0) poly = false;
+        if (t.kind == 2) user = true;
+    }
+    return user || (!poly && method != 2);
 }
 
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,

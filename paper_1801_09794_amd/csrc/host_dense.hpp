@@ -106,6 +106,26 @@ bool contour_pairs(int m, const std::vector<Term>& terms, const cplx* Ahat, cons
                    std::vector<cplx>& lam, std::vector<cplx>& Y, double* ms_points = nullptr,
                    double* ms_rank_eig = nullptr);
 
+// The two stages of contour_pairs, so that the first can run elsewhere (the solver forms the
+// moments on the device).  contour_points: the CONTOUR_POINTS trapezoid points z_q of the
+// enlarged ellipse, their weights w_q (including 1/(2 pi i)) and mu_q = (z_q - c)/L.
+// Moments: M holds CONTOUR_MOMENTS blocks m x m, M_p = sum_q w_q mu_q^p T(z_q)^{-1}, and isize
+// the CONTOUR_POINTS values |w_q| ||T(z_q)^{-1}||_F.  contour_pairs_from_moments: the rank
+// decision, the reduced k x k eigenproblem and the eigenvectors (as in contour_pairs).
+constexpr int CONTOUR_KMAX = 3;
+constexpr int CONTOUR_MOMENTS = 2 * CONTOUR_KMAX;
+void contour_points(const Ellipse& E, std::vector<cplx>& z, std::vector<cplx>& w, std::vector<cplx>& mu);
+bool contour_pairs_from_moments(int m, const Ellipse& E, const std::vector<cplx>& M,
+                                const std::vector<double>& isize, std::vector<cplx>& lam,
+                                std::vector<cplx>& Y);
+// Steps 1-2 by the contour-integral route from moments formed elsewhere: contour_pairs_from_moments,
+// then the Newton refinement and completion of reduced_solve.
+ReducedResult contour_reduced_from_moments(int m, const std::vector<Term>& terms, const cplx* Ahat,
+                                           const Ellipse& E, int m_keep, const std::vector<cplx>& M,
+                                           const std::vector<double>& isize);
+// Whether reduced_solve takes the contour-integral route for these terms and method.
+bool takes_contour_route(const std::vector<Term>& terms, int method);
+
 // Complex Schur decomposition A = Z T Z^H of a dense N x N matrix (column-major) by
 // Householder reduction to Hessenberg form and the shifted QR algorithm (Givens rotations,
 // Wilkinson shifts); eigenvectors of selected eigenvalues by back substitution on T.

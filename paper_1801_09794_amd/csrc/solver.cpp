@@ -227,6 +227,11 @@ namespace {
 struct RegionLayout {
     size_t Q = 0, X = 0, W = 0, R = 0, Ys = 0, QT = 0, stmp = 0, R32 = 0, Y32 = 0, E = 0, E32 = 0;
     size_t Ahat = 0, G = 0, Ymat = 0, Gall = 0, rho = 0, acoef = 0, norms = 0, splitws = 0, hh = 0;
+    // contour-integral reduced solve on the device (non-polynomial problems): the reduced
+    // matrices at the points (then their LU factors), their inverses, pivots, exchange lists,
+    // the identity, the functions at the points, the moment weights, the moments, the norms
+    size_t cpts = 0, cinv = 0, cpiv = 0, cperm = 0, cinfo = 0, clist = 0, cid = 0, ccoef = 0, cw = 0,
+           cmom = 0, cnorm = 0;
     int64_t splitws_elems = 0;
     int node0 = 0, col0 = 0;
 };
@@ -240,7 +245,7 @@ struct Layout {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-Layout make_layout(const nlfeast_ctx* h, int prec) {
+Layout make_layout(const nlfeast_ctx* h, int prec, bool contour) {
     Layout L;
     const int64_t n = h->n;
     for (const auto& r : h->regions) {
@@ -298,6 +303,20 @@ Layout make_layout(const nlfeast_ctx* h, int prec) {
         R.splitws_elems = (int64_t)std::max<size_t>(std::max<size_t>(64 * mm * J, 8 * blk), 1 << 16);
         R.splitws = take(16 * (size_t)R.splitws_elems);
         R.hh = take(16 * (size_t)householder_scratch_elems(m));
+        if (contour) {
+            const int NP = CONTOUR_POINTS;
+            R.cpts = take(16 * mm * NP);
+            R.cinv = take(16 * mm * NP);
+            R.cpiv = take(sizeof(int32_t) * (size_t)m * NP);
+            R.cperm = take(sizeof(int32_t) * (size_t)m * NP);
+            R.cinfo = take(sizeof(int32_t) * (size_t)NP);
+            R.clist = take(sizeof(int32_t) * (size_t)getrf_scratch_ints(m, NP));
+            R.cid = take(16 * mm);
+            R.ccoef = take(16 * (size_t)NP * J);
+            R.cw = take(16 * (size_t)NP * CONTOUR_MOMENTS);
+            R.cmom = take(16 * mm * CONTOUR_MOMENTS);
+            R.cnorm = take(8 * (size_t)(NP + block_sqnorms_scratch(NP)));
+        }
         L.reg.push_back(R);
         node0 += nc;
         col0 += m;
@@ -691,6 +710,33 @@ std::vector<char> stagnant(const std::vector<cplx>& lam, const std::vector<doubl
     return out;
 }
 
+// The moments of the reduced resolvent for the contour-integral reduced solve, on the device:
+// T_red(z_q) = sum_j f_j(z_q) Ahat_j at the CONTOUR_POINTS points of the enlarged contour (the
+// assembly kernel with n = m), their batched LU and inverses T_red(z_q)^{-1} (solves against
+// the identity), the squared Frobenius norms of the inverses, and the CONTOUR_MOMENTS sums
+// M_p = sum_q w_q mu_q^p T_red(z_q)^{-1} as one GEMM of the m^2 x CONTOUR_POINTS block of
+// inverses with the weights.  Inputs in the region's buffers: ccoef (f_j(z_q) at q J + j), cw
+// (w_q mu_q^p at q + p CONTOUR_POINTS), cid (the m x m identity).
+void device_moments(hipStream_t s, int m, int J, const z128* Ahat_d, void* ws, const RegionLayout& RL) {
+    const int NP = CONTOUR_POINTS, NM = CONTOUR_MOMENTS;
+    const size_t mm = (size_t)m * m;
+    const double flops = NP * (8.0 * J * mm + 8.0 / 3.0 * m * (double)mm + 8.0 * m * (double)mm) + 8.0 * mm * NP * NM;
+    ProfScope ps(NLF_PROF_REDUCED, s, flops, 16.0 * mm * NP * 4);
+    ProfilerGuard off(nullptr);   // the launches below are timed as one span
+    std::vector<const z128*> A(J);
+    for (int j = 0; j < J; ++j) A[j] = Ahat_d + (size_t)j * mm;
+    z128* T = at<z128>(ws, RL.cpts);
+    z128* Inv = at<z128>(ws, RL.cinv);
+    int32_t* perm = at<int32_t>(ws, RL.cperm);
+    assemble(s, m, J, A.data(), m, NP, at<z128>(ws, RL.ccoef), T, nullptr, m, (int64_t)mm);
+    getrf<double>(s, m, NP, T, m, (int64_t)mm, at<int32_t>(ws, RL.cpiv), perm, at<int32_t>(ws, RL.cinfo),
+                  at<int32_t>(ws, RL.clist));
+    getrs<double>(s, m, m, NP, T, m, (int64_t)mm, perm, at<z128>(ws, RL.cid), m, 0, Inv, m, (int64_t)mm);
+    block_sqnorms(s, m, m, NP, Inv, m, (int64_t)mm, at<double>(ws, RL.cnorm), at<double>(ws, RL.cnorm) + NP);
+    gemm<double>(s, false, (int64_t)mm, NM, NP, z128(1, 0), Inv, (int64_t)mm, 0, at<z128>(ws, RL.cw), NP, 0,
+                 z128(0, 0), at<z128>(ws, RL.cmom), (int64_t)mm, 0, 1);
+}
+
 struct RegionIO {
     const void* X0;
     void* Xout;
@@ -770,6 +816,35 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
 
         std::vector<cplx> Ahat((size_t)J * m * m), lam(m), Gh((size_t)J * m * m), rho(m),
             acoef((size_t)nc * m);
+        // contour-integral reduced solve: its moments are formed on the device; the points, the
+        // functions there and the moment weights are fixed for the whole solve
+        const bool cdev = takes_contour_route(terms, opt->reduced_solver);
+        std::vector<cplx> cmom;
+        std::vector<double> cnorm, isize;
+        std::vector<int32_t> cinfo;
+        std::vector<cplx> cwt;
+        if (cdev) {
+            const int NP = CONTOUR_POINTS, NM = CONTOUR_MOMENTS;
+            std::vector<cplx> cz, cmu;
+            contour_points(E, cz, cwt, cmu);
+            std::vector<cplx> fz((size_t)J * NP), coef((size_t)NP * J), wts((size_t)NP * NM), ident((size_t)m * m, 0.0);
+            for (int j = 0; j < J; ++j) term_values(terms[j], cz.data(), NP, &fz[(size_t)j * NP]);
+            NLF_REQUIRE(!user_failed(terms), NLF_ERR_ARG, "solve: the user function reported an error");
+            for (int q = 0; q < NP; ++q) {
+                for (int j = 0; j < J; ++j) coef[(size_t)q * J + j] = fz[(size_t)j * NP + q];
+                cplx wp = cwt[q];
+                for (int p = 0; p < NM; ++p, wp *= cmu[q]) wts[q + (size_t)p * NP] = wp;
+            }
+            for (int i = 0; i < m; ++i) ident[i + (size_t)i * m] = 1.0;
+            h2d(s, at<void>(ws, RL.ccoef), coef.data(), sizeof(cplx) * coef.size());
+            h2d(s, at<void>(ws, RL.cw), wts.data(), sizeof(cplx) * wts.size());
+            h2d(s, at<void>(ws, RL.cid), ident.data(), sizeof(cplx) * ident.size());
+            NLF_HIP(hipStreamSynchronize(s));   // the host vectors above go out of scope
+            cmom.resize((size_t)NM * m * m);
+            cnorm.resize(NP);
+            isize.resize(NP);
+            cinfo.resize(NP);
+        }
         std::vector<double> res(m), enorm(nc);
         // once a refinement check passes without a correction, the complex64 factors have shown
         // themselves accurate enough for this region's right-hand sides and later iterations
@@ -791,6 +866,15 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         while (true) {
             // Step 1: projections and the reduced problem
             project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems, adj);
+            if (cdev) {
+                device_moments(s, m, J, Ahat_d, ws, RL);
+                NLF_HIP(hipMemcpyAsync(cmom.data(), at<void>(ws, RL.cmom), sizeof(cplx) * cmom.size(),
+                                       hipMemcpyDeviceToHost, s));
+                NLF_HIP(hipMemcpyAsync(cnorm.data(), at<void>(ws, RL.cnorm), sizeof(double) * cnorm.size(),
+                                       hipMemcpyDeviceToHost, s));
+                NLF_HIP(hipMemcpyAsync(cinfo.data(), at<void>(ws, RL.cinfo), sizeof(int32_t) * cinfo.size(),
+                                       hipMemcpyDeviceToHost, s));
+            }
             d2h_sync(s, Ahat.data(), Ahat_d, sizeof(cplx) * Ahat.size());
             const auto t0 = std::chrono::steady_clock::now();
             std::vector<cplx> prev;
@@ -799,7 +883,21 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
                 const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
                 host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
             }
-            rr = reduced_solve(m, terms, Ahat.data(), E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
+            if (cdev) {
+                bool singular = false;
+                for (int q = 0; q < CONTOUR_POINTS; ++q) {
+                    singular = singular || cinfo[q] != 0;
+                    isize[q] = std::abs(cwt[q]) * std::sqrt(cnorm[q]);
+                }
+                if (singular) {
+                    rr = ReducedResult();
+                    rr.ok = false;
+                } else {
+                    rr = contour_reduced_from_moments(m, terms, Ahat.data(), E, m, cmom, isize);
+                }
+            } else {
+                rr = reduced_solve(m, terms, Ahat.data(), E, m, it > 0 ? &prev : nullptr, opt->reduced_solver);
+            }
             const double hms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             host_ms(hms);
             if (opt->verbose)
@@ -1104,7 +1202,7 @@ nlfeast_status nlfeast_workspace_size(nlfeast_handle h, const nlfeast_options* o
         NLF_REQUIRE(h && opt && bytes, NLF_ERR_ARG, "workspace_size: null argument");
         NLF_REQUIRE(!h->regions.empty() && h->J > 0, NLF_ERR_STATE,
                     "workspace_size: call set_coeffs and set_contour first");
-        *bytes = make_layout(h, opt->precision).total;
+        *bytes = make_layout(h, opt->precision, takes_contour_route(h->terms, opt->reduced_solver)).total;
         return NLF_OK;
     })
 }
@@ -1153,7 +1251,7 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         NLF_REQUIRE(!has_user || h->ufn.fn, NLF_ERR_STATE,
                     "solve: a term of kind NLF_F_USER needs nlfeast_set_user_function first");
         h->ufn.failed.store(0);
-        const Layout L = make_layout(h, opt->precision);
+        const Layout L = make_layout(h, opt->precision, takes_contour_route(h->terms, opt->reduced_solver));
         NLF_REQUIRE(ws_bytes >= L.total, NLF_ERR_NOMEM, "solve: workspace too small");
         NLF_HIP(hipSetDevice(h->device));
         hipStream_t s = h->stream;
