@@ -247,6 +247,7 @@ void nlfeast_destroy(nlfeast_handle h);
  * coefficient table, nlf_getrf_batched and nlf_getrf_batched_blocked their row-exchange lists and
  * staging, nlf_block_residual a diagonal m x m block per term, nlf_accumulate its coefficient
  * table).
+ * nlf_getrf_batched_noalloc is the variant that allocates nothing.
  * ---------------------------------------------------------------------------------------- */
 
 /* T(z_k) = sum_j f_j(z_k) A_j for k = 0..nz-1 (the matrices whose inverses Step 4 applies).
@@ -281,6 +282,21 @@ nlfeast_status nlf_getrf_batched_blocked(int32_t dtype, int64_t n, int32_t batch
                                          int64_t lda, int64_t strideA, int32_t* ipiv_dev,
                                          int32_t* perm_dev, int32_t* info_dev, void* dinv_dev,
                                          void* stream);
+
+/* Allocation-free variant of nlf_getrf_batched, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, factorisation, pivots and statuses; the row-exchange lists that
+ * nlf_getrf_batched allocates per call live in a fixed device array of
+ * NLF_NOALLOC_SCRATCH_INTS int32 (4 MiB) per GPU, held until the process ends.  Needs
+ * 4 * n * batch <= NLF_NOALLOC_SCRATCH_INTS (n * batch <= 262144, e.g. n = 8192 with 32
+ * matrices); larger calls return NLF_ERR_ARG before any launch.  Calls no hipMalloc/hipFree.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  Nothing in the array carries from
+ * one call to the next (each call writes every entry it reads). */
+#define NLF_NOALLOC_SCRATCH_INTS (1 << 20)
+nlfeast_status nlf_getrf_batched_noalloc(int32_t dtype, int64_t n, int32_t batch, void* A_dev,
+                                         int64_t lda, int64_t strideA, int32_t* ipiv_dev,
+                                         int32_t* perm_dev, int32_t* info_dev, void* stream);
 
 /* X_b = A_b^{-1} B_b from nlf_getrf_batched factors (same dtype), nrhs columns.  B_dev
  * (ldb, strideB; strideB = 0 shares one right-hand side across the batch) is read, X_dev

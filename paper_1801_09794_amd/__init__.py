@@ -108,6 +108,7 @@ _SIGS = {
     "nlf_assemble": (c_i32, [c_i64, c_i32, P_i32, P_dbl, P_vp, c_i64, c_i32, P_dbl, c_vp, c_vp,
                              c_i64, c_i64, c_vp]),
     "nlf_getrf_batched": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]),
+    "nlf_getrf_batched_noalloc": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "nlf_getrf_batched_blocked": (c_i32, [c_i32, c_i64, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp,
                                           c_vp, c_vp]),
     "nlf_getrs_batched": (c_i32, [c_i32, c_i64, c_i32, c_i32, c_vp, c_i64, c_i64, c_vp, c_vp,
@@ -322,6 +323,19 @@ def nlf_getrf_batched(A, ipiv, perm, info, stream=None):
     batch, n = A.shape[0], A.shape[-1]
     _check(lib().nlf_getrf_batched(dtype, n, batch, _ptr(A), n, n * n, _ptr(ipiv), _ptr(perm),
                                    _ptr(info), _stream(stream)))
+
+
+def nlf_getrf_batched_noalloc(A, ipiv, perm, info, stream=None):
+    """nlf_getrf_batched without any device allocation (the exchange lists use the library's
+    fixed per-GPU scratch; 4 n batch <= NLF_NOALLOC_SCRATCH_INTS)."""
+    import torch
+    dtype = NLF_C128 if A.dtype == torch.complex128 else NLF_C64
+    batch, n = A.shape[0], A.shape[-1]
+    _check(lib().nlf_getrf_batched_noalloc(dtype, n, batch, _ptr(A), n, n * n, _ptr(ipiv), _ptr(perm),
+                                           _ptr(info), _stream(stream)))
+
+
+NLF_NOALLOC_SCRATCH_INTS = 1 << 20
 
 
 def nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv, stream=None):

@@ -81,6 +81,9 @@ struct Error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// The text nlfeast_last_error(NULL) returns for a failed call without a handle.
+void record_error(const std::string& msg);
+
 // Kernel classes of the launch profiler (same numbering as nlfeast_kernel_class).
 enum ProfClass {
     NLF_PROF_ASSEMBLE = 0, NLF_PROF_LU_GEMM = 1, NLF_PROF_PANEL = 2, NLF_PROF_TRSM = 3,

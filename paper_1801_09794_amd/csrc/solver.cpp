@@ -131,6 +131,8 @@ struct ProfilerGuard {
 
 static thread_local std::string g_last_error;
 
+void record_error(const std::string& msg) { g_last_error = msg; }
+
 }  // namespace nlf
 
 using namespace nlf;
