@@ -157,7 +157,11 @@ __device__ __forceinline__ void gemm_stage(Cx<R>* As, Cx<R>* Bs, int tid, const 
     }
 }
 
-template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT>
+// M3: the complex products by three real MFMAs instead of four (the "3M" scheme): with
+// T1 = Ar Br, T2 = Ai Bi and T3 = (Ar + Ai)(Br + Bi) accumulated separately, Cr = T1 - T2 and
+// Ci = T3 - T1 - T2 in the epilogue (one accumulator more, a quarter fewer matrix instructions;
+// the imaginary part's rounding error grows to about (|Ar| + |Ai|)(|Br| + |Bi|) eps per term).
+template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT, bool M3 = false>
 __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
     using T = GemmTile<R, TM, TN, BK, CONJA>;
     constexpr int BM = T::BM, BN = T::BN, LA = T::LA, LB = T::LB, PAD = T::PAD;
@@ -186,13 +190,15 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
         kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
     }
 
-    acc_t accR[TM][TN], accI[TM][TN];
+    // 4M: accR, accI; 3M: accR = T1, accI = T2, acc3 = T3 (combined in the epilogue)
+    acc_t accR[TM][TN], accI[TM][TN], acc3[M3 ? TM : 1][M3 ? TN : 1];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             accR[i][j] = acc_t{0, 0, 0, 0};
             accI[i][j] = acc_t{0, 0, 0, 0};
+            if constexpr (M3) acc3[i][j] = acc_t{0, 0, 0, 0};
         }
 
     Cx<R> ra[LA], rb[LB];
@@ -213,6 +219,26 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
                 for (int i = 0; i < TM; ++i) a[i] = As[buf][kk + krow][wm * 16 * TM + i * 16 + col];
 #pragma unroll
                 for (int j = 0; j < TN; ++j) b[j] = Bs[buf][kk + krow][wn * 16 * TN + j * 16 + col];
+                if constexpr (M3) {
+                    R as[TM], bs[TN];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) as[i] = a[i].re + a[i].im;
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) bs[j] = b[j].re + b[j].im;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) accR[i][j] = Mfma<R>::mma(b[j].re, a[i].re, accR[i][j]);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) accI[i][j] = Mfma<R>::mma(b[j].im, a[i].im, accI[i][j]);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc3[i][j] = Mfma<R>::mma(bs[j], as[i], acc3[i][j]);
+                    continue;
+                }
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -236,6 +262,16 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
         }
     }
 
+    if constexpr (M3) {   // Cr = T1 - T2, Ci = T3 - T1 - T2
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const acc_t t1 = accR[i][j], t2 = accI[i][j];
+                accR[i][j] = t1 - t2;
+                accI[i][j] = acc3[i][j] - t1 - t2;
+            }
+    }
     // epilogue: lane holds, for tile (i, j) and register r, C(m, n) with
     // m = m0 + wm*16TM + 16i + (lane & 15), n = n0 + wn*16TN + 16j + acc_row(lane >> 4, r)
     if (SPLIT) {
@@ -281,9 +317,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
 
 // The same tile program under its own symbol for the rank-NB trailing updates of the blocked
 // LU, so that traces and counters can single out the dominant launches of the factorisation.
+// In FP64 it takes the 3M products (FP32 keeps 4M: the 3M rounding of the imaginary part
+// would cost the complex64 factors accuracy that the refinement has to win back).
 template <typename R, int TM, int TN, int BK>
 __global__ __launch_bounds__(256) void lu_update_kernel(GemmArgs<R> g) {
-    gemm_tile_body<R, TM, TN, BK, false, false>(g);
+    gemm_tile_body<R, TM, TN, BK, false, false, sizeof(R) == 8>(g);
 }
 
 // C = sum_s P_s + beta C over the split-K partials.
@@ -328,8 +366,10 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
 
 // Default tile choice, from measured sweeps on MI355X: FP64 runs best with the 64 x 64 tile
 // (two waves per SIMD); FP32 with 128 x 64 once there are enough tiles to fill the chip.
-// Small problems (the deep levels of the recursive triangular solves) take the 32 x 32 tile,
-// which quadruples the number of workgroups and cuts the serial MFMA chain per tile by 4.
+// Problems with fewer than four 64 x 64 tiles per compute unit take the 32 x 32 tile, which
+// quadruples the number of workgroups and cuts the serial MFMA chain per tile by 4 (measured:
+// A_j Q at 8192 x 160 x 8192, 38 -> 54 TFLOP/s; the 256 x 160 x 256 diagonal-block solves of
+// 24 nodes, 23 -> 36 TFLOP/s; the 8192 x 160 x 640 block residual, 34 -> 45 TFLOP/s).
 template <typename R>
 static GemmConfig pick_config(int64_t M, int64_t N, int64_t K, int batch) {
     GemmConfig c;
@@ -337,7 +377,7 @@ static GemmConfig pick_config(int64_t M, int64_t N, int64_t K, int batch) {
     if (sizeof(R) == 4 && ceil_div(M, 128) * ceil_div(N, 64) * batch >= 512) {
         c.tm = 4;
         c.tn = 2;
-    } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch < 256) {
+    } else if (ceil_div(M, 64) * ceil_div(N, 64) * batch < 1024) {
         c.tm = 1;
         c.tn = 1;
     }

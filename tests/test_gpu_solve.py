@@ -354,17 +354,21 @@ def test_regions_concurrent_equal_sequential():
     assert match_err(a["lam"][:20][conv[:20]], brute, r) < 1e-10
 
 
-@pytest.mark.parametrize("prec,tol_eig", [(nl.NLF_PREC_FP64, 1e-10), (nl.NLF_PREC_FP32_REFINE, 1e-9)])
-def test_qep2048x8_batched_regions(prec, tol_eig):
+@pytest.mark.parametrize("prec,tol_eig,tuned", [(nl.NLF_PREC_FP64, 1e-10, 0), (nl.NLF_PREC_FP32_REFINE, 1e-9, 0),
+                                                (nl.NLF_PREC_FP64, 1e-10, 1), (nl.NLF_PREC_FP32_REFINE, 1e-9, 1)])
+def test_qep2048x8_batched_regions(prec, tol_eig, tuned):
     # eight disjoint regions with m0 from 16 to 128 share one batched factorisation of the 128
-    # node matrices; every region's converged eigenvalues are exactly the brute-force set
+    # node matrices; every region's converged eigenvalues are exactly the brute-force set.
+    # tuned = 1 is the benchmarked launch configuration: autotuned LU launch parameters and the
+    # factorisation captured in a hipGraph
     cfg = wl.CONFIGS["qep2048x8"]
     terms, mats = wl.make_problem("qep2048x8")
     gs = contours("qep2048x8")
     regs = [dict(centre=complex(*g["centre"]), a=g["radius"], nc=cfg["nc"], m0=g["m0"]) for g in gs]
     M = sum(g["m0"] for g in gs)
     out = gpu_solve(terms, mats, regs, wl.initial_block(cfg["n"], M, 2000 + cfg["id"]),
-                    nl.options(tol=cfg["tol"], precision=prec), quad_rule=nl.NLF_QUAD_TRAPEZOID)
+                    nl.options(tol=cfg["tol"], precision=prec, autotune=tuned, graph=tuned),
+                    quad_rule=nl.NLF_QUAD_TRAPEZOID)
     assert status_ok(out)
     col = 0
     for ri, g in enumerate(gs):
