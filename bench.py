@@ -140,7 +140,7 @@ def load_workload(name):
 
 
 def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0, graph=0, user_fn=None,
-            reduced_solver=0):
+            reduced_solver=0, region_streams=0):
     import torch
     import paper_1801_09794_amd as nl
     n = cfg["n"]
@@ -154,7 +154,8 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     X0d = nl.to_colmajor(X0, "cuda:0")
     opts = nl.options(tol=cfg["tol"], precision=precision, max_refine=5, refine_eta=args.refine_eta,
                       lu_streams=args.lu_streams, panel_width=args.panel_width,
-                      autotune=autotune, graph=graph, lookahead=args.lookahead, reduced_solver=reduced_solver)
+                      autotune=autotune, graph=graph, lookahead=args.lookahead, reduced_solver=reduced_solver,
+                      region_streams=region_streams)
     for _ in range(args.warmup):
         S.set_contour(regions, quad_rule=quad)
         S.solve(opts, X0d)
@@ -225,20 +226,30 @@ def leg_stats(args, name, key, n, nz, regions, cfg, t, o, p):
             "hbm_kernels": hbm_kernels(p)}
 
 
-def extra_leg(args, name, description, autotune, graph):
+def extra_leg(args, name, description, autotune, graph, plain_fp64=False, reduced_solver=0):
     """A workload beside the headline in FP64 and in FP32 LU + FP64 refinement (same inputs,
     same tolerance), with the speedup of the precision form over FP64 on this workload and the
-    converged eigenvalues checked against the stored reference."""
+    converged eigenvalues checked against the stored reference.  plain_fp64: also the plain
+    FP64 path on the same inputs (regions one after another on one stream, eager launches, no
+    tuner), the baseline the batched precision form is measured against."""
     import paper_1801_09794_amd as nl
     cfg, terms, mats, regions, X0 = load_workload(name)
     n, nz = cfg["n"], sum(r["nc"] for r in regions)
     out = {"workload": description % dict(n=n, m0=[r["m0"] for r in regions], nc=cfg["nc"], nz=nz,
                                           tol=cfg["tol"], inside=cfg.get("inside") or 0)}
     for key, prec in (("fp64", nl.NLF_PREC_FP64), ("fp32_refine", nl.NLF_PREC_FP32_REFINE)):
-        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph)
+        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph,
+                          reduced_solver=reduced_solver)
         out[key] = leg_stats(args, name, key, n, nz, regions, cfg, t, o, p)
     out["fp32_refine_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
     out["fp32_refine_vs_fp64_eigenpairs_per_s"] = out["fp32_refine"]["value"] / out["fp64"]["value"]
+    if plain_fp64:
+        t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, True, autotune=0, graph=0,
+                          region_streams=1)
+        out["fp64_plain"] = leg_stats(args, name, "fp64", n, nz, regions, cfg, t, o, p)
+        out["fp64_plain"]["launch"] = ("regions one after another on one stream, eager launches, default LU "
+                                       "parameters, companion linearisation of the reduced problem")
+        out["batched_fp32_refine_vs_plain_fp64_eigenpairs_per_s"] = out["fp32_refine"]["value"] / out["fp64_plain"]["value"]
     return out
 
 
@@ -551,7 +562,8 @@ def main():
                 args, "qep2048x8",
                 "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
                 "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
-                "parameters), tol %(tol).0e", autotune=1, graph=1)
+                "parameters, contour-integral reduced solve with device moments), tol %(tol).0e",
+                autotune=1, graph=1, plain_fp64=True, reduced_solver=3)
         if not args.no_nc_sweep and name != "quartic1024":
             result["nc_sweep"] = nc_sweep(args)
         if not args.no_left:

@@ -117,14 +117,19 @@ typedef struct {
     int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
                                     the trailing update of panel k runs; -1 = one stream;
                                     0 = library default (one stream) */
-    int32_t reduced_solver;      /* Steps 1-2 for non-polynomial T: 0 (default) or 1 = the
-                                    contour-integral solve (moments of the reduced resolvent on
-                                    the contour enlarged 1.5 times, block Hankel matrices, Newton
-                                    refinement); 2 = Taylor linearisation about the contour centre
-                                    and Newton refinement (NLF_F_EXP terms).  Problems with an
-                                    NLF_F_USER term always take the contour-integral solve;
-                                    polynomial problems always the exact companion
-                                    linearisation */
+    int32_t reduced_solver;      /* Steps 1-2 (Sec. 4.2: the projected problem may be solved by
+                                    any suitable method).  Non-polynomial T: 0 (default) or 1 =
+                                    the contour-integral solve (moments of the reduced resolvent
+                                    on the contour enlarged 1.5 times, formed on the device; block
+                                    Hankel matrices, Newton refinement); 2 = Taylor linearisation
+                                    about the contour centre and Newton refinement (NLF_F_EXP
+                                    terms).  Polynomial T: the exact companion linearisation for
+                                    0..2; 3 = the contour-integral solve for every problem (for
+                                    polynomial problems cheaper than the companion matrix of order
+                                    degree x m0 once m0 reaches ~100, but it needs the enlarged
+                                    contour to hold fewer than 3 m0 eigenvalues of the reduced
+                                    problem).  Problems with an NLF_F_USER term always take the
+                                    contour-integral solve */
 } nlfeast_options;
 
 typedef struct nlfeast_ctx* nlfeast_handle;
@@ -412,9 +417,10 @@ nlfeast_status nlf_reduced_solve(int32_t m, int32_t J, const int32_t* fkind,
                                  double* Y_out);
 
 /* As nlf_reduced_solve, with terms of kind NLF_F_USER evaluated by fn(user, ...) and the
- * choice `method` of nlfeast_options.reduced_solver (0..2).  The contour-integral solve
- * (Sec. 3 eq. cauchymoments applied to the reduced function; taken for NLF_F_USER terms, and for
- * any non-polynomial term unless method is 2) needs m_keep <= m: it returns the eigenpairs found
+ * choice `method` of nlfeast_options.reduced_solver (0..3).  The contour-integral solve
+ * (Sec. 3 eq. cauchymoments applied to the reduced function; taken for NLF_F_USER terms, for
+ * any non-polynomial term unless method is 2, and for every problem with method 3; here the
+ * moments are formed on the host) needs m_keep <= m: it returns the eigenpairs found
  * inside the contour enlarged 1.5 times, Newton-refined and in ascending normalised radius,
  * followed, when fewer than m_keep were found, by completing pairs (unit vectors orthogonal to
  * those found, with values spread over the enlarged contour); found_out (m_keep int32, may be

@@ -310,9 +310,9 @@ __device__ __forceinline__ void gemm_tile_body(const GemmArgs<R>& g) {
     }
 }
 
-template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT>
+template <typename R, int TM, int TN, int BK, bool CONJA, bool SPLIT, bool M3>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
-    gemm_tile_body<R, TM, TN, BK, CONJA, SPLIT>(g);
+    gemm_tile_body<R, TM, TN, BK, CONJA, SPLIT, M3>(g);
 }
 
 // The same tile program under its own symbol for the rank-NB trailing updates of the blocked
@@ -346,8 +346,9 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, 
 
 // ---------------------------------------------------------------------------- host side
 
+// m3: the 3M products (FP64 only; see gemm_tile_body).
 template <typename R, int TM, int TN, int BK, bool CONJA>
-static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, bool lu_update) {
+static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, bool lu_update, bool m3) {
     constexpr int BM = 32 * TM, BN = 32 * TN;
     g.tilesM = (int)ceil_div(g.M, BM);
     g.tilesN = (int)ceil_div(g.N, BN);
@@ -358,10 +359,19 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
             return;
         }
     }
+    if constexpr (sizeof(R) == 8 && !CONJA) {
+        if (m3) {
+            if (nsplit > 1)
+                hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, true, true>), grid, dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, false, true>), grid, dim3(256), 0, s, g);
+            return;
+        }
+    }
     if (nsplit > 1)
-        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, true>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, true, false>), grid, dim3(256), 0, s, g);
     else
-        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, false>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, false, false>), grid, dim3(256), 0, s, g);
 }
 
 // Default tile choice, from measured sweeps on MI355X: FP64 runs best with the 64 x 64 tile
@@ -418,11 +428,14 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     }
 // K step per LDS stage: 8 for the 64- and 128-row tiles (half the LDS, so four workgroups
 // share a CU and hide each other's barriers; measured 4-6% faster), 16 otherwise
+    // FP64 products op(A) = A take 3M once the reduction is long enough to pay for the third
+    // accumulator (every contraction of the path but the Gram and projection products Q^H X)
+    const bool m3 = sizeof(R) == 8 && !conjA && K >= 64;
 #define NLF_GEMM_CASE(TM_, TN_)                                                          \
     if (c.tm == TM_ && c.tn == TN_) {                                                   \
         constexpr int BKX = (TM_ == 1 || (TM_ == 4 && TN_ == 4)) ? 16 : 8;               \
-        if (conjA) launch_tiles<R, TM_, TN_, BKX, true>(s, g, batch, nsplit, false);     \
-        else       launch_tiles<R, TM_, TN_, BKX, false>(s, g, batch, nsplit, lu_update);\
+        if (conjA) launch_tiles<R, TM_, TN_, BKX, true>(s, g, batch, nsplit, false, false);   \
+        else       launch_tiles<R, TM_, TN_, BKX, false>(s, g, batch, nsplit, lu_update, m3); \
     } else
     NLF_GEMM_CASE(1, 1)
     NLF_GEMM_CASE(2, 2)

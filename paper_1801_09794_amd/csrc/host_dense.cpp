@@ -1216,7 +1216,7 @@ bool takes_contour_route(const std::vector<Term>& terms, int method) {
         if (t.kind != 0) poly = false;
         if (t.kind == 2) user = true;
     }
-    return user || (!poly && method != 2);
+    return user || (!poly && method != 2) || method == 3;
 }
 
 ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* Ahat,
@@ -1230,7 +1230,7 @@ ReducedResult reduced_solve(int m, const std::vector<Term>& terms, const cplx* A
         else poly = false;
         if (t.kind == 2) user = true;
     }
-    if (user || (!poly && method != 2)) return contour_reduced(m, terms, Ahat, E, m_keep);
+    if (user || (!poly && method != 2) || method == 3) return contour_reduced(m, terms, Ahat, E, m_keep);
     const size_t mm = (size_t)m * m;
     const std::vector<cplx> shifts = shift_candidates(E, avoid);
     int deg = maxpow, N = 0;

@@ -1244,8 +1244,8 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         NLF_REQUIRE((opt->region_streams == 0 || opt->region_streams == 1) && (opt->graph == 0 || opt->graph == 1) &&
                         (opt->autotune == 0 || opt->autotune == 1),
                     NLF_ERR_ARG, "solve: region_streams, graph and autotune are 0 or 1");
-        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && opt->reduced_solver >= 0 && opt->reduced_solver <= 2,
-                    NLF_ERR_ARG, "solve: lookahead in -1..1, reduced_solver in 0..2");
+        NLF_REQUIRE(opt->lookahead >= -1 && opt->lookahead <= 1 && opt->reduced_solver >= 0 && opt->reduced_solver <= 3,
+                    NLF_ERR_ARG, "solve: lookahead in -1..1, reduced_solver in 0..3");
         bool has_user = false;
         for (const Term& t : h->terms) has_user = has_user || t.kind == NLF_F_USER;
         NLF_REQUIRE(!has_user || h->ufn.fn, NLF_ERR_STATE,
@@ -1361,8 +1361,10 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
             for (int ri = 0; ri < nreg; ++ri) {
                 out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[0], h->profiling ? &h->prof : nullptr, io,
                                      factored, nullptr, adj);
-                if (out[ri].status != NLF_OK && out[ri].status != NLF_ERR_NOT_CONVERGED &&
-                    out[ri].status != NLF_ERR_M0_TOO_SMALL)
+                // a hard error ends the sequence; the convergence statuses (spurious values
+                // flagged, not converged, m0 too small) leave the later regions to run
+                if (out[ri].status != NLF_OK && out[ri].status != NLF_SPURIOUS &&
+                    out[ri].status != NLF_ERR_NOT_CONVERGED && out[ri].status != NLF_ERR_M0_TOO_SMALL)
                     break;
             }
             NLF_HIP(hipEventRecord(h->rdone[0], h->rstream[0]));
@@ -1827,7 +1829,7 @@ static void reduced_solve_c(int32_t m, int32_t J, const int32_t* fkind, const do
                             int32_t m_keep, const double* avoid, int32_t n_avoid, double* lambda_out, double* Y_out,
                             int32_t* found_out, const char* who) {
     NLF_REQUIRE(m >= 1 && J >= 1 && J <= 8 && fkind && fparam && Ahat && a > 0 && b > 0 && m_keep >= 1 &&
-                    lambda_out && Y_out && method >= 0 && method <= 2,
+                    lambda_out && Y_out && method >= 0 && method <= 3,
                 NLF_ERR_ARG, std::string(who) + ": bad arguments");
     std::vector<Term> terms(J);
     bool user = false;

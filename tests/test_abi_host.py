@@ -133,6 +133,30 @@ def test_contour_reduced_matches_oracle(lib, route, shape, m, seed):
     assert np.linalg.norm(np.linalg.norm(Y, axis=0) - 1) < 1e-12
 
 
+@pytest.mark.parametrize("m,seed", [(16, 51), (40, 52)])
+def test_contour_route_on_a_polynomial_matches_the_companion(lib, m, seed):
+    """reduced_solver = 3 takes the contour-integral solve for a polynomial reduced problem too:
+    inside the contour its eigenvalues are the exact companion's (method 0), and the oracle's
+    contour reading (SVD of the Hankel matrix) finds the same values."""
+    rng = np.random.default_rng(seed)
+    A = [np.eye(m, dtype=complex), wl.cn(rng, (m, m)) / np.sqrt(m), wl.cn(rng, (m, m)) / np.sqrt(m)]
+    C = qd.Contour(0.15 - 0.1j, 0.55)
+    lc, Yc, fc = nl.nlf_reduced_solve_ex(wl.QUADRATIC, A, C.c, C.a, C.b, m, method=3)
+    lp, _, fp = nl.nlf_reduced_solve_ex(wl.QUADRATIC, A, C.c, C.a, C.b, m, method=0)
+    assert fp.all()
+    ins = lambda l: np.sort_complex(l[C.inside(l)])
+    a, b = ins(lc[fc]), ins(lp)
+    assert len(a) == len(b) >= 3
+    assert np.max(np.abs(a - b)) < 1e-12
+    lo, _, fo = reduced.contour_reduced(wl.QUADRATIC, A, C, m)
+    o = ins(lo[fo])
+    assert len(o) == len(a) and np.max(np.abs(o - a)) < 1e-12
+    for l, y in zip(lc[fc], Yc[:, fc].T):
+        if C.inside(l):
+            T = l * l * A[0] + l * A[1] + A[2]
+            assert np.linalg.norm(T @ y) < 1e-12 * np.linalg.norm(T)
+
+
 def test_reduced_solver_choice(lib):
     """Method 2 keeps the Taylor route for exponential terms (every pair marked found, the same
     values as nlf_reduced_solve); method 0 takes the contour-integral solve."""
