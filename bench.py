@@ -63,6 +63,8 @@ def parse():
                     help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
     ap.add_argument("--lu-streams", type=int, default=0,
                     help="node-matrix groups factored on separate streams (0 = library default)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched qep2048x8 leg (for kernel traces of it) and print its result")
     ap.add_argument("--probe-lu", action="store_true",
                     help="counter runs: one 1 GiB device copy (calibration), then one FP64 "
                          "batched blocked LU of the headline shape, nothing else")
@@ -438,6 +440,18 @@ def oracle_full_run(name):
     return {k: e[k] for k in ("seconds", "converged", "iterations", "cores", "host") if k in e}
 
 
+def batched_leg(args):
+    """The eight-region quadratic: one batched factorisation of all 128 node matrices (tuned
+    launch parameters, one hipGraph), regions iterating concurrently with contour-integral
+    reduced solves; FP64, FP32 + refinement and the plain FP64 path."""
+    return extra_leg(
+        args, "qep2048x8",
+        "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
+        "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
+        "parameters, contour-integral reduced solve with device moments), tol %(tol).0e",
+        autotune=1, graph=1, plain_fp64=True, reduced_solver=3)
+
+
 def main():
     args = parse()
     if args.probe_lu:
@@ -452,6 +466,12 @@ def main():
     nl.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.batched_only:
+        args.steps = max(1, min(args.steps, args.leg_steps))
+        args.warmup = min(args.warmup, 1)
+        print(json.dumps({"leg": "batched", "steps": args.steps, "warmup": args.warmup,
+                          "result": batched_leg(args)}))
+        return
     name = args.workload
     cfg, terms, mats, regions, X0 = load_workload(name)
     n = cfg["n"]
@@ -558,12 +578,7 @@ def main():
                 "complex128, circle enclosing 40 eigenvalues, m0 %(m0)s, %(nc)d Gauss-Legendre nodes, "
                 "factorisation replayed as hipGraph segments, tol %(tol).0e", autotune=0, graph=args.graph)
         if not args.no_batched and name != "qep2048x8":
-            result["batched"] = extra_leg(
-                args, "qep2048x8",
-                "qep2048x8: T(l) = l^2 I + l A1 + A0, n=%(n)d complex Gaussian/sqrt(n), 8 disjoint circles, "
-                "m0 %(m0)s, %(nc)d trapezoid nodes each (%(nz)d LUs, one hipGraph, tuned launch "
-                "parameters, contour-integral reduced solve with device moments), tol %(tol).0e",
-                autotune=1, graph=1, plain_fp64=True, reduced_solver=3)
+            result["batched"] = batched_leg(args)
         if not args.no_nc_sweep and name != "quartic1024":
             result["nc_sweep"] = nc_sweep(args)
         if not args.no_left:

@@ -113,30 +113,51 @@ void col_norms(hipStream_t s, int64_t n, int m, const z128* X, int64_t ld, doubl
 }
 
 // Q = X diag(rho) - sum_k Y_k diag(c_k): column c of Q from column c of X and of every Y_k
-// (the coefficients of the column are uniform across the workgroup).
+// (the coefficients of the column are uniform across the workgroup).  Thread t of workgroup
+// (x, c) handles rows x 256 RPT + t + 256 r, r < RPT.  The nodes are taken KU at a time with all
+// their loads issued before the multiply-adds, so KU RPT loads per thread are in flight; the
+// sum still runs over k in ascending order.  Large blocks take four rows and one node at a time
+// (enough workgroups to cover the latency), smaller ones fewer rows per thread and more nodes
+// per load batch: more workgroups, and fewer round trips to memory per thread.
+template <int RPT, int KU>
 __global__ __launch_bounds__(256) void accumulate_kernel(int64_t n, int m, int nz,
                                                          const z128* __restrict__ X,
                                                          const z128* __restrict__ Y, int64_t sY,
                                                          const z128* __restrict__ rho,
                                                          const z128* __restrict__ coef, z128* Q) {
     const int64_t c = blockIdx.y;
-    const int64_t e0 = (int64_t)blockIdx.x * EW_ROWS + threadIdx.x + c * n;
+    const int64_t e0 = (int64_t)blockIdx.x * (256 * RPT) + threadIdx.x + c * n;
     const int64_t end = (c + 1) * n;
     const z128 rc = rho[c];
-    z128 q[EW_RPT];
+    z128 q[RPT];
 #pragma unroll
-    for (int r = 0; r < EW_RPT; ++r) q[r] = e0 + 256 * r < end ? rc * ld_stream(X + e0 + 256 * r) : z128(0, 0);
-    for (int k = 0; k < nz; ++k) {
+    for (int r = 0; r < RPT; ++r) q[r] = e0 + 256 * r < end ? rc * ld_stream(X + e0 + 256 * r) : z128(0, 0);
+    int k = 0;
+    for (; k + KU <= nz; k += KU) {
+        z128 w[KU], y[KU][RPT];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            w[u] = coef[(int64_t)(k + u) * m + c];
+            const z128* Yk = Y + (k + u) * sY;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) y[u][r] = e0 + 256 * r < end ? ld_stream(Yk + e0 + 256 * r) : z128(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) cfms(q[r], w[u], y[u][r]);
+    }
+    for (; k < nz; ++k) {
         const z128 w = coef[(int64_t)k * m + c];
         const z128* Yk = Y + k * sY;
-        z128 y[EW_RPT];
+        z128 y[RPT];
 #pragma unroll
-        for (int r = 0; r < EW_RPT; ++r) y[r] = e0 + 256 * r < end ? ld_stream(Yk + e0 + 256 * r) : z128(0, 0);
+        for (int r = 0; r < RPT; ++r) y[r] = e0 + 256 * r < end ? ld_stream(Yk + e0 + 256 * r) : z128(0, 0);
 #pragma unroll
-        for (int r = 0; r < EW_RPT; ++r) cfms(q[r], w, y[r]);
+        for (int r = 0; r < RPT; ++r) cfms(q[r], w, y[r]);
     }
 #pragma unroll
-    for (int r = 0; r < EW_RPT; ++r)
+    for (int r = 0; r < RPT; ++r)
         if (e0 + 256 * r < end) Q[e0 + 256 * r] = q[r];
 }
 
@@ -144,8 +165,20 @@ void accumulate(hipStream_t s, int64_t n, int m, int nz, const z128* X, const z1
                 int64_t sY, const z128* rho, const z128* c, z128* Q) {
     if (n <= 0 || m <= 0) return;
     ProfScope ps(NLF_PROF_ACCUMULATE, s, 8.0 * n * m * nz, 16.0 * n * m * (nz + 2));
-    hipLaunchKernelGGL(accumulate_kernel, dim3((unsigned)ceil_div(n, EW_ROWS), (unsigned)m), dim3(256), 0, s, n,
-                       m, nz, X, Y, sY, rho, c, Q);
+    // measured on MI355X (complex128, 16-24 nodes): four-row threads, one node at a time, are
+    // fastest from about 1024 such workgroups (n = 8192, m = 160: 6.7 TB/s); two rows and four
+    // nodes from 128 (n = 4096, m = 64: 12.9 us against 17.8); one row and eight nodes below
+    // (n = 2048, m = 16: 6.2 us against 12.9)
+    const int64_t w4 = ceil_div(n, 1024) * m;
+    if (w4 >= 1024)
+        hipLaunchKernelGGL((accumulate_kernel<4, 1>), dim3((unsigned)ceil_div(n, 1024), (unsigned)m), dim3(256), 0,
+                           s, n, m, nz, X, Y, sY, rho, c, Q);
+    else if (w4 >= 128)
+        hipLaunchKernelGGL((accumulate_kernel<2, 4>), dim3((unsigned)ceil_div(n, 512), (unsigned)m), dim3(256), 0,
+                           s, n, m, nz, X, Y, sY, rho, c, Q);
+    else
+        hipLaunchKernelGGL((accumulate_kernel<1, 8>), dim3((unsigned)ceil_div(n, 256), (unsigned)m), dim3(256), 0,
+                           s, n, m, nz, X, Y, sY, rho, c, Q);
     NLF_HIP(hipGetLastError());
 }
 

@@ -415,6 +415,20 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // split-K for small outputs with long reductions (projections, Gram matrices)
     int nsplit = 1;
     const int64_t tiles = ceil_div(M, 32 * c.tm) * ceil_div(N, 32 * c.tn) * batch;
+    // A ragged last column of 64-wide tiles that would hold at most 32 columns (N = 160 = 2 x 64
+    // + 32: a sixth of the tile's MFMA work wasted) goes to a second launch of 32 x 32 tiles.
+    // Measured on the right-looking updates of the block triangular solves (n = 8192, 160
+    // right-hand sides, 24 nodes, K = 256): 64 x 64 tiles 61 TFLOP/s, 32 x 32 tiles 62
+    if (!force && !lu_update && c.tn == 2 && N > 64 && N % 64 != 0 && N % 64 <= 32 &&
+        !(ws && tiles < 256 && K >= 512)) {
+        const int64_t N0 = N - N % 64;
+        gemm<R>(s, conjA, M, N0, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws, ws_elems, &c,
+                lu_update);
+        const GemmConfig c1{1, 1};
+        gemm<R>(s, conjA, M, N - N0, K, alpha, A, lda, sA, B + N0 * ldb, ldb, sB, beta, C + N0 * ldc, ldc, sC,
+                batch, ws, ws_elems, &c1, lu_update);
+        return;
+    }
     if (ws && tiles < 256 && K >= 512) {
         int want = (int)std::min<int64_t>(ceil_div(512, tiles), ceil_div(K, 256));
         while (want > 1 && (int64_t)want * M * N * batch > ws_elems) --want;

@@ -16,6 +16,76 @@ namespace nlf {
 static const double kEps = 2.220446049250313e-16;
 static const double kPi = 3.14159265358979323846;
 
+// Complex dot products with independent partial sums in AVX2 registers (two complex values per
+// register, two registers per sum), so consecutive multiply-adds do not wait on each other as
+// they would in one running complex sum.  With x = [ar, ai, ...] and y = [br, bi, ...]:
+// x*y = [ar br, ai bi], x*swap(y) = [ar bi, ai br], from which conj(a) b and a b follow.
+template <bool CONJ>
+static inline cplx cdot(int64_t n, const cplx* a, const cplx* b) {
+    const double* x = reinterpret_cast<const double*>(a);
+    const double* y = reinterpret_cast<const double*>(b);
+    __m256d p0 = _mm256_setzero_pd(), q0 = _mm256_setzero_pd();
+    __m256d p1 = _mm256_setzero_pd(), q1 = _mm256_setzero_pd();
+    int64_t i = 0;
+    for (; i + 4 <= n; i += 4) {
+        const __m256d xa = _mm256_loadu_pd(x + 2 * i), ya = _mm256_loadu_pd(y + 2 * i);
+        const __m256d xb = _mm256_loadu_pd(x + 2 * i + 4), yb = _mm256_loadu_pd(y + 2 * i + 4);
+        p0 = _mm256_fmadd_pd(xa, ya, p0);
+        q0 = _mm256_fmadd_pd(xa, _mm256_permute_pd(ya, 0x5), q0);
+        p1 = _mm256_fmadd_pd(xb, yb, p1);
+        q1 = _mm256_fmadd_pd(xb, _mm256_permute_pd(yb, 0x5), q1);
+    }
+    for (; i + 2 <= n; i += 2) {
+        const __m256d xa = _mm256_loadu_pd(x + 2 * i), ya = _mm256_loadu_pd(y + 2 * i);
+        p0 = _mm256_fmadd_pd(xa, ya, p0);
+        q0 = _mm256_fmadd_pd(xa, _mm256_permute_pd(ya, 0x5), q0);
+    }
+    alignas(32) double P[4], Q[4];
+    _mm256_store_pd(P, _mm256_add_pd(p0, p1));
+    _mm256_store_pd(Q, _mm256_add_pd(q0, q1));
+    // P = [ar br, ai bi] summed over both lanes pairs; Q = [ar bi, ai br]
+    double rr = P[0] + P[2], ii = P[1] + P[3], ri = Q[0] + Q[2], ir = Q[1] + Q[3];
+    if (i < n) {
+        rr += x[2 * i] * y[2 * i];
+        ii += x[2 * i + 1] * y[2 * i + 1];
+        ri += x[2 * i] * y[2 * i + 1];
+        ir += x[2 * i + 1] * y[2 * i];
+    }
+    return CONJ ? cplx(rr + ii, ri - ir) : cplx(rr - ii, ri + ir);
+}
+static inline cplx cdotc(int64_t n, const cplx* a, const cplx* b) { return cdot<true>(n, a, b); }
+static inline cplx cdotu(int64_t n, const cplx* a, const cplx* b) { return cdot<false>(n, a, b); }
+// y_i += alpha x_i (two complex values per register: x alpha = fmaddsub(x, re(alpha),
+// swap(x) im(alpha)))
+static inline void caxpy(int64_t n, cplx alpha, const cplx* x, cplx* y) {
+    const double* xs = reinterpret_cast<const double*>(x);
+    double* ys = reinterpret_cast<double*>(y);
+    const __m256d ar = _mm256_set1_pd(alpha.real()), ai = _mm256_set1_pd(alpha.imag());
+    int64_t i = 0;
+    for (; i + 2 <= n; i += 2) {
+        const __m256d xv = _mm256_loadu_pd(xs + 2 * i);
+        const __m256d prod = _mm256_fmaddsub_pd(xv, ar, _mm256_mul_pd(_mm256_permute_pd(xv, 0x5), ai));
+        _mm256_storeu_pd(ys + 2 * i, _mm256_add_pd(_mm256_loadu_pd(ys + 2 * i), prod));
+    }
+    for (; i < n; ++i) y[i] += alpha * x[i];
+}
+// sum_i |a_i|^2 with independent partial sums
+static inline double csumsq(int64_t n, const cplx* a) {
+    const double* x = reinterpret_cast<const double*>(a);
+    __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+    int64_t i = 0;
+    for (; i + 4 <= n; i += 4) {
+        const __m256d xa = _mm256_loadu_pd(x + 2 * i), xb = _mm256_loadu_pd(x + 2 * i + 4);
+        s0 = _mm256_fmadd_pd(xa, xa, s0);
+        s1 = _mm256_fmadd_pd(xb, xb, s1);
+    }
+    alignas(32) double S[4];
+    _mm256_store_pd(S, _mm256_add_pd(s0, s1));
+    double t = (S[0] + S[1]) + (S[2] + S[3]);
+    for (; i < n; ++i) t += std::norm(a[i]);
+    return t;
+}
+
 double Ellipse::radius(cplx l) const {
     if (!std::isfinite(l.real()) || !std::isfinite(l.imag())) return std::numeric_limits<double>::infinity();
     const cplx d = l - c;
@@ -225,10 +295,9 @@ bool Schur::compute(int N_, std::vector<cplx>& A, bool vecs) {
         if (vn2 == 0.0) continue;
         const double beta = 2.0 / vn2;
         for (int j = k + 1; j < N; ++j) {                  // rows k+1.., columns k+1..
-            cplx t = 0.0;
-            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * H[i + (size_t)j * N];
+            cplx t = cdotc(N - k - 1, &v[k + 1], &H[k + 1 + (size_t)j * N]);
             t *= beta;
-            for (int i = k + 1; i < N; ++i) H[i + (size_t)j * N] -= v[i] * t;
+            caxpy(N - k - 1, -t, &v[k + 1], &H[k + 1 + (size_t)j * N]);
         }
         std::fill(s.begin(), s.end(), cplx(0.0));          // columns k+1.., all rows
         for (int j = k + 1; j < N; ++j)
@@ -508,10 +577,9 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
             // H <- (I - bt v v^H) H on rows k+1.., columns k+1..
             for (int j = j0; j < j1; ++j) {
                 cplx* hj = &H[(size_t)j * N];
-                cplx tt = 0.0;
-                for (int i = k + 1; i < N; ++i) tt += std::conj(v[i]) * hj[i];
+                cplx tt = cdotc(N - k - 1, v + k + 1, hj + k + 1);
                 tt *= bt;
-                for (int i = k + 1; i < N; ++i) hj[i] -= v[i] * tt;
+                caxpy(N - k - 1, -tt, v + k + 1, hj + k + 1);
             }
             if (P > 1) team.barrier();
             // s = H v over all rows (this thread's row range)
@@ -520,14 +588,14 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
             for (int j = k + 1; j < N; ++j) {
                 const cplx vj = v[j];
                 const cplx* hj = &H[(size_t)j * N];
-                for (int i = i0; i < i1; ++i) s[i] += hj[i] * vj;
+                caxpy(i1 - i0, vj, hj + i0, &s[i0]);
             }
             if (P > 1) team.barrier();
             // H <- H (I - bt v v^H) on columns k+1..
             for (int j = j0; j < j1; ++j) {
                 const cplx cv = bt * std::conj(v[j]);
                 cplx* hj = &H[(size_t)j * N];
-                for (int i = 0; i < N; ++i) hj[i] -= s[i] * cv;
+                caxpy(N, -cv, s.data(), hj);
             }
             if (P > 1) team.barrier();
             if (t == 0) {
@@ -625,8 +693,7 @@ void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) cons
             if (rk[k] == 0.0) rk[k] = smin;
             const cplx lk = rk1[k] / rk[k];
             rk1[k] = lk;
-            if (lk != 0.0)
-                for (int j = k + 1; j < N; ++j) rk1[j] -= lk * rk[j];
+            if (lk != 0.0) caxpy(N - k - 1, -lk, rk + k + 1, rk1 + k + 1);
         }
         if (M[(size_t)(N - 1) * N + N - 1] == 0.0) M[(size_t)(N - 1) * N + N - 1] = smin;
         for (int i = 0; i < N; ++i) x[i] = 1.0 / std::sqrt((double)N);
@@ -637,8 +704,7 @@ void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) cons
             }
             for (int i = N - 1; i >= 0; --i) {         // back: U^{-1}
                 const cplx* ri = &M[(size_t)i * N];
-                cplx t = x[i];
-                for (int j = i + 1; j < N; ++j) t -= ri[j] * x[j];
+                const cplx t = x[i] - cdotu(N - i - 1, ri + i + 1, &x[i + 1]);
                 cplx d = ri[i];
                 if (std::abs(d) < smin) d = smin;
                 x[i] = t / d;
@@ -652,10 +718,9 @@ void HessEig::vectors(const std::vector<int>& want, std::vector<cplx>& out) cons
         for (int k = N - 3; k >= 0; --k) {
             if (beta[k] == 0.0) continue;
             const cplx* v = &V[(size_t)k * N];
-            cplx t = 0.0;
-            for (int i = k + 1; i < N; ++i) t += std::conj(v[i]) * x[i];
+            cplx t = cdotc(N - k - 1, v + k + 1, &x[k + 1]);
             t *= beta[k];
-            for (int i = k + 1; i < N; ++i) x[i] -= v[i] * t;
+            caxpy(N - k - 1, -t, v + k + 1, &x[k + 1]);
         }
         double nr = 0.0;
         for (int i = 0; i < N; ++i) nr += std::norm(x[i]);
@@ -859,10 +924,7 @@ static int pivoted_qr(int N, std::vector<cplx>& A, std::vector<cplx>& tau, std::
     // recomputed when the downdate has cancelled most of the value
     std::vector<double> nrm2(N), ref(N);
     auto colnorm = [&](int c, int from) {
-        double t = 0.0;
-        const cplx* col = &A[(size_t)c * N];
-        for (int i = from; i < N; ++i) t += std::norm(col[i]);
-        return t;
+        return csumsq(N - from, &A[(size_t)c * N + from]);
     };
     const int nth = host_threads((int64_t)N * N, 1 << 14);
     std::atomic<int> rank{N};
@@ -902,11 +964,10 @@ static int pivoted_qr(int N, std::vector<cplx>& A, std::vector<cplx>& tau, std::
             const cplx ct = std::conj(tau[j]);
             for (int c = j + 1 + t; c < N; c += nth) {   // column c <- (I - conj(tau) v v^H) column c
                 cplx* b = &A[(size_t)c * N];
-                cplx w = b[j];
-                for (int i = j + 1; i < N; ++i) w += std::conj(a[i]) * b[i];
+                cplx w = b[j] + cdotc(N - j - 1, a + j + 1, b + j + 1);
                 w *= ct;
                 b[j] -= w;
-                for (int i = j + 1; i < N; ++i) b[i] -= a[i] * w;
+                caxpy(N - j - 1, -w, a + j + 1, b + j + 1);
                 const double d = nrm2[c] - std::norm(b[j]);
                 if (d <= 1e-6 * ref[c]) {
                     nrm2[c] = ref[c] = colnorm(c, j + 1);
@@ -1026,11 +1087,10 @@ bool contour_pairs_from_moments(int m, const Ellipse& E, const std::vector<cplx>
             cplx* q = &Qk[(size_t)c * N];
             for (int j = std::min(c, k - 1); j >= 0; --j) {   // H_j leaves e_c alone for j > c
                 const cplx* v = &H0[(size_t)j * N];
-                cplx s = q[j];
-                for (int i = j + 1; i < N; ++i) s += std::conj(v[i]) * q[i];
+                cplx s = q[j] + cdotc(N - j - 1, v + j + 1, q + j + 1);
                 s *= tau[j];
                 q[j] -= s;
-                for (int i = j + 1; i < N; ++i) q[i] -= v[i] * s;
+                caxpy(N - j - 1, -s, v + j + 1, q + j + 1);
             }
         }
     });
@@ -1044,9 +1104,7 @@ bool contour_pairs_from_moments(int m, const Ellipse& E, const std::vector<cplx>
             }
             for (int i = 0; i < k; ++i) {
                 const cplx* q = &Qk[(size_t)i * N];
-                cplx s = 0.0;
-                for (int r = 0; r < N; ++r) s += std::conj(q[r]) * h1[r];
-                G[i + (size_t)c * k] = s;
+                G[i + (size_t)c * k] = cdotc(N, q, h1.data());
             }
         }
     });
@@ -1074,20 +1132,21 @@ bool contour_pairs_from_moments(int m, const Ellipse& E, const std::vector<cplx>
     }
     lam.resize(k);
     Y.assign((size_t)m * k, 0.0);
-    for (int i = 0; i < k; ++i) {
-        lam[i] = E.c + L * ev[i];
-        cplx* y = &Y[(size_t)i * m];
-        for (int p = 0; p < k; ++p) {
-            const cplx sp = S[p + (size_t)i * k];
-            const cplx* q = &Qk[(size_t)p * N];
-            for (int r = 0; r < m; ++r) y[r] += q[r] * sp;
+    for (int i = 0; i < k; ++i) lam[i] = E.c + L * ev[i];
+    // y_i = the first block of Q_k s_i, normalised (the vectors are independent)
+    Team(nth).run([&](int t) {
+        for (int i = t; i < k; i += nth) {
+            cplx* y = &Y[(size_t)i * m];
+            for (int p = 0; p < k; ++p) {
+                const cplx sp = S[p + (size_t)i * k];
+                const cplx* q = &Qk[(size_t)p * N];
+                caxpy(m, sp, q, y);
+            }
+            const double nn = std::sqrt(csumsq(m, y));
+            if (nn > 0.0)
+                for (int r = 0; r < m; ++r) y[r] /= nn;
         }
-        double nn = 0.0;
-        for (int r = 0; r < m; ++r) nn += std::norm(y[r]);
-        nn = std::sqrt(nn);
-        if (nn > 0.0)
-            for (int r = 0; r < m; ++r) y[r] /= nn;
-    }
+    });
     return true;
 }
 

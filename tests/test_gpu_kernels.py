@@ -296,9 +296,12 @@ def test_getrf_large_backward_error():
         assert np.array_equal(np.sort(perm[b].cpu().numpy()), np.arange(n))
 
 
-def test_accumulate_matches_oracle():
-    rng = np.random.default_rng(5)
-    n, m, nz = 333, 11, 6
+@pytest.mark.parametrize("n,m,nz", [(333, 11, 6), (333, 11, 19), (700, 200, 7), (1030, 520, 5)])
+def test_accumulate_matches_oracle(n, m, nz):
+    # the three launch forms by block size: one row per thread and eight nodes per load batch,
+    # two rows and four nodes (700 x 200), four rows and one node (1030 x 520: 1040
+    # workgroups); ragged row slabs and node tails in each
+    rng = np.random.default_rng(5 + nz)
     X = wl.cn(rng, (n, m))
     Ys = [wl.cn(rng, (n, m)) for _ in range(nz)]
     C = qd.Contour(0.1, 0.5)
