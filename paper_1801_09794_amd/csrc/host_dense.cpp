@@ -539,11 +539,12 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
     V.assign((size_t)N * N, 0.0);
     beta.assign(N, 0.0);
     std::vector<cplx> s(N);
-    // each reduction step ends in barriers: one thread up to N = 128 (0.97 ms at N = 128 against
-    // 2.3 ms on four threads, the headline's size), the thread budget above (measured on whole
-    // solves: the batched eight-region workload 322-333 ms with it, 352-392 ms with two threads
-    // at N = 256)
-    const int P = N <= 128 ? 1 : host_threads((int64_t)N * N, 4096);
+    // each reduction step ends in barriers: one thread up to N = 200 (measured on the machine's host,
+    // reduction and QR sweeps together: N = 162, 6.2 ms on one thread against 7.5-10 ms on six;
+    // N = 132, 3.8 ms against 4.8-6.7 ms on four), the thread budget above (whole solves of the
+    // batched eight-region workload with companion matrices of N = 256: 322-333 ms with it,
+    // 352-392 ms with two threads)
+    const int P = N <= 200 ? 1 : host_threads((int64_t)N * N, 4096);
     Team team(P);
     cplx alpha_k = 0.0;
     std::vector<char> skip(N, 0);

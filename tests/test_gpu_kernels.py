@@ -198,9 +198,11 @@ def test_getrs_matches_solve(dtype, n, nrhs, batch):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,nrhs,batch", [(100, 7, 2), (300, 64, 3), (700, 20, 2), (1000, 33, 1)])
+@pytest.mark.parametrize("n,nrhs,batch", [(100, 7, 2), (300, 64, 3), (700, 20, 2), (1000, 33, 1),
+                                           (1200, 24, 2)])
 def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
-    # n spans one partial 256-block, several blocks and a ragged last block
+    # n spans one partial 256-block, several blocks and a ragged last block; the updates outside
+    # a chunk of two blocks come once per chunk (1200: five blocks, chunks of 2, 2 and 1)
     rng = np.random.default_rng(n + 3 * nrhs)
     dt = torch.complex128 if dtype == "c128" else torch.complex64
     mats = [wl.cn(rng, (n, n)) + 3 * np.eye(n) for _ in range(batch)]
