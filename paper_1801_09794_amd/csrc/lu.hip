@@ -862,9 +862,10 @@ void lu_block_inverses(hipStream_t s, int64_t n, int batch, const Cx<R>* LU, int
 // batched MFMA GEMM; tmp holds NB x nrhs per matrix.  The rows outside a chunk of
 // LU_SOLVE_CHUNK diagonal blocks are updated once per chunk, with a reduction of
 // LU_SOLVE_CHUNK NB (the longer reduction keeps the matrix cores busier than one update per
-// block: measured at n = 8192, 160 right-hand sides, 24 nodes); the rows inside the chunk are
-// updated block by block.
-constexpr int64_t LU_SOLVE_CHUNK = 2;
+// block: measured on one box at n = 8192, 160 right-hand sides, 24 nodes, 35.5 ms per
+// iteration's solves with chunks of two blocks, 34.7 ms with four); the rows inside the chunk
+// are updated block by block.
+constexpr int64_t LU_SOLVE_CHUNK = 4;
 
 template <typename R>
 void getrs_inv(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R>* LU, int64_t lda,
@@ -947,24 +948,29 @@ void getrs_inv_adjoint(hipStream_t s, int64_t n, int nrhs, int batch, const Cx<R
                            (const Cx<R>*)tmp, NB, st, Z + s0, n, sZ);
         NLF_HIP(hipGetLastError());
     };
-    for (int64_t b = 0; b < nblk; ++b) {          // U^H V = B, forwards
-        solve_block(b, true);
-        const int64_t s0 = b * NB, s1 = s0 + NB;
-        if (s1 < n) {
-            const int64_t sb = std::min<int64_t>(NB, n - s0);
-            ProfScope ps(trsm_class(), s, 8.0 * (n - s1) * nrhs * sb * batch, 0);
-            gemm<R>(s, true, n - s1, nrhs, sb, mone, LU + s0 + s1 * lda, lda, sA, Z + s0, n, sZ, one, Z + s1, n,
-                    sZ, batch);
+    // Z[r0:r1] -= (A[k0:k1, r0:r1])^H Z[k0:k1], A the stored U (above the diagonal) or L (below)
+    auto update = [&](int64_t r0, int64_t r1, int64_t k0, int64_t k1) {
+        if (r1 <= r0 || k1 <= k0) return;
+        ProfScope ps(trsm_class(), s, 8.0 * (r1 - r0) * nrhs * (k1 - k0) * batch, 0);
+        gemm<R>(s, true, r1 - r0, nrhs, k1 - k0, mone, LU + k0 + r0 * lda, lda, sA, Z + k0, n, sZ, one, Z + r0, n,
+                sZ, batch);
+    };
+    // chunks of LU_SOLVE_CHUNK diagonal blocks, as in getrs_inv
+    for (int64_t c0 = 0; c0 < nblk; c0 += LU_SOLVE_CHUNK) {          // U^H V = B, forwards
+        const int64_t c1 = std::min(nblk, c0 + LU_SOLVE_CHUNK), e = std::min(n, c1 * NB);
+        for (int64_t b = c0; b < c1; ++b) {
+            solve_block(b, true);
+            update((b + 1) * NB, e, b * NB, std::min(n, (b + 1) * NB));
         }
+        update(e, n, c0 * NB, e);
     }
-    for (int64_t b = nblk - 1; b >= 0; --b) {     // L^H W = V, backwards
-        solve_block(b, false);
-        const int64_t s0 = b * NB;
-        if (s0 > 0) {
-            const int64_t sb = std::min<int64_t>(NB, n - s0);
-            ProfScope ps(trsm_class(), s, 8.0 * s0 * nrhs * sb * batch, 0);
-            gemm<R>(s, true, s0, nrhs, sb, mone, LU + s0, lda, sA, Z + s0, n, sZ, one, Z, n, sZ, batch);
+    for (int64_t c1 = nblk; c1 > 0; c1 -= LU_SOLVE_CHUNK) {           // L^H W = V, backwards
+        const int64_t c0 = std::max<int64_t>(0, c1 - LU_SOLVE_CHUNK), e = std::min(n, c1 * NB);
+        for (int64_t b = c1 - 1; b >= c0; --b) {
+            solve_block(b, false);
+            update(c0 * NB, b * NB, b * NB, std::min(n, (b + 1) * NB));
         }
+        update(0, c0 * NB, c0 * NB, e);
     }
     {
         ProfScope ps(trsm_class(), s, 0, 2.0 * n * nrhs * sizeof(Cx<R>) * batch);

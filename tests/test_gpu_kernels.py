@@ -202,7 +202,7 @@ def test_getrs_matches_solve(dtype, n, nrhs, batch):
                                            (1200, 24, 2)])
 def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
     # n spans one partial 256-block, several blocks and a ragged last block; the updates outside
-    # a chunk of two blocks come once per chunk (1200: five blocks, chunks of 2, 2 and 1)
+    # a chunk of four blocks come once per chunk (1200: five blocks, chunks of 4 and 1)
     rng = np.random.default_rng(n + 3 * nrhs)
     dt = torch.complex128 if dtype == "c128" else torch.complex64
     mats = [wl.cn(rng, (n, n)) + 3 * np.eye(n) for _ in range(batch)]
@@ -226,7 +226,7 @@ def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,nrhs,batch,inplace", [(100, 7, 2, False), (300, 64, 3, True), (700, 20, 2, False),
-                                                  (1000, 33, 1, True)])
+                                                  (1000, 33, 1, True), (1200, 24, 2, False)])
 def test_getrs_adjoint_matches_solve(dtype, n, nrhs, batch, inplace):
     # X = A^{-H} B from the factors of A (the adjoint problem's solves): B shared by the batch
     # with a separate scratch Z, or one B per matrix used as Z itself
