@@ -317,11 +317,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs<R> g) {
 
 // The same tile program under its own symbol for the rank-NB trailing updates of the blocked
 // LU, so that traces and counters can single out the dominant launches of the factorisation.
-// In FP64 it takes the 3M products (FP32 keeps 4M: the 3M rounding of the imaginary part
-// would cost the complex64 factors accuracy that the refinement has to win back).
+// It takes the 3M products in both precisions: in FP32 the larger rounding of the imaginary
+// parts is left to the FP64 refinement, which needs no more sweeps for it (measured on the
+// box, delay8192 FP32 + refinement: trailing updates 271 -> 222 ms per solve, the same six
+// iterations and 27 ms of refinement; damped4096: 22.5 -> 18.3 ms).
 template <typename R, int TM, int TN, int BK>
 __global__ __launch_bounds__(256) void lu_update_kernel(GemmArgs<R> g) {
-    gemm_tile_body<R, TM, TN, BK, false, false, sizeof(R) == 8>(g);
+    gemm_tile_body<R, TM, TN, BK, false, false, true>(g);
 }
 
 // C = sum_s P_s + beta C over the split-K partials.
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, 
 
 // ---------------------------------------------------------------------------- host side
 
-// m3: the 3M products (FP64 only; see gemm_tile_body).
+// m3: the 3M products (see gemm_tile_body).
 template <typename R, int TM, int TN, int BK, bool CONJA>
 static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, bool lu_update, bool m3) {
     constexpr int BM = 32 * TM, BN = 32 * TN;
@@ -359,7 +361,7 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
             return;
         }
     }
-    if constexpr (sizeof(R) == 8 && !CONJA) {
+    if constexpr (!CONJA) {
         if (m3) {
             if (nsplit > 1)
                 hipLaunchKernelGGL((gemm_kernel<R, TM, TN, BK, CONJA, true, true>), grid, dim3(256), 0, s, g);
@@ -442,9 +444,12 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     }
 // K step per LDS stage: 8 for the 64- and 128-row tiles (half the LDS, so four workgroups
 // share a CU and hide each other's barriers; measured 4-6% faster), 16 otherwise
-    // FP64 products op(A) = A take 3M once the reduction is long enough to pay for the third
-    // accumulator (every contraction of the path but the Gram and projection products Q^H X)
-    const bool m3 = sizeof(R) == 8 && !conjA && K >= 64;
+    // Products op(A) = A take 3M once the reduction is long enough to pay for the third
+    // accumulator (every contraction of the path but the Gram and projection products Q^H X).
+    // In FP32 these are the complex64 factorisation and solves of the precision form, whose
+    // FP64 refinement absorbs the larger rounding (delay8192: solves 144 -> 123 ms per solve,
+    // the same six iterations and refinement sweeps)
+    const bool m3 = !conjA && K >= 64;
 #define NLF_GEMM_CASE(TM_, TN_)                                                          \
     if (c.tm == TM_ && c.tn == TN_) {                                                   \
         constexpr int BKX = (TM_ == 1 || (TM_ == 4 && TN_ == 4)) ? 16 : 8;               \

@@ -32,6 +32,16 @@ def batch_dev(mats, dtype=torch.complex128):
 def rel(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
+def solve_tol(dtype, M):
+    """Bound on the relative error of a solve with the LU factors of M: the normwise forward
+    error of a backward-stable solve is about g * cond(M) * u; g = 20 leaves room for the
+    complex64 factors, whose products take the 3M scheme (imaginary parts rounded up to about
+    twice as coarsely as with four real products).  complex128 keeps the fixed 1e-11."""
+    if dtype == "c128":
+        return 1e-11
+    return 20 * np.linalg.cond(M) * 2.0 ** -24
+
+
 
 @pytest.mark.parametrize("dt,tol", [(torch.complex128, 1e-14), (torch.complex64, 3e-6)])
 def test_mfma_lane_layout_single_tile(dt, tol):
@@ -191,10 +201,9 @@ def test_getrs_matches_solve(dtype, n, nrhs, batch):
     X = torch.empty((batch, nrhs, n), dtype=dt, device="cuda")
     nl.nlf_getrs_batched(A, perm, dev(B, dt), X, shared_rhs=True)
     torch.cuda.synchronize()
-    tol = 1e-11 if dtype == "c128" else 2e-3
     for b in range(batch):
         ref = np.linalg.solve(mats[b], B)
-        assert rel(nl.from_colmajor(X[b]), ref) < tol
+        assert rel(nl.from_colmajor(X[b]), ref) < solve_tol(dtype, mats[b])
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -218,10 +227,9 @@ def test_getrs_block_inverse_matches_solve(dtype, n, nrhs, batch):
     tmp = torch.empty(batch * 256 * nrhs, dtype=dt, device="cuda")
     nl.nlf_getrs_batched_inv(A, perm, dinv, dev(B, dt), X, tmp, shared_rhs=True)
     torch.cuda.synchronize()
-    tol = 1e-11 if dtype == "c128" else 2e-3
     for b in range(batch):
         ref = np.linalg.solve(mats[b], B)
-        assert rel(nl.from_colmajor(X[b]), ref) < tol
+        assert rel(nl.from_colmajor(X[b]), ref) < solve_tol(dtype, mats[b])
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -252,9 +260,8 @@ def test_getrs_adjoint_matches_solve(dtype, n, nrhs, batch, inplace):
         nl.nlf_getrs_batched_inv_adjoint(A, perm, dinv, dev(Bs[0], dt), Z, X, tmp, shared_rhs=True)
         refs = [np.linalg.solve(M.conj().T, Bs[0]) for M in mats]
     torch.cuda.synchronize()
-    tol = 1e-11 if dtype == "c128" else 2e-3
     for b in range(batch):
-        assert rel(nl.from_colmajor(X[b]), refs[b]) < tol
+        assert rel(nl.from_colmajor(X[b]), refs[b]) < solve_tol(dtype, mats[b])
 
 
 def test_getrs_adjoint_rejects_overlap():
