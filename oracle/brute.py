@@ -153,7 +153,26 @@ def logdet(M):
     return np.sum(np.log(d.astype(complex))) + (0 if sign > 0 else 1j * np.pi)
 
 
-def winding_count(problem, contour, npts=256, max_step=0.5, deflate=None):
+def logdet_slope(problem, z):
+    """d/dz log det T(z) = trace(T(z)^{-1} T'(z)), from LU factors of T(z)."""
+    lu = scipy.linalg.lu_factor(problem.T(z), check_finite=False)
+    return complex(np.trace(scipy.linalg.lu_solve(lu, problem.dT(z), check_finite=False)))
+
+
+def phase_trend(problem, c, h, deflate=None):
+    """Coefficients (a1, a2, a3) of the cubic Taylor polynomial of log g about c, g(z) =
+    det T(z) / prod_i (z - mu_i): a1 = (log g)'(c) exactly, a2 and a3 from central differences of
+    the exact slope at c - h, c, c + h."""
+    mu = np.asarray([] if deflate is None else deflate, dtype=complex)
+
+    def s(z):
+        return logdet_slope(problem, z) - np.sum(1.0 / (z - mu))
+
+    sm, s0, sp = s(c - h), s(c), s(c + h)
+    return (s0, (sp - sm) / (4 * h), (sp - 2 * s0 + sm) / (6 * h * h))
+
+
+def winding_count(problem, contour, npts=256, max_step=0.5, deflate=None, trend=(), log=None):
     """Number of eigenvalues of T inside C: (1/2 pi) times the total change of
     arg det T(z) around C (argument principle).  The sampling is refined until every step of
     the unwrapped phase is below max_step radians.
@@ -163,7 +182,15 @@ def winding_count(problem, contour, npts=256, max_step=0.5, deflate=None):
     number of g plus the number of mu_i inside C.  This is exact whatever the mu_i are (a
     wrong or missing mu_i changes the winding of g by the same amount); it only makes the
     phase vary slowly where the mu_i sit next to true eigenvalues, so far fewer samples are
-    needed when many eigenvalues lie inside."""
+    needed when many eigenvalues lie inside.
+
+    trend (optional): coefficients a_1, a_2, ... of a polynomial p(z) = sum_k a_k (z - c)^k, c
+    the contour's centre; the phase followed is then that of g(z) exp(-p(z)).  The factor is
+    entire and has no zeros, so the count is unchanged for any coefficients; with those of the
+    Taylor polynomial of log g (phase_trend) it takes out the smooth part of the phase, which
+    for large n (a delay problem's exponential terms give log det T a slope of order n) would
+    otherwise change by more than pi between samples and alias.
+    log (optional): called with the number of evaluations of det T so far, every 16."""
     mu = np.asarray([] if deflate is None else deflate, dtype=complex)
     theta = np.linspace(0.0, 2 * np.pi, npts + 1)
     vals = {}
@@ -171,8 +198,12 @@ def winding_count(problem, contour, npts=256, max_step=0.5, deflate=None):
     def phase(t):
         if t not in vals:
             z = contour.point(t)
-            ph = logdet(problem.T(z)).imag - np.sum(np.angle(z - mu))
+            w = z - contour.c
+            ph = logdet(problem.T(z)).imag - np.sum(np.angle(z - mu)) - sum(
+                (a * w ** (k + 1)).imag for k, a in enumerate(trend))
             vals[t] = np.angle(np.exp(1j * ph))
+            if log is not None and len(vals) % 16 == 0:
+                log(len(vals))
         return vals[t]
 
     pts = list(theta)

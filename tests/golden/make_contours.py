@@ -42,7 +42,8 @@ they are):
                    itself, an upper bound of the smallest singular value of T there.
   --winding NAME   winding_count = the number of eigenvalues inside the circle by the argument
                    principle (det T from LU factors along the circle), with the stored values
-                   deflated from the phase only to keep the number of samples small.
+                   deflated from the phase and its smooth cubic trend taken out, only to keep
+                   the number of samples small without aliasing.
   rational300 A0 - l I + l/(l - sigma) C: all 2n companion eigenvalues of the quadratic
               (l - sigma) T(l); centre = a seeded pick among them with |c| <= 0.9; radius =
               midpoint between the 12th and 13th distances, rejected under a 5% gap.
@@ -247,9 +248,18 @@ def winding(name):
     data = json.load(open(OUT))
     for g in data[name]["regions"]:
         t0 = time.time()
-        C = qd.Contour(complex(*g["centre"]), g["radius"])
+        c = complex(*g["centre"])
+        C = qd.Contour(c, g["radius"])
         mu = [complex(*v) for v in g["eigenvalues"]]
-        g["winding_count"] = brute.winding_count(P, C, npts=128, max_step=0.8, deflate=mu)
+        # the smooth part of log g (cubic Taylor polynomial about the centre) is taken out of
+        # the phase so that coarse samples do not alias (the count itself does not depend on it)
+        trend = brute.phase_trend(P, c, 0.05 * g["radius"], deflate=mu)
+        print("  %s: phase trend |a1| r = %.1f, |a2| r^2 = %.1f, |a3| r^3 = %.1f rad (%.0fs)"
+              % (name, abs(trend[0]) * g["radius"], abs(trend[1]) * g["radius"] ** 2,
+                 abs(trend[2]) * g["radius"] ** 3, time.time() - t0), flush=True)
+        g["winding_count"] = brute.winding_count(
+            P, C, npts=32, max_step=0.8, deflate=mu, trend=trend,
+            log=lambda k: print("    %d evaluations of det T (%.0fs)" % (k, time.time() - t0), flush=True))
         print("  %s: winding count %d, %d stored (%.0fs)" % (name, g["winding_count"], len(mu), time.time() - t0),
               flush=True)
     return data[name]

@@ -587,13 +587,14 @@ def test_lookahead_factors_equal_single_stream(prec, es):
 def test_delay8192_full_size(prec, tol_eig, rs):
     # the delay problem at full size (24 nodes of n = 8192, m0 = 160), reduced problem by the
     # default contour-integral solve (rs = 0) or the Taylor route (rs = 2): every eigenvalue
-    # inside the circle against the surrogate + Rayleigh-refined reference, residuals
-    # recomputed on the host
+    # inside the circle against the surrogate + Rayleigh-refined reference, whose count is the
+    # argument-principle count of det T along the circle; residuals recomputed on the host
     cfg = wl.CONFIGS["delay8192"]
     terms, mats = wl.make_problem("delay8192")
     g = contours("delay8192")[0]
     c, r = complex(*g["centre"]), g["radius"]
     ref = np.array([complex(*v) for v in g["eigenvalues"]])
+    assert len(ref) == g["winding_count"] == 99
     out = gpu_solve(terms, mats, [dict(centre=c, a=r, nc=cfg["nc"], m0=cfg["m0"])],
                     wl.initial_block(cfg["n"], cfg["m0"], 2000 + cfg["id"]),
                     nl.options(tol=cfg["tol"], precision=prec, reduced_solver=rs))

@@ -338,6 +338,46 @@ def test_deflated_winding_count_equals_the_plain_count():
     assert brute.winding_count(P, C, npts=64, deflate=np.append(inside + 0.02, C.c + 0.3j)) == want
 
 
+def test_winding_trend_keeps_the_count():
+    # an entire zero-free factor exp(-p(z)) taken out of the phase changes no winding: any
+    # trend coefficients give the companion count; the fitted ones agree with the exact slope
+    terms, mats = wl.random_qep(40, 12)
+    P = pb.Problem(terms, mats)
+    full = brute.companion_eigs(P)
+    C = qd.Contour(full[3] + 0.07 - 0.04j, 0.5)    # centre off the spectrum (T(c) regular)
+    inside = full[C.inside(full)]
+    want = len(inside)
+    assert want >= 4
+    # a trend whose own phase swings a few radians along C: the samples still resolve it
+    assert brute.winding_count(P, C, npts=64, trend=(0.8 - 0.4j, -1.0 + 0.5j, 2.0j)) == want
+    assert brute.winding_count(P, C, npts=64, deflate=inside, trend=(3.0, 0.0, -6.0 + 1.0j)) == want
+    tr = brute.phase_trend(P, C.c, 0.05 * C.a, deflate=inside)
+    # log det T(z) - sum log(z - mu) for the companion eigenvalues is log det C_k (a constant),
+    # so with every eigenvalue deflated the slope of log g at the centre is that of the ones
+    # outside C: compare with the exact sum over the full companion spectrum
+    outside = full[~C.inside(full)]
+    assert abs(tr[0] - np.sum(1.0 / (C.c - outside))) < 1e-8 * max(1.0, abs(tr[0]))
+    assert brute.winding_count(P, C, npts=8, deflate=inside, trend=tr) == want
+
+
+def test_winding_trend_removes_aliasing_on_a_delay_problem():
+    # the exponential terms of a delay problem give log det T a slope of order n: with the stored
+    # delay512 eigenvalues deflated, eight coarse samples along the stored circle still alias
+    # unless the fitted trend is taken out; with it, the coarse count equals the stored count
+    # (the plain winding number of det T at 256 samples, no deflation)
+    terms, mats = wl.make_problem("delay512")
+    P = pb.Problem(terms, mats)
+    g = json.load(open(os.path.join(GOLDEN, "contours.json")))["delay512"]["regions"][0]
+    c, r = complex(*g["centre"]), g["radius"]
+    C = qd.Contour(c, r)
+    mu = np.array([complex(*v) for v in g["eigenvalues"]])
+    tr = brute.phase_trend(P, c, 0.05 * r, deflate=mu)
+    assert abs(tr[0]) * r > 5.0                      # the linear trend alone is several turns
+    assert brute.winding_count(P, C, npts=8, max_step=0.8, deflate=mu, trend=tr) == g["winding_count"] == 12
+    # the same count from a displaced deflation set (exactness does not rest on the stored values)
+    assert brute.winding_count(P, C, npts=8, max_step=0.8, deflate=mu[:9] + 1e-3, trend=tr) == 12
+
+
 def test_lu_pivot_convention_small():
     A = np.array([[1, 2, 3], [4, 5, 6], [7, 8, 10]], dtype=complex)
     _, ipiv = dense.lu_partial_pivot(A)
