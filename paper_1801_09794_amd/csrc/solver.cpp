@@ -763,7 +763,7 @@ struct RegionOutcome {
 // eigenvalues the conjugates of T's (returned conjugated back).
 RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, const Layout& L, int ri,
                          hipStream_t s, Profiler* prof, const RegionIO& io, hipEvent_t factored,
-                         std::atomic<int>* active = nullptr, bool adj = false) {
+                         std::atomic<int64_t>* active = nullptr, bool adj = false) {
     RegionOutcome res_out;
     try {
         ProfilerGuard pg(prof);
@@ -879,9 +879,11 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
             const auto t0 = std::chrono::steady_clock::now();
             std::vector<cplx> prev;
             if (it > 0) prev = rr.lambda;
-            if (active) {   // share the host threads among the regions still iterating
+            if (active) {   // share the host threads among the regions still iterating, in
+                            // proportion to their reduced solves' work (m^3)
                 const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-                host_thread_budget() = std::max(1, hw / std::max(1, active->load()));
+                const double share = (double)m * m * m / (double)std::max<int64_t>(1, active->load());
+                host_thread_budget() = std::max(1, (int)std::lround(hw * std::min(1.0, share)));
             }
             if (cdev) {
                 bool singular = false;
@@ -1375,18 +1377,22 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
             for (int ri = 0; ri < nreg; ++ri) h->rprof[ri]->reset();
             std::vector<std::thread> threads;
             threads.reserve(nreg);
-            std::atomic<int> active{nreg};
+            // the regions' pending reduced-solve work (sum of m0^3 over the regions still
+            // iterating), by which they share the host threads
+            auto work = [&](int ri) { const int64_t m = h->regions[ri].m0; return m * m * m; };
+            std::atomic<int64_t> active{0};
+            for (int ri = 0; ri < nreg; ++ri) active.fetch_add(work(ri));
             for (int ri = 0; ri < nreg; ++ri)
                 threads.emplace_back([&, ri] {
                     if (hipSetDevice(h->device) != hipSuccess) {
                         out[ri].status = NLF_ERR_DEVICE;
                         out[ri].msg = "hipSetDevice failed in a region thread";
-                        active.fetch_sub(1);
+                        active.fetch_sub(work(ri));
                         return;
                     }
                     out[ri] = run_region(h, *opt, ws, L, ri, h->rstream[ri],
                                          h->profiling ? h->rprof[ri].get() : nullptr, io, factored, &active, adj);
-                    active.fetch_sub(1);
+                    active.fetch_sub(work(ri));
                 });
             for (auto& t : threads) t.join();
             for (int ri = 0; ri < nreg; ++ri) {
