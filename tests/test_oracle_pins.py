@@ -735,3 +735,27 @@ def test_left_solve_of_a_user_function_problem():
     assert match_error(left.eigenvalues, right.eigenvalues, C.a) < 1e-11
     for l, y in zip(left.lam[good], left.X[:, good].T):
         assert np.linalg.norm(y.conj() @ P.T(l)) < 1e-11
+
+
+def test_stored_full_oracle_runs_reproduce_the_reference_sets():
+    # the oracle's complete runs of the benchmark workloads (make_oracle_runs.py) against the
+    # independent reference sets of contours.json (brute force, certified refinement, winding
+    # count): every region's converged eigenvalues inside are exactly that set, to the parity
+    # metric's relative error
+    runs = json.load(open(os.path.join(GOLDEN, "oracle_runs.json")))
+    refs = json.load(open(os.path.join(GOLDEN, "contours.json")))
+    assert set(runs) >= {"damped4096", "qep2048x8", "delay8192"}
+    for name, run in runs.items():
+        cfg = wl.CONFIGS[name]
+        for got, g in zip(run["regions"], refs[name]["regions"]):
+            lam = np.array([complex(*v) for v in got["eigenvalues"]])
+            ref = np.array([complex(*v) for v in g["eigenvalues"]])
+            assert len(lam) == len(ref) == got["converged"], (name, len(lam), len(ref))
+            assert got["max_residual"] <= cfg["tol"]
+            scale = np.maximum(np.abs(ref), g["radius"]) if len(ref) else 1.0
+            if len(ref):
+                from scipy.optimize import linear_sum_assignment
+                cost = np.abs(lam[:, None] - ref[None, :]) / np.asarray(scale)[None, :]
+                i, j = linear_sum_assignment(cost)
+                assert cost[i, j].max() < 1e-9, (name, cost[i, j].max())
+        assert run["converged"] == sum(len(g["eigenvalues"]) for g in refs[name]["regions"])
