@@ -310,6 +310,31 @@ void random_normal(hipStream_t s, int64_t rows, int64_t cols, uint64_t seed, z12
     NLF_HIP(hipGetLastError());
 }
 
+// flags[j] = 1 when the n x n matrix A_j (ld lda) differs anywhere from the identity; every
+// thread that finds a difference writes the same value, so plain stores suffice (the flags are
+// cleared beforehand)
+__global__ __launch_bounds__(256) void identity_check_kernel(int64_t n, APtrs A, int64_t lda, int32_t* flags) {
+    const int j = blockIdx.y;
+    const z128* a = A.p[j];
+    const int64_t total = n * n;
+    bool diff = false;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e % n, c = e / n;
+        const z128 v = a[i + c * lda];
+        diff = diff || v.im != 0.0 || v.re != (i == c ? 1.0 : 0.0);
+    }
+    if (diff) flags[j] = 1;
+}
+
+void identity_flags(hipStream_t s, int64_t n, int J, const z128* const* A, int64_t lda, int32_t* flags) {
+    NLF_REQUIRE(J >= 1 && J <= MAXJ, 1, "identity_flags: 1 <= J <= 8 terms");
+    fill_i32(s, flags, J, 0);
+    APtrs ap{};
+    for (int j = 0; j < J; ++j) ap.p[j] = A[j];
+    hipLaunchKernelGGL(identity_check_kernel, dim3(grid_for(n * n, 2048), J), dim3(256), 0, s, n, ap, lda, flags);
+    NLF_HIP(hipGetLastError());
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t v) {
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
         p[e] = v;

@@ -108,6 +108,8 @@ void copy_block(hipStream_t s, int64_t rows, int64_t cols, const z128* in, int64
                 z128* out, int64_t ldo);
 // p[0..count) = v (a kernel, so that the sequence stays capturable in a HIP graph)
 void fill_i32(hipStream_t s, int32_t* p, int64_t count, int32_t v);
+// flags[j] = 0 when the n x n matrix A[j] (ld lda) is exactly the identity, else 1
+void identity_flags(hipStream_t s, int64_t n, int J, const z128* const* A, int64_t lda, int32_t* flags);
 // counter-based standard complex normal draws CN(0,1) for an n x m block
 void random_normal(hipStream_t s, int64_t rows, int64_t cols, uint64_t seed, z128* out, int64_t ld);
 

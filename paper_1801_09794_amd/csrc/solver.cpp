@@ -162,6 +162,10 @@ struct nlfeast_ctx {
     UserFunction ufn;                                      // for terms of kind NLF_F_USER
     std::vector<const z128*> A;
     int64_t lda = 0;
+    // per coefficient matrix: exactly the identity (then A_j Q is Q itself); checked on the
+    // device at the first solve after set_coeffs
+    std::vector<char> ident;
+    bool ident_known = false;
     struct Region {
         Ellipse E;
         int nc = 0, m0 = 0;
@@ -241,6 +245,7 @@ struct RegionLayout {
 struct Layout {
     size_t total = 0;
     size_t fact = 0, t64 = 0, ipiv = 0, perm = 0, info = 0, list = 0, dinv = 0, ftmp = 0, coef = 0;
+    size_t ident = 0;   // one flag per coefficient matrix: nonzero when it is not the identity
     std::vector<RegionLayout> reg;
     int NZ = 0, M = 0, mmax = 0, ncmax = 0;
 };
@@ -275,6 +280,7 @@ Layout make_layout(const nlfeast_ctx* h, int prec, bool contour) {
     L.dinv = take((size_t)lu_inverse_elems(n) * L.NZ * es);
     L.ftmp = take((size_t)getrf_tmp_elems(n) * L.NZ * es);
     L.coef = take(16 * (size_t)L.NZ * J);
+    L.ident = take(sizeof(int32_t) * J);
     int node0 = 0, col0 = 0;
     for (const auto& rg : h->regions) {
         RegionLayout R;
@@ -376,8 +382,13 @@ void orthonormalize(hipStream_t s, int64_t n, int m, z128* Q, z128* QT, z128* Gd
 
 // W_j = op(A_j) Q and Ahat_j = Q^H W_j, with op(A) = A^H for the adjoint problem.
 void project(hipStream_t s, int64_t n, int m, int J, const z128* const* A, int64_t lda,
-             const z128* Q, z128* W, z128* Ahat, z128* splitws, int64_t split_elems, bool adj = false) {
+             const z128* Q, z128* W, z128* Ahat, z128* splitws, int64_t split_elems, bool adj = false,
+             const char* ident = nullptr) {
     for (int j = 0; j < J; ++j) {
+        if (ident && ident[j]) {   // A_j = I (and I^H = I): W_j = Q
+            NLF_HIP(hipMemcpyAsync(W + (size_t)j * n * m, Q, sizeof(z128) * n * m, hipMemcpyDeviceToDevice, s));
+            continue;
+        }
         ProfScope ps(NLF_PROF_PROJECT, s, 8.0 * n * n * m, 16.0 * ((double)n * n + 2.0 * n * m));
         gemm<double>(s, adj, n, m, n, z128(1, 0), A[j], lda, 0, Q, n, 0, z128(0, 0),
                      W + (size_t)j * n * m, n, 0, 1, splitws, split_elems);
@@ -865,7 +876,8 @@ RegionOutcome run_region(nlfeast_ctx* h, const nlfeast_options& o, void* ws, con
         const z64* D64 = at<z64>(ws, L.dinv) + (size_t)node0 * dper;
         while (true) {
             // Step 1: projections and the reduced problem
-            project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems, adj);
+            project(s, n, m, J, h->A.data(), h->lda, Q, W, Ahat_d, splitws, RL.splitws_elems, adj,
+                    h->ident_known ? h->ident.data() : nullptr);
             if (cdev) {
                 device_moments(s, m, J, Ahat_d, ws, RL);
                 NLF_HIP(hipMemcpyAsync(cmom.data(), at<void>(ws, RL.cmom), sizeof(cplx) * cmom.size(),
@@ -1154,6 +1166,8 @@ nlfeast_status nlfeast_set_coeffs(nlfeast_handle h, int32_t J, const int32_t* fk
         h->A.assign(J, nullptr);
         for (int j = 0; j < J; ++j) h->A[j] = (const z128*)A_dev[j];
         h->lda = lda;
+        h->ident.assign(J, 0);
+        h->ident_known = false;
         h->factors_valid = false;
         return NLF_OK;
     })
@@ -1262,6 +1276,17 @@ static nlfeast_status solve_impl(nlfeast_handle h, const nlfeast_options* opt, v
         const bool p32 = opt->precision == NLF_PREC_FP32_REFINE;
         if (h->profiling) h->prof.reset();
         ProfilerGuard pg(h->profiling ? &h->prof : nullptr);
+        // which coefficient matrices are exactly the identity (once per set_coeffs: the A_j are
+        // borrowed unmodified until the next one)
+        if (!h->ident_known) {
+            int32_t* flags = at<int32_t>(ws, L.ident);
+            identity_flags(s, n, J, h->A.data(), h->lda, flags);
+            std::vector<int32_t> f(J);
+            NLF_HIP(hipMemcpyAsync(f.data(), flags, sizeof(int32_t) * J, hipMemcpyDeviceToHost, s));
+            NLF_HIP(hipStreamSynchronize(s));
+            for (int j = 0; j < J; ++j) h->ident[j] = f[j] == 0;
+            h->ident_known = true;
+        }
 
         // ---- fixed shifts: assemble and factor T(z_k) once per contour; the regions start
         // from ev_start (the caller's prior work) and wait for ev_factored before Step 4

@@ -290,6 +290,26 @@ def test_restart_from_previous_ritz_vectors():
     assert match_err(again["lam"][b], first["lam"][a], r) < 1e-12
 
 
+def test_identity_coefficient_equals_a_scaled_problem():
+    # an identity coefficient matrix is recognised on the device and its product with Q is Q
+    # itself; the same problem scaled by 2 (no identity left) has the same eigenpairs
+    terms, mats = wl.make_problem("qep200")
+    g = contours("qep200")[0]
+    c, r = complex(*g["centre"]), g["radius"]
+    ident = [bool(np.array_equal(M, np.eye(200))) for M in mats]
+    assert any(ident)
+    X0 = wl.initial_block(200, 20, 2001)
+    regs = [dict(centre=c, a=r, nc=8, m0=20)]
+    a = gpu_solve(terms, mats, regs, X0, nl.options(tol=1e-12))
+    b = gpu_solve(terms, [2.0 * M for M in mats], regs, X0, nl.options(tol=1e-12))
+    for o in (a, b):
+        assert status_ok(o)
+    ca, cb = converged(a, 1e-12), converged(b, 1e-12)
+    brute = np.array([complex(*v) for v in g["eigenvalues"]])
+    assert match_err(a["lam"][ca], brute, r) < 1e-10
+    assert match_err(b["lam"][cb], brute, r) < 1e-10
+
+
 def test_m0_too_small_status():
     terms, mats = wl.mass_spring(50, 10.0, 5.0)      # r = 19 encloses 34 > m0 = 25
     out = gpu_solve(terms, mats, [dict(centre=-20.5, a=19.0, nc=8, m0=25)],
