@@ -7,13 +7,14 @@
 //
 // There is no complex MFMA, so one complex multiply-add of a 16x16x4 block is four real
 // v_mfma_*_16x16x4 instructions (the "4M" scheme): Cr += Ar Br, Cr -= Ai Bi, Ci += Ar Bi,
-// Ci += Ai Br.  The MFMA's A operand is fed from op(B) and its B operand from op(A), so the
+// Ci += Ai Br, or three (the "3M" scheme of gemm_tile_body, taken by every product with
+// op(A) = A and a reduction of at least 64).  The MFMA's A operand is fed from op(B) and its B operand from op(A), so the
 // 16 consecutive output columns of one MFMA row are 16 consecutive rows m of C: each store
 // instruction writes 256-byte contiguous runs of the column-major C without an LDS transpose.
 //
 // Work decomposition: a 256-thread workgroup (4 waves as 2x2) owns a (32 TM) x (32 TN)
 // complex tile of C; each wave owns (16 TM) x (16 TN), i.e. TM x TN MFMA tiles with a real
-// and an imaginary accumulator each.  K advances in steps of BK complex elements staged in
+// and an imaginary accumulator each (and a third one under 3M).  K advances in steps of BK complex elements staged in
 // LDS as [k][m] and [k][n] (interleaved complex, so one ds_read_b64/b128 gives re and im).
 // The next K step is fetched into registers while the current one is multiplied.
 // Optional split-K writes alpha-scaled partial products to a workspace; gemm_reduce sums them.
