@@ -849,6 +849,8 @@ static int newton_polish(int m, const std::vector<Term>& terms, const cplx* Ahat
     const int J = (int)terms.size();
     const size_t mm = (size_t)m * m;
     std::atomic<int> steps{0};
+    std::vector<double> anorm(J);   // ||Ahat_j||_F, for the scale of the residual test
+    for (int j = 0; j < J; ++j) anorm[j] = std::sqrt(csumsq((int64_t)mm, Ahat + (size_t)j * mm));
     auto polish = [&](int q) {
         std::vector<cplx> Jm((size_t)(m + 1) * (m + 1)), rhs(m + 1), Tl(mm), dT(mm);
         cplx l = lam[q];
@@ -856,29 +858,25 @@ static int newton_polish(int m, const std::vector<Term>& terms, const cplx* Ahat
         const std::vector<cplx> v0 = y;   // unit norm, so v0^H y = 1 initially
         for (int it = 0; it < 8; ++it) {
             std::fill(Tl.begin(), Tl.end(), cplx(0.0));
-            std::fill(dT.begin(), dT.end(), cplx(0.0));
             double scale = 0.0;
             for (int j = 0; j < J; ++j) {
-                const cplx f = term_value(terms[j], l), fd = term_deriv(terms[j], l);
+                const cplx f = term_value(terms[j], l);
                 const cplx* A = Ahat + (size_t)j * mm;
-                double an = 0.0;
-                for (size_t e = 0; e < mm; ++e) {
-                    Tl[e] += f * A[e];
-                    dT[e] += fd * A[e];
-                    an += std::norm(A[e]);
-                }
-                scale += std::abs(f) * std::sqrt(an);
+                caxpy((int64_t)mm, f, A, Tl.data());
+                scale += std::abs(f) * anorm[j];
             }
             if (!std::isfinite(scale)) break;
             double rn = 0.0;
             for (int r = 0; r < m; ++r) rhs[r] = 0.0;
-            for (int c = 0; c < m; ++c)
-                for (int r = 0; r < m; ++r) rhs[r] -= Tl[r + (size_t)c * m] * y[c];
+            for (int c = 0; c < m; ++c) caxpy(m, -y[c], &Tl[(size_t)c * m], rhs.data());
             for (int r = 0; r < m; ++r) rn += std::norm(rhs[r]);
             cplx vy = 0.0;
             for (int i = 0; i < m; ++i) vy += std::conj(v0[i]) * y[i];
             rhs[m] = -(vy - 1.0);
             if (std::sqrt(rn) <= 1e-15 * scale && std::abs(rhs[m]) < 1e-15) break;
+            // T'(l) only when a step is taken
+            std::fill(dT.begin(), dT.end(), cplx(0.0));
+            for (int j = 0; j < J; ++j) caxpy((int64_t)mm, term_deriv(terms[j], l), Ahat + (size_t)j * mm, dT.data());
             for (int c = 0; c < m; ++c)
                 for (int r = 0; r < m; ++r) Jm[r + (size_t)c * (m + 1)] = Tl[r + (size_t)c * m];
             for (int r = 0; r < m; ++r) Jm[r + (size_t)m * (m + 1)] = 0.0;
