@@ -471,18 +471,145 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
                 C[m + n * g.ldc] = out;
             }
 }
-#undef NLF_GPTR
-#undef NLF_LPTR
-
 // shapes the direct-to-LDS tile covers exactly
 inline bool fits(int64_t M, int64_t N, int64_t K) {
     return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % (2 * BK) == 0;
 }
+
+// The FP32 counterpart: the 128 x 64 tile of gemm_tile_body<float, 4, 2, 8> (wave tile 64 x 32)
+// with 3M products. One 16-byte load lane carries two complex64 elements, so:
+//  * op(A): [k][128 + 16] complex64, one row per load instruction (lane l: rows 2l, 2l + 1); the
+//    16-element pad puts rows k and k + 1 on opposite halves of the LDS banks, so the operand
+//    reads of two k rows by 32 lanes do not collide;
+//  * B: blocks of 16 columns x 8 k, four 16-byte units (k pairs) per column; lane l of the load
+//    for block q fetches column n = 16 q + (l >> 2), unit (l & 3) ^ ((n >> 2) & 3), so the 4
+//    lanes of a column read its 64 contiguous bytes and 32 operand reads (16 columns, two k)
+//    fall on distinct banks.
+// Needs 16-byte aligned rows pairs: even leading dimensions and 16-byte aligned A and B.
+using Y = Cx<float>;
+constexpr int APAD32 = 16;
+using acc32_t = Mfma<float>::acc_t;
+
+__device__ __forceinline__ void issue32(Y* As, Y* Bs, const Y* const* ga, const Y* gb, int64_t lda, int64_t k0,
+                                        int wave) {
+#pragma unroll
+    for (int r = 0; r < BK / 4; ++r)
+        __builtin_amdgcn_global_load_lds(NLF_GPTR(ga[r] + k0 * lda), NLF_LPTR(As + (wave + 4 * r) * (128 + APAD32)),
+                                         16, 0, 0);
+    __builtin_amdgcn_global_load_lds(NLF_GPTR(gb + k0), NLF_LPTR(Bs + wave * 128), 16, 0, 0);
+}
+
+__device__ __forceinline__ void multiply32(const Y* As, const Y* Bs, int aoff, const int* boff,
+                                           acc32_t (&t1)[4][2], acc32_t (&t2)[4][2], acc32_t (&t3)[4][2]) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+        Y a[4], b[2];
+        float as[4], bs[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = As[kk * (128 + APAD32) + aoff + i * 16];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[boff[j] ^ kk];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) as[i] = a[i].re + a[i].im;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bs[j] = b[j].re + b[j].im;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) t1[i][j] = Mfma<float>::mma(b[j].re, a[i].re, t1[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) t2[i][j] = Mfma<float>::mma(b[j].im, a[i].im, t2[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) t3[i][j] = Mfma<float>::mma(bs[j], as[i], t3[i][j]);
+    }
+}
+
+__device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
+    __shared__ Y A0[BK * (128 + APAD32)], A1[BK * (128 + APAD32)], B0[BK * 64], B1[BK * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
+    int tm, tn;
+    tile_coords(xcd_remap(blockIdx.x, g.tilesM * g.tilesN), g.tilesM, g.tilesN, tm, tn);
+    const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 128, n0 = (int64_t)tn * 64;
+    const Y* A = g.A + batch * g.sA;
+    const Y* B = g.B + batch * g.sB;
+    const int64_t K = g.K, lda = g.lda, ldb = g.ldb;
+
+    // this lane's sources: A rows k = wave + 4 r (elements 2 lane, 2 lane + 1), B block q = wave
+    const Y* ga[BK / 4];
+#pragma unroll
+    for (int r = 0; r < BK / 4; ++r) ga[r] = A + (m0 + 2 * lane) + (int64_t)(wave + 4 * r) * lda;
+    const int nq = 16 * wave + (lane >> 2);
+    const Y* gb = B + 2 * ((lane & 3) ^ ((nq >> 2) & 3)) + (n0 + nq) * ldb;
+    // this lane's MFMA operands: A element (k, wm 64 + 16 i + col), B element (k, wn 32 + 16 j + col)
+    const int col = lane & 15, krow = lane >> 4;
+    const int aoff = krow * (128 + APAD32) + wm * 64 + col;
+    int boff[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        boff[j] = (wn * 2 + j) * 128 + col * 8 + 2 * ((krow >> 1) ^ ((col >> 2) & 3)) + (krow & 1);
+    acc32_t t1[4][2], t2[4][2], t3[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            t1[i][j] = acc32_t{0, 0, 0, 0};
+            t2[i][j] = acc32_t{0, 0, 0, 0};
+            t3[i][j] = acc32_t{0, 0, 0, 0};
+        }
+
+    issue32(A0, B0, ga, gb, lda, 0, wave);
+    wait_loads();
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < K; k0 += 2 * BK) {
+        issue32(A1, B1, ga, gb, lda, k0 + BK, wave);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply32(A0, B0, aoff, boff, t1, t2, t3);
+        __builtin_amdgcn_sched_barrier(0);
+        wait_loads();
+        __syncthreads();
+        if (k0 + 2 * BK < K) issue32(A0, B0, ga, gb, lda, k0 + 2 * BK, wave);
+        __builtin_amdgcn_sched_barrier(0);
+        multiply32(A1, B1, aoff, boff, t1, t2, t3);
+        __builtin_amdgcn_sched_barrier(0);
+        wait_loads();
+        __syncthreads();
+    }
+
+    Y* C = g.C + batch * g.sC;
+    const bool useBeta = (g.beta.re != 0.0f || g.beta.im != 0.0f);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm * 64 + i * 16 + col;
+                const int64_t n = n0 + wn * 32 + j * 16 + Mfma<float>::acc_row(krow, r);
+                const float p1 = t1[i][j][r], p2 = t2[i][j][r];
+                Y out = g.alpha * Y(p1 - p2, t3[i][j][r] - p1 - p2);
+                if (useBeta) out = out + g.beta * C[m + n * g.ldc];
+                C[m + n * g.ldc] = out;
+            }
+}
+
+inline bool fits32(const GemmArgs<float>& g) {
+    return g.M > 0 && g.N > 0 && g.K > 0 && g.M % 128 == 0 && g.N % 64 == 0 && g.K % (2 * BK) == 0 &&
+           g.lda % 2 == 0 && g.ldb % 2 == 0 && g.sA % 2 == 0 && g.sB % 2 == 0 &&
+           reinterpret_cast<uintptr_t>(g.A) % 16 == 0 && reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+}
+#undef NLF_GPTR
+#undef NLF_LPTR
 }  // namespace dma
 
 __global__ __launch_bounds__(256) void gemm_dma_kernel(GemmArgs<double> g) { dma::tile_body(g); }
 // the trailing updates of the blocked LU under their own symbol (see lu_update_kernel)
 __global__ __launch_bounds__(256) void lu_update_dma_kernel(GemmArgs<double> g) { dma::tile_body(g); }
+__global__ __launch_bounds__(256) void gemm_dma32_kernel(GemmArgs<float> g) { dma::tile_body32(g); }
+__global__ __launch_bounds__(256) void lu_update_dma32_kernel(GemmArgs<float> g) { dma::tile_body32(g); }
 
 // C = sum_s P_s + beta C over the split-K partials.
 template <typename R>
@@ -519,6 +646,15 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
                 hipLaunchKernelGGL(lu_update_dma_kernel, grid, dim3(256), 0, s, g);
             else
                 hipLaunchKernelGGL(gemm_dma_kernel, grid, dim3(256), 0, s, g);
+            return;
+        }
+    }
+    if constexpr (std::is_same<R, float>::value && TM == 4 && TN == 2 && !CONJA) {
+        if ((lu_update || m3) && nsplit == 1 && dma::fits32(g)) {
+            if (lu_update)
+                hipLaunchKernelGGL(lu_update_dma32_kernel, grid, dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL(gemm_dma32_kernel, grid, dim3(256), 0, s, g);
             return;
         }
     }

@@ -98,25 +98,32 @@ def test_assemble_matches_oracle():
         assert np.array_equal(nl.from_colmajor(T32[k]), r32) or rel(nl.from_colmajor(T32[k]), ref[k]) < 1e-7
 
 
-@pytest.mark.parametrize("M,N,K,batch", [(2048, 1536, 80, 2), (1024, 2048, 512, 2)])
-def test_gemm_direct_lds_tile_matches_definition(M, N, K, batch):
-    # complex128 products with op(A) = A whose tiles all lie inside the matrix (M, N multiples of
-    # 64, K of 16) and that fill the chip with 64 x 64 tiles: the direct-to-LDS 3M form, here on
-    # sub-matrices (leading dimensions above the row counts) with general alpha and beta
-    rng = np.random.default_rng(M + 3 * N + K)
-    lda, ldb, ldc = M + 64, K + 16, M + 128
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("M,N,K,batch,odd_ld", [(2048, 1536, 80, 2, False), (1024, 2048, 512, 2, False),
+                                                (2048, 1536, 80, 2, True)])
+def test_gemm_direct_lds_tile_matches_definition(dtype, M, N, K, batch, odd_ld):
+    # products with op(A) = A whose tiles all lie inside the matrix (M, N multiples of 128 and 64,
+    # K of 16) and that fill the chip: the direct-to-LDS 3M forms, here on sub-matrices (leading
+    # dimensions above the row counts) with general alpha and beta.  An odd leading dimension
+    # breaks the 16-byte alignment of complex64 element pairs, so that case takes the staged form
+    rng = np.random.default_rng(M + 3 * N + K + odd_ld)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    tol = 1e-13 if dtype == "c128" else 2e-5
+    lda, ldb, ldc = M + 64 + odd_ld, K + 16 + odd_ld, M + 128
     alpha, beta = -1.0 + 0.25j, 0.5 - 0.75j
     A = [wl.cn(rng, (lda, K)) for _ in range(batch)]
     B = [wl.cn(rng, (ldb, N)) for _ in range(batch)]
     C = [wl.cn(rng, (ldc, N)) for _ in range(batch)]
-    Ad, Bd, Cd = batch_dev(A), batch_dev(B), batch_dev(C)
+    if dtype == "c64":
+        A, B, C = ([X.astype(np.complex64).astype(complex) for X in Y] for Y in (A, B, C))
+    Ad, Bd, Cd = batch_dev(A, dt), batch_dev(B, dt), batch_dev(C, dt)
     nl.nlf_gemm_batched("N", M, N, K, alpha, Ad, lda, lda * K, Bd, ldb, ldb * N, beta, Cd, ldc, ldc * N, batch)
     torch.cuda.synchronize()
     for b in range(batch):
-        got = nl.from_colmajor(Cd[b])
+        got = nl.from_colmajor(Cd[b]).astype(complex)
         ref = C[b].copy()
         ref[:M] = alpha * (A[b][:M] @ B[b][:K]) + beta * C[b][:M]
-        assert rel(got[:M], ref[:M]) < 1e-13 * np.sqrt(K)
+        assert rel(got[:M], ref[:M]) < tol * np.sqrt(K)
         assert np.array_equal(got[M:], C[b][M:])      # rows between M and ldc untouched
 
 
