@@ -76,7 +76,7 @@ def parse():
 def probe_lu(n, bt):
     """Counter runs: a plain device copy of known size (to scale the HBM counters), then one
     batched blocked LU of n x n complex128 matrices (the headline: 24 of n = 8192), whose
-    lu_update_kernel launches are the dominant kernel's."""
+    trailing-update launches are the dominant kernel's."""
     import torch
     import paper_1801_09794_amd as nl
     torch.cuda.set_device(0)
@@ -521,8 +521,9 @@ def main():
                "trailing_gemm_tflops": lu_tflops,
                "trailing_gemm_frac_fp64_peak": lu_tflops / PEAK["fp64_mfma_tflops"]},
         "roofline": {
-            "kernel": "lu_update_kernel<double, 2, 2, 8> (rank-512 trailing updates of the blocked LU, "
-                      "%d complex128 matrices of n = %d; complex products by the 3M scheme)" % (nnodes, n),
+            "kernel": "lu_update_dma_kernel (rank-512 trailing updates of the blocked LU, %d complex128 "
+                      "matrices of n = %d: 64 x 64 tiles, operands loaded straight into LDS, complex "
+                      "products by the 3M scheme)" % (nnodes, n),
             "bound": "mfma",
             "achieved": lu_tflops if lu["ms"] > 0 else None,
             "peak": PEAK["fp64_mfma_tflops"],
@@ -533,7 +534,7 @@ def main():
             "executed_tflops": 0.75 * lu_tflops if lu["ms"] > 0 else None,
             "executed_frac": 0.75 * lu_tflops / PEAK["fp64_mfma_tflops"] if lu["ms"] > 0 else None,
             "traffic": load_traffic(n, nnodes),
-            "traffic_note": "HBM bytes per launch, averaged over the lu_update_kernel launches "
+            "traffic_note": "HBM bytes per launch, averaged over the trailing-update launches "
                             "of one FP64 factorisation of this shape, from FETCH_SIZE + "
                             "WRITE_SIZE counters scaled by a 1 GiB copy (profiles/)",
             "algorithmic_bytes_per_launch": lu["bytes"] / max(lu["launches"], 1),
