@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void lu_update_kernel(GemmArgs<R> g) {
 // ------------------------------------------------ FP64 3M tile with direct-to-LDS operand loads
 //
 // The same 64 x 64 tile, 2 x 2 waves and 3M products as gemm_tile_body<double, 2, 2, 8>, for
-// problems whose every tile lies inside the matrix (M, N multiples of 64, K a multiple of 16).
+// reductions that are a multiple of 16 (RAGGED: tiles reaching past the last row or column).
 // The operand tiles go from global memory straight into LDS (global_load_lds_dwordx4: each lane
 // moves one complex element, which lands at the instruction's LDS base + 16 x lane), so no
 // staging registers, masks or LDS store instructions sit between the MFMA blocks; each stage
@@ -353,15 +353,20 @@ using Z = Cx<double>;
 #define NLF_GPTR(p) ((__attribute__((address_space(1))) void*)(p))
 #define NLF_LPTR(p) ((__attribute__((address_space(3))) void*)(p))
 
+// RAGGED: lanes whose row (aok) or column (bit r of bok) lies outside the matrix load nothing;
+// the stale LDS entries they leave only feed output rows or columns that are never stored
+template <bool RAGGED>
 __device__ __forceinline__ void issue(Z* As, Z* Bs, const Z* ga, const Z* const* gb, int64_t lda, int64_t k0,
-                                      int wave) {
+                                      int wave, bool aok, unsigned bok) {
 #pragma unroll
     for (int r = 0; r < BK / 4; ++r)
-        __builtin_amdgcn_global_load_lds(NLF_GPTR(ga + (k0 + 4 * r) * lda), NLF_LPTR(As + (wave + 4 * r) * 64), 16,
-                                         0, 0);
+        if (!RAGGED || aok)
+            __builtin_amdgcn_global_load_lds(NLF_GPTR(ga + (k0 + 4 * r) * lda), NLF_LPTR(As + (wave + 4 * r) * 64),
+                                             16, 0, 0);
 #pragma unroll
     for (int r = 0; r < BK / 4; ++r)
-        __builtin_amdgcn_global_load_lds(NLF_GPTR(gb[r] + k0), NLF_LPTR(Bs + (wave + 4 * r) * 64), 16, 0, 0);
+        if (!RAGGED || ((bok >> r) & 1u))
+            __builtin_amdgcn_global_load_lds(NLF_GPTR(gb[r] + k0), NLF_LPTR(Bs + (wave + 4 * r) * 64), 16, 0, 0);
 }
 
 using acc_t = Mfma<double>::acc_t;
@@ -397,6 +402,7 @@ __device__ __forceinline__ void multiply(const Z* As, const Z* Bs, int aoff, con
 // s_waitcnt vmcnt(0), other counters left alone (gfx9 encoding: expcnt 7, lgkmcnt 15)
 __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+template <bool RAGGED>
 __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
     __shared__ Z A0[BK * 64], A1[BK * 64], B0[BK * 64], B1[BK * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
@@ -410,12 +416,17 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
     // this lane's source of the A rows k = wave + 4 r and of the B blocks b = wave + 4 r
     const Z* ga = A + (m0 + lane) + (int64_t)wave * lda;
     const Z* gb[BK / 4];
+    unsigned bok = 0;
 #pragma unroll
     for (int r = 0; r < BK / 4; ++r) {
         const int b = wave + 4 * r, kh = b >> 3, grp = b & 7;
         const int n = 8 * grp + (lane >> 3), k = 8 * kh + ((lane & 7) ^ ((n >> 1) & 7));
         gb[r] = B + k + (n0 + n) * ldb;
+        bok |= (unsigned)(n0 + n < g.N) << r;
     }
+    const bool aok = m0 + lane < g.M;
+    // a wave whose 32 rows or 32 columns all lie outside C has no MFMA work
+    const bool active = !RAGGED || (m0 + wm * 32 < g.M && n0 + wn * 32 < g.N);
     // this lane's MFMA operands: A element (k, wm 32 + 16 i + col), B element (k, wn 32 + 16 j + col)
     const int col = lane & 15, krow = lane >> 4;
     const int aoff = krow * 64 + wm * 32 + col;
@@ -435,21 +446,21 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
             t3[i][j] = acc_t{0, 0, 0, 0};
         }
 
-    issue(A0, B0, ga, gb, lda, 0, wave);
+    issue<RAGGED>(A0, B0, ga, gb, lda, 0, wave, aok, bok);
     wait_loads();
     __syncthreads();
     // K is a multiple of 2 BK: every trip multiplies both buffers; the scheduling barriers keep
     // the loads of the next stage ahead of the MFMAs and the wait behind them
     for (int64_t k0 = 0; k0 < K; k0 += 2 * BK) {
-        issue(A1, B1, ga, gb, lda, k0 + BK, wave);
+        issue<RAGGED>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        multiply(A0, B0, aoff, boff, t1, t2, t3);
+        if (active) multiply(A0, B0, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
-        if (k0 + 2 * BK < K) issue(A0, B0, ga, gb, lda, k0 + 2 * BK, wave);
+        if (k0 + 2 * BK < K) issue<RAGGED>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        multiply(A1, B1, aoff, boff, t1, t2, t3);
+        if (active) multiply(A1, B1, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
@@ -465,16 +476,17 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm * 32 + i * 16 + col;
                 const int64_t n = n0 + wn * 32 + j * 16 + Mfma<double>::acc_row(krow, r);
+                if (RAGGED && (m >= g.M || n >= g.N)) continue;
                 const double p1 = t1[i][j][r], p2 = t2[i][j][r];
                 Z out = g.alpha * Z(p1 - p2, t3[i][j][r] - p1 - p2);
                 if (useBeta) out = out + g.beta * C[m + n * g.ldc];
                 C[m + n * g.ldc] = out;
             }
 }
-// shapes the direct-to-LDS tile covers exactly
-inline bool fits(int64_t M, int64_t N, int64_t K) {
-    return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % (2 * BK) == 0;
-}
+// shapes the direct-to-LDS tile takes: any M and N (ragged edges through the predicated form), a
+// reduction that is a multiple of two stages (a partial stage would mix stale LDS into every output)
+inline bool fits(int64_t M, int64_t N, int64_t K) { return M > 0 && N > 0 && K > 0 && K % (2 * BK) == 0; }
+inline bool full_tiles(int64_t M, int64_t N) { return M % 64 == 0 && N % 64 == 0; }
 
 // The FP32 counterpart: the 128 x 64 tile of gemm_tile_body<float, 4, 2, 8> (wave tile 64 x 32)
 // with 3M products. One 16-byte load lane carries two complex64 elements, so:
@@ -485,18 +497,20 @@ inline bool fits(int64_t M, int64_t N, int64_t K) {
 //    for block q fetches column n = 16 q + (l >> 2), unit (l & 3) ^ ((n >> 2) & 3), so the 4
 //    lanes of a column read its 64 contiguous bytes and 32 operand reads (16 columns, two k)
 //    fall on distinct banks.
-// Needs 16-byte aligned rows pairs: even leading dimensions and 16-byte aligned A and B.
+// Needs 16-byte aligned row pairs: even M and leading dimensions, 16-byte aligned A and B.
 using Y = Cx<float>;
 constexpr int APAD32 = 16;
 using acc32_t = Mfma<float>::acc_t;
 
+template <bool RAGGED>
 __device__ __forceinline__ void issue32(Y* As, Y* Bs, const Y* const* ga, const Y* gb, int64_t lda, int64_t k0,
-                                        int wave) {
+                                        int wave, bool aok, bool bok) {
 #pragma unroll
     for (int r = 0; r < BK / 4; ++r)
-        __builtin_amdgcn_global_load_lds(NLF_GPTR(ga[r] + k0 * lda), NLF_LPTR(As + (wave + 4 * r) * (128 + APAD32)),
-                                         16, 0, 0);
-    __builtin_amdgcn_global_load_lds(NLF_GPTR(gb + k0), NLF_LPTR(Bs + wave * 128), 16, 0, 0);
+        if (!RAGGED || aok)
+            __builtin_amdgcn_global_load_lds(NLF_GPTR(ga[r] + k0 * lda),
+                                             NLF_LPTR(As + (wave + 4 * r) * (128 + APAD32)), 16, 0, 0);
+    if (!RAGGED || bok) __builtin_amdgcn_global_load_lds(NLF_GPTR(gb + k0), NLF_LPTR(Bs + wave * 128), 16, 0, 0);
 }
 
 __device__ __forceinline__ void multiply32(const Y* As, const Y* Bs, int aoff, const int* boff,
@@ -528,6 +542,7 @@ __device__ __forceinline__ void multiply32(const Y* As, const Y* Bs, int aoff, c
     }
 }
 
+template <bool RAGGED>
 __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
     __shared__ Y A0[BK * (128 + APAD32)], A1[BK * (128 + APAD32)], B0[BK * 64], B1[BK * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
@@ -544,6 +559,9 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
     for (int r = 0; r < BK / 4; ++r) ga[r] = A + (m0 + 2 * lane) + (int64_t)(wave + 4 * r) * lda;
     const int nq = 16 * wave + (lane >> 2);
     const Y* gb = B + 2 * ((lane & 3) ^ ((nq >> 2) & 3)) + (n0 + nq) * ldb;
+    // M is even on this path, so a lane's row pair is either inside or outside the matrix
+    const bool aok = m0 + 2 * lane < g.M, bok = n0 + nq < g.N;
+    const bool active = !RAGGED || (m0 + wm * 64 < g.M && n0 + wn * 32 < g.N);
     // this lane's MFMA operands: A element (k, wm 64 + 16 i + col), B element (k, wn 32 + 16 j + col)
     const int col = lane & 15, krow = lane >> 4;
     const int aoff = krow * (128 + APAD32) + wm * 64 + col;
@@ -561,19 +579,19 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
             t3[i][j] = acc32_t{0, 0, 0, 0};
         }
 
-    issue32(A0, B0, ga, gb, lda, 0, wave);
+    issue32<RAGGED>(A0, B0, ga, gb, lda, 0, wave, aok, bok);
     wait_loads();
     __syncthreads();
     for (int64_t k0 = 0; k0 < K; k0 += 2 * BK) {
-        issue32(A1, B1, ga, gb, lda, k0 + BK, wave);
+        issue32<RAGGED>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        multiply32(A0, B0, aoff, boff, t1, t2, t3);
+        if (active) multiply32(A0, B0, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
-        if (k0 + 2 * BK < K) issue32(A0, B0, ga, gb, lda, k0 + 2 * BK, wave);
+        if (k0 + 2 * BK < K) issue32<RAGGED>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        multiply32(A1, B1, aoff, boff, t1, t2, t3);
+        if (active) multiply32(A1, B1, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
@@ -589,6 +607,7 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm * 64 + i * 16 + col;
                 const int64_t n = n0 + wn * 32 + j * 16 + Mfma<float>::acc_row(krow, r);
+                if (RAGGED && (m >= g.M || n >= g.N)) continue;
                 const float p1 = t1[i][j][r], p2 = t2[i][j][r];
                 Y out = g.alpha * Y(p1 - p2, t3[i][j][r] - p1 - p2);
                 if (useBeta) out = out + g.beta * C[m + n * g.ldc];
@@ -597,7 +616,7 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
 }
 
 inline bool fits32(const GemmArgs<float>& g) {
-    return g.M > 0 && g.N > 0 && g.K > 0 && g.M % 128 == 0 && g.N % 64 == 0 && g.K % (2 * BK) == 0 &&
+    return g.M > 0 && g.N > 0 && g.K > 0 && g.M % 2 == 0 && g.K % (2 * BK) == 0 &&
            g.lda % 2 == 0 && g.ldb % 2 == 0 && g.sA % 2 == 0 && g.sB % 2 == 0 &&
            reinterpret_cast<uintptr_t>(g.A) % 16 == 0 && reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
 }
@@ -605,11 +624,16 @@ inline bool fits32(const GemmArgs<float>& g) {
 #undef NLF_LPTR
 }  // namespace dma
 
-__global__ __launch_bounds__(256) void gemm_dma_kernel(GemmArgs<double> g) { dma::tile_body(g); }
+__global__ __launch_bounds__(256) void gemm_dma_kernel(GemmArgs<double> g) { dma::tile_body<false>(g); }
 // the trailing updates of the blocked LU under their own symbol (see lu_update_kernel)
-__global__ __launch_bounds__(256) void lu_update_dma_kernel(GemmArgs<double> g) { dma::tile_body(g); }
-__global__ __launch_bounds__(256) void gemm_dma32_kernel(GemmArgs<float> g) { dma::tile_body32(g); }
-__global__ __launch_bounds__(256) void lu_update_dma32_kernel(GemmArgs<float> g) { dma::tile_body32(g); }
+__global__ __launch_bounds__(256) void lu_update_dma_kernel(GemmArgs<double> g) { dma::tile_body<false>(g); }
+// ragged M or N (predicated loads, idle waves, guarded stores); the LU updates share it
+__global__ __launch_bounds__(256) void gemm_dma_ragged_kernel(GemmArgs<double> g) { dma::tile_body<true>(g); }
+// FP32 takes the predicated form for every shape: with the per-wave MFMA branch the compiler keeps
+// the two unrolled stages apart and allocates 142 VGPRs (three waves per SIMD) instead of 180
+// (two); measured at 7680^2 x 512, 24 matrices: 33.5 against 34.9 ms
+__global__ __launch_bounds__(256) void gemm_dma32_kernel(GemmArgs<float> g) { dma::tile_body32<true>(g); }
+__global__ __launch_bounds__(256) void lu_update_dma32_kernel(GemmArgs<float> g) { dma::tile_body32<true>(g); }
 
 // C = sum_s P_s + beta C over the split-K partials.
 template <typename R>
@@ -633,6 +657,15 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, 
 
 // ---------------------------------------------------------------------------- host side
 
+// Whether the direct-to-LDS tiles take a product of this shape whole (ragged edges included):
+// 3M products with op(A) = A on the 64 x 64 (FP64) or 128 x 64 (FP32) tile, no split-K.
+static bool dma_takes(const GemmArgs<double>& g, const GemmConfig& c, bool conjA, bool lu_update) {
+    return !conjA && (lu_update || g.K >= 64) && c.tm == 2 && c.tn == 2 && dma::fits(g.M, g.N, g.K);
+}
+static bool dma_takes(const GemmArgs<float>& g, const GemmConfig& c, bool conjA, bool lu_update) {
+    return !conjA && (lu_update || g.K >= 64) && c.tm == 4 && c.tn == 2 && dma::fits32(g);
+}
+
 // m3: the 3M products (see gemm_tile_body).
 template <typename R, int TM, int TN, int BK, bool CONJA>
 static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, bool lu_update, bool m3) {
@@ -642,7 +675,9 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
     dim3 grid(g.tilesM * g.tilesN, batch, nsplit);
     if constexpr (std::is_same<R, double>::value && TM == 2 && TN == 2 && !CONJA) {
         if ((lu_update || m3) && nsplit == 1 && dma::fits(g.M, g.N, g.K)) {
-            if (lu_update)
+            if (!dma::full_tiles(g.M, g.N))
+                hipLaunchKernelGGL(gemm_dma_ragged_kernel, grid, dim3(256), 0, s, g);
+            else if (lu_update)
                 hipLaunchKernelGGL(lu_update_dma_kernel, grid, dim3(256), 0, s, g);
             else
                 hipLaunchKernelGGL(gemm_dma_kernel, grid, dim3(256), 0, s, g);
@@ -724,8 +759,12 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // + 32: a sixth of the tile's MFMA work wasted) goes to a second launch of 32 x 32 tiles.
     // Measured on the right-looking updates of the block triangular solves (n = 8192, 160
     // right-hand sides, 24 nodes, K = 256): 64 x 64 tiles 61 TFLOP/s, 32 x 32 tiles 62
+    // Not for the complex64 products the direct-to-LDS tile takes whole: there the tile column
+    // holding the ragged edge skips its idle waves' MFMAs, as fast or faster (7680 x 160 x 1024, 24
+    // nodes: 1.67 against 1.68 ms; 3584 rows: 0.83 against 0.87). In FP64 the split stays ahead
+    // (3.14 against 3.20 ms; 1920 x 80 x 256, 128 nodes: 0.66 against 0.77)
     if (!force && !lu_update && c.tn == 2 && N > 64 && N % 64 != 0 && N % 64 <= 32 &&
-        !(ws && tiles < 256 && K >= 512)) {
+        !(ws && tiles < 256 && K >= 512) && !(sizeof(R) == 4 && dma_takes(g, c, conjA, lu_update))) {
         const int64_t N0 = N - N % 64;
         gemm<R>(s, conjA, M, N0, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws, ws_elems, &c,
                 lu_update);

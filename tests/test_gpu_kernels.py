@@ -100,12 +100,16 @@ def test_assemble_matches_oracle():
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("M,N,K,batch,odd_ld", [(2048, 1536, 80, 2, False), (1024, 2048, 512, 2, False),
-                                                (2048, 1536, 80, 2, True)])
+                                                (2048, 1536, 80, 2, True), (2000, 1530, 96, 2, False),
+                                                (2046, 1500, 64, 2, False), (2047, 1530, 96, 2, False),
+                                                (2048, 1536, 88, 2, False)])
 def test_gemm_direct_lds_tile_matches_definition(dtype, M, N, K, batch, odd_ld):
-    # products with op(A) = A whose tiles all lie inside the matrix (M, N multiples of 128 and 64,
-    # K of 16) and that fill the chip: the direct-to-LDS 3M forms, here on sub-matrices (leading
-    # dimensions above the row counts) with general alpha and beta.  An odd leading dimension
-    # breaks the 16-byte alignment of complex64 element pairs, so that case takes the staged form
+    # products with op(A) = A that fill the chip with 64 x 64 (complex128) or 128 x 64 (complex64)
+    # tiles: the direct-to-LDS 3M forms, here on sub-matrices (leading dimensions above the row
+    # counts) with general alpha and beta.  Full tiles; ragged rows and columns (predicated loads,
+    # idle waves, guarded stores; complex128 with at most 32 ragged columns splits them off); an
+    # odd leading dimension or an odd row count (complex64 element pairs lose their 16-byte
+    # alignment) and a reduction that is not a multiple of 16 take the staged form
     rng = np.random.default_rng(M + 3 * N + K + odd_ld)
     dt = torch.complex128 if dtype == "c128" else torch.complex64
     tol = 1e-13 if dtype == "c128" else 2e-5
