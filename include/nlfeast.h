@@ -116,7 +116,8 @@ typedef struct {
                                     factorisation are then profiled only through NLF_K_FACTOR */
     int32_t lookahead;           /* blocked LU: 1 = factor panel k+1 on a second stream while
                                     the trailing update of panel k runs; -1 = one stream;
-                                    0 = library default (one stream) */
+                                    0 = library default (one stream).  1 together with
+                                    lu_streams > 1 is refused (NLF_ERR_ARG) */
     int32_t reduced_solver;      /* Steps 1-2 (Sec. 4.2: the projected problem may be solved by
                                     any suitable method).  Non-polynomial T: 0 (default) or 1 =
                                     the contour-integral solve (moments of the reduced resolvent

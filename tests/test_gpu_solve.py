@@ -733,7 +733,7 @@ def test_option_and_state_validation():
         S.set_contour([dict(centre=complex(*g["centre"]), a=g["radius"], nc=8, m0=20)])
         bad = [dict(reduced_solver=4), dict(reduced_solver=-1), dict(lookahead=2), dict(precision=7),
                dict(tol=0.0), dict(max_iter=0), dict(lu_streams=5), dict(panel_width=3), dict(graph=2),
-               dict(region_streams=2), dict(autotune=2)]
+               dict(region_streams=2), dict(autotune=2), dict(lookahead=1, lu_streams=2)]
         for kw in bad:
             with pytest.raises(nl.NLFError) as e:
                 S.solve(nl.options(**kw))
