@@ -402,7 +402,9 @@ __device__ __forceinline__ void multiply(const Z* As, const Z* Bs, int aoff, con
 // s_waitcnt vmcnt(0), other counters left alone (gfx9 encoding: expcnt 7, lgkmcnt 15)
 __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
-template <bool RAGGED>
+// SPLIT: blockIdx.z takes the reduction range [z kchunk, (z + 1) kchunk) and writes alpha times
+// its partial product to g.P (summed with beta C by gemm_reduce_kernel)
+template <bool RAGGED, bool SPLIT = false>
 __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
     __shared__ Z A0[BK * 64], A1[BK * 64], B0[BK * 64], B1[BK * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
@@ -411,7 +413,12 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
     const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 64, n0 = (int64_t)tn * 64;
     const Z* A = g.A + batch * g.sA;
     const Z* B = g.B + batch * g.sB;
-    const int64_t K = g.K, lda = g.lda, ldb = g.ldb;
+    const int64_t lda = g.lda, ldb = g.ldb;
+    int64_t kbeg = 0, K = g.K;
+    if (SPLIT) {
+        kbeg = (int64_t)blockIdx.z * g.kchunk;
+        K = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    }
 
     // this lane's source of the A rows k = wave + 4 r and of the B blocks b = wave + 4 r
     const Z* ga = A + (m0 + lane) + (int64_t)wave * lda;
@@ -446,12 +453,12 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
             t3[i][j] = acc_t{0, 0, 0, 0};
         }
 
-    issue<RAGGED>(A0, B0, ga, gb, lda, 0, wave, aok, bok);
+    issue<RAGGED>(A0, B0, ga, gb, lda, kbeg, wave, aok, bok);
     wait_loads();
     __syncthreads();
-    // K is a multiple of 2 BK: every trip multiplies both buffers; the scheduling barriers keep
-    // the loads of the next stage ahead of the MFMAs and the wait behind them
-    for (int64_t k0 = 0; k0 < K; k0 += 2 * BK) {
+    // the range is a multiple of 2 BK: every trip multiplies both buffers; the scheduling
+    // barriers keep the loads of the next stage ahead of the MFMAs and the wait behind them
+    for (int64_t k0 = kbeg; k0 < K; k0 += 2 * BK) {
         issue<RAGGED>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
         if (active) multiply(A0, B0, aoff, boff, t1, t2, t3);
@@ -467,6 +474,7 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
     }
 
     Z* C = g.C + batch * g.sC;
+    Z* P = SPLIT ? g.P + (batch * g.nsplit + blockIdx.z) * g.M * g.N : nullptr;
     const bool useBeta = (g.beta.re != 0.0 || g.beta.im != 0.0);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -479,6 +487,10 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
                 if (RAGGED && (m >= g.M || n >= g.N)) continue;
                 const double p1 = t1[i][j][r], p2 = t2[i][j][r];
                 Z out = g.alpha * Z(p1 - p2, t3[i][j][r] - p1 - p2);
+                if (SPLIT) {
+                    P[m + n * g.M] = out;
+                    continue;
+                }
                 if (useBeta) out = out + g.beta * C[m + n * g.ldc];
                 C[m + n * g.ldc] = out;
             }
@@ -629,6 +641,8 @@ __global__ __launch_bounds__(256) void gemm_dma_kernel(GemmArgs<double> g) { dma
 __global__ __launch_bounds__(256) void lu_update_dma_kernel(GemmArgs<double> g) { dma::tile_body<false>(g); }
 // ragged M or N (predicated loads, idle waves, guarded stores); the LU updates share it
 __global__ __launch_bounds__(256) void gemm_dma_ragged_kernel(GemmArgs<double> g) { dma::tile_body<true>(g); }
+// split-K partial products (long reductions into few output tiles; any M and N)
+__global__ __launch_bounds__(256) void gemm_dma_split_kernel(GemmArgs<double> g) { dma::tile_body<true, true>(g); }
 // FP32 takes the predicated form for every shape: with the per-wave MFMA branch the compiler keeps
 // the two unrolled stages apart and allocates 142 VGPRs (three waves per SIMD) instead of 180
 // (two); measured at 7680^2 x 512, 24 matrices: 33.5 against 34.9 ms
@@ -755,6 +769,34 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // split-K for small outputs with long reductions (projections, Gram matrices)
     int nsplit = 1;
     const int64_t tiles = ceil_div(M, 32 * c.tm) * ceil_div(N, 32 * c.tn) * batch;
+    // FP64 3M products with a long reduction into fewer 64 x 64 tiles than three workgroups per
+    // compute unit (the projections A_j Q, 8192 x 160 x 8192): the direct-to-LDS tile with the
+    // reduction split so that at least two rounds of workgroups are in flight, partial products
+    // summed by gemm_reduce (measured 8192 x 160 x 8192: 32 x 32 tiles, 1280 workgroups, against
+    // 64 x 64 tiles with 4 splits, 1536 workgroups)
+    if constexpr (sizeof(R) == 8) {
+        const int64_t t64 = ceil_div(M, 64) * ceil_div(N, 64) * batch;
+        if (!force && ws && !conjA && !lu_update && K >= 2048 && K % (2 * dma::BK) == 0 && t64 < 768) {
+            int want = (int)std::min<int64_t>(ceil_div(1536, t64), K / 1024);
+            while (want > 1 && (int64_t)want * M * N * batch > ws_elems) --want;
+            if (want >= 2 && t64 * want >= 768) {
+                g.tilesM = (int)ceil_div(M, 64);
+                g.tilesN = (int)ceil_div(N, 64);
+                g.kchunk = ceil_div(ceil_div(K, want), 2 * dma::BK) * 2 * dma::BK;
+                g.nsplit = (int)ceil_div(K, g.kchunk);
+                g.P = ws;
+                dim3 grid(g.tilesM * g.tilesN, batch, g.nsplit);
+                hipLaunchKernelGGL(gemm_dma_split_kernel, grid, dim3(256), 0, s, g);
+                NLF_HIP(hipGetLastError());
+                const int64_t MN = M * N;
+                dim3 rgrid((unsigned)std::min<int64_t>(ceil_div(MN, 256), 1024), batch);
+                hipLaunchKernelGGL((gemm_reduce_kernel<R>), rgrid, dim3(256), 0, s, M, N, g.nsplit,
+                                   (const Cx<R>*)g.P, beta, C, ldc, sC);
+                NLF_HIP(hipGetLastError());
+                return;
+            }
+        }
+    }
     // A ragged last column of 64-wide tiles that would hold at most 32 columns (N = 160 = 2 x 64
     // + 32: a sixth of the tile's MFMA work wasted) goes to a second launch of 32 x 32 tiles.
     // Measured on the right-looking updates of the block triangular solves (n = 8192, 160

@@ -387,6 +387,26 @@ def test_project_matches_oracle():
         assert rel(nl.from_colmajor(Ah[j]), ref[j]) < 1e-13
 
 
+def test_project_long_reduction_matches_definition():
+    # n = 4096, m = 160: W_j = A_j Q has a 4096-long reduction into 192 output tiles of 64 x 64,
+    # which the library runs as split-K partial products (direct-to-LDS 3M tile) summed by a
+    # reduction kernel; W_j itself and Ahat_j = Q^H W_j against their definitions
+    rng = np.random.default_rng(11)
+    n, m, J = 4096, 160, 2
+    mats = [wl.cn(rng, (n, n)) / np.sqrt(n) for _ in range(J)]
+    Q, _ = np.linalg.qr(wl.cn(rng, (n, m)))
+    W = torch.empty((J * m, n), dtype=torch.complex128, device="cuda")
+    Ah = torch.empty((J, m, m), dtype=torch.complex128, device="cuda")
+    ws = torch.empty(nl.nlf_project_workspace(n, m, J), dtype=torch.complex128, device="cuda")
+    nl.nlf_project([dev(M) for M in mats], dev(Q), W, Ah, ws)
+    torch.cuda.synchronize()
+    Wh = nl.from_colmajor(W)
+    for j in range(J):
+        Wj = mats[j] @ Q
+        assert rel(Wh[:, j * m:(j + 1) * m], Wj) < 1e-13 * np.sqrt(n)
+        assert rel(nl.from_colmajor(Ah[j]), Q.conj().T @ Wj) < 1e-13 * np.sqrt(n)
+
+
 @pytest.mark.parametrize("n,m", [(1500, 45), (300, 64)])
 def test_orthonormalize_rank_deficient_block(n, m):
     # singular values from 1 down to 1e-20: the Gram matrix is numerically singular, so the
