@@ -1210,7 +1210,8 @@ static ReducedResult contour_finish(int m, const std::vector<Term>& terms, const
         for (int i = 0; i < m; ++i) nn += std::norm(x[i]);
         return std::sqrt(nn);
     };
-    for (int c = 0; c < kf; ++c) {
+    // (the basis only serves the completion: with m_keep vectors found there is nothing to add)
+    for (int c = 0; c < kf && kf < m_keep; ++c) {
         std::copy(res.Y.begin() + (size_t)c * m, res.Y.begin() + (size_t)(c + 1) * m, v.begin());
         const double nn = orthogonalise(v);
         if (nn < 1e-8) continue;   // numerically inside the span already
