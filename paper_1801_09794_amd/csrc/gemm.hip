@@ -355,7 +355,8 @@ using Z = Cx<double>;
 
 // RAGGED: lanes whose row (aok) or column (bit r of bok) lies outside the matrix load nothing;
 // the stale LDS entries they leave only feed output rows or columns that are never stored
-template <bool RAGGED>
+// BR: B blocks (8 columns x 8 k) loaded per wave and stage
+template <bool RAGGED, int BR>
 __device__ __forceinline__ void issue(Z* As, Z* Bs, const Z* ga, const Z* const* gb, int64_t lda, int64_t k0,
                                       int wave, bool aok, unsigned bok) {
 #pragma unroll
@@ -364,38 +365,40 @@ __device__ __forceinline__ void issue(Z* As, Z* Bs, const Z* ga, const Z* const*
             __builtin_amdgcn_global_load_lds(NLF_GPTR(ga + (k0 + 4 * r) * lda), NLF_LPTR(As + (wave + 4 * r) * 64),
                                              16, 0, 0);
 #pragma unroll
-    for (int r = 0; r < BK / 4; ++r)
+    for (int r = 0; r < BR; ++r)
         if (!RAGGED || ((bok >> r) & 1u))
             __builtin_amdgcn_global_load_lds(NLF_GPTR(gb[r] + k0), NLF_LPTR(Bs + (wave + 4 * r) * 64), 16, 0, 0);
 }
 
 using acc_t = Mfma<double>::acc_t;
-__device__ __forceinline__ void multiply(const Z* As, const Z* Bs, int aoff, const int* boff, acc_t (&t1)[2][2],
-                                         acc_t (&t2)[2][2], acc_t (&t3)[2][2]) {
+// TN: 16-column MFMA blocks per wave (the tile is 64 x 32 TN); B holds 8 TN column blocks per k half
+template <int TN>
+__device__ __forceinline__ void multiply(const Z* As, const Z* Bs, int aoff, const int* boff, acc_t (&t1)[2][TN],
+                                         acc_t (&t2)[2][TN], acc_t (&t3)[2][TN]) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-        Z a[2], b[2];
-        double as[2], bs[2];
+        Z a[2], b[TN];
+        double as[2], bs[TN];
 #pragma unroll
         for (int i = 0; i < 2; ++i) a[i] = As[kk * 64 + aoff + i * 16];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[(kk >> 3) * 512 + (boff[j] ^ (kk & 4))];
+        for (int j = 0; j < TN; ++j) b[j] = Bs[(kk >> 3) * (256 * TN) + (boff[j] ^ (kk & 4))];
 #pragma unroll
         for (int i = 0; i < 2; ++i) as[i] = a[i].re + a[i].im;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bs[j] = b[j].re + b[j].im;
+        for (int j = 0; j < TN; ++j) bs[j] = b[j].re + b[j].im;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t1[i][j] = Mfma<double>::mma(b[j].re, a[i].re, t1[i][j]);
+            for (int j = 0; j < TN; ++j) t1[i][j] = Mfma<double>::mma(b[j].re, a[i].re, t1[i][j]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t2[i][j] = Mfma<double>::mma(b[j].im, a[i].im, t2[i][j]);
+            for (int j = 0; j < TN; ++j) t2[i][j] = Mfma<double>::mma(b[j].im, a[i].im, t2[i][j]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t3[i][j] = Mfma<double>::mma(bs[j], as[i], t3[i][j]);
+            for (int j = 0; j < TN; ++j) t3[i][j] = Mfma<double>::mma(bs[j], as[i], t3[i][j]);
     }
 }
 
@@ -404,13 +407,16 @@ __device__ __forceinline__ void wait_loads() { __builtin_amdgcn_s_waitcnt(0x0F70
 
 // SPLIT: blockIdx.z takes the reduction range [z kchunk, (z + 1) kchunk) and writes alpha times
 // its partial product to g.P (summed with beta C by gemm_reduce_kernel)
-template <bool RAGGED, bool SPLIT = false>
+// TN = 2: the 64 x 64 tile; TN = 1: 64 x 32 (ragged 32-column edges of FP64 products)
+template <bool RAGGED, bool SPLIT = false, int TN = 2>
 __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
-    __shared__ Z A0[BK * 64], A1[BK * 64], B0[BK * 64], B1[BK * 64];
+    constexpr int BN = 32 * TN, BR = (BN / 8) * (BK / 8) / 4;
+    static_assert(BR >= 1 && (BN / 8) * (BK / 8) % 4 == 0, "B blocks per wave");
+    __shared__ Z A0[BK * 64], A1[BK * 64], B0[BK * BN], B1[BK * BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
     int tm, tn;
     tile_coords(xcd_remap(blockIdx.x, g.tilesM * g.tilesN), g.tilesM, g.tilesN, tm, tn);
-    const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 64, n0 = (int64_t)tn * 64;
+    const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 64, n0 = (int64_t)tn * BN;
     const Z* A = g.A + batch * g.sA;
     const Z* B = g.B + batch * g.sB;
     const int64_t lda = g.lda, ldb = g.ldb;
@@ -422,52 +428,52 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
 
     // this lane's source of the A rows k = wave + 4 r and of the B blocks b = wave + 4 r
     const Z* ga = A + (m0 + lane) + (int64_t)wave * lda;
-    const Z* gb[BK / 4];
+    const Z* gb[BR];
     unsigned bok = 0;
 #pragma unroll
-    for (int r = 0; r < BK / 4; ++r) {
-        const int b = wave + 4 * r, kh = b >> 3, grp = b & 7;
+    for (int r = 0; r < BR; ++r) {
+        const int b = wave + 4 * r, kh = b / (BN / 8), grp = b % (BN / 8);
         const int n = 8 * grp + (lane >> 3), k = 8 * kh + ((lane & 7) ^ ((n >> 1) & 7));
         gb[r] = B + k + (n0 + n) * ldb;
         bok |= (unsigned)(n0 + n < g.N) << r;
     }
     const bool aok = m0 + lane < g.M;
-    // a wave whose 32 rows or 32 columns all lie outside C has no MFMA work
-    const bool active = !RAGGED || (m0 + wm * 32 < g.M && n0 + wn * 32 < g.N);
-    // this lane's MFMA operands: A element (k, wm 32 + 16 i + col), B element (k, wn 32 + 16 j + col)
+    // a wave whose 32 rows or 16 TN columns all lie outside C has no MFMA work
+    const bool active = !RAGGED || (m0 + wm * 32 < g.M && n0 + wn * 16 * TN < g.N);
+    // this lane's MFMA operands: A element (k, wm 32 + 16 i + col), B element (k, wn 16 TN + 16 j + col)
     const int col = lane & 15, krow = lane >> 4;
     const int aoff = krow * 64 + wm * 32 + col;
-    int boff[2];
+    int boff[TN];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int n = wn * 32 + j * 16 + col;
+    for (int j = 0; j < TN; ++j) {
+        const int n = wn * 16 * TN + j * 16 + col;
         boff[j] = (n >> 3) * 64 + (n & 7) * 8 + (krow ^ ((n >> 1) & 7));
     }
-    acc_t t1[2][2], t2[2][2], t3[2][2];
+    acc_t t1[2][TN], t2[2][TN], t3[2][TN];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < TN; ++j) {
             t1[i][j] = acc_t{0, 0, 0, 0};
             t2[i][j] = acc_t{0, 0, 0, 0};
             t3[i][j] = acc_t{0, 0, 0, 0};
         }
 
-    issue<RAGGED>(A0, B0, ga, gb, lda, kbeg, wave, aok, bok);
+    issue<RAGGED, BR>(A0, B0, ga, gb, lda, kbeg, wave, aok, bok);
     wait_loads();
     __syncthreads();
     // the range is a multiple of 2 BK: every trip multiplies both buffers; the scheduling
     // barriers keep the loads of the next stage ahead of the MFMAs and the wait behind them
     for (int64_t k0 = kbeg; k0 < K; k0 += 2 * BK) {
-        issue<RAGGED>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
+        issue<RAGGED, BR>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        if (active) multiply(A0, B0, aoff, boff, t1, t2, t3);
+        if (active) multiply<TN>(A0, B0, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
-        if (k0 + 2 * BK < K) issue<RAGGED>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
+        if (k0 + 2 * BK < K) issue<RAGGED, BR>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        if (active) multiply(A1, B1, aoff, boff, t1, t2, t3);
+        if (active) multiply<TN>(A1, B1, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
@@ -479,11 +485,11 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm * 32 + i * 16 + col;
-                const int64_t n = n0 + wn * 32 + j * 16 + Mfma<double>::acc_row(krow, r);
+                const int64_t n = n0 + wn * 16 * TN + j * 16 + Mfma<double>::acc_row(krow, r);
                 if (RAGGED && (m >= g.M || n >= g.N)) continue;
                 const double p1 = t1[i][j][r], p2 = t2[i][j][r];
                 Z out = g.alpha * Z(p1 - p2, t3[i][j][r] - p1 - p2);
@@ -643,6 +649,13 @@ __global__ __launch_bounds__(256) void lu_update_dma_kernel(GemmArgs<double> g) 
 __global__ __launch_bounds__(256) void gemm_dma_ragged_kernel(GemmArgs<double> g) { dma::tile_body<true>(g); }
 // split-K partial products (long reductions into few output tiles; any M and N)
 __global__ __launch_bounds__(256) void gemm_dma_split_kernel(GemmArgs<double> g) { dma::tile_body<true, true>(g); }
+// 64 x 32 tiles: the ragged last columns that FP64 products split off (N = 160 = 2 x 64 + 32)
+__global__ __launch_bounds__(256) void gemm_dma_n32_kernel(GemmArgs<double> g) {
+    dma::tile_body<false, false, 1>(g);
+}
+__global__ __launch_bounds__(256) void gemm_dma_n32_ragged_kernel(GemmArgs<double> g) {
+    dma::tile_body<true, false, 1>(g);
+}
 // FP32 takes the predicated form for every shape: with the per-wave MFMA branch the compiler keeps
 // the two unrolled stages apart and allocates 142 VGPRs (three waves per SIMD) instead of 180
 // (two); measured at 7680^2 x 512, 24 matrices: 33.5 against 34.9 ms
@@ -695,6 +708,15 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
                 hipLaunchKernelGGL(lu_update_dma_kernel, grid, dim3(256), 0, s, g);
             else
                 hipLaunchKernelGGL(gemm_dma_kernel, grid, dim3(256), 0, s, g);
+            return;
+        }
+    }
+    if constexpr (std::is_same<R, double>::value && TM == 2 && TN == 1 && !CONJA) {
+        if ((lu_update || m3) && nsplit == 1 && dma::fits(g.M, g.N, g.K)) {
+            if (g.M % 64 == 0 && g.N % 32 == 0)
+                hipLaunchKernelGGL(gemm_dma_n32_kernel, grid, dim3(256), 0, s, g);
+            else
+                hipLaunchKernelGGL(gemm_dma_n32_ragged_kernel, grid, dim3(256), 0, s, g);
             return;
         }
     }
@@ -810,7 +832,9 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
         const int64_t N0 = N - N % 64;
         gemm<R>(s, conjA, M, N0, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws, ws_elems, &c,
                 lu_update);
-        const GemmConfig c1{1, 1};
+        // the remaining columns on 64 x 32 direct-to-LDS tiles where the 3M product qualifies
+        const bool n32 = sizeof(R) == 8 && !conjA && K >= 64 && K % (2 * dma::BK) == 0;
+        const GemmConfig c1 = n32 ? GemmConfig{2, 1} : GemmConfig{1, 1};
         gemm<R>(s, conjA, M, N - N0, K, alpha, A, lda, sA, B + N0 * ldb, ldb, sB, beta, C + N0 * ldc, ldc, sC,
                 batch, ws, ws_elems, &c1, lu_update);
         return;
@@ -841,6 +865,7 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
         else       launch_tiles<R, TM_, TN_, BKX, false>(s, g, batch, nsplit, lu_update, m3); \
     } else
     NLF_GEMM_CASE(1, 1)
+    NLF_GEMM_CASE(2, 1)
     NLF_GEMM_CASE(2, 2)
     NLF_GEMM_CASE(4, 2)
     if constexpr (sizeof(R) == 4) {

@@ -102,12 +102,13 @@ def test_assemble_matches_oracle():
 @pytest.mark.parametrize("M,N,K,batch,odd_ld", [(2048, 1536, 80, 2, False), (1024, 2048, 512, 2, False),
                                                 (2048, 1536, 80, 2, True), (2000, 1530, 96, 2, False),
                                                 (2046, 1500, 64, 2, False), (2047, 1530, 96, 2, False),
-                                                (2048, 1536, 88, 2, False)])
+                                                (2048, 1536, 88, 2, False), (2048, 1568, 80, 2, False)])
 def test_gemm_direct_lds_tile_matches_definition(dtype, M, N, K, batch, odd_ld):
     # products with op(A) = A that fill the chip with 64 x 64 (complex128) or 128 x 64 (complex64)
     # tiles: the direct-to-LDS 3M forms, here on sub-matrices (leading dimensions above the row
     # counts) with general alpha and beta.  Full tiles; ragged rows and columns (predicated loads,
-    # idle waves, guarded stores; complex128 with at most 32 ragged columns splits them off); an
+    # idle waves, guarded stores; complex128 with at most 32 ragged columns splits them off onto
+    # 64 x 32 tiles, full for N = 1568 = 24 x 64 + 32, ragged for N = 1500); an
     # odd leading dimension or an odd row count (complex64 element pairs lose their 16-byte
     # alignment) and a reduction that is not a multiple of 16 take the staged form
     rng = np.random.default_rng(M + 3 * N + K + odd_ld)
@@ -445,3 +446,20 @@ def test_orthonormalize_keeps_span():
     ref, _ = np.linalg.qr(Q0)
     # same column space: the projector onto span(Q0) reproduces q
     assert np.max(np.abs(ref @ (ref.conj().T @ q) - q)) < 1e-11
+
+
+@pytest.mark.parametrize("M,N,K,batch", [(2048, 96, 256, 24), (1000, 70, 64, 8)])
+def test_gemm_forced_64x32_tile_matches_definition(M, N, K, batch):
+    # complex128 products on the 64 x 32 tile through the explicit-tile entry point: the
+    # direct-to-LDS form (full and ragged tiles) against the plain definition
+    rng = np.random.default_rng(M + N + K)
+    A = [wl.cn(rng, (M, K)) for _ in range(batch)]
+    B = [wl.cn(rng, (K, N)) for _ in range(batch)]
+    C = [wl.cn(rng, (M, N)) for _ in range(batch)]
+    alpha, beta = 0.5 + 0.5j, -1.0
+    Ad, Bd, Cd = batch_dev(A), batch_dev(B), batch_dev(C)
+    nl.nlf_gemm_batched_tile("N", M, N, K, alpha, Ad, M, M * K, Bd, K, K * N, beta, Cd, M, M * N, batch, 2, 1)
+    torch.cuda.synchronize()
+    for b in range(batch):
+        ref = alpha * (A[b] @ B[b]) + beta * C[b]
+        assert rel(nl.from_colmajor(Cd[b]), ref) < 1e-13 * np.sqrt(K)
