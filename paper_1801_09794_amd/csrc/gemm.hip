@@ -788,6 +788,14 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
         g.K = 0;
     }
     GemmConfig c = force ? *force : pick_config<R>(M, N, K, batch);
+    // FP64 3M products too small for 64 x 64 tiles take the 64 x 32 direct-to-LDS tile once it
+    // gives 256 workgroups (measured against 32 x 32 tiles: the triangular solves' diagonal
+    // blocks 256 x 160 x 256, 24 nodes, 55 -> 50 us; their chunk-internal updates 768 x 160 x 256
+    // 125 -> 105 us; X = Q Y, 8192 x 160 x 160, 47 -> 45 us; the block residual 8192 x 160 x 640
+    // 127 -> 116 us; below 256 workgroups, 256 x 64 x 256 with 16 nodes, 28 against 31 us)
+    if (!force && sizeof(R) == 8 && c.tm == 1 && c.tn == 1 && !conjA && K >= 64 && K % (2 * dma::BK) == 0 &&
+        ceil_div(M, 64) * ceil_div(N, 32) * batch >= 256)
+        c = GemmConfig{2, 1};
     // split-K for small outputs with long reductions (projections, Gram matrices)
     int nsplit = 1;
     const int64_t tiles = ceil_div(M, 32 * c.tm) * ceil_div(N, 32 * c.tn) * batch;
