@@ -18,6 +18,13 @@
 // LDS as [k][m] and [k][n] (interleaved complex, so one ds_read_b64/b128 gives re and im).
 // The next K step is fetched into registers while the current one is multiplied.
 // Optional split-K writes alpha-scaled partial products to a workspace; gemm_reduce sums them.
+//
+// 3M products with a reduction that is a multiple of 16 take the direct-to-LDS forms (namespace
+// dma below): the operand tiles go from global memory straight into LDS, with no staging
+// registers between the MFMA blocks.  FP64: 64 x 64 tiles (the LU trailing updates and the
+// triangular-solve updates), 64 x 32 tiles (32-column edges and small products), a split-K
+// variant (long reductions into few tiles); FP32: 128 x 64 tiles.  The staged program above
+// serves the conjugated products (Gram matrices, Q^H W) and shapes the direct forms do not take.
 #include "common.hpp"
 #include "kernels.hpp"
 
