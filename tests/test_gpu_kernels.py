@@ -463,3 +463,33 @@ def test_gemm_forced_64x32_tile_matches_definition(M, N, K, batch):
     for b in range(batch):
         ref = alpha * (A[b] @ B[b]) + beta * C[b]
         assert rel(nl.from_colmajor(Cd[b]), ref) < 1e-13 * np.sqrt(K)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_getrf_ragged_tiles_backward_error(dtype):
+    # n = 2000 = 31 x 64 + 16, 4 matrices: the trailing updates and U12 products have ragged
+    # 64 x 64 (complex128) and 128 x 64 (complex64) tiles, the predicated direct-to-LDS forms,
+    # from the first panel on; P A = L U to working accuracy and a valid permutation
+    n, batch = 2000, 4
+    rng = np.random.default_rng(2000)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    eps = 2.2e-16 if dtype == "c128" else 1.2e-7
+    mats = [wl.cn(rng, (n, n)) / np.sqrt(n) for _ in range(batch)]
+    if dtype == "c64":
+        mats = [M.astype(np.complex64).astype(complex) for M in mats]
+    A = batch_dev(mats, dt)
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    dinv = torch.empty(batch * nl.nlf_lu_inverse_elems(n), dtype=dt, device="cuda")
+    nl.nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv)
+    torch.cuda.synchronize()
+    assert info.cpu().numpy().tolist() == [0] * batch
+    for b in range(batch):
+        LU = nl.from_colmajor(A[b]).astype(complex)
+        L = np.tril(LU, -1) + np.eye(n)
+        U = np.triu(LU)
+        p = perm[b].cpu().numpy()
+        assert np.array_equal(np.sort(p), np.arange(n))
+        err = np.max(np.abs(mats[b][p] - L @ U)) / np.max(np.abs(mats[b]))
+        assert err < 30 * n * eps, err
