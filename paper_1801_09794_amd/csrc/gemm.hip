@@ -509,8 +509,12 @@ __device__ __forceinline__ void tile_body(const GemmArgs<double>& g) {
             }
 }
 // shapes the direct-to-LDS tile takes: any M and N (ragged edges through the predicated form), a
-// reduction that is a multiple of two stages (a partial stage would mix stale LDS into every output)
-inline bool fits(int64_t M, int64_t N, int64_t K) { return M > 0 && N > 0 && K > 0 && K % (2 * BK) == 0; }
+// reduction that is a multiple of two stages (a partial stage would mix stale LDS into every output),
+// 16-byte aligned operands (one load lane moves one whole complex128)
+inline bool fits(const GemmArgs<double>& g) {
+    return g.M > 0 && g.N > 0 && g.K > 0 && g.K % (2 * BK) == 0 && reinterpret_cast<uintptr_t>(g.A) % 16 == 0 &&
+           reinterpret_cast<uintptr_t>(g.B) % 16 == 0;
+}
 inline bool full_tiles(int64_t M, int64_t N) { return M % 64 == 0 && N % 64 == 0; }
 
 // The FP32 counterpart: the 128 x 64 tile of gemm_tile_body<float, 4, 2, 8> (wave tile 64 x 32)
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, 
 // Whether the direct-to-LDS tiles take a product of this shape whole (ragged edges included):
 // 3M products with op(A) = A on the 64 x 64 (FP64) or 128 x 64 (FP32) tile, no split-K.
 static bool dma_takes(const GemmArgs<double>& g, const GemmConfig& c, bool conjA, bool lu_update) {
-    return !conjA && (lu_update || g.K >= 64) && c.tm == 2 && c.tn == 2 && dma::fits(g.M, g.N, g.K);
+    return !conjA && (lu_update || g.K >= 64) && c.tm == 2 && c.tn == 2 && dma::fits(g);
 }
 static bool dma_takes(const GemmArgs<float>& g, const GemmConfig& c, bool conjA, bool lu_update) {
     return !conjA && (lu_update || g.K >= 64) && c.tm == 4 && c.tn == 2 && dma::fits32(g);
@@ -708,7 +712,7 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
     g.tilesN = (int)ceil_div(g.N, BN);
     dim3 grid(g.tilesM * g.tilesN, batch, nsplit);
     if constexpr (std::is_same<R, double>::value && TM == 2 && TN == 2 && !CONJA) {
-        if ((lu_update || m3) && nsplit == 1 && dma::fits(g.M, g.N, g.K)) {
+        if ((lu_update || m3) && nsplit == 1 && dma::fits(g)) {
             if (!dma::full_tiles(g.M, g.N))
                 hipLaunchKernelGGL(gemm_dma_ragged_kernel, grid, dim3(256), 0, s, g);
             else if (lu_update)
@@ -719,7 +723,7 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
         }
     }
     if constexpr (std::is_same<R, double>::value && TM == 2 && TN == 1 && !CONJA) {
-        if ((lu_update || m3) && nsplit == 1 && dma::fits(g.M, g.N, g.K)) {
+        if ((lu_update || m3) && nsplit == 1 && dma::fits(g)) {
             if (g.M % 64 == 0 && g.N % 32 == 0)
                 hipLaunchKernelGGL(gemm_dma_n32_kernel, grid, dim3(256), 0, s, g);
             else
@@ -813,7 +817,7 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // 64 x 64 tiles with 4 splits, 1536 workgroups)
     if constexpr (sizeof(R) == 8) {
         const int64_t t64 = ceil_div(M, 64) * ceil_div(N, 64) * batch;
-        if (!force && ws && !conjA && !lu_update && K >= 2048 && K % (2 * dma::BK) == 0 && t64 < 768) {
+        if (!force && ws && !conjA && !lu_update && K >= 2048 && t64 < 768 && dma::fits(g)) {
             int want = (int)std::min<int64_t>(ceil_div(1536, t64), K / 1024);
             while (want > 1 && (int64_t)want * M * N * batch > ws_elems) --want;
             if (want >= 2 && t64 * want >= 768) {
