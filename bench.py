@@ -63,6 +63,9 @@ def parse():
                     help="blocked LU look-ahead: 1 on, -1 off, 0 library default")
     ap.add_argument("--lu-streams", type=int, default=0,
                     help="node-matrix groups factored on separate streams (0 = library default)")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="run only the FP32 LU + FP64 refinement leg of --workload (for kernel traces of "
+                         "the precision form) and print its result")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched qep2048x8 leg (for kernel traces of it) and print its result")
     ap.add_argument("--probe-lu", action="store_true",
@@ -224,6 +227,7 @@ def leg_stats(args, name, key, n, nz, regions, cfg, t, o, p):
             "trailing_gemm_tflops": gt, "trailing_gemm_frac_peak": gt / peak if gt else None,
             # the trailing updates take 3M products in both precisions: 3/4 of the counted flops
             "trailing_gemm_executed_frac_peak": 0.75 * gt / peak if gt else None,
+            "trailing_gemm_avg_launch_us": g["ms"] * 1e3 / g["launches"] if g["launches"] else None,
             "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
             "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()},
             "hbm_kernels": hbm_kernels(p)}
@@ -477,6 +481,13 @@ def main():
     cfg, terms, mats, regions, X0 = load_workload(name)
     n = cfg["n"]
     nnodes = sum(r["nc"] for r in regions)
+    if args.fp32_only:
+        t32, out32, prof32 = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP32_REFINE, True,
+                                     graph=args.graph)
+        st = leg_stats(args, name, "fp32_refine", n, nnodes, regions, cfg, t32, out32, prof32)
+        print(json.dumps({"leg": "fp32_refine", "workload": name, "steps": args.steps, "warmup": args.warmup,
+                          "result": st}))
+        return
 
     t64, out64, prof = run_gpu(args, cfg, terms, mats, regions, X0, nl.NLF_PREC_FP64, True, graph=args.graph)
     conv64 = converged_pairs(out64, cfg["tol"])
