@@ -354,7 +354,7 @@ nlfeast_status nlf_gemm_batched(int32_t dtype, char opA, char opB, int64_t M, in
                                 int32_t batch, void* stream);
 
 /* nlf_gemm_batched with an explicit workgroup tile of (32 tm) x (32 tn) complex elements,
- * (tm, tn) in {(1, 1), (2, 1), (2, 2), (4, 2)}, and (4, 4) for c64.  Used by the GEMM autotuner; returns NLF_ERR_ARG
+ * (tm, tn) in {(1, 1), (2, 1), (2, 2), (4, 2)}, and (4, 1), (4, 4) for c64.  Used by the GEMM autotuner; returns NLF_ERR_ARG
  * for a tile that is not compiled. */
 nlfeast_status nlf_gemm_batched_tile(int32_t dtype, char opA, int64_t M, int64_t N, int64_t K,
                                      const double* alpha, const void* A_dev, int64_t lda,

@@ -531,7 +531,9 @@ using Y = Cx<float>;
 constexpr int APAD32 = 16;
 using acc32_t = Mfma<float>::acc_t;
 
-template <bool RAGGED>
+// TN: 16-column MFMA blocks per wave (tile 128 x 32 TN); the B tile has 2 TN blocks of 16 columns,
+// loaded by waves 0 .. 2 TN - 1
+template <bool RAGGED, int TN = 2>
 __device__ __forceinline__ void issue32(Y* As, Y* Bs, const Y* const* ga, const Y* gb, int64_t lda, int64_t k0,
                                         int wave, bool aok, bool bok) {
 #pragma unroll
@@ -539,45 +541,48 @@ __device__ __forceinline__ void issue32(Y* As, Y* Bs, const Y* const* ga, const 
         if (!RAGGED || aok)
             __builtin_amdgcn_global_load_lds(NLF_GPTR(ga[r] + k0 * lda),
                                              NLF_LPTR(As + (wave + 4 * r) * (128 + APAD32)), 16, 0, 0);
-    if (!RAGGED || bok) __builtin_amdgcn_global_load_lds(NLF_GPTR(gb + k0), NLF_LPTR(Bs + wave * 128), 16, 0, 0);
+    if ((TN == 2 || wave < 2 * TN) && (!RAGGED || bok))
+        __builtin_amdgcn_global_load_lds(NLF_GPTR(gb + k0), NLF_LPTR(Bs + wave * 128), 16, 0, 0);
 }
 
+template <int TN>
 __device__ __forceinline__ void multiply32(const Y* As, const Y* Bs, int aoff, const int* boff,
-                                           acc32_t (&t1)[4][2], acc32_t (&t2)[4][2], acc32_t (&t3)[4][2]) {
+                                           acc32_t (&t1)[4][TN], acc32_t (&t2)[4][TN], acc32_t (&t3)[4][TN]) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-        Y a[4], b[2];
-        float as[4], bs[2];
+        Y a[4], b[TN];
+        float as[4], bs[TN];
 #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = As[kk * (128 + APAD32) + aoff + i * 16];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[boff[j] ^ kk];
+        for (int j = 0; j < TN; ++j) b[j] = Bs[boff[j] ^ kk];
 #pragma unroll
         for (int i = 0; i < 4; ++i) as[i] = a[i].re + a[i].im;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bs[j] = b[j].re + b[j].im;
+        for (int j = 0; j < TN; ++j) bs[j] = b[j].re + b[j].im;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t1[i][j] = Mfma<float>::mma(b[j].re, a[i].re, t1[i][j]);
+            for (int j = 0; j < TN; ++j) t1[i][j] = Mfma<float>::mma(b[j].re, a[i].re, t1[i][j]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t2[i][j] = Mfma<float>::mma(b[j].im, a[i].im, t2[i][j]);
+            for (int j = 0; j < TN; ++j) t2[i][j] = Mfma<float>::mma(b[j].im, a[i].im, t2[i][j]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) t3[i][j] = Mfma<float>::mma(bs[j], as[i], t3[i][j]);
+            for (int j = 0; j < TN; ++j) t3[i][j] = Mfma<float>::mma(bs[j], as[i], t3[i][j]);
     }
 }
 
-template <bool RAGGED>
+template <bool RAGGED, int TN = 2>
 __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
-    __shared__ Y A0[BK * (128 + APAD32)], A1[BK * (128 + APAD32)], B0[BK * 64], B1[BK * 64];
+    constexpr int BN = 32 * TN;
+    __shared__ Y A0[BK * (128 + APAD32)], A1[BK * (128 + APAD32)], B0[BK * BN], B1[BK * BN];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave & 1, wn = wave >> 1;
     int tm, tn;
     tile_coords(xcd_remap(blockIdx.x, g.tilesM * g.tilesN), g.tilesM, g.tilesN, tm, tn);
-    const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 128, n0 = (int64_t)tn * 64;
+    const int64_t batch = blockIdx.y, m0 = (int64_t)tm * 128, n0 = (int64_t)tn * BN;
     const Y* A = g.A + batch * g.sA;
     const Y* B = g.B + batch * g.sB;
     const int64_t K = g.K, lda = g.lda, ldb = g.ldb;
@@ -590,37 +595,37 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
     const Y* gb = B + 2 * ((lane & 3) ^ ((nq >> 2) & 3)) + (n0 + nq) * ldb;
     // M is even on this path, so a lane's row pair is either inside or outside the matrix
     const bool aok = m0 + 2 * lane < g.M, bok = n0 + nq < g.N;
-    const bool active = !RAGGED || (m0 + wm * 64 < g.M && n0 + wn * 32 < g.N);
-    // this lane's MFMA operands: A element (k, wm 64 + 16 i + col), B element (k, wn 32 + 16 j + col)
+    const bool active = !RAGGED || (m0 + wm * 64 < g.M && n0 + wn * 16 * TN < g.N);
+    // this lane's MFMA operands: A element (k, wm 64 + 16 i + col), B element (k, wn 16 TN + 16 j + col)
     const int col = lane & 15, krow = lane >> 4;
     const int aoff = krow * (128 + APAD32) + wm * 64 + col;
-    int boff[2];
+    int boff[TN];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-        boff[j] = (wn * 2 + j) * 128 + col * 8 + 2 * ((krow >> 1) ^ ((col >> 2) & 3)) + (krow & 1);
-    acc32_t t1[4][2], t2[4][2], t3[4][2];
+    for (int j = 0; j < TN; ++j)
+        boff[j] = (wn * TN + j) * 128 + col * 8 + 2 * ((krow >> 1) ^ ((col >> 2) & 3)) + (krow & 1);
+    acc32_t t1[4][TN], t2[4][TN], t3[4][TN];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < TN; ++j) {
             t1[i][j] = acc32_t{0, 0, 0, 0};
             t2[i][j] = acc32_t{0, 0, 0, 0};
             t3[i][j] = acc32_t{0, 0, 0, 0};
         }
 
-    issue32<RAGGED>(A0, B0, ga, gb, lda, 0, wave, aok, bok);
+    issue32<RAGGED, TN>(A0, B0, ga, gb, lda, 0, wave, aok, bok);
     wait_loads();
     __syncthreads();
     for (int64_t k0 = 0; k0 < K; k0 += 2 * BK) {
-        issue32<RAGGED>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
+        issue32<RAGGED, TN>(A1, B1, ga, gb, lda, k0 + BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        if (active) multiply32(A0, B0, aoff, boff, t1, t2, t3);
+        if (active) multiply32<TN>(A0, B0, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
-        if (k0 + 2 * BK < K) issue32<RAGGED>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
+        if (k0 + 2 * BK < K) issue32<RAGGED, TN>(A0, B0, ga, gb, lda, k0 + 2 * BK, wave, aok, bok);
         __builtin_amdgcn_sched_barrier(0);
-        if (active) multiply32(A1, B1, aoff, boff, t1, t2, t3);
+        if (active) multiply32<TN>(A1, B1, aoff, boff, t1, t2, t3);
         __builtin_amdgcn_sched_barrier(0);
         wait_loads();
         __syncthreads();
@@ -631,11 +636,11 @@ __device__ __forceinline__ void tile_body32(const GemmArgs<float>& g) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t m = m0 + wm * 64 + i * 16 + col;
-                const int64_t n = n0 + wn * 32 + j * 16 + Mfma<float>::acc_row(krow, r);
+                const int64_t n = n0 + wn * 16 * TN + j * 16 + Mfma<float>::acc_row(krow, r);
                 if (RAGGED && (m >= g.M || n >= g.N)) continue;
                 const float p1 = t1[i][j][r], p2 = t2[i][j][r];
                 Y out = g.alpha * Y(p1 - p2, t3[i][j][r] - p1 - p2);
@@ -672,6 +677,8 @@ __global__ __launch_bounds__(256) void gemm_dma_n32_ragged_kernel(GemmArgs<doubl
 // (two); measured at 7680^2 x 512, 24 matrices: 33.5 against 34.9 ms
 __global__ __launch_bounds__(256) void gemm_dma32_kernel(GemmArgs<float> g) { dma::tile_body32<true>(g); }
 __global__ __launch_bounds__(256) void lu_update_dma32_kernel(GemmArgs<float> g) { dma::tile_body32<true>(g); }
+// 128 x 32 tiles: the 32-column edges split off complex64 products
+__global__ __launch_bounds__(256) void gemm_dma32_n32_kernel(GemmArgs<float> g) { dma::tile_body32<true, 1>(g); }
 
 // C = sum_s P_s + beta C over the split-K partials.
 template <typename R>
@@ -694,15 +701,6 @@ __global__ __launch_bounds__(256) void gemm_reduce_kernel(int64_t M, int64_t N, 
 }
 
 // ---------------------------------------------------------------------------- host side
-
-// Whether the direct-to-LDS tiles take a product of this shape whole (ragged edges included):
-// 3M products with op(A) = A on the 64 x 64 (FP64) or 128 x 64 (FP32) tile, no split-K.
-static bool dma_takes(const GemmArgs<double>& g, const GemmConfig& c, bool conjA, bool lu_update) {
-    return !conjA && (lu_update || g.K >= 64) && c.tm == 2 && c.tn == 2 && dma::fits(g);
-}
-static bool dma_takes(const GemmArgs<float>& g, const GemmConfig& c, bool conjA, bool lu_update) {
-    return !conjA && (lu_update || g.K >= 64) && c.tm == 4 && c.tn == 2 && dma::fits32(g);
-}
 
 // m3: the 3M products (see gemm_tile_body).
 template <typename R, int TM, int TN, int BK, bool CONJA>
@@ -728,6 +726,12 @@ static void launch_tiles(hipStream_t s, GemmArgs<R>& g, int batch, int nsplit, b
                 hipLaunchKernelGGL(gemm_dma_n32_kernel, grid, dim3(256), 0, s, g);
             else
                 hipLaunchKernelGGL(gemm_dma_n32_ragged_kernel, grid, dim3(256), 0, s, g);
+            return;
+        }
+    }
+    if constexpr (std::is_same<R, float>::value && TM == 4 && TN == 1 && !CONJA) {
+        if ((lu_update || m3) && nsplit == 1 && dma::fits32(g)) {
+            hipLaunchKernelGGL(gemm_dma32_n32_kernel, grid, dim3(256), 0, s, g);
             return;
         }
     }
@@ -842,18 +846,19 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     // + 32: a sixth of the tile's MFMA work wasted) goes to a second launch of 32 x 32 tiles.
     // Measured on the right-looking updates of the block triangular solves (n = 8192, 160
     // right-hand sides, 24 nodes, K = 256): 64 x 64 tiles 61 TFLOP/s, 32 x 32 tiles 62
-    // Not for the complex64 products the direct-to-LDS tile takes whole: there the tile column
-    // holding the ragged edge skips its idle waves' MFMAs, as fast or faster (7680 x 160 x 1024, 24
-    // nodes: 1.67 against 1.68 ms; 3584 rows: 0.83 against 0.87). In FP64 the split stays ahead
-    // (3.14 against 3.20 ms; 1920 x 80 x 256, 128 nodes: 0.66 against 0.77)
+    // With the edge on 64 x 32 (FP64) or 128 x 32 (FP32) direct-to-LDS tiles the split also beats
+    // one launch whose last tile column idles half its waves: FP64 3.14 against 3.20 ms, and
+    // 1920 x 80 x 256 with 128 nodes 0.66 against 0.77; complex64 7168 x 160 x 1024 with 24 nodes
+    // 1.63 against 1.75 ms, 1920 x 80 x 256 with 128 nodes 0.39 against 0.44
     if (!force && !lu_update && c.tn == 2 && N > 64 && N % 64 != 0 && N % 64 <= 32 &&
-        !(ws && tiles < 256 && K >= 512) && !(sizeof(R) == 4 && dma_takes(g, c, conjA, lu_update))) {
+        !(ws && tiles < 256 && K >= 512)) {
         const int64_t N0 = N - N % 64;
         gemm<R>(s, conjA, M, N0, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, batch, ws, ws_elems, &c,
                 lu_update);
-        // the remaining columns on 64 x 32 direct-to-LDS tiles where the 3M product qualifies
-        const bool n32 = sizeof(R) == 8 && !conjA && K >= 64 && K % (2 * dma::BK) == 0;
-        const GemmConfig c1 = n32 ? GemmConfig{2, 1} : GemmConfig{1, 1};
+        // the remaining columns on 64 x 32 (FP64) or 128 x 32 (FP32) direct-to-LDS tiles where the 3M
+        // product qualifies
+        const bool dq = !conjA && K >= 64 && K % (2 * dma::BK) == 0;
+        const GemmConfig c1 = dq ? (sizeof(R) == 8 ? GemmConfig{2, 1} : GemmConfig{4, 1}) : GemmConfig{1, 1};
         gemm<R>(s, conjA, M, N - N0, K, alpha, A, lda, sA, B + N0 * ldb, ldb, sB, beta, C + N0 * ldc, ldc, sC,
                 batch, ws, ws_elems, &c1, lu_update);
         return;
@@ -888,6 +893,7 @@ void gemm(hipStream_t s, bool conjA, int64_t M, int64_t N, int64_t K, Cx<R> alph
     NLF_GEMM_CASE(2, 2)
     NLF_GEMM_CASE(4, 2)
     if constexpr (sizeof(R) == 4) {
+        NLF_GEMM_CASE(4, 1)
         NLF_GEMM_CASE(4, 4)
         { throw Error{1, "gemm: unsupported tile config"}; }
     } else {

@@ -1722,7 +1722,7 @@ nlfeast_status nlf_gemm_batched_tile(int32_t dtype, char opA, int64_t M, int64_t
                         (dtype == NLF_C64 || dtype == NLF_C128),
                     NLF_ERR_ARG, "nlf_gemm_batched_tile: bad arguments");
         const bool ok = (tm == 1 && tn == 1) || (tm == 2 && tn == 1) || (tm == 2 && tn == 2) || (tm == 4 && tn == 2) ||
-                        (tm == 4 && tn == 4 && dtype == NLF_C64);
+                        (tm == 4 && tn == 4 && dtype == NLF_C64) || (tm == 4 && tn == 1 && dtype == NLF_C64);
         NLF_REQUIRE(ok, NLF_ERR_ARG, "nlf_gemm_batched_tile: tile not compiled");
         GemmConfig c;
         c.tm = tm;

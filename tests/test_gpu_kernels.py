@@ -448,21 +448,28 @@ def test_orthonormalize_keeps_span():
     assert np.max(np.abs(ref @ (ref.conj().T @ q) - q)) < 1e-11
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("M,N,K,batch", [(2048, 96, 256, 24), (1000, 70, 64, 8)])
-def test_gemm_forced_64x32_tile_matches_definition(M, N, K, batch):
-    # complex128 products on the 64 x 32 tile through the explicit-tile entry point: the
-    # direct-to-LDS form (full and ragged tiles) against the plain definition
+def test_gemm_forced_32_column_tile_matches_definition(dtype, M, N, K, batch):
+    # products on the 32-column tiles through the explicit-tile entry point (64 x 32 for
+    # complex128, 128 x 32 for complex64): the direct-to-LDS forms, full and ragged, against the
+    # plain definition
     rng = np.random.default_rng(M + N + K)
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    tol = 1e-13 if dtype == "c128" else 2e-5
     A = [wl.cn(rng, (M, K)) for _ in range(batch)]
     B = [wl.cn(rng, (K, N)) for _ in range(batch)]
     C = [wl.cn(rng, (M, N)) for _ in range(batch)]
+    if dtype == "c64":
+        A, B, C = ([X.astype(np.complex64).astype(complex) for X in Y] for Y in (A, B, C))
     alpha, beta = 0.5 + 0.5j, -1.0
-    Ad, Bd, Cd = batch_dev(A), batch_dev(B), batch_dev(C)
-    nl.nlf_gemm_batched_tile("N", M, N, K, alpha, Ad, M, M * K, Bd, K, K * N, beta, Cd, M, M * N, batch, 2, 1)
+    Ad, Bd, Cd = batch_dev(A, dt), batch_dev(B, dt), batch_dev(C, dt)
+    tm, tn = (2, 1) if dtype == "c128" else (4, 1)
+    nl.nlf_gemm_batched_tile("N", M, N, K, alpha, Ad, M, M * K, Bd, K, K * N, beta, Cd, M, M * N, batch, tm, tn)
     torch.cuda.synchronize()
     for b in range(batch):
         ref = alpha * (A[b] @ B[b]) + beta * C[b]
-        assert rel(nl.from_colmajor(Cd[b]), ref) < 1e-13 * np.sqrt(K)
+        assert rel(nl.from_colmajor(Cd[b]).astype(complex), ref) < tol * np.sqrt(K)
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
