@@ -1202,13 +1202,9 @@ static ReducedResult contour_finish(int m, const std::vector<Term>& terms, const
         for (int pass = 0; pass < 2; ++pass)
             for (int c = 0; c < nb; ++c) {
                 const cplx* u = &B[(size_t)c * m];
-                cplx d = 0.0;
-                for (int i = 0; i < m; ++i) d += std::conj(u[i]) * x[i];
-                for (int i = 0; i < m; ++i) x[i] -= u[i] * d;
+                caxpy(m, -cdotc(m, u, x.data()), u, x.data());
             }
-        double nn = 0.0;
-        for (int i = 0; i < m; ++i) nn += std::norm(x[i]);
-        return std::sqrt(nn);
+        return std::sqrt(csumsq(m, x.data()));
     };
     // (the basis only serves the completion: with m_keep vectors found there is nothing to add)
     for (int c = 0; c < kf && kf < m_keep; ++c) {
