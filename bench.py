@@ -189,14 +189,31 @@ def run_gpu(args, cfg, terms, mats, regions, X0, precision, profile, autotune=0,
     return (t1 - t0) / args.steps, out, prof
 
 
-def reference_error(name, regions, out, tol):
-    """Largest relative error of the converged eigenvalues of each region against the stored
-    brute-force reference (tests/golden/contours.json), min-cost matched; None when a region's
-    converged count differs from the reference count."""
+def matched_rel_errors(lam, ref, scale):
+    """Relative differences |lam - ref| / max(|ref|, scale) of two equally long eigenvalue sets,
+    paired by minimum-cost assignment; the pairs are returned in order of the reference values
+    (real part, then imaginary part)."""
     import numpy as np
     from scipy.optimize import linear_sum_assignment
+    cost = np.abs(lam[:, None] - ref[None, :]) / np.maximum(np.abs(ref)[None, :], scale)
+    i, j = linear_sum_assignment(cost)
+    order = np.lexsort((ref[j].imag, ref[j].real))
+    return ref[j][order], cost[i, j][order]
+
+
+def per_eigenpair(ref, err):
+    """[[Re, Im, relative error], ...] with 2 significant digits in the error."""
+    return [[round(float(v.real), 6), round(float(v.imag), 6), float("%.2g" % e)] for v, e in zip(ref, err)]
+
+
+def reference_errors(name, regions, out, tol):
+    """Relative errors of the converged eigenvalues of each region against the stored brute-force
+    reference (tests/golden/contours.json, written by the FP64 oracle), min-cost matched, one
+    entry per reference eigenvalue; None when a region's converged count differs from the
+    reference count."""
+    import numpy as np
     gs = json.load(open(os.path.join(ROOT, "tests", "golden", "contours.json")))[name]["regions"]
-    col, worst = 0, 0.0
+    col, rows = 0, []
     for r, g in zip(regions, gs):
         sl = slice(col, col + r["m0"])
         conv = out["inside"][sl] & (out["res"][sl] <= tol)
@@ -205,11 +222,15 @@ def reference_error(name, regions, out, tol):
         if len(lam) != len(ref):
             return None
         if len(ref):
-            cost = np.abs(lam[:, None] - ref[None, :]) / np.maximum(np.abs(ref)[None, :], g["radius"])
-            i, j = linear_sum_assignment(cost)
-            worst = max(worst, float(cost[i, j].max()))
+            rows += per_eigenpair(*matched_rel_errors(lam, ref, g["radius"]))
         col += r["m0"]
-    return worst
+    return rows
+
+
+def reference_error(name, regions, out, tol):
+    """Largest of reference_errors (0 when no region holds an eigenvalue)."""
+    rows = reference_errors(name, regions, out, tol)
+    return None if rows is None else max([e for _, _, e in rows], default=0.0)
 
 
 def leg_stats(args, name, key, n, nz, regions, cfg, t, o, p):
@@ -229,6 +250,8 @@ def leg_stats(args, name, key, n, nz, regions, cfg, t, o, p):
             "trailing_gemm_executed_frac_peak": 0.75 * gt / peak if gt else None,
             "trailing_gemm_avg_launch_us": g["ms"] * 1e3 / g["launches"] if g["launches"] else None,
             "max_rel_err_vs_reference": reference_error(name, regions, o, cfg["tol"]),
+            **({"rel_err_vs_reference_per_eigenpair": reference_errors(name, regions, o, cfg["tol"])}
+               if key == "fp32_refine" else {}),
             "profile_ms_per_step": {k: v["ms"] / args.steps for k, v in p.items()},
             "hbm_kernels": hbm_kernels(p)}
 
@@ -244,10 +267,16 @@ def extra_leg(args, name, description, autotune, graph, plain_fp64=False, reduce
     n, nz = cfg["n"], sum(r["nc"] for r in regions)
     out = {"workload": description % dict(n=n, m0=[r["m0"] for r in regions], nc=cfg["nc"], nz=nz,
                                           tol=cfg["tol"], inside=cfg.get("inside") or 0)}
+    outs = {}
     for key, prec in (("fp64", nl.NLF_PREC_FP64), ("fp32_refine", nl.NLF_PREC_FP32_REFINE)):
         t, o, p = run_gpu(args, cfg, terms, mats, regions, X0, prec, True, autotune=autotune, graph=graph,
                           reduced_solver=reduced_solver)
         out[key] = leg_stats(args, name, key, n, nz, regions, cfg, t, o, p)
+        outs[key] = o
+    out["fp32_refine"]["max_rel_eig_diff_vs_fp64"] = eig_diff(outs["fp32_refine"], outs["fp64"], cfg["tol"],
+                                                              min(r["a"] for r in regions))
+    out["fp32_refine"]["rel_eig_diff_vs_fp64_per_eigenpair"] = eig_diffs(
+        outs["fp32_refine"], outs["fp64"], cfg["tol"], min(r["a"] for r in regions))
     out["fp32_refine_speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["fp32_refine"]["ms_per_step"]
     out["fp32_refine_vs_fp64_eigenpairs_per_s"] = out["fp32_refine"]["value"] / out["fp64"]["value"]
     if plain_fp64:
@@ -363,18 +392,21 @@ def hbm_kernels(prof):
     return out
 
 
-def eig_diff(a, b, tol, scale):
-    """Largest relative difference between the converged eigenvalues of two solves, matched by
-    minimum-cost assignment (None when the converged counts differ)."""
-    import numpy as np
-    from scipy.optimize import linear_sum_assignment
+def eig_diffs(a, b, tol, scale):
+    """Relative differences between the converged eigenvalues of two solves, matched by
+    minimum-cost assignment, one entry per eigenvalue of b (None when the converged counts differ
+    or nothing converged)."""
     ca, cb = a["inside"] & (a["res"] <= tol), b["inside"] & (b["res"] <= tol)
     la, lb = a["lam"][ca], b["lam"][cb]
     if len(la) != len(lb) or len(la) == 0:
         return None
-    cost = np.abs(la[:, None] - lb[None, :]) / np.maximum(np.abs(lb)[None, :], scale)
-    r, c = linear_sum_assignment(cost)
-    return float(cost[r, c].max())
+    return per_eigenpair(*matched_rel_errors(la, lb, scale))
+
+
+def eig_diff(a, b, tol, scale):
+    """Largest of eig_diffs."""
+    rows = eig_diffs(a, b, tol, scale)
+    return None if rows is None else max(e for _, _, e in rows)
 
 
 def converged_pairs(out, tol):
@@ -562,6 +594,7 @@ def main():
         st = leg_stats(args, name, "fp32_refine", n, nnodes, regions, cfg, t32, out32, prof32)
         st["speedup_vs_fp64"] = t64 / t32
         st["max_rel_eig_diff_vs_fp64"] = eig_diff(out32, out64, cfg["tol"], regions[0]["a"])
+        st["rel_eig_diff_vs_fp64_per_eigenpair"] = eig_diffs(out32, out64, cfg["tol"], regions[0]["a"])
         result["fp32_refine"] = st
     if not args.headline_only and not args.no_cpu:
         est, cores, d = cpu_baseline(cfg, terms, mats, regions, X0, int(out64["iters"][0]))
