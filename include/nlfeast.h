@@ -228,7 +228,9 @@ typedef enum {
     NLF_K_AUTOTUNE = 13,         /* trial factorisations of the LU tuner (first use of a shape) */
     NLF_K_LU_REC_GEMM = 14,      /* GEMM updates inside the recursive panel factorisation
                                     (NLF_K_LU_GEMM: the rank-512 trailing updates of the blocked
-                                    LU, kernel symbol lu_update_kernel) */
+                                    LU, kernel symbols lu_update_dma_kernel and
+                                    lu_update_dma32_kernel, or lu_update_kernel where the
+                                    direct-to-LDS form does not apply) */
     NLF_K_REDUCED = 15,          /* device part of the contour-integral reduced solve: the reduced
                                     matrices at the enlarged contour's points, their batched LU
                                     and inverses, and the moment sums */
