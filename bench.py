@@ -73,13 +73,16 @@ def parse():
                          "batched blocked LU of the headline shape, nothing else")
     ap.add_argument("--probe-n", type=int, default=8192)
     ap.add_argument("--probe-batch", type=int, default=24)
+    ap.add_argument("--probe-c64", action="store_true",
+                    help="with --probe-lu: complex64 matrices (the FP32 + refinement factorisation)")
     return ap.parse_args()
 
 
-def probe_lu(n, bt):
+def probe_lu(n, bt, c64=False):
     """Counter runs: a plain device copy of known size (to scale the HBM counters), then one
     batched blocked LU of n x n complex128 matrices (the headline: 24 of n = 8192), whose
-    trailing-update launches are the dominant kernel's."""
+    trailing-update launches are the dominant kernel's; complex64 with c64 (the factorisation
+    of the FP32 + refinement form)."""
     import torch
     import paper_1801_09794_amd as nl
     torch.cuda.set_device(0)
@@ -89,14 +92,16 @@ def probe_lu(n, bt):
     torch.cuda.synchronize()
     del a, b
     g = torch.Generator(device="cuda").manual_seed(7)
-    A = torch.randn((bt, n, n), dtype=torch.complex128, device="cuda", generator=g)
+    dt = torch.complex64 if c64 else torch.complex128
+    A = torch.randn((bt, n, n), dtype=dt, device="cuda", generator=g)
     ipiv = torch.empty((bt, n), dtype=torch.int32, device="cuda")
     perm = torch.empty_like(ipiv)
     info = torch.empty(bt, dtype=torch.int32, device="cuda")
-    dinv = torch.empty(bt * nl.nlf_lu_inverse_elems(n), dtype=torch.complex128, device="cuda")
+    dinv = torch.empty(bt * nl.nlf_lu_inverse_elems(n), dtype=dt, device="cuda")
     nl.nlf_getrf_batched_blocked(A, ipiv, perm, info, dinv)
     torch.cuda.synchronize()
-    print(json.dumps(dict(probe="blocked LU c128", copy_bytes=2 * (1 << 27) * 8, n=n, batch=bt)))
+    print(json.dumps(dict(probe="blocked LU " + ("c64" if c64 else "c128"), copy_bytes=2 * (1 << 27) * 8,
+                          n=n, batch=bt)))
 
 
 def source_digest():
@@ -492,7 +497,7 @@ def batched_leg(args):
 def main():
     args = parse()
     if args.probe_lu:
-        probe_lu(args.probe_n, args.probe_batch)
+        probe_lu(args.probe_n, args.probe_batch, args.probe_c64)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
