@@ -500,3 +500,56 @@ def test_getrf_ragged_tiles_backward_error(dtype):
         assert np.array_equal(np.sort(p), np.arange(n))
         err = np.max(np.abs(mats[b][p] - L @ U)) / np.max(np.abs(mats[b]))
         assert err < 30 * n * eps, err
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_getrf_headline_shape_sampled_rows(dtype):
+    # the benchmarked factorisation shape and launch sequence: 24 matrices of n = 8192 (the
+    # headline's node count and order), factored by the blocked LU.  A property that holds at any
+    # size, checked on sampled rows: row i of L U equals row perm[i] of A to working accuracy;
+    # perm is a permutation and |l_ij| <= sqrt(2) (partial pivoting on |Re| + |Im|, which bounds
+    # the modulus of a multiplier by sqrt(2)).  A is regenerated from its seed
+    # rather than kept, so only the factors occupy the device.
+    n, batch = 8192, 24
+    dt = torch.complex128 if dtype == "c128" else torch.complex64
+    eps = 2.2e-16 if dtype == "c128" else 1.2e-7
+
+    def gen():
+        g = torch.Generator(device="cuda").manual_seed(8192)
+        return torch.randn((batch, n, n), dtype=dt, device="cuda", generator=g)
+
+    F = gen()            # (batch, n, n) storage read as column-major: matrix b is F[b].T
+    ipiv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    perm = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    dinv = torch.empty(batch * nl.nlf_lu_inverse_elems(n), dtype=dt, device="cuda")
+    nl.nlf_getrf_batched_blocked(F, ipiv, perm, info, dinv)
+    torch.cuda.synchronize()
+    del dinv
+    assert info.cpu().numpy().tolist() == [0] * batch
+    rng = np.random.default_rng(24)
+    rows = np.unique(np.concatenate([[0, 1, 511, 512, 4095, 7679, 7680, n - 1],
+                                     rng.choice(n, 8, replace=False)]))
+    ri = torch.as_tensor(rows, device="cuda")
+    G = gen()
+    for b in range(batch):
+        p = perm[b].cpu().numpy()
+        assert np.array_equal(np.sort(p), np.arange(n))
+        LU = F[b].T                                  # the factors, row-major view
+        Lfull = torch.tril(LU, -1)
+        assert float(Lfull.abs().max()) <= np.sqrt(2.0) * (1 + 4 * eps)
+        del Lfull
+        # the sampled rows of L: entries left of the diagonal, and the unit diagonal
+        cols = torch.arange(n, device="cuda")
+        Lr = torch.where(cols[None, :] < ri[:, None], LU[ri], torch.zeros((), dtype=dt, device="cuda"))
+        Lr[torch.arange(len(rows), device="cuda"), ri] = 1
+        U = torch.triu(LU)
+        got = (Lr.to(torch.complex128) @ U.to(torch.complex128)).cpu().numpy()
+        del U
+        Ab = G[b].T                                  # matrix b
+        want = Ab[torch.as_tensor(p[rows].astype(np.int64), device="cuda")].to(torch.complex128).cpu().numpy()
+        scale = float(Ab.abs().max())
+        err = np.max(np.abs(got - want)) / scale
+        assert err < 30 * n * eps, (b, err)
+    del F, G
+    torch.cuda.empty_cache()      # 2 x 26 GB (complex128) back to the device for the later tests
