@@ -539,7 +539,7 @@ bool HessEig::compute(int N_, std::vector<cplx>& A) {
     V.assign((size_t)N * N, 0.0);
     beta.assign(N, 0.0);
     std::vector<cplx> s(N);
-    // each reduction step ends in barriers: one thread up to N = 200 (measured on the machine's host,
+    // each reduction step ends in barriers: one thread up to N = 200 (measured on the MI355X machine's host CPU,
     // reduction and QR sweeps together: N = 162, 6.2 ms on one thread against 7.5-10 ms on six;
     // N = 132, 3.8 ms against 4.8-6.7 ms on four), the thread budget above (whole solves of the
     // batched eight-region workload with companion matrices of N = 256: 322-333 ms with it,
